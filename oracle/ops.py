@@ -1,0 +1,186 @@
+"""ctypes shim over the FP64 oracle library (test infrastructure only).
+
+Each function takes and returns float64 numpy arrays and forwards to the plain
+C definitions in ``misr_oracle.c``.  Shapes: HR images (H, W); LR frames
+(K, H//s, W//s); shifts (K, 2) as (dx, dy) in LR pixels; psf the 1-D taps whose
+outer product is the 2-D PSF.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "misr_oracle.c")
+_LIB = os.path.join(_HERE, "libmisr_oracle.so")
+_lib = None
+
+_D = ctypes.c_double
+_I = ctypes.c_int
+_P = ctypes.POINTER(ctypes.c_double)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-fno-fast-math", "-ffp-contract=off",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    sig = {
+        "orc_warp": [_I, _I, _D, _D, _P, _P],
+        "orc_warp_T": [_I, _I, _D, _D, _P, _P],
+        "orc_blur": [_I, _I, _I, _P, _P, _P],
+        "orc_blur_T": [_I, _I, _I, _P, _P, _P],
+        "orc_bin": [_I, _I, _I, _P, _P],
+        "orc_bin_T": [_I, _I, _I, _P, _P],
+        "orc_forward": [_I, _I, _I, _I, _P, _I, _P, _P, _P],
+        "orc_adjoint": [_I, _I, _I, _I, _P, _I, _P, _P, _P],
+        "orc_btv": [_I, _I, _D, _D, _D, _I, _P, _P],
+        "orc_cost_grad": [_I, _I, _I, _I, _P, _I, _P, _D, _D, _D, _I, _I, _D, _P, _P,
+                          _P, _P],
+        "orc_psi_quotient": [_D, _D, _D],
+        "orc_curv_exact": [_I, _I, _I, _I, _P, _I, _P, _D, _D, _D, _I, _D, _P, _P, _P],
+        "orc_num_threads": [],
+        "orc_set_threads": [_I],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = None
+    lib.orc_btv.restype = _D
+    lib.orc_cost_grad.restype = _D
+    lib.orc_psi_quotient.restype = _D
+    lib.orc_curv_exact.restype = _D
+    lib.orc_num_threads.restype = _I
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(_P)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return _load().orc_num_threads()
+
+
+def set_threads(n: int) -> None:
+    _load().orc_set_threads(int(n))
+
+
+def warp(x, tx, ty):
+    x = _f64(x)
+    out = np.empty_like(x)
+    _load().orc_warp(x.shape[0], x.shape[1], tx, ty, _p(x), _p(out))
+    return out
+
+
+def warp_T(z, tx, ty):
+    z = _f64(z)
+    out = np.empty_like(z)
+    _load().orc_warp_T(z.shape[0], z.shape[1], tx, ty, _p(z), _p(out))
+    return out
+
+
+def blur(z, psf):
+    z, psf = _f64(z), _f64(psf)
+    out = np.empty_like(z)
+    _load().orc_blur(z.shape[0], z.shape[1], psf.size, _p(psf), _p(z), _p(out))
+    return out
+
+
+def blur_T(w, psf):
+    w, psf = _f64(w), _f64(psf)
+    out = np.empty_like(w)
+    _load().orc_blur_T(w.shape[0], w.shape[1], psf.size, _p(psf), _p(w), _p(out))
+    return out
+
+
+def bin_(z, s):
+    z = _f64(z)
+    out = np.empty((z.shape[0] // s, z.shape[1] // s))
+    _load().orc_bin(z.shape[0], z.shape[1], s, _p(z), _p(out))
+    return out
+
+
+def bin_T(r, s, H, W):
+    r = _f64(r)
+    out = np.empty((H, W))
+    _load().orc_bin_T(H, W, s, _p(r), _p(out))
+    return out
+
+
+def forward(x, shifts, psf, s):
+    """y_k = D B M_k x for every frame; returns (K, H//s, W//s)."""
+    x, shifts, psf = _f64(x), _f64(shifts), _f64(psf)
+    H, W = x.shape
+    K = shifts.shape[0]
+    y = np.empty((K, H // s, W // s))
+    _load().orc_forward(H, W, s, K, _p(shifts), psf.size, _p(psf), _p(x), _p(y))
+    return y
+
+
+def adjoint(r, shifts, psf, s, H, W):
+    """sum_k A_k^T r_k; returns (H, W)."""
+    r, shifts, psf = _f64(r), _f64(shifts), _f64(psf)
+    K = shifts.shape[0]
+    x = np.empty((H, W))
+    _load().orc_adjoint(H, W, s, K, _p(shifts), psf.size, _p(psf), _p(r), _p(x))
+    return x
+
+
+def btv(x, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3, w=3, grad=True):
+    x = _f64(x)
+    g = np.zeros_like(x) if grad else None
+    E = _load().orc_btv(x.shape[0], x.shape[1], lambda_reg, alpha_btv, eps, w, _p(x), _p(g))
+    return (E, g) if grad else E
+
+
+def cost_grad(x, y, shifts, psf, s, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3, w=3,
+              data_p=2, eps_data=1e-3, grad=True):
+    """Returns (J, grad J or None, (E_data, E_reg))."""
+    x, y, shifts, psf = _f64(x), _f64(y), _f64(shifts), _f64(psf)
+    H, W = x.shape
+    K = shifts.shape[0]
+    g = np.empty_like(x) if grad else None
+    parts = np.zeros(2)
+    J = _load().orc_cost_grad(H, W, s, K, _p(shifts), psf.size, _p(psf), lambda_reg,
+                              alpha_btv, eps, w, data_p, eps_data, _p(x), _p(y), _p(g),
+                              _p(parts))
+    return J, g, (float(parts[0]), float(parts[1]))
+
+
+def psi_quotient(b, h, eps):
+    return _load().orc_psi_quotient(float(b), float(h), float(eps))
+
+
+def curvature_exact(x, p, shifts, psf, s, sk, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3,
+                    w=3):
+    """p^T (grad J(x + sk p) - grad J(x)) / sk for the L2 data term, closed form.
+
+    Returns (delta, (data part, BTV part))."""
+    x, p, shifts, psf = _f64(x), _f64(p), _f64(shifts), _f64(psf)
+    H, W = x.shape
+    parts = np.zeros(2)
+    d = _load().orc_curv_exact(H, W, s, shifts.shape[0], _p(shifts), psf.size, _p(psf),
+                               lambda_reg, alpha_btv, eps, w, sk, _p(x), _p(p), _p(parts))
+    return d, (float(parts[0]), float(parts[1]))

@@ -1,0 +1,505 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each operator is checked against an independent library routine (scipy's
+bilinear map_coordinates, scipy's 2-D convolution, a numpy reshape-mean), a
+closed form, or a mathematical property (adjointness, finite differences,
+exact reduction of SCG to linear CG on a quadratic).  Citations name the
+paper's section / equation.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage, signal
+
+import oracle
+from oracle import scg as oscg
+from paper_2108_04315_amd import synth
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+# --------------------------------------------------------------------------
+# independent library pipeline for A_k = D B M_k (Sec. 2.1, Eq. sisr)
+def lib_warp(x, tx, ty):
+    H, W = x.shape
+    uu, vv = np.meshgrid(np.arange(H, dtype=float), np.arange(W, dtype=float), indexing="ij")
+    return ndimage.map_coordinates(x, [uu + ty, vv + tx], order=1, mode="grid-constant",
+                                   cval=0.0, prefilter=False)
+
+
+def lib_blur(z, psf):
+    return signal.convolve2d(z, np.outer(psf, psf), mode="same", boundary="fill",
+                             fillvalue=0.0)
+
+
+def lib_bin(z, s):
+    H, W = z.shape
+    return z.reshape(H // s, s, W // s, s).mean(axis=(1, 3))
+
+
+def lib_forward(x, shifts, psf, s):
+    return np.stack([lib_bin(lib_blur(lib_warp(x, s * dx, s * dy), psf), s)
+                     for dx, dy in shifts])
+
+
+def dense_A(H, W, shifts, psf, s):
+    """Dense (K*m) x n matrix from impulse responses of the library pipeline."""
+    n = H * W
+    cols = []
+    for idx in range(n):
+        e = np.zeros(n)
+        e[idx] = 1.0
+        cols.append(lib_forward(e.reshape(H, W), shifts, psf, s).ravel())
+    return np.stack(cols, axis=1)
+
+
+CASES = [
+    # (H, W, s, shifts (dx, dy) LR px, psf sigma, P)
+    (8, 8, 2, [(0.0, 0.0), (0.5, 0.0), (0.5, 0.5), (0.0, 0.5)], 0.6, 5),
+    (9, 9, 3, [(0.0, 0.0), (1 / 3, 0.0), (2 / 3, 1 / 3), (0.37, 0.61)], 1.0, 7),
+    (8, 12, 2, [(0.0, 0.0), (-0.53, 0.21), (1.26, -0.77)], 0.8, 7),
+]
+
+
+@pytest.mark.parametrize("H,W,s,shifts,sig,P", CASES)
+def test_forward_matches_library_pipeline(H, W, s, shifts, sig, P):
+    """Sec. 2.1 Eq. sisr: A_k = D B M_k with bilinear M, P x P Gaussian B, s x s mean D."""
+    rng = np.random.default_rng(0)
+    shifts = np.array(shifts)
+    psf = synth.psf_taps(sig, P)
+    x = rng.standard_normal((H, W))
+    y_or = oracle.forward(x, shifts, psf, s)
+    y_lib = lib_forward(x, shifts, psf, s)
+    assert np.max(np.abs(y_or - y_lib)) <= 1e-14 * max(1.0, np.max(np.abs(y_lib)))
+
+
+@pytest.mark.parametrize("H,W,s,shifts,sig,P", CASES)
+def test_adjoint_matches_dense_transpose(H, W, s, shifts, sig, P):
+    rng = np.random.default_rng(1)
+    shifts = np.array(shifts)
+    psf = synth.psf_taps(sig, P)
+    A = dense_A(H, W, shifts, psf, s)
+    r = rng.standard_normal((len(shifts), H // s, W // s))
+    x_or = oracle.adjoint(r, shifts, psf, s, H, W)
+    assert np.max(np.abs(x_or.ravel() - A.T @ r.ravel())) <= 1e-13
+    # the dense system matrix applied to x equals the oracle's forward
+    x = rng.standard_normal((H, W))
+    assert np.max(np.abs(A @ x.ravel() - oracle.forward(x, shifts, psf, s).ravel())) <= 1e-13
+
+
+def test_individual_operators_match_library():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((11, 13))
+    for tx, ty in [(0.0, 0.0), (0.5, -1.25), (2.0, 3.0), (-0.3, 0.9)]:
+        assert np.allclose(oracle.warp(x, tx, ty), lib_warp(x, tx, ty), atol=1e-14, rtol=0)
+    psf = synth.psf_taps(0.8, 7)
+    assert np.allclose(oracle.blur(x, psf), lib_blur(x, psf), atol=1e-14, rtol=0)
+    z = rng.standard_normal((12, 15))
+    assert np.allclose(oracle.bin_(z, 3), lib_bin(z, 3), atol=1e-15, rtol=0)
+
+
+@pytest.mark.parametrize("H,W,s,K", [(48, 64, 2, 4), (45, 36, 3, 9), (10, 10, 1, 1)])
+def test_adjoint_dot_product(H, W, s, K):
+    """|<Ax,y> - <x,A^T y>| / (|<Ax,y>| + |<x,A^T y>|) <= 1e-12 on random inputs."""
+    rng = np.random.default_rng(3)
+    shifts = synth.frame_shifts(s, K, jitter=0.05, seed=4) if s > 1 else np.zeros((1, 2))
+    psf = synth.psf_taps(0.8)
+    x = rng.standard_normal((H, W))
+    y = rng.standard_normal((K, H // s, W // s))
+    lhs = float(np.sum(oracle.forward(x, shifts, psf, s) * y))
+    rhs = float(np.sum(x * oracle.adjoint(y, shifts, psf, s, H, W)))
+    assert abs(lhs - rhs) / (abs(lhs) + abs(rhs)) <= 1e-12
+
+
+def test_identity_special_case():
+    """s = 1, P = 1, zero shift: A is the identity."""
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((7, 9))
+    y = oracle.forward(x, np.zeros((1, 2)), np.ones(1), 1)
+    assert np.array_equal(y[0], x)
+
+
+def test_integer_shift_is_exact_copy():
+    """An integer HR shift moves the image with zero fill and no blending."""
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((10, 12))
+    out = oracle.warp(x, 2.0, -3.0)   # out(u,v) = x(u-3, v+2)
+    ref = np.zeros_like(x)
+    ref[3:, :-2] = x[:-3, 2:]
+    assert np.array_equal(out, ref)
+
+
+def test_bilinear_reproduces_linear_ramp_interior():
+    H, W = 16, 16
+    uu, vv = np.meshgrid(np.arange(H, dtype=float), np.arange(W, dtype=float), indexing="ij")
+    x = 0.3 * uu - 0.7 * vv + 2.0
+    tx, ty = 0.37, -0.61
+    out = oracle.warp(x, tx, ty)
+    ref = 0.3 * (uu + ty) - 0.7 * (vv + tx) + 2.0
+    assert np.max(np.abs(out[2:-2, 2:-2] - ref[2:-2, 2:-2])) <= 1e-13
+
+
+def test_constant_interior_preserved_by_blur_and_bin():
+    x = np.full((20, 20), 0.75)
+    psf = synth.psf_taps(0.8)
+    b = oracle.blur(x, psf)
+    assert np.max(np.abs(b[3:-3, 3:-3] - 0.75)) <= 1e-15
+    d = oracle.bin_(b, 2)
+    assert np.max(np.abs(d[2:-2, 2:-2] - 0.75)) <= 1e-15
+
+
+def test_zero_data_cost_at_ground_truth_noiseless():
+    """Eq. l2misr at x_gt with y generated by the same discrete A is exactly 0."""
+    prob = synth.make_problem(oracle.forward, L=24, s=2, sigma=0.6, P=5, noise=("none", 0),
+                              jitter=0.05, n_iter=1, seeds=(0, 1, 2))
+    J, g, (Ed, Er) = oracle.cost_grad(prob.x_gt, prob.y, prob.shifts, prob.psf, prob.s)
+    assert Ed <= 1e-24 * float(np.sum(prob.y ** 2))
+    # and the data part of the gradient equals 2 A^T (A x - y) = 0 there
+    _, g_reg = oracle.btv(prob.x_gt)
+    assert np.max(np.abs(g - g_reg)) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# BTV prior (Eq. prior) with the paper's gamma(d) = alpha^(dx+dy)
+def test_gamma_table_golden():
+    """tests/golden/btv_gamma.txt: gamma(d) = alpha^(dx+dy), alpha = 0.4, w = 3 (Eq. prior;
+    alpha = 0.4 is the paper's setting in Sec. 3)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "btv_gamma.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    tab = {(int(a), int(b)): float(c) for a, b, c in rows}
+    assert len(tab) == 8
+    # one isolated bright pixel in a zero image: E_reg = sum over the pairs
+    # that contain it, each phi(1)
+    H = W = 9
+    x = np.zeros((H, W))
+    x[4, 4] = 1.0
+    eps = 1e-3
+    E = oracle.btv(x, lambda_reg=1.0, alpha_btv=0.4, eps=eps, w=3, grad=False)
+    phi1 = math.sqrt(1 + eps * eps) - eps
+    assert abs(E - 2 * phi1 * sum(tab.values())) <= 1e-13
+
+
+def test_btv_constant_image_zero():
+    x = np.full((12, 10), 0.3)
+    E, g = oracle.btv(x, 0.05, 0.4, 1e-3, 3)
+    assert E == 0.0 and np.all(g == 0.0)
+
+
+@pytest.mark.parametrize("eps", [1e-3, 0.0])
+def test_btv_vertical_step_edge_closed_form(eps):
+    """x = 0 left of column c, h right of it.  Pair (u,v)-(u+dy,v+dx) crosses the
+    edge iff v in [c-dx, c-1]: E = lam phi(h) sum_{dx>=1,dy} a^(dx+dy) dx (H-dy)."""
+    H, W, c, h, lam, a, w = 10, 12, 5, 0.8, 0.05, 0.4, 3
+    x = np.zeros((H, W))
+    x[:, c:] = h
+    E, g = oracle.btv(x, lam, a, eps, w)
+    phi = math.sqrt(h * h + eps * eps) - eps
+    ref = lam * phi * sum(a ** (dx + dy) * dx * (H - dy)
+                          for dx in range(1, w) for dy in range(w))
+    assert abs(E - ref) <= 1e-14
+    # gradient non-zero only within w-1 columns of the edge
+    nz = np.nonzero(np.any(g != 0, axis=0))[0]
+    assert nz.min() >= c - (w - 1) and nz.max() <= c + (w - 2)
+    # hand check on the 6x6 case at one pixel left of the edge, interior row:
+    # pairs from (u, c-1) to the right cross with z = -h for dx in {1, 2}; pairs
+    # from (u, c-2) with dx = 2 end at (., c); pairs into (u, c-1) from the left
+    # have z = 0.
+    x6 = np.zeros((6, 6))
+    x6[:, 3:] = h
+    _, g6 = oracle.btv(x6, lam, a, eps, w)
+    psi = (-h / math.sqrt(h * h + eps * eps)) if eps > 0 else -1.0
+    # u = 2 (rows u+dy for dy in 0..2 exist), v = 2
+    ref_g = lam * psi * sum(a ** (dx + dy) for dx in (1, 2) for dy in (0, 1, 2))
+    assert abs(g6[2, 2] - ref_g) <= 1e-14
+
+
+# --------------------------------------------------------------------------
+# gradient of J (Eq. objective) by central differences
+@pytest.mark.parametrize("s,K,sig", [(2, 4, 0.6), (3, 9, 1.0)])
+def test_gradient_central_differences(s, K, sig):
+    rng = np.random.default_rng(7)
+    H = W = 8 * s
+    shifts = synth.frame_shifts(s, K, 0.05, 3)
+    psf = synth.psf_taps(sig)
+    x = rng.uniform(0, 1, (H, W))
+    y = rng.uniform(0, 1, (K, H // s, W // s))
+    J, g, _ = oracle.cost_grad(x, y, shifts, psf, s)
+    v = rng.uniform(-1, 1, (H, W))
+    v /= np.max(np.abs(v))
+    h = 1e-7
+    Jp = oracle.cost_grad(x + h * v, y, shifts, psf, s, grad=False)[0]
+    Jm = oracle.cost_grad(x - h * v, y, shifts, psf, s, grad=False)[0]
+    fd = (Jp - Jm) / (2 * h)
+    an = float(np.sum(g * v))
+    assert abs(an - fd) / abs(an) <= 1e-6
+
+
+def test_gradient_each_coordinate_8x8():
+    rng = np.random.default_rng(8)
+    H = W = 8
+    shifts = synth.frame_shifts(2, 4, 0.05, 3)
+    psf = synth.psf_taps(0.6)
+    x = rng.uniform(0, 1, (H, W))
+    y = rng.uniform(0, 1, (4, 4, 4))
+    _, g, _ = oracle.cost_grad(x, y, shifts, psf, 2)
+    h = 1e-6
+    for idx in range(H * W):
+        e = np.zeros(H * W)
+        e[idx] = h
+        e = e.reshape(H, W)
+        fd = (oracle.cost_grad(x + e, y, shifts, psf, 2, grad=False)[0]
+              - oracle.cost_grad(x - e, y, shifts, psf, 2, grad=False)[0]) / (2 * h)
+        assert abs(fd - g.ravel()[idx]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_l1_data_term_gradient():
+    """Eq. misr with p = 1 (Charbonnier-smoothed): central differences."""
+    rng = np.random.default_rng(9)
+    shifts = synth.frame_shifts(2, 4, 0.05, 3)
+    psf = synth.psf_taps(0.6)
+    x = rng.uniform(0, 1, (16, 16))
+    y = rng.uniform(0, 1, (4, 8, 8))
+    J, g, _ = oracle.cost_grad(x, y, shifts, psf, 2, data_p=1, eps_data=1e-2)
+    v = rng.uniform(-1, 1, x.shape)
+    h = 1e-7
+    fd = (oracle.cost_grad(x + h * v, y, shifts, psf, 2, data_p=1, eps_data=1e-2, grad=False)[0]
+          - oracle.cost_grad(x - h * v, y, shifts, psf, 2, data_p=1, eps_data=1e-2,
+                             grad=False)[0]) / (2 * h)
+    assert abs(float(np.sum(g * v)) - fd) <= 1e-6 * abs(fd)
+
+
+# --------------------------------------------------------------------------
+# curvature: literal finite difference vs closed form vs dense Hessian
+def dense_btv_hessian(x, lam, a, eps, w):
+    H, W = x.shape
+    n = H * W
+    Hs = np.zeros((n, n))
+    for dy in range(w):
+        for dx in range(w):
+            if dx == dy == 0:
+                continue
+            for u in range(H - dy):
+                for v in range(W - dx):
+                    i, j = u * W + v, (u + dy) * W + v + dx
+                    z = x.flat[i] - x.flat[j]
+                    c = lam * a ** (dx + dy) * eps * eps / (z * z + eps * eps) ** 1.5
+                    Hs[i, i] += c
+                    Hs[j, j] += c
+                    Hs[i, j] -= c
+                    Hs[j, i] -= c
+    return Hs
+
+
+def test_curvature_forms_agree():
+    rng = np.random.default_rng(10)
+    H = W = 8
+    s, K = 2, 4
+    shifts = synth.frame_shifts(s, K, 0.05, 1)
+    psf = synth.psf_taps(0.6)
+    x = rng.uniform(0, 1, (H, W))
+    x[2, 3] = x[2, 4]             # a pair with z = 0 exactly
+    y = rng.uniform(0, 1, (K, 4, 4))
+    p = rng.standard_normal((H, W))
+    sk = 1e-4 / np.linalg.norm(p)
+    _, g0, _ = oracle.cost_grad(x, y, shifts, psf, s)
+    _, g1, _ = oracle.cost_grad(x + sk * p, y, shifts, psf, s)
+    d_fd = float(np.sum(p * (g1 - g0))) / sk
+    d_ex, _ = oracle.curvature_exact(x, p, shifts, psf, s, sk)
+    assert abs(d_fd - d_ex) / abs(d_ex) <= 1e-9
+    # dense Hessian: 2 A^T A + BTV second derivative, from independent code
+    A = dense_A(H, W, shifts, psf, s)
+    Hd = 2 * A.T @ A + dense_btv_hessian(x, 0.01, 0.4, 1e-3, 3)
+    d_h = float(p.ravel() @ Hd @ p.ravel())
+    # the quotient tends to p^T H p as the perturbation shrinks (it is stable
+    # for tiny h); at sigma = 1e-4 they differ by O(sk |q| / eps)
+    d_lim, _ = oracle.curvature_exact(x, p, shifts, psf, s, 1e-12)
+    assert abs(d_h - d_lim) / abs(d_h) <= 1e-9
+    assert abs(d_h - d_ex) / abs(d_h) <= 10 * sk * np.max(np.abs(p)) / 1e-3
+
+
+def test_psi_quotient_stable_form():
+    eps = 1e-3
+    for b in [0.0, 1e-5, -3e-4, 2e-3, -0.5, 0.7]:
+        for h in [1e-9, 1e-6, -2e-4, 1e-3, -1.2]:
+            a = b + h
+            lit = (a / math.sqrt(a * a + eps * eps) - b / math.sqrt(b * b + eps * eps)) / h
+            q = oracle.psi_quotient(b, h, eps)
+            # the literal difference loses about ulp(psi) / |h| to cancellation
+            lost = 4 * 2.0 ** -53 * (abs(a) / math.sqrt(a * a + eps * eps)
+                                     + abs(b) / math.sqrt(b * b + eps * eps)) / abs(h)
+            assert abs(q - lit) <= 1e-12 * abs(q) + lost
+
+
+# --------------------------------------------------------------------------
+# SCG (Moller 1993, cited for the solver in Sec. 2.1; loop of Algorithm 1)
+def test_moller_scale_delta_rules():
+    # positive delta: only the lam shift
+    d, l, lb = oscg.moller_scale_delta(2.0, 0.5, 0.0, 4.0)
+    assert (d, l, lb) == (4.0, 0.5, 0.0)
+    # negative delta after the shift: Hessian made positive definite
+    d, l, lb = oscg.moller_scale_delta(-3.0, 0.25, 0.0, 2.0)
+    # delta = -3 + 0.5 = -2.5 -> lam_bar = 2 (0.25 + 1.25) = 3, delta = 2.5 + 0.5 = 3
+    assert lb == 3.0 and l == 3.0 and d == 3.0
+    # failure carry-over: lam_bar = lam, then lam raised; rescale adds the rise only
+    d, l, lb = oscg.moller_scale_delta(1.0, 0.75, 0.5, 2.0)
+    assert d == 1.5 and l == 0.75 and lb == 0.5
+
+
+def test_moller_lambda_rules():
+    assert oscg.moller_update_lambda(0.8, 1.0, 3.0, 2.0) == 0.25
+    assert oscg.moller_update_lambda(0.75, 1.0, 3.0, 2.0) == 0.25
+    assert oscg.moller_update_lambda(0.5, 1.0, 3.0, 2.0) == 1.0
+    assert oscg.moller_update_lambda(0.25, 1.0, 3.0, 2.0) == 1.0
+    assert oscg.moller_update_lambda(0.1, 1.0, 3.0, 2.0) == 1.0 + 3.0 * 0.9 / 2.0
+    assert oscg.moller_update_lambda(-1.0, 1.0, 3.0, 2.0) == 1.0 + 3.0 * 2.0 / 2.0
+
+
+def _quadratic(y):
+    def f(x, need_grad=True):
+        d = x - y
+        return float(np.sum(d * d)), 2 * d
+    return f
+
+
+def test_scg_one_step_closed_form():
+    """A = I, no prior: x1 = y + (x0 - y) lam1 / (2 + lam1)."""
+    rng = np.random.default_rng(11)
+    y = rng.standard_normal((6, 7))
+    x0 = rng.standard_normal((6, 7))
+    lam1 = 1e-6
+    ref = y + (x0 - y) * lam1 / (2 + lam1)
+    scale = max(1, np.max(np.abs(ref)))
+    # curvature in closed form (2 |p|^2 for this J): exact to rounding
+    x1, tr, _ = oscg.scg_minimize(_quadratic(y), x0, 1, lam1=lam1,
+                                  curvature=lambda x, p, sk: 2 * float(np.sum(p * p)))
+    assert np.max(np.abs(x1 - ref)) <= 1e-15 * scale
+    # literal finite-difference curvature: its quotient of two FP64 gradients
+    # carries a relative error ~ ulp * |g| / (sk |H p|) ~ 1e-12
+    x1, tr, _ = oscg.scg_minimize(_quadratic(y), x0, 1, lam1=lam1)
+    assert np.max(np.abs(x1 - ref)) <= 1e-10 * scale
+    # same through the MISR operators with s = 1, P = 1, zero shift, lambda = 0
+    x1b, _, _ = oscg.solve(y[None], np.zeros((1, 2)), np.ones(1), 1, x0, 1, lambda_reg=0.0,
+                           exact_curvature=True)
+    assert np.max(np.abs(x1b - ref)) <= 1e-15 * scale
+
+
+def _tiny_full_rank():
+    rng = np.random.default_rng(12)
+    H = W = 8
+    psf = synth.psf_taps(0.5, 3)
+    shifts = np.zeros((1, 2))
+    xt = rng.uniform(0, 1, (H, W))
+    y = oracle.forward(xt, shifts, psf, 1) + 0.01 * rng.standard_normal((1, H, W))
+    return H, W, psf, shifts, y
+
+
+def test_scg_tracks_linear_cg_on_quadratic():
+    """lambda_reg = 0, p = 2: J is quadratic, SCG iterates follow linear CG on
+    A^T A x = A^T y (hand-written CG on the dense matrix)."""
+    H, W, psf, shifts, y = _tiny_full_rank()
+    A = dense_A(H, W, shifts, psf, 1)
+    Hm = 2 * A.T @ A
+    b = 2 * A.T @ y.ravel()
+    x = np.zeros(H * W)
+    r = b - Hm @ x
+    p = r.copy()
+    cg = []
+    for _ in range(10):
+        Hp = Hm @ p
+        al = (r @ r) / (p @ Hp)
+        x = x + al * p
+        rn = r - al * Hp
+        p = rn + (rn @ rn) / (r @ r) * p
+        r = rn
+        cg.append(x.copy())
+    for k in range(1, 11):
+        xs, tr, _ = oscg.solve(y, shifts, psf, 1, np.zeros((H, W)), k, lambda_reg=0.0)
+        assert all(t["success"] for t in tr)
+        rel = np.linalg.norm(xs.ravel() - cg[k - 1]) / np.linalg.norm(cg[k - 1])
+        assert rel <= 1e-5, (k, rel)
+
+
+def test_scg_converges_to_normal_equation_solution():
+    H, W, psf, shifts, y = _tiny_full_rank()
+    A = dense_A(H, W, shifts, psf, 1)
+    xs_ref = np.linalg.solve(A.T @ A, A.T @ y.ravel())
+    xs, tr, _ = oscg.solve(y, shifts, psf, 1, np.zeros((H, W)), 120, lambda_reg=0.0)
+    assert np.linalg.norm(xs.ravel() - xs_ref) / np.linalg.norm(xs_ref) <= 1e-8
+
+
+def test_scg_reaches_dense_newton_minimiser():
+    """Strictly convex J (eps > 0, full-rank A, BTV on): SCG after 400 passes
+    equals the minimiser found by Newton's method on independently built dense
+    derivatives."""
+    H, W, psf, shifts, y = _tiny_full_rank()
+    lam, a, eps = 0.01, 0.4, 1e-2
+    A = dense_A(H, W, shifts, psf, 1)
+
+    def grad_np(x):
+        g = 2 * A.T @ (A @ x - y.ravel())
+        X = x.reshape(H, W)
+        G = np.zeros((H, W))
+        for dy in range(3):
+            for dx in range(3):
+                if dx == dy == 0:
+                    continue
+                z = X[:H - dy, :W - dx] - X[dy:, dx:]
+                ps = lam * a ** (dx + dy) * z / np.sqrt(z * z + eps * eps)
+                G[:H - dy, :W - dx] += ps
+                G[dy:, dx:] -= ps
+        return g + G.ravel()
+
+    x = np.zeros(H * W)
+    for _ in range(50):
+        Hd = 2 * A.T @ A + dense_btv_hessian(x.reshape(H, W), lam, a, eps, 3)
+        x = x - np.linalg.solve(Hd, grad_np(x))
+    assert np.linalg.norm(grad_np(x)) <= 1e-12
+    xs, _, _ = oscg.solve(y, shifts, psf, 1, np.zeros((H, W)), 400, lambda_reg=lam,
+                          alpha_btv=a, eps=eps)
+    assert np.linalg.norm(xs.ravel() - x) / np.linalg.norm(x) <= 1e-8
+
+
+def test_scg_energy_monotone_and_lambda_positive():
+    prob = synth.make_problem(oracle.forward, L=24, s=2, sigma=0.6, P=5,
+                              noise=("gauss", 0.01), jitter=0.0, n_iter=30, seeds=(0, 0, 1))
+    _, tr, _ = oscg.solve(prob.y, prob.shifts, prob.psf, 2, prob.x0, 30)
+    Es = [t["E"] for t in tr]
+    assert all(b <= a for a, b in zip(Es, Es[1:]))
+    assert all(t["lam"] > 0 for t in tr)
+
+
+def test_exact_curvature_solve_matches_literal():
+    """The closed-form curvature (used on the GPU) gives the same trajectory."""
+    prob = synth.make_problem(oracle.forward, L=32, s=2, sigma=0.6, P=5,
+                              noise=("gauss", 0.01), jitter=0.0, n_iter=20, seeds=(0, 0, 1))
+    xa, ta, _ = oscg.solve(prob.y, prob.shifts, prob.psf, 2, prob.x0, 20)
+    xb, tb, _ = oscg.solve(prob.y, prob.shifts, prob.psf, 2, prob.x0, 20, exact_curvature=True)
+    assert [t["success"] for t in ta] == [t["success"] for t in tb]
+    assert np.linalg.norm(xa - xb) / np.linalg.norm(xa) <= 1e-9
+
+
+# --------------------------------------------------------------------------
+# input generator
+def test_bicubic_reproduces_quadratic_interior():
+    lr = np.add.outer(np.arange(10.0) ** 2 * 0.01, np.arange(12.0) * 0.3)
+    hr = synth.bicubic_upsample(lr, 2)
+    c = (np.arange(20) + 0.5) / 2 - 0.5
+    d = (np.arange(24) + 0.5) / 2 - 0.5
+    ref = np.add.outer(c ** 2 * 0.01, d * 0.3)
+    # Keys a = -1/2 is exact for quadratics away from the clamped border
+    assert np.max(np.abs(hr[4:-4, 4:-4] - ref[4:-4, 4:-4])) <= 1e-12
+
+
+def test_psf_sizes_and_shift_order():
+    assert synth.psf_size(0.6) == 5 and synth.psf_size(0.8) == 7 and synth.psf_size(1.0) == 7
+    assert abs(synth.psf_taps(0.8).sum() - 1) <= 1e-15
+    sh = synth.frame_shifts(2)
+    assert sh.tolist() == [[0, 0], [0.5, 0], [0.5, 0.5], [0, 0.5]]
+    sh3 = synth.frame_shifts(3, jitter=0.05, seed=1)
+    assert sh3.shape == (9, 2) and np.all(sh3[0] == 0)
+    assert np.all(np.abs(sh3[1:] - synth.frame_shifts(3)[1:]) <= 0.05)
