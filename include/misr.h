@@ -1,0 +1,243 @@
+/*
+ * misr.h -- C ABI of libmisr.so: the SCG cost/gradient hot path of multi-image
+ * super-resolution (FL-MISR, arXiv 2108.04315) on one AMD MI355X (gfx950).
+ *
+ * Problem statement (Sec. 2.1): K low-resolution frames y_k, each the image of
+ * the unknown high-resolution image x under a known system matrix
+ * A_k = D B M_k (Eq. sisr: M_k motion, B blur, D decimation), plus noise.
+ * x minimises (Eq. objective, split as in Eq. reformulated)
+ *
+ *     J(x) = sum_k || A_k x - y_k ||_p^p  +  lambda * sum_d gamma(d) || x - S_d x ||_1
+ *
+ * with the bilateral total variation prior of Eq. prior, gamma(d) = alpha^(dx+dy),
+ * d in [0, w-1]^2 minus the origin.  The minimiser is found with the scaled
+ * conjugate gradient method the paper uses (Sec. 2.1, Algorithm 1; Moller 1993)
+ * for a fixed number of passes (Algorithm 1's loop bound).
+ *
+ * Readings fixed by this library where the paper is silent:
+ *   - M_k is a bilinear translation by (dx_k, dy_k) LR pixels = s*(dx_k, dy_k)
+ *     HR pixels, zero outside the image: (M_k x)(u,v) = x~(u + s dy_k, v + s dx_k);
+ *   - B is a "same" 2-D convolution with zero padding by the P x P PSF
+ *     psf_1d (outer) psf_1d;
+ *   - D is s x s block averaging; A_k is applied M first, then B, then D;
+ *   - the L1 norms are smoothed: phi(z) = sqrt(z^2 + eps^2) - eps
+ *     (eps = 0 gives |z| with sign(0) = 0);
+ *   - BTV pairs (i, i + d) count only when both pixels are inside the image.
+ *
+ * Layouts.  Images are dense row-major, row stride = width.  x is H x W.
+ * y is K contiguous frames of (H/s) x (W/s).  The gradient and all scratch
+ * vectors are float32.  x and y are stored as misr_dtype (f32, f16 or bf16);
+ * arithmetic is float32, and inner products and SCG scalars are float64.
+ *
+ * Ownership.  The caller owns every data buffer (device memory unless stated);
+ * the library never frees them and keeps no pointer past the call, except for
+ * server requests, whose buffers must stay valid until the request is DONE,
+ * FAILED or CANCELLED.  The library owns ctx, op and server handles and frees
+ * them in the matching *_destroy call.  Workspace is library-owned and cached
+ * per op.
+ *
+ * Errors.  Every entry point returns misr_status; no C++ exception crosses the
+ * ABI.  Arguments are validated on the host before any launch (MISR_E_INVAL,
+ * with a message in misr_last_error()).  Work is enqueued asynchronously on the
+ * given HIP stream (a hipStream_t passed as void*, NULL = default stream) unless
+ * a function says it synchronises.  Calls that share an op must not overlap in
+ * time on different streams (the op's workspace is shared).
+ */
+#ifndef MISR_H
+#define MISR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MISR_OK = 0,
+    MISR_E_INVAL = 1,     /* bad argument; nothing was launched */
+    MISR_E_NOMEM = 2,     /* device allocation failed or HBM budget exceeded */
+    MISR_E_HIP = 3,       /* a HIP runtime call failed */
+    MISR_E_NUMERIC = 4,   /* non-finite cost or curvature: solve stopped early */
+    MISR_E_BUSY = 5,      /* server queue full */
+    MISR_E_NOTFOUND = 6,  /* unknown request id */
+    MISR_E_CANCELLED = 7, /* request was cancelled */
+    MISR_E_TIMEOUT = 8    /* wait timed out */
+} misr_status;
+
+typedef enum { MISR_F32 = 0, MISR_F16 = 1, MISR_BF16 = 2 } misr_dtype;
+
+typedef struct misr_ctx misr_ctx;
+typedef struct misr_op misr_op;
+typedef struct misr_server misr_server;
+
+/* Acquisition geometry (Sec. 2.1 Eq. sisr; Sec. 2.2: frames shifted by a
+ * fraction of a detector pixel).  All pointers are host memory, read during
+ * misr_op_create only. */
+typedef struct {
+    int32_t hr_h, hr_w;       /* HR image size; both divisible by scale */
+    int32_t scale;            /* s >= 1: LR frame is (hr_h/s) x (hr_w/s) */
+    int32_t n_frames;         /* K >= 1 */
+    const double *shifts_lr;  /* [K][2] = (dx, dy) in LR pixels, |dx|,|dy| <= 1 */
+    int32_t psf_size;         /* P, odd, 1 <= P <= 15 */
+    const double *psf_1d;     /* [P] taps; the 2-D PSF is their outer product */
+} misr_geometry;
+
+/* Objective and solver settings (Eq. objective, Eq. prior, Algorithm 1). */
+typedef struct {
+    double lambda_reg;   /* lambda >= 0 (default 0.01) */
+    double alpha_btv;    /* alpha in (0, 1) (default 0.4) */
+    double eps;          /* Charbonnier eps of the prior >= 0 (default 1e-3) */
+    int32_t btv_w;       /* window w in [1, 3] (default 3) */
+    int32_t data_p;      /* data norm p in {1, 2} (default 2) */
+    double eps_data;     /* Charbonnier eps of the L1 data term (p = 1) >= 0 */
+    double scg_sigma;    /* SCG sigma > 0 (default 1e-4) */
+    double scg_lambda1;  /* SCG initial scale lambda_1 > 0 (default 1e-6) */
+    int32_t n_iter;      /* SCG passes >= 0, failed passes included */
+    misr_dtype img_dtype;/* storage of x and y */
+    int32_t tile_lr;     /* 0: solve the image whole; else split into tiles of
+                            tile_lr x tile_lr LR pixels held separately in HBM
+                            with a halo exchanged every pass */
+    int32_t halo_lr;     /* halo width in LR pixels for tile_lr > 0 */
+} misr_params;
+
+/* One SCG pass as recorded on the device. */
+typedef struct {
+    double E;        /* cost after the pass */
+    double E_t;      /* cost at the trial point x + alpha p */
+    double delta;    /* scaled curvature used for alpha */
+    double mu;       /* p . r */
+    double alpha;    /* step size mu / delta */
+    double Delta;    /* comparison parameter */
+    double lam;      /* scale parameter after the pass */
+    int32_t success; /* 1 if the step was accepted */
+    int32_t pad_;
+} misr_scg_iter;
+
+typedef struct {
+    misr_scg_iter *iters; /* host array with room for `capacity` passes, or NULL */
+    int32_t capacity;
+    int32_t n_passes;     /* out: passes run (< n_iter only on early stop) */
+    int32_t n_success;    /* out: accepted passes */
+    int32_t stop;         /* out: 0 ran all passes, 1 ||r|| = 0, 2 non-finite */
+    double E0;            /* out: cost at x0 */
+    double E_final;       /* out: cost at the returned x */
+} misr_scg_trace;
+
+/* ------------------------------------------------------------------ setup */
+/* Fills p with the defaults listed above (n_iter = 50, f32, untiled). */
+void misr_params_default(misr_params *p);
+
+/* Host-only validation (no device is touched). */
+misr_status misr_geometry_check(const misr_geometry *g);
+misr_status misr_params_check(const misr_params *p);
+
+/* Thread-local description of the last error on this thread; valid until the
+ * next misr_* call on the same thread. */
+const char *misr_last_error(void);
+
+/* Binds a context to HIP device `hip_device` (ordinal). */
+misr_status misr_ctx_create(int hip_device, misr_ctx **out);
+misr_status misr_ctx_destroy(misr_ctx *ctx);
+
+/* Precomputes the operator: per frame, the 1-D band weights of A_k's row and
+ * column factors (A_k = C_y,k (x) C_x,k is exact because M, B and D are all
+ * separable, zero padding included).  Built once and reused by every call on
+ * this geometry, as the paper builds A_i once per acquisition (Sec. 2.2). */
+misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, misr_op **out);
+misr_status misr_op_destroy(misr_op *op);
+/* Band length L of the per-frame 1-D factors (taps per LR pixel per axis). */
+int misr_op_band(const misr_op *op);
+
+/* --------------------------------------------------------------- operators */
+/* y[k] = A_k x for every frame (Eq. sisr without noise).
+ * x: device, H*W elements of dtype dt.  y: device, K*(H/s)*(W/s) of dtype dt. */
+misr_status misr_forward(const misr_op *op, misr_dtype dt, const void *x, void *y,
+                         void *stream);
+
+/* x = sum_k A_k^T r_k.  r: device, K*(H/s)*(W/s) of dtype dt.  x: device, H*W
+ * float32 (overwritten). */
+misr_status misr_adjoint(const misr_op *op, misr_dtype dt, const void *r, float *x,
+                         void *stream);
+
+/* J(x) and grad J(x) (Eq. objective).  x, y: device, params->img_dtype.
+ * g: device float32 H*W (overwritten).  cost_dev: device double[3] receiving
+ * {J, data term, lambda * prior}.  Honours params->tile_lr. */
+misr_status misr_cost_grad(const misr_op *op, const misr_params *params, const void *x,
+                           const void *y, float *g, double *cost_dev, void *stream);
+
+/* SCG solve (Algorithm 1 on one GPU): params->n_iter passes from x_inout,
+ * result written back to x_inout (device, params->img_dtype).  y: device.
+ * trace (host, nullable): when given, the call synchronises the stream and
+ * fills it.  Returns MISR_E_NUMERIC (only when trace is given) if the solve
+ * stopped on a non-finite value; x_inout then holds the last finite iterate. */
+misr_status misr_scg_solve(const misr_op *op, const misr_params *params, const void *y,
+                           void *x_inout, misr_scg_trace *trace, void *stream);
+
+/* n independent solves advanced together: every SCG pass of every projection
+ * runs in the same kernel launches (one work list over all projections' tiles).
+ * Per-projection state stays separate, so each result equals its solo solve.
+ * ops/params/y/x/traces are host arrays of length n (traces nullable, entries
+ * nullable).  Projections may differ in geometry and n_iter but must share
+ * img_dtype and have tile_lr == 0. */
+misr_status misr_scg_solve_batch(int n, const misr_op *const *ops,
+                                 const misr_params *params, const void *const *y,
+                                 void *const *x_inout, misr_scg_trace *traces, void *stream);
+
+/* ------------------------------------------------------------------ serving */
+/* On-the-fly acquisition (Sec. 2.2): each rotation angle's frames arrive as a
+ * request; requests are admitted while device memory allows and solved
+ * together, each pass of every admitted solve in the same launches. */
+typedef enum {
+    MISR_REQ_QUEUED = 0,
+    MISR_REQ_RUNNING = 1,
+    MISR_REQ_DONE = 2,
+    MISR_REQ_FAILED = 3,
+    MISR_REQ_CANCELLED = 4
+} misr_req_state;
+
+typedef void (*misr_done_cb)(uint64_t id, misr_status status, void *user);
+
+typedef struct {
+    misr_geometry geom;       /* host arrays read during submit */
+    misr_params params;       /* tile_lr > 0 splits a large request into tiles */
+    const void *y;            /* K frames (device or host, see below) */
+    const void *x0;           /* initial HR image */
+    void *x_out;              /* result (device or host) */
+    int32_t on_device;        /* 1: y, x0, x_out are device pointers; 0: host */
+    misr_done_cb done_cb;     /* nullable; called from the scheduler thread */
+    void *user;
+} misr_request;
+
+typedef struct {
+    size_t hbm_budget_bytes;  /* cap on device memory for admitted requests */
+    int32_t max_slots;        /* cap on concurrently admitted requests */
+    int32_t max_queue;        /* submit returns MISR_E_BUSY beyond this */
+    int32_t fail_alloc_n;     /* fault hook: the n-th slot allocation fails (0 off) */
+    int32_t pad_;
+} misr_server_config;
+
+typedef struct {
+    double t_submit_us, t_admit_us, t_done_us;  /* host steady clock */
+    int32_t n_passes, n_success;
+    misr_status status;
+    int32_t pad_;
+    double E_final;
+} misr_req_stats;
+
+misr_status misr_server_create(misr_ctx *ctx, const misr_server_config *cfg,
+                               misr_server **out);
+/* Non-blocking; assigns *id. */
+misr_status misr_server_submit(misr_server *s, const misr_request *req, uint64_t *id);
+misr_status misr_server_poll(misr_server *s, uint64_t id, misr_req_state *state,
+                             misr_req_stats *stats);
+/* Blocks until the request leaves QUEUED/RUNNING or timeout_us passes (<0: forever). */
+misr_status misr_server_wait(misr_server *s, uint64_t id, int64_t timeout_us);
+misr_status misr_server_cancel(misr_server *s, uint64_t id);
+/* Drains every submitted request, then frees the server. */
+misr_status misr_server_destroy(misr_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MISR_H */

@@ -1,0 +1,85 @@
+// internal.h -- device-side data structures shared by the kernels and the
+// host runtime of libmisr.so (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace misr {
+
+constexpr int kNT = 256;     // threads per workgroup of the image kernels
+constexpr int kNV = 6;       // FP64 partial sums per work item
+constexpr int kMaxK = 16;    // frames per projection
+constexpr int kMaxL = 16;    // band length
+
+enum StorageType : int { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+
+// Operator of one geometry: per frame the two 1-D factors of A_k.
+// Row factor: LR row i reads HR rows s*i + offy[k] + l, l in [0, L), with
+// weight wy[(k*h + i)*L + l]; columns likewise with wx / offx.
+struct OpDev {
+    const float *wy;
+    const float *wx;
+    int offy[kMaxK];
+    int offx[kMaxK];
+    int H, W, s, K, L;
+};
+
+// One image (or one tile of an image held separately in HBM) in a work list.
+// Buffers are H-major with row stride ld; buffer pixel (u, v) is global
+// pixel (gy0 + u, gx0 + v).  The owned rectangle [oy0,oy1) x [ox0,ox1)
+// (buffer coordinates, multiples of s in global coordinates) is what this
+// view computes, writes and counts in its reductions; the rest is halo.
+struct Proj {
+    void *x[2];          // storage type
+    float *p[2];
+    float *g[2];
+    const void *y;       // global frames K x h x w, storage type
+    int ld, Hb, Wb;
+    int gy0, gx0;
+    int oy0, oy1, ox0, ox1;
+    int ntx;             // tiles per row of the owned rectangle
+    int req;             // index of the solve this view belongs to
+    const OpDev *op;
+};
+
+struct Item {
+    int proj;            // index into Proj array
+    int ty, tx;          // tile coordinates in the owned rectangle
+    int pad_;
+};
+
+// Objective weights for the kernels (float) plus solver constants.
+struct Weights {
+    float gam[9];        // lambda * alpha^(dx+dy) at [dy*3+dx]; 0 outside window
+    float eps;           // prior Charbonnier eps
+    float eps_data;      // data Charbonnier eps (p = 1)
+    int data_p;
+};
+
+// Device-resident SCG state of one solve (Moller's scalars, FP64).
+struct ScgState {
+    double E, E0, lam, lam_bar, delta, mu, pi, rr;
+    double alpha, beta, sigma, sigk;
+    double E_t, Delta;
+    long long N;         // restart period: number of unknowns
+    int k, it, n_iter, n_success;
+    int success;         // last pass accepted (curvature to be recomputed)
+    int cur;             // g[cur] is the current gradient
+    int xc;              // x[xc], p[xc] hold the current iterate
+    int upd_src;         // k_upcurv reads x/p[upd_src], writes x/p[upd_src ^ 1]
+    int active;          // 0 once stopped
+    int stop;            // 0 running/complete, 1 ||r|| = 0, 2 non-finite
+    int do_update;       // k_upcurv runs this pass
+    int item0, nitems;   // this solve's range of work items (partials)
+    float alpha_f, beta_f, sigk_f;
+    int pad_;
+    Weights wt;
+};
+
+struct IterRec {
+    double E, E_t, delta, mu, alpha, Delta, lam;
+    int success, pad_;
+};
+
+}  // namespace misr

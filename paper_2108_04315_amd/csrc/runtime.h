@@ -1,0 +1,132 @@
+// runtime.h -- host-side runtime of libmisr.so (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/misr.h"
+#include "internal.h"
+
+namespace misr {
+
+// launchers (kernels.hip)
+int padded_band(int S, int L);
+int tile_hr(int S, int Lp);
+hipError_t launch_image(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
+                        const Item *items, const int *n_items, const ScgState *states,
+                        double *partials, int kind, int stype);
+hipError_t launch_forward(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
+                          const Item *items, int n, int stype, void *y);
+hipError_t launch_adjoint(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
+                          const Item *items, int n, int stype, const void *r, float *x);
+hipError_t launch_scalar(int grid, hipStream_t stream, ScgState *states, const int *n_states,
+                         const double *partials, IterRec *const *traces, int phase);
+hipError_t launch_cost_out(hipStream_t stream, const double *partials, int nitems,
+                           double *out);
+hipError_t launch_fill(hipStream_t stream, float *p, long long n, float v);
+hipError_t launch_finalize(hipStream_t stream, const Proj *projs, int nproj,
+                           const ScgState *states, int stype);
+
+enum { KIND_COSTGRAD = 0, KIND_TRIAL = 1, KIND_UPCURV = 2 };
+enum { PHASE_INIT = 0, PHASE_A = 1, PHASE_B = 2 };
+
+misr_status set_error(misr_status st, const char *fmt, ...);
+misr_status hip_fail(hipError_t e, const char *what);
+#define MISR_HIP(call)                                         \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return misr::hip_fail(e_, #call); \
+    } while (0)
+
+size_t dtype_size(misr_dtype dt);
+
+// A device allocation owned by the library.
+struct DevMem {
+    void *p = nullptr;
+    size_t n = 0;
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    ~DevMem() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= n && p) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+        if (e == hipSuccess) n = bytes;
+        else p = nullptr;
+        return e;
+    }
+    template <typename T>
+    T *as() const { return (T *)p; }
+};
+
+// Work list and device state for a set of solves advanced together.
+struct Plan {
+    struct Cls {
+        int S, Lp, start, count;
+    };
+    std::vector<Proj> projs;
+    std::vector<Item> items;
+    std::vector<ScgState> states;
+    std::vector<Cls> classes;
+    std::vector<int> counts;          // per class item count, then n_states
+};
+
+// Per-solve image buffers owned by the library (x1, p0, p1, g0, g1).
+struct SolveBufs {
+    DevMem x1, p0, p1, g0, g1;
+    hipError_t ensure(long long n, size_t es) {
+        hipError_t e;
+        if ((e = x1.ensure(n * es)) != hipSuccess) return e;
+        if ((e = p0.ensure(n * 4)) != hipSuccess) return e;
+        if ((e = p1.ensure(n * 4)) != hipSuccess) return e;
+        if ((e = g0.ensure(n * 4)) != hipSuccess) return e;
+        return g1.ensure(n * 4);
+    }
+};
+
+// Device mirrors of a Plan plus an instantiated graph of the whole solve.
+struct PlanDev {
+    DevMem projs, items, counts, states, partials, traces, trace_ptrs;
+    int n_iter_max = 0;
+    size_t trace_ns = 0;
+    hipGraphExec_t exec = nullptr;
+    std::string graph_key;
+    ~PlanDev() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+    hipError_t upload(const Plan &pl, int n_iter_max, hipStream_t stream);
+};
+
+}  // namespace misr
+
+struct misr_ctx {
+    int dev;
+    int ncu;
+    hipStream_t stream;     // library stream that runs captured solves
+    hipEvent_t ev_in, ev_out;
+    std::mutex mu;
+};
+
+struct misr_op {
+    misr_ctx *ctx;
+    int H, W, s, K, P, L, Lp, TH;
+    std::vector<double> shifts, psf;
+    misr::DevMem wy, wx, opdev;
+    misr::OpDev host;
+    std::mutex mu;
+    // cached workspace of the single-image entry points
+    misr::SolveBufs bufs;
+    misr::PlanDev pdev;
+    misr::Plan plan;
+};

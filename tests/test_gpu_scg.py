@@ -1,0 +1,161 @@
+"""GPU SCG solves (device-resident Moller state machine, graph-replayed passes)
+against the FP64 oracle's literal SCG, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import scg as oscg
+from gpu_common import TOL_LOWP, TOL_SCG, problem, psnr, rel_l2, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def misr():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2108_04315_amd import misr as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(misr):
+    c = misr.Context(0)
+    yield c
+    c.close()
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _oracle_solve(prob, n_iter, **kw):
+    return oscg.solve(_f32(prob.y), prob.shifts, prob.psf, prob.s, _f32(prob.x0), n_iter, **kw)
+
+
+def _gpu_solve(misr, ctx, prob, n_iter, dtype=None, **kw):
+    import torch
+    dtype = dtype or torch.float32
+    op = misr.Operator(ctx, prob.H, prob.W, prob.s, prob.shifts, prob.psf)
+    x = to_dev(_f32(prob.x0), dtype)
+    y = to_dev(_f32(prob.y), dtype)
+    its, info = op.scg_solve(y, x, misr.default_params(n_iter=n_iter, **kw))
+    return to_np(x), its, info
+
+
+def _compare_traces(its_g, tr_o, n_check=None):
+    succ_g = [t["success"] for t in its_g]
+    succ_o = [t["success"] for t in tr_o]
+    assert succ_g == succ_o
+    for a, b in list(zip(its_g, tr_o))[:n_check]:
+        assert abs(a["E"] - b["E"]) <= 1e-5 * abs(b["E"])
+
+
+def test_plain128_solve_matches_oracle(misr, ctx):
+    """The plain 128^2 workload: 4 frames 64^2, x2, 5x5 PSF sigma 0.6,
+    Gaussian noise 0.01, lambda 0.01, 50 SCG passes from bicubic x0."""
+    prob = problem(64, 2, 0.6, 5, noise=("gauss", 0.01), jitter=0.0, n_iter=50,
+                   seeds=(0, 0, 1))
+    x_o, tr_o, _ = _oracle_solve(prob, 50)
+    x_g, its, info = _gpu_solve(misr, ctx, prob, 50)
+    assert info["n_passes"] == 50 and info["stop"] == 0
+    err = rel_l2(x_g, x_o)
+    print(f"plain128 rel-L2 vs oracle {err:.3e}, PSNR vs gt {psnr(x_g, prob.x_gt):.2f} dB")
+    assert err <= TOL_SCG
+    _compare_traces(its, tr_o)
+
+
+@pytest.mark.parametrize("L,s,sig,jit,n_iter", [(48, 3, 1.0, 0.05, 30), (40, 2, 0.8, 0.05, 40),
+                                                (52, 2, 0.8, 0.05, 25)])
+def test_small_solves_match_oracle(misr, ctx, L, s, sig, jit, n_iter):
+    prob = problem(L, s, sig, None, noise=("poisson", 1e4), jitter=jit, n_iter=n_iter,
+                   seeds=(L, L + 1, L + 2))
+    x_o, tr_o, _ = _oracle_solve(prob, n_iter)
+    x_g, its, info = _gpu_solve(misr, ctx, prob, n_iter)
+    err = rel_l2(x_g, x_o)
+    print(f"L={L} s={s}: rel-L2 {err:.3e}")
+    assert err <= TOL_SCG
+    _compare_traces(its, tr_o)
+
+
+def test_zero_passes_returns_x0_and_cost(misr, ctx):
+    prob = problem(32, 2, 0.6, 5, noise=("gauss", 0.01), jitter=0.0, seeds=(1, 1, 2))
+    x_g, its, info = _gpu_solve(misr, ctx, prob, 0)
+    assert info["n_passes"] == 0
+    assert np.array_equal(x_g, _f32(prob.x0))
+    J, _, _ = oracle.cost_grad(_f32(prob.x0), _f32(prob.y), prob.shifts, prob.psf, 2)
+    assert abs(info["E0"] - J) <= 1e-5 * J
+
+
+def test_one_pass_closed_form(misr, ctx):
+    """s = 1, P = 1, no shift, lambda = 0: x1 = y + (x0 - y) lam1 / (2 + lam1)."""
+    import torch
+    rng = np.random.default_rng(4)
+    H, W = 70, 90
+    y = _f32(rng.uniform(0, 1, (1, H, W)))
+    x0 = _f32(rng.uniform(0, 1, (H, W)))
+    op = misr.Operator(ctx, H, W, 1, np.zeros((1, 2)), [1.0])
+    x = to_dev(x0)
+    op.scg_solve(to_dev(y), x, misr.default_params(n_iter=1, lambda_reg=0.0))
+    lam1 = 1e-6
+    ref = y[0] + (x0 - y[0]) * lam1 / (2 + lam1)
+    assert np.max(np.abs(to_np(x) - ref)) <= 1e-6
+
+
+@pytest.mark.parametrize("dtype_name,tol", [("float16", TOL_LOWP), ("bfloat16", TOL_LOWP)])
+def test_lowp_storage_solve(misr, ctx, dtype_name, tol):
+    import torch
+    dt = getattr(torch, dtype_name)
+    prob = problem(48, 3, 1.0, 7, noise=("poisson", 1e4), jitter=0.05, n_iter=30,
+                   seeds=(3, 4, 5))
+    x_o, _, _ = _oracle_solve(prob, 30)
+    x_g, its, info = _gpu_solve(misr, ctx, prob, 30, dtype=dt)
+    err = rel_l2(x_g, x_o)
+    print(f"{dtype_name}: rel-L2 {err:.3e}, PSNR vs oracle {psnr(x_g, x_o):.2f} dB")
+    assert err <= tol
+
+
+def test_batch_equals_solo_and_oracle(misr, ctx):
+    """Projections of different size and scale advanced in shared launches:
+    each equals its own solo solve bit for bit, and the oracle within 1e-4."""
+    import torch
+    specs = [(40, 2, 0.8, 20), (30, 3, 1.0, 15), (56, 2, 0.8, 25), (24, 3, 1.0, 20)]
+    probs = [problem(L, s, sig, None, jitter=0.05, n_iter=n, seeds=(i, i + 7, i + 9))
+             for i, (L, s, sig, n) in enumerate(specs)]
+    ops = [misr.Operator(ctx, p.H, p.W, p.s, p.shifts, p.psf) for p in probs]
+    ys = [to_dev(_f32(p.y)) for p in probs]
+    xs = [to_dev(_f32(p.x0)) for p in probs]
+    prms = [misr.default_params(n_iter=n) for (_, _, _, n) in specs]
+    outs = misr.scg_solve_batch(ops, ys, xs, prms)
+    for i, p in enumerate(probs):
+        xsolo = to_dev(_f32(p.x0))
+        its, info = ops[i].scg_solve(ys[i], xsolo, misr.default_params(n_iter=specs[i][3]))
+        assert torch.equal(xsolo, xs[i]), f"projection {i} differs from its solo solve"
+        assert outs[i][1]["n_passes"] == specs[i][3]
+        x_o, tr_o, _ = _oracle_solve(p, specs[i][3])
+        assert rel_l2(to_np(xs[i]), x_o) <= TOL_SCG
+
+
+def test_repeat_solves_deterministic(misr, ctx):
+    import torch
+    prob = problem(64, 2, 0.8, None, jitter=0.05, n_iter=20, seeds=(9, 9, 9))
+    op = misr.Operator(ctx, prob.H, prob.W, 2, prob.shifts, prob.psf)
+    y = to_dev(_f32(prob.y))
+    outs = []
+    for _ in range(3):
+        x = to_dev(_f32(prob.x0))
+        op.scg_solve(y, x, misr.default_params(n_iter=20), trace=False)
+        torch.cuda.synchronize()
+        outs.append(x.clone())
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[1], outs[2])
+
+
+def test_nonfinite_input_stops_with_numeric(misr, ctx):
+    prob = problem(32, 2, 0.6, 5, noise=("gauss", 0.01), jitter=0.0, seeds=(2, 2, 3))
+    y = _f32(prob.y)
+    y[1, 3, 4] = np.nan
+    op = misr.Operator(ctx, prob.H, prob.W, 2, prob.shifts, prob.psf)
+    x = to_dev(_f32(prob.x0))
+    its, info = op.scg_solve(to_dev(y), x, misr.default_params(n_iter=10))
+    assert info["stop"] == 2 and info["status"] == "E_NUMERIC"
+    assert np.all(np.isfinite(to_np(x)))
