@@ -1,18 +1,21 @@
 """Builds libmisr.so (HIP, gfx950) in the package directory.
 
-    python -m paper_2108_04315_amd.build
+    python -m paper_2108_04315_amd.build [-v]
+
+The image kernels are compiled once per scale factor (-DMISR_SCALE=s); the
+translation units compile in parallel.
 """
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmisr.so")
-SOURCES = ["kernels.hip", "abi.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -23,19 +26,32 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
-    for src in SOURCES:
-        path = os.path.join(CSRC, src)
-        if not os.path.exists(path):
-            continue
-        obj = os.path.join(CSRC, "_" + os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [HIPCC] + FLAGS + lang + ["-c", path, "-o", obj]
+def _units():
+    units = [("image_kernels.hip", [f"-DMISR_SCALE={s}"], f"_image_s{s}.o") for s in (1, 2, 3, 4)]
+    units.append(("scalar_kernels.hip", [], "_scalar.o"))
+    for src in ("abi.cpp", "server.cpp"):
+        if os.path.exists(os.path.join(CSRC, src)):
+            units.append((src, ["-x", "hip"], "_" + src.replace(".cpp", ".o")))
+    return units
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    jobs = jobs or min(8, os.cpu_count() or 4)
+
+    def compile_one(u):
+        src, extra, obj = u
+        cmd = [HIPCC] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o",
+                                          os.path.join(CSRC, obj)]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {src} {extra}\n{r.stderr}")
+        return os.path.join(CSRC, obj)
+
+    units = _units()
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(compile_one, units))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     if verbose:

@@ -252,10 +252,12 @@ extern "C" misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, mis
     op->L = band_length(g);
     op->Lp = padded_band(op->s, op->L);
     op->TH = tile_hr(op->s, op->Lp);
+    op->TW = tile_wr(op->s, op->Lp);
     op->shifts.assign(g->shifts_lr, g->shifts_lr + 2 * g->n_frames);
     op->psf.assign(g->psf_1d, g->psf_1d + g->psf_size);
     const int h = op->H / op->s, w = op->W / op->s, R = (op->P - 1) / 2;
-    std::vector<float> wy((size_t)op->K * h * op->Lp), wx((size_t)op->K * w * op->Lp);
+    const size_t fy = (size_t)(h + 2 * kPadRows) * op->Lp, fx = (size_t)(w + 2 * kPadRows) * op->Lp;
+    std::vector<float> wy((size_t)op->K * fy, 0.f), wx((size_t)op->K * fx, 0.f);
     OpDev &hd = op->host;
     std::memset(&hd, 0, sizeof hd);
     for (int k = 0; k < op->K; ++k) {
@@ -263,17 +265,17 @@ extern "C" misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, mis
         hd.offy[k] = (int)std::floor(ty) - R;
         hd.offx[k] = (int)std::floor(tx) - R;
         band_weights(op->H, op->s, ty, op->P, op->psf.data(), op->Lp, hd.offy[k],
-                     wy.data() + (size_t)k * h * op->Lp);
+                     wy.data() + k * fy + (size_t)kPadRows * op->Lp);
         band_weights(op->W, op->s, tx, op->P, op->psf.data(), op->Lp, hd.offx[k],
-                     wx.data() + (size_t)k * w * op->Lp);
+                     wx.data() + k * fx + (size_t)kPadRows * op->Lp);
     }
     MISR_HIP(op->wy.ensure(wy.size() * 4));
     MISR_HIP(op->wx.ensure(wx.size() * 4));
     MISR_HIP(op->opdev.ensure(sizeof(OpDev)));
     MISR_HIP(hipMemcpy(op->wy.p, wy.data(), wy.size() * 4, hipMemcpyHostToDevice));
     MISR_HIP(hipMemcpy(op->wx.p, wx.data(), wx.size() * 4, hipMemcpyHostToDevice));
-    hd.wy = op->wy.as<float>();
-    hd.wx = op->wx.as<float>();
+    hd.wy = op->wy.as<float>() + (size_t)kPadRows * op->Lp;
+    hd.wx = op->wx.as<float>() + (size_t)kPadRows * op->Lp;
     hd.H = op->H;
     hd.W = op->W;
     hd.s = op->s;
@@ -357,7 +359,7 @@ static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
             P.Wb = op->W;
             P.oy1 = op->H;
             P.ox1 = op->W;
-            P.ntx = (op->W + op->TH - 1) / op->TH;
+            P.ntx = (op->W + op->TW - 1) / op->TW;
             P.req = i;
             P.op = op->opdev.as<OpDev>();
             const int nty = (op->H + op->TH - 1) / op->TH;

@@ -1,0 +1,865 @@
+// image_kernels.hip -- gfx950 image kernels of the MISR SCG hot path, for one
+// scale factor S (compiled once per S with -DMISR_SCALE=S).
+//
+// Work decomposition: every kernel walks a work list of (view, tile) items;
+// a tile is TH x TW owned HR pixels.  A 512-thread workgroup stages the tile's
+// window (owned pixels plus EXT = max(L-1, 2) on each side) into LDS once and
+// runs every frame's separable band passes from there:
+//
+//   forward  A_k x  : pass 1 along rows    (HR rows -> LR columns, L taps, stride S)
+//                     pass 2 along columns (HR rows -> LR rows,    L taps, stride S)
+//   adjoint A_k^T r : pass 3 along columns (LR rows -> HR rows, ceil(L/S) taps)
+//                     pass 4 along rows    (LR cols -> HR cols)
+//
+// A_k = C_y,k (x) C_x,k holds exactly because the warp, the PSF and the
+// binning of the observation model (Sec. 2.1, Eq. sisr) are all separable,
+// zero padding included, so each 2-D operator becomes two 1-D banded ones.
+// Band weights are read per LR row/column from the operator's tables with
+// wave-uniform (scalar) loads: every pass maps one weight row to one wave.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+#ifndef MISR_SCALE
+#error "compile with -DMISR_SCALE=<s>"
+#endif
+
+namespace misr {
+
+constexpr int kNTI = 512;          // threads per workgroup of the image kernels
+constexpr int kNWI = kNTI / 64;    // waves per workgroup
+
+template <int S, int L>
+struct Tile {
+    static constexpr int EXT = (L - 1 > 2) ? L - 1 : 2;   // window margin (HR px)
+    static constexpr int NTAP = (L + S - 1) / S;         // adjoint taps per output
+    static constexpr int CJ = 4;                         // pass 1 LR columns per wave step
+    static constexpr int CI = 4;                         // pass 2 LR rows per wave step
+    static constexpr int CU = (S == 4) ? 8 : 6;          // pass 3 HR rows per wave step
+    static constexpr int calc_th() {
+        int best = S;
+        for (int th = S; th + 2 <= 64; th += S)
+            if (S * ((th + L - 2) / S) + L <= 64) best = th;
+        return best;
+    }
+    static constexpr int TH = calc_th();
+    static constexpr int NIM = (TH + L - 2) / S + 1;     // LR rows touching the tile
+    static constexpr int NRM = S * (NIM - 1) + L;        // HR rows those read
+    static constexpr int odd(int v) { return (v % 2) ? v : v + 1; }
+    static constexpr int lds_floats(int tw) {
+        const int wcp = odd(tw + 2 * EXT);
+        const int njp = odd((tw + L - 2) / S + 1);
+        const int xs = (TH + 2 * EXT) * wcp + S * CJ + 8;
+        const int hx = NRM * njp + S * CI * njp;
+        const int hr = hx + NIM * njp;
+        const int gs = TH * (tw + 1);
+        const int trial = xs + (hr > gs ? hr : gs);
+        const int upd = 2 * xs + hx;
+        return trial > upd ? trial : upd;
+    }
+    static constexpr int calc_tw() {
+        int best = kNWI * S;
+        for (int tw = kNWI * S; tw <= 1024; tw += kNWI * S)
+            if ((tw + L - 2) / S + 1 <= 64 && lds_floats(tw) * 4 <= 79 * 1024) best = tw;
+        return best;
+    }
+    static constexpr int TW = calc_tw();
+    static constexpr int WR = TH + 2 * EXT, WC = TW + 2 * EXT, WCP = odd(WC);
+    static constexpr int NJM = (TW + L - 2) / S + 1;
+    static constexpr int NJP = odd(NJM);
+    static constexpr int CV = TW / kNWI;                 // pass 4 / prior columns per wave
+    static constexpr int XS = WR * WCP + S * CJ + 8;
+    static constexpr int HXS = NRM * NJP + S * CI * NJP;
+    static constexpr int RSS = NIM * NJP;
+    static constexpr int GP = TW + 1;                    // row stride of the LDS gradient
+    static constexpr int SMEM = lds_floats(TW);
+    static constexpr int NSTAGE = (WR * WC + kNTI - 1) / kNTI;
+    static_assert(NRM <= 64 && TH + 2 <= 64 && NJM <= 64, "a wave spans a tile dimension");
+    static_assert(CV % S == 0 && CU % S == 0, "phase-aligned groups");
+    static_assert(TH * GP <= SMEM - XS && TH <= NRM, "LDS aliasing");
+};
+
+// pass 1: hx[r][j] = sum_l wx[jA+j][l] win[wr0+r][wc0+S j+l], r < NR, j < NJ.
+// Waves take groups of CJ LR columns (their weights are scalar loads), lanes
+// take rows; each lane keeps the S(CJ-1)+L window samples it needs in
+// registers.
+template <int S, int L>
+FI void pass1(const float *win, int wr0, int wc0, int NR, int NJ, const AS4 float *wxk, int jA,
+              int jlast, float *hx) {
+    using T = Tile<S, L>;
+    constexpr int CJ = T::CJ, NX = S * (CJ - 1) + L;
+    const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
+    for (int jg = wv; jg * CJ < NJ; jg += kNWI) {
+        const int j0 = jg * CJ;
+        // rows past the end of the table read its zero padding
+        const AS4 float *wb = wxk + (jA + j0) * L;
+        float wgt[CJ][L];
+#pragma unroll
+        for (int c = 0; c < CJ; ++c)
+#pragma unroll
+            for (int l = 0; l < L; ++l) wgt[c][l] = wb[c * L + l];
+        if (lane < NR) {
+            const float *src = win + (wr0 + lane) * T::WCP + wc0 + S * j0;
+            float xv[NX];
+#pragma unroll
+            for (int t = 0; t < NX; ++t) xv[t] = src[t];
+#pragma unroll
+            for (int c = 0; c < CJ; ++c) {
+                float a = 0.f;
+#pragma unroll
+                for (int l = 0; l < L; ++l) a = fmaf(wgt[c][l], xv[S * c + l], a);
+                if (j0 + c < NJ) hx[lane * T::NJP + j0 + c] = a;
+            }
+        }
+    }
+}
+
+// pass 2: a = sum_l wy[iA+i][l] hx[S i + l][j]; waves take groups of CI LR
+// rows, lanes take LR columns; out(i, j, a) consumes each result.
+template <int S, int L, class F>
+FI void pass2(const float *hx, int NI, int NJ, const AS4 float *wyk, int iA, int ilast, F out) {
+    using T = Tile<S, L>;
+    constexpr int CI = T::CI, NH = S * (CI - 1) + L;
+    const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
+    for (int ig = wv; ig * CI < NI; ig += kNWI) {
+        const int i0 = ig * CI;
+        const AS4 float *wb = wyk + (iA + i0) * L;
+        float wgt[CI][L];
+#pragma unroll
+        for (int c = 0; c < CI; ++c)
+#pragma unroll
+            for (int l = 0; l < L; ++l) wgt[c][l] = wb[c * L + l];
+        if (lane < NJ) {
+            float hv[NH];
+#pragma unroll
+            for (int t = 0; t < NH; ++t) hv[t] = hx[(S * i0 + t) * T::NJP + lane];
+            float av[CI];
+#pragma unroll
+            for (int c = 0; c < CI; ++c) {
+                float a = 0.f;
+#pragma unroll
+                for (int l = 0; l < L; ++l) a = fmaf(wgt[c][l], hv[S * c + l], a);
+                av[c] = a;
+            }
+            out(i0, lane, av);
+        }
+    }
+}
+
+// pass 3: tt[u][j] = sum_i wy[i][U - S i - offy] rs[i][j] for the TH rows.
+// PH = (U0 - offy) mod S fixes every tap offset at compile time.
+template <int S, int L, int PH>
+FI void pass3_ph(const float *rs, float *tt, int U0, int offy, int iA, int iB, int NJ,
+                 const AS4 float *wyk) {
+    using T = Tile<S, L>;
+    constexpr int CU = T::CU, NTAP = T::NTAP;
+    constexpr int NIG = (PH + CU - 1) / S + NTAP;
+    const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
+    for (int ug = wv; ug * CU < T::TH; ug += kNWI) {
+        const int u0 = ug * CU;
+        const int q0 = fdiv(U0 + u0 - offy, S);
+        const int ib = q0 - (NTAP - 1);
+        // LR rows outside [0, h) read the zero padding of the table
+        const AS4 float *wb = wyk + ib * L;
+        float wg[CU][NTAP];
+#pragma unroll
+        for (int c = 0; c < CU; ++c) {
+            const int dq = (PH + c) / S, ph = (PH + c) % S;
+#pragma unroll
+            for (int m = 0; m < NTAP; ++m) {
+                const int l = ph + S * m;
+                wg[c][m] = (l < L) ? wb[(dq - m + NTAP - 1) * L + l] : 0.f;
+            }
+        }
+        if (lane < NJ) {
+            float rv[NIG];
+#pragma unroll
+            for (int t = 0; t < NIG; ++t) {
+                const int i = ib + t;
+                const float v = rs[(min(max(i, iA), iB) - iA) * T::NJP + lane];
+                rv[t] = (i >= iA && i <= iB) ? v : 0.f;
+            }
+#pragma unroll
+            for (int c = 0; c < CU; ++c) {
+                const int dq = (PH + c) / S;
+                float a = 0.f;
+#pragma unroll
+                for (int m = 0; m < NTAP; ++m) a = fmaf(wg[c][m], rv[dq - m + NTAP - 1], a);
+                if (u0 + c < T::TH) tt[(u0 + c) * T::NJP + lane] = a;
+            }
+        }
+    }
+}
+
+// pass 4: g[u][v] += sum_j wx[j][V - S j - offx] tt[u][j] for the wave's CV
+// columns; lanes take rows (u = lane - 2).
+template <int S, int L, int PH>
+FI void pass4_ph(const float *tt, float (&gacc)[Tile<S, L>::CV], int V0, int offx, int jA,
+                 int jB, const AS4 float *wxk) {
+    using T = Tile<S, L>;
+    constexpr int CV = T::CV, NTAP = T::NTAP;
+    constexpr int NJG = (PH + CV - 1) / S + NTAP;
+    const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
+    const int u = lane - 2;
+    const int cv0 = wv * CV;
+    const int q0 = fdiv(V0 + cv0 - offx, S);
+    const int jb = q0 - (NTAP - 1);
+    const AS4 float *wb = wxk + jb * L;
+    const int ur = min(max(u, 0), T::TH - 1);
+    float tv[NJG];
+#pragma unroll
+    for (int t = 0; t < NJG; ++t) {
+        const int j = jb + t;
+        const float v = tt[ur * T::NJP + (min(max(j, jA), jB) - jA)];
+        tv[t] = (j >= jA && j <= jB) ? v : 0.f;
+    }
+#pragma unroll
+    for (int c = 0; c < CV; ++c) {
+        const int dq = (PH + c) / S, ph = (PH + c) % S;
+        float a = 0.f;
+#pragma unroll
+        for (int m = 0; m < NTAP; ++m) {
+            const int l = ph + S * m;
+            if (l < L) a = fmaf(wb[(dq - m + NTAP - 1) * L + l], tv[dq - m + NTAP - 1], a);
+        }
+        gacc[c] += a;
+    }
+}
+
+template <int S, int L>
+FI void pass3(int ph, const float *rs, float *tt, int U0, int offy, int iA, int iB, int NJ,
+              const AS4 float *wyk) {
+    if (ph == 0) pass3_ph<S, L, 0>(rs, tt, U0, offy, iA, iB, NJ, wyk);
+    if constexpr (S > 1) if (ph == 1) pass3_ph<S, L, 1>(rs, tt, U0, offy, iA, iB, NJ, wyk);
+    if constexpr (S > 2) if (ph == 2) pass3_ph<S, L, 2>(rs, tt, U0, offy, iA, iB, NJ, wyk);
+    if constexpr (S > 3) if (ph == 3) pass3_ph<S, L, 3>(rs, tt, U0, offy, iA, iB, NJ, wyk);
+}
+
+template <int S, int L>
+FI void pass4(int ph, const float *tt, float (&gacc)[Tile<S, L>::CV], int V0, int offx, int jA,
+              int jB, const AS4 float *wxk) {
+    if (ph == 0) pass4_ph<S, L, 0>(tt, gacc, V0, offx, jA, jB, wxk);
+    if constexpr (S > 1) if (ph == 1) pass4_ph<S, L, 1>(tt, gacc, V0, offx, jA, jB, wxk);
+    if constexpr (S > 2) if (ph == 2) pass4_ph<S, L, 2>(tt, gacc, V0, offx, jA, jB, wxk);
+    if constexpr (S > 3) if (ph == 3) pass4_ph<S, L, 3>(tt, gacc, V0, offx, jA, jB, wxk);
+}
+
+// The 8 BTV offsets d = (dx, dy) in [0, 2]^2 minus the origin (Eq. prior, w = 3).
+__device__ constexpr int kDX[8] = {1, 2, 0, 1, 2, 0, 1, 2};
+__device__ constexpr int kDY[8] = {0, 0, 1, 1, 1, 2, 2, 2};
+
+// BTV prior on the window, swept left to right over the wave's CV columns
+// with lanes on rows (u = lane - 2, two rows of halo).  Each pair (i, i+d)
+// is evaluated once, by the lane of i; the lane of i+d takes its share from
+// its running history (same row) or by a lane shift (rows below).  The
+// gradient accumulates into gs (LDS, row stride GP).
+template <int S, int L, bool EPS0>
+FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, int U0, int V0,
+                  int H, int W, int th_own, int tw_own, float &e_reg) {
+    using T = Tile<S, L>;
+    const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
+    const int u = lane - 2;
+    const int cv0 = wv * T::CV;
+    const int U = U0 + u;
+    const int ur = min(u, T::TH - 1);
+    const float e2 = eps * eps;
+    const bool row_in = U >= 0 && U < H;
+    const bool row_own = u >= 0 && u < th_own;
+    const bool row_tile = u >= 0 && u < T::TH;
+    const float *base = xs + (T::EXT + ur) * T::WCP + T::EXT;
+    float *grow = gs + max(u, 0) * T::GP;
+    float win[3][3];   // win[dy][dx] = x(u + dy, v + dx)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) win[dy][dx + 1] = base[dy * T::WCP + cv0 - 2 + dx];
+    float h1[8], h2[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) h1[d] = h2[d] = 0.f;
+    float eacc = 0.f;
+#pragma unroll 2
+    for (int vs = -2; vs < T::CV; ++vs) {
+        const int v = cv0 + vs, V = V0 + v;
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            win[dy][0] = win[dy][1];
+            win[dy][1] = win[dy][2];
+            win[dy][2] = base[dy * T::WCP + v + 2];
+        }
+        const bool in = row_in && V >= 0 && V < W;
+        float cur[8];
+        float eb = 0.f;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const int dx = kDX[d], dy = kDY[d];
+            const float z = win[0][0] - win[dy][dx];
+            const bool valid = in && (U + dy < H) && (V + dx < W);
+            float ps, ph;
+            if (EPS0) {
+                ps = (z > 0.f) ? 1.f : ((z < 0.f) ? -1.f : 0.f);
+                ph = fabsf(z);
+            } else {
+                const float dd = fmaf(z, z, e2);
+                const float r = rsq(dd);
+                ps = z * r;
+                ph = fmaf(dd, r, -eps);
+            }
+            cur[d] = valid ? gam[d] * ps : 0.f;
+            eb = fmaf(valid ? gam[d] : 0.f, ph, eb);
+        }
+        float gsum = 0.f;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const int dx = kDX[d], dy = kDY[d];
+            const float src = (dx == 0) ? cur[d] : ((dx == 1) ? h1[d] : h2[d]);
+            const float bk = (dy == 0) ? src : __shfl_up(src, dy, 64);
+            gsum += cur[d] - bk;
+        }
+        if (vs >= 0) {
+            if (row_tile) grow[v] += gsum;
+            if (row_own && v < tw_own) eacc += eb;
+        }
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            h2[d] = h1[d];
+            h1[d] = cur[d];
+        }
+    }
+    e_reg += eacc;
+}
+
+// --------------------------------------------------------------- the tiles
+struct TileOrigin {
+    int u0, v0, u1, v1, U0, V0;
+};
+
+template <int S, int L>
+FI TileOrigin tile_origin(const AS4 Proj &P, int ty, int tx) {
+    using T = Tile<S, L>;
+    TileOrigin o;
+    o.u0 = P.oy0 + ty * T::TH;
+    o.v0 = P.ox0 + tx * T::TW;
+    o.u1 = min(o.u0 + T::TH, P.oy1);
+    o.v1 = min(o.v0 + T::TW, P.ox1);
+    o.U0 = P.gy0 + o.u0;
+    o.V0 = P.gx0 + o.v0;
+    return o;
+}
+
+// Fused cost + gradient at x_t = x + alpha p (mode 1) or at x (mode 0):
+// every frame's forward, residual, data cost and adjoint, then the BTV cost
+// and gradient; writes g_t = grad J(x_t) to g[cur^1] for the owned pixels and
+// the partial sums {E_data, E_reg, |g_t|^2, g_t.g_k, g_t.p}.
+template <int S, int L, class ST>
+FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, int mode,
+                   float *sm, double *red, double *part) {
+    using T = Tile<S, L>;
+    using raw = typename ST::raw;
+    const AS4 OpDev &op = *cst(P.op);
+    const int tid = threadIdx.x;
+    const TileOrigin o = tile_origin<S, L>(P, ty, tx);
+    const int H = op.H, W = op.W, h = H / S, w = W / S, K = op.K;
+    float *xs = sm;
+    float *hx = xs + T::XS;
+    float *rs = hx + T::HXS;
+
+    const int xc = st.xc;
+    const AS1 raw *xb = glb((const raw *)P.x[xc]);
+    const AS1 float *pb = glb(P.p[xc]);
+    const float af = (mode == 1) ? st.alpha_f : 0.f;
+    const int Hb = P.Hb, Wb = P.Wb, ld = P.ld;
+    {
+        float val[T::NSTAGE];
+#pragma unroll
+        for (int s = 0; s < T::NSTAGE; ++s) {
+            const int q = tid + s * kNTI;
+            const int r = q / T::WC, c = q - r * T::WC;
+            const int ub = o.u0 - T::EXT + r, vb = o.v0 - T::EXT + c;
+            val[s] = 0.f;
+            if (q < T::WR * T::WC && ub >= 0 && ub < Hb && vb >= 0 && vb < Wb) {
+                const i64 idx = (i64)ub * ld + vb;
+                const float xv = ST::ld(xb, idx);
+                val[s] = (mode == 1) ? ST::rnd(fmaf(af, pb[idx], xv)) : xv;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < T::NSTAGE; ++s) {
+            const int q = tid + s * kNTI;
+            const int r = q / T::WC, c = q - r * T::WC;
+            if (q < T::WR * T::WC) xs[r * T::WCP + c] = val[s];
+        }
+    }
+    float gacc[T::CV];
+#pragma unroll
+    for (int c = 0; c < T::CV; ++c) gacc[c] = 0.f;
+    double e_data = 0.0;
+    const int data_p = st.wt.data_p;
+    const float epsd = st.wt.eps_data, e2d = epsd * epsd;
+    const AS1 raw *yb = glb((const raw *)P.y);
+    __syncthreads();
+
+    for (int k = 0; k < K; ++k) {
+        const int offy = op.offy[k], offx = op.offx[k];
+        const int iA = max(0, cdiv(o.U0 - L + 1 - offy, S));
+        const int iB = min(h - 1, fdiv(o.U0 + T::TH - 1 - offy, S));
+        const int jA = max(0, cdiv(o.V0 - L + 1 - offx, S));
+        const int jB = min(w - 1, fdiv(o.V0 + T::TW - 1 - offx, S));
+        const int NI = iB - iA + 1, NJ = jB - jA + 1;
+        if (NI <= 0 || NJ <= 0) continue;
+        const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
+        const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
+        pass1<S, L>(xs, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
+                    S * (NI - 1) + L, NJ, wxk, jA, w - 1, hx);
+        __syncthreads();
+        const AS1 raw *yk = yb + (i64)k * h * w;
+        pass2<S, L>(hx, NI, NJ, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
+            const int gj = jA + j;
+            float yv[T::CI];
+#pragma unroll
+            for (int c = 0; c < T::CI; ++c)
+                yv[c] = ST::ld(yk, (i64)min(iA + i0 + c, h - 1) * w + gj);
+            const bool own_j = (S * gj >= o.V0) && (S * gj < P.gx0 + o.v1);
+#pragma unroll
+            for (int c = 0; c < T::CI; ++c) {
+                if (i0 + c >= NI) break;
+                const int gi = iA + i0 + c;
+                const float r = av[c] - yv[c];
+                const bool own = own_j && (S * gi >= o.U0) && (S * gi < P.gy0 + o.u1);
+                float rv;
+                if (data_p == 2) {
+                    if (own) e_data += (double)r * (double)r;
+                    rv = 2.f * r;
+                } else {
+                    float ph, ps;
+                    phi_psi(r, epsd, e2d, ph, ps);
+                    if (own) e_data += (double)ph;
+                    rv = ps;
+                }
+                rs[(i0 + c) * T::NJP + j] = rv;
+            }
+        });
+        __syncthreads();
+        pass3<S, L>(pmod(o.U0 - offy, S), rs, hx, o.U0, offy, iA, iB, NJ, wyk);
+        __syncthreads();
+        pass4<S, L>(pmod(o.V0 - offx, S), hx, gacc, o.V0, offx, jA, jB, wxk);
+        __syncthreads();
+    }
+
+    // data-term gradient to LDS (lanes hold rows), then the prior adds in place
+    float *gs = hx;
+    {
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int u = lane - 2;
+        if (u >= 0 && u < T::TH)
+#pragma unroll
+            for (int c = 0; c < T::CV; ++c) gs[u * T::GP + wv * T::CV + c] = gacc[c];
+    }
+    float gam[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) gam[d] = st.wt.gam[kDY[d] * 3 + kDX[d]];
+    const float eps = st.wt.eps;
+    float e_reg = 0.f;
+    if (eps == 0.f)
+        btv_sweep<S, L, true>(xs, gs, gam, eps, o.U0, o.V0, H, W, o.u1 - o.u0, o.v1 - o.v0,
+                              e_reg);
+    else
+        btv_sweep<S, L, false>(xs, gs, gam, eps, o.U0, o.V0, H, W, o.u1 - o.u0, o.v1 - o.v0,
+                               e_reg);
+    __syncthreads();
+    double gg = 0.0, ggk = 0.0, gp = 0.0;
+    const int cur = st.cur;
+    AS1 float *gout = glbw(P.g[cur ^ 1]);
+    const AS1 float *gk = glb(P.g[cur]);
+    AS1 float *pz = glbw(P.p[xc]);
+    for (int q = tid; q < T::TH * T::TW; q += kNTI) {
+        const int uu = q / T::TW, vv = q - uu * T::TW;
+        if (o.u0 + uu >= o.u1 || o.v0 + vv >= o.v1) continue;
+        const float gv = gs[uu * T::GP + vv];
+        const i64 idx = (i64)(o.u0 + uu) * ld + o.v0 + vv;
+        gout[idx] = gv;
+        gg += (double)gv * (double)gv;
+        if (mode == 0) pz[idx] = 0.f;   // start direction buffer for the init pass
+        if (mode == 1) {
+            ggk += (double)gv * (double)gk[idx];
+            gp += (double)gv * (double)pb[idx];
+        }
+    }
+    double v[5] = {e_data, (double)e_reg, gg, ggk, gp};
+    block_sum_store<5, kNTI>(v, part, red);
+}
+
+// Accepted step: x <- x + alpha p, p <- -g_t + beta p (into the other buffer
+// of each pair), then Moller's curvature at the new (x, p) without forming
+// x + sigma_k p: data part 2 sum_k |A_k p|^2 (exact: the data term is
+// quadratic), prior part lambda sum gamma q^2 Q(z, sigma_k q).  Partial sums
+// {2 |A p|^2, prior part, |p|^2, p.r}.
+template <int S, int L, class ST>
+FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, float *sm,
+                    double *red, double *part) {
+    using T = Tile<S, L>;
+    using raw = typename ST::raw;
+    const AS4 OpDev &op = *cst(P.op);
+    const int tid = threadIdx.x;
+    const TileOrigin o = tile_origin<S, L>(P, ty, tx);
+    const int H = op.H, W = op.W, h = H / S, w = W / S, K = op.K;
+    float *xs = sm;
+    float *ps = xs + T::XS;
+    float *hx = ps + T::XS;
+
+    const int src = st.upd_src, dst = src ^ 1;
+    const AS1 raw *xb = glb((const raw *)P.x[src]);
+    const AS1 float *pb = glb(P.p[src]);
+    const AS1 float *gt = glb(P.g[st.cur]);
+    AS1 raw *xo = glbw((raw *)P.x[dst]);
+    AS1 float *po = glbw(P.p[dst]);
+    const float af = st.alpha_f, bf = st.beta_f;
+    const int Hb = P.Hb, Wb = P.Wb, ld = P.ld;
+    double pp = 0.0, pr = 0.0;
+    {
+        float xv[T::NSTAGE], pv[T::NSTAGE];
+#pragma unroll
+        for (int s = 0; s < T::NSTAGE; ++s) {
+            const int q = tid + s * kNTI;
+            const int r = q / T::WC, c = q - r * T::WC;
+            const int ub = o.u0 - T::EXT + r, vb = o.v0 - T::EXT + c;
+            xv[s] = 0.f;
+            pv[s] = 0.f;
+            if (q < T::WR * T::WC && ub >= 0 && ub < Hb && vb >= 0 && vb < Wb) {
+                const i64 idx = (i64)ub * ld + vb;
+                const float p0 = pb[idx], g0 = gt[idx];
+                xv[s] = ST::rnd(fmaf(af, p0, ST::ld(xb, idx)));
+                pv[s] = fmaf(bf, p0, -g0);
+                if (ub >= o.u0 && ub < o.u1 && vb >= o.v0 && vb < o.v1) {
+                    ST::st(xo, idx, xv[s]);
+                    po[idx] = pv[s];
+                    pp += (double)pv[s] * (double)pv[s];
+                    pr -= (double)pv[s] * (double)g0;
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < T::NSTAGE; ++s) {
+            const int q = tid + s * kNTI;
+            const int r = q / T::WC, c = q - r * T::WC;
+            if (q < T::WR * T::WC) {
+                xs[r * T::WCP + c] = xv[s];
+                ps[r * T::WCP + c] = pv[s];
+            }
+        }
+    }
+    __syncthreads();
+    // data part: |A_k p|^2 over the owned LR pixels
+    double ap2 = 0.0;
+    const int NIo = (o.u1 - o.u0) / S, NJo = (o.v1 - o.v0) / S;
+    const int iA = o.U0 / S, jA = o.V0 / S;
+    if (NIo > 0 && NJo > 0) {
+        for (int k = 0; k < K; ++k) {
+            const int offy = op.offy[k], offx = op.offx[k];
+            const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
+            const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
+            pass1<S, L>(ps, offy + T::EXT, offx + T::EXT, S * (NIo - 1) + L, NJo, wxk, jA, w - 1,
+                        hx);
+            __syncthreads();
+            pass2<S, L>(hx, NIo, NJo, wyk, iA, h - 1,
+                        [&](int i0, int, const float (&av)[T::CI]) {
+#pragma unroll
+                            for (int c = 0; c < T::CI; ++c)
+                                if (i0 + c < NIo) ap2 += (double)av[c] * (double)av[c];
+                        });
+            __syncthreads();
+        }
+    }
+    // prior part over the owned pairs (i, i+d)
+    const float eps = st.wt.eps, e2 = eps * eps, sk = st.sigk_f;
+    float gam[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) gam[d] = st.wt.gam[kDY[d] * 3 + kDX[d]];
+    float dreg = 0.f;
+    for (int q = tid; q < T::TH * T::TW; q += kNTI) {
+        const int uu = q / T::TW, vv = q - uu * T::TW;
+        if (o.u0 + uu >= o.u1 || o.v0 + vv >= o.v1) continue;
+        const int U = o.U0 + uu, V = o.V0 + vv;
+        const int wi = (uu + T::EXT) * T::WCP + vv + T::EXT;
+        const float xi = xs[wi], pi = ps[wi];
+        float acc = 0.f;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const int dx = kDX[d], dy = kDY[d];
+            const int of = dy * T::WCP + dx;
+            const float z = xi - xs[wi + of];
+            const float qd = pi - ps[wi + of];
+            const bool valid = (U + dy < H) && (V + dx < W);
+            const float t = gam[d] * qd * qd * psi_quot(z, sk * qd, eps, e2);
+            acc += valid ? t : 0.f;
+        }
+        dreg += acc;
+    }
+    double v[4] = {2.0 * ap2, (double)dreg, pp, pr};
+    block_sum_store<4, kNTI>(v, part, red);
+}
+
+// y[k] = A_k x on the owned LR pixels of one tile.
+template <int S, int L, class ST>
+FI void tile_forward(const AS4 Proj &P, int ty, int tx, void *yout, float *sm) {
+    using T = Tile<S, L>;
+    using raw = typename ST::raw;
+    const AS4 OpDev &op = *cst(P.op);
+    const int tid = threadIdx.x;
+    const TileOrigin o = tile_origin<S, L>(P, ty, tx);
+    const int h = op.H / S, w = op.W / S, K = op.K;
+    float *xs = sm;
+    float *hx = xs + T::XS;
+    const AS1 raw *xb = glb((const raw *)P.x[0]);
+    const int Hb = P.Hb, Wb = P.Wb, ld = P.ld;
+    for (int q = tid; q < T::WR * T::WC; q += kNTI) {
+        const int r = q / T::WC, c = q - r * T::WC;
+        const int ub = o.u0 - T::EXT + r, vb = o.v0 - T::EXT + c;
+        float val = 0.f;
+        if (ub >= 0 && ub < Hb && vb >= 0 && vb < Wb) val = ST::ld(xb, (i64)ub * ld + vb);
+        xs[r * T::WCP + c] = val;
+    }
+    __syncthreads();
+    const int NIo = (o.u1 - o.u0) / S, NJo = (o.v1 - o.v0) / S;
+    const int iA = o.U0 / S, jA = o.V0 / S;
+    if (NIo <= 0 || NJo <= 0) return;
+    AS1 raw *yo = glbw((raw *)yout);
+    for (int k = 0; k < K; ++k) {
+        const int offy = op.offy[k], offx = op.offx[k];
+        const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
+        const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
+        pass1<S, L>(xs, offy + T::EXT, offx + T::EXT, S * (NIo - 1) + L, NJo, wxk, jA, w - 1, hx);
+        __syncthreads();
+        const i64 yb = (i64)k * h * w;
+        pass2<S, L>(hx, NIo, NJo, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
+#pragma unroll
+            for (int c = 0; c < T::CI; ++c)
+                if (i0 + c < NIo) ST::st(yo, yb + (i64)(iA + i0 + c) * w + jA + j, av[c]);
+        });
+        __syncthreads();
+    }
+}
+
+// x = sum_k A_k^T r_k on the owned HR pixels of one tile.
+template <int S, int L, class ST>
+FI void tile_adjoint(const AS4 Proj &P, int ty, int tx, const void *r, float *xout, float *sm) {
+    using T = Tile<S, L>;
+    using raw = typename ST::raw;
+    const AS4 OpDev &op = *cst(P.op);
+    const int tid = threadIdx.x;
+    const TileOrigin o = tile_origin<S, L>(P, ty, tx);
+    const int h = op.H / S, w = op.W / S, K = op.K;
+    float *gs = sm;
+    float *tt = gs + T::XS;
+    float *rs = tt + T::HXS;
+    const AS1 raw *rb = glb((const raw *)r);
+    float gacc[T::CV];
+#pragma unroll
+    for (int c = 0; c < T::CV; ++c) gacc[c] = 0.f;
+    for (int k = 0; k < K; ++k) {
+        const int offy = op.offy[k], offx = op.offx[k];
+        const int iA = max(0, cdiv(o.U0 - L + 1 - offy, S));
+        const int iB = min(h - 1, fdiv(o.U0 + T::TH - 1 - offy, S));
+        const int jA = max(0, cdiv(o.V0 - L + 1 - offx, S));
+        const int jB = min(w - 1, fdiv(o.V0 + T::TW - 1 - offx, S));
+        const int NI = iB - iA + 1, NJ = jB - jA + 1;
+        if (NI <= 0 || NJ <= 0) continue;
+        const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
+        const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
+        for (int q = tid; q < NI * T::NJP; q += kNTI) {
+            const int ii = q / T::NJP, jj = q - ii * T::NJP;
+            if (jj < NJ) rs[q] = ST::ld(rb, (i64)k * h * w + (i64)(iA + ii) * w + jA + jj);
+        }
+        __syncthreads();
+        pass3<S, L>(pmod(o.U0 - offy, S), rs, tt, o.U0, offy, iA, iB, NJ, wyk);
+        __syncthreads();
+        pass4<S, L>(pmod(o.V0 - offx, S), tt, gacc, o.V0, offx, jA, jB, wxk);
+        __syncthreads();
+    }
+    {
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int u = lane - 2;
+        if (u >= 0 && u < T::TH)
+#pragma unroll
+            for (int c = 0; c < T::CV; ++c) gs[u * T::GP + wv * T::CV + c] = gacc[c];
+    }
+    __syncthreads();
+    AS1 float *xo = glbw(xout);
+    const int ld = P.ld;
+    for (int q = tid; q < T::TH * T::TW; q += kNTI) {
+        const int uu = q / T::TW, vv = q - uu * T::TW;
+        if (o.u0 + uu >= o.u1 || o.v0 + vv >= o.v1) continue;
+        xo[(i64)(o.u0 + uu) * ld + o.v0 + vv] = gs[uu * T::GP + vv];
+    }
+}
+
+// -------------------------------------------------------------- the kernels
+// Each kernel walks the work list with a grid stride; the item count is read
+// from device memory so that one captured launch can serve a changing list.
+template <int S, int L, class ST>
+__global__ void __launch_bounds__(kNTI) k_trial(const Proj *projs, const Item *items,
+                                                const int *n_items, const ScgState *states,
+                                                double *partials, int mode) {
+    __shared__ float sm[Tile<S, L>::SMEM];
+    __shared__ double red[kNV * kNWI];
+    const int n = *cst(n_items);
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const AS4 Item &itm = cst(items)[it];
+        const AS4 Proj &P = cst(projs)[itm.proj];
+        const AS4 ScgState &st = cst(states)[P.req];
+        if (mode == 1 && !st.active) continue;
+        tile_trial<S, L, ST>(P, st, itm.ty, itm.tx, mode, sm, red, partials + (i64)it * kNV);
+        __syncthreads();
+    }
+}
+
+template <int S, int L, class ST>
+__global__ void __launch_bounds__(kNTI) k_upcurv(const Proj *projs, const Item *items,
+                                                 const int *n_items, const ScgState *states,
+                                                 double *partials) {
+    __shared__ float sm[Tile<S, L>::SMEM];
+    __shared__ double red[kNV * kNWI];
+    const int n = *cst(n_items);
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const AS4 Item &itm = cst(items)[it];
+        const AS4 Proj &P = cst(projs)[itm.proj];
+        const AS4 ScgState &st = cst(states)[P.req];
+        if (!st.do_update) continue;
+        tile_upcurv<S, L, ST>(P, st, itm.ty, itm.tx, sm, red, partials + (i64)it * kNV);
+        __syncthreads();
+    }
+}
+
+template <int S, int L, class ST>
+__global__ void __launch_bounds__(kNTI) k_forward(const Proj *projs, const Item *items, int n,
+                                                  void *yout) {
+    __shared__ float sm[Tile<S, L>::SMEM];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const AS4 Item &itm = cst(items)[it];
+        tile_forward<S, L, ST>(cst(projs)[itm.proj], itm.ty, itm.tx, yout, sm);
+        __syncthreads();
+    }
+}
+
+template <int S, int L, class ST>
+__global__ void __launch_bounds__(kNTI) k_adjoint(const Proj *projs, const Item *items, int n,
+                                                  const void *r, float *xout) {
+    __shared__ float sm[Tile<S, L>::SMEM];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const AS4 Item &itm = cst(items)[it];
+        tile_adjoint<S, L, ST>(cst(projs)[itm.proj], itm.ty, itm.tx, r, xout, sm);
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------- launchers for this S
+// Band lengths instantiated per scale (the operator's L is rounded up).
+#if MISR_SCALE == 1
+#define MISR_LIST(X) X(4) X(8) X(16)
+#elif MISR_SCALE == 2
+#define MISR_LIST(X) X(6) X(8) X(9) X(12) X(16)
+#elif MISR_SCALE == 3
+#define MISR_LIST(X) X(6) X(9) X(10) X(12) X(16)
+#elif MISR_SCALE == 4
+#define MISR_LIST(X) X(12) X(16)
+#endif
+
+#define MISR_CAT2(a, b) a##b
+#define MISR_CAT(a, b) MISR_CAT2(a, b)
+#define MISR_FN(name) MISR_CAT(name, MISR_SCALE)
+
+// Tile shape of band length Lp at this scale (0 if not instantiated).
+int MISR_FN(tile_dims_s)(int Lp, int *th, int *tw) {
+#define X(l)                       \
+    if (Lp == l) {                 \
+        *th = Tile<MISR_SCALE, l>::TH; \
+        *tw = Tile<MISR_SCALE, l>::TW; \
+        return 1;                  \
+    }
+    MISR_LIST(X)
+#undef X
+    return 0;
+}
+
+hipError_t MISR_FN(launch_trial_s)(int Lp, int stype, int grid, hipStream_t s, const Proj *projs,
+                                   const Item *items, const int *n_items,
+                                   const ScgState *states, double *partials, int mode) {
+#define X(l)                                                                                    \
+    if (Lp == l) {                                                                              \
+        if (stype == ST_F32)                                                                    \
+            hipLaunchKernelGGL((k_trial<MISR_SCALE, l, StF32>), dim3(grid), dim3(kNTI), 0, s,     \
+                               projs, items, n_items, states, partials, mode);                  \
+        else if (stype == ST_F16)                                                               \
+            hipLaunchKernelGGL((k_trial<MISR_SCALE, l, StF16>), dim3(grid), dim3(kNTI), 0, s,     \
+                               projs, items, n_items, states, partials, mode);                  \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_trial<MISR_SCALE, l, StBF16>), dim3(grid), dim3(kNTI), 0, s,    \
+                               projs, items, n_items, states, partials, mode);                  \
+        return hipGetLastError();                                                               \
+    }
+    MISR_LIST(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t MISR_FN(launch_upcurv_s)(int Lp, int stype, int grid, hipStream_t s, const Proj *projs,
+                                    const Item *items, const int *n_items,
+                                    const ScgState *states, double *partials) {
+#define X(l)                                                                                     \
+    if (Lp == l) {                                                                               \
+        if (stype == ST_F32)                                                                     \
+            hipLaunchKernelGGL((k_upcurv<MISR_SCALE, l, StF32>), dim3(grid), dim3(kNTI), 0, s,     \
+                               projs, items, n_items, states, partials);                         \
+        else if (stype == ST_F16)                                                                \
+            hipLaunchKernelGGL((k_upcurv<MISR_SCALE, l, StF16>), dim3(grid), dim3(kNTI), 0, s,     \
+                               projs, items, n_items, states, partials);                         \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_upcurv<MISR_SCALE, l, StBF16>), dim3(grid), dim3(kNTI), 0, s,    \
+                               projs, items, n_items, states, partials);                         \
+        return hipGetLastError();                                                                \
+    }
+    MISR_LIST(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t MISR_FN(launch_forward_s)(int Lp, int stype, int grid, hipStream_t s, const Proj *projs,
+                                     const Item *items, int n, void *y) {
+#define X(l)                                                                                      \
+    if (Lp == l) {                                                                                \
+        if (stype == ST_F32)                                                                      \
+            hipLaunchKernelGGL((k_forward<MISR_SCALE, l, StF32>), dim3(grid), dim3(kNTI), 0, s,     \
+                               projs, items, n, y);                                               \
+        else if (stype == ST_F16)                                                                 \
+            hipLaunchKernelGGL((k_forward<MISR_SCALE, l, StF16>), dim3(grid), dim3(kNTI), 0, s,     \
+                               projs, items, n, y);                                               \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_forward<MISR_SCALE, l, StBF16>), dim3(grid), dim3(kNTI), 0, s,    \
+                               projs, items, n, y);                                               \
+        return hipGetLastError();                                                                 \
+    }
+    MISR_LIST(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t MISR_FN(launch_adjoint_s)(int Lp, int stype, int grid, hipStream_t s, const Proj *projs,
+                                     const Item *items, int n, const void *r, float *x) {
+#define X(l)                                                                                      \
+    if (Lp == l) {                                                                                \
+        if (stype == ST_F32)                                                                      \
+            hipLaunchKernelGGL((k_adjoint<MISR_SCALE, l, StF32>), dim3(grid), dim3(kNTI), 0, s,     \
+                               projs, items, n, r, x);                                            \
+        else if (stype == ST_F16)                                                                 \
+            hipLaunchKernelGGL((k_adjoint<MISR_SCALE, l, StF16>), dim3(grid), dim3(kNTI), 0, s,     \
+                               projs, items, n, r, x);                                            \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_adjoint<MISR_SCALE, l, StBF16>), dim3(grid), dim3(kNTI), 0, s,    \
+                               projs, items, n, r, x);                                            \
+        return hipGetLastError();                                                                 \
+    }
+    MISR_LIST(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace misr

@@ -11,12 +11,15 @@ constexpr int kNT = 256;     // threads per workgroup of the image kernels
 constexpr int kNV = 6;       // FP64 partial sums per work item
 constexpr int kMaxK = 16;    // frames per projection
 constexpr int kMaxL = 16;    // band length
+constexpr int kPadRows = 16; // zero weight rows before and after each frame's table
 
 enum StorageType : int { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 
 // Operator of one geometry: per frame the two 1-D factors of A_k.
 // Row factor: LR row i reads HR rows s*i + offy[k] + l, l in [0, L), with
-// weight wy[(k*h + i)*L + l]; columns likewise with wx / offx.
+// weight wy[(k*(h + 2*kPadRows) + i)*L + l]; columns likewise with wx / offx.
+// wy/wx point at row 0 of frame 0; kPadRows zero rows sit before and after
+// every frame's rows so that kernels may index slightly outside [0, h).
 struct OpDev {
     const float *wy;
     const float *wx;

@@ -17,6 +17,7 @@ namespace misr {
 // launchers (kernels.hip)
 int padded_band(int S, int L);
 int tile_hr(int S, int Lp);
+int tile_wr(int S, int Lp);
 hipError_t launch_image(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
                         const Item *items, const int *n_items, const ScgState *states,
                         double *partials, int kind, int stype);
@@ -120,7 +121,7 @@ struct misr_ctx {
 
 struct misr_op {
     misr_ctx *ctx;
-    int H, W, s, K, P, L, Lp, TH;
+    int H, W, s, K, P, L, Lp, TH, TW;  // TH x TW: HR tile of the image kernels
     std::vector<double> shifts, psf;
     misr::DevMem wy, wx, opdev;
     misr::OpDev host;

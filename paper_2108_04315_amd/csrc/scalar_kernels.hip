@@ -1,0 +1,326 @@
+// scalar_kernels.hip -- the device-resident SCG state machine (Moller's
+// scalar steps in FP64), small helper kernels, and the dispatch from a
+// geometry's (scale, band length) to the image-kernel instances.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace misr {
+
+// ------------------------------------------------------------ scalar kernels
+// One workgroup per solve: sums that solve's partials in a fixed order, then
+// thread 0 runs Moller's scalar steps in FP64.
+enum Phase { PH_INIT = 0, PH_A = 1, PH_B = 2 };
+
+__device__ void scg_init(ScgState &s, const double *v) {
+    s.E = v[0] + v[1];
+    s.E0 = s.E;
+    s.rr = v[2];
+    s.pi = v[2];
+    s.mu = v[2];
+    s.alpha = 0.0;
+    s.beta = 0.0;
+    s.alpha_f = 0.f;
+    s.beta_f = 0.f;
+    s.lam_bar = 0.0;
+    s.k = 1;
+    s.it = 0;
+    s.n_success = 0;
+    s.stop = 0;
+    if (!isfinite(s.E) || !isfinite(s.rr)) {
+        s.active = 0;
+        s.stop = 2;
+        s.do_update = 0;
+        return;
+    }
+    s.active = (s.n_iter > 0);
+    s.success = 1;
+    s.cur ^= 1;          // the gradient at x0 went to g[cur ^ 1]
+    s.upd_src = s.xc;    // p[xc] is zero: the update pass sets p = -g0, x unchanged
+    s.xc ^= 1;
+    s.do_update = 1;
+    s.sigk = (s.pi > 0.0) ? s.sigma / sqrt(s.pi) : 0.0;
+    s.sigk_f = (float)s.sigk;
+}
+
+// steps 1-5 of the pass
+__device__ void scg_phase_a(ScgState &s, const double *v) {
+    if (!s.active) return;
+    if (s.success) {
+        s.delta = v[0] + v[1];
+        s.pi = v[2];
+        s.mu = v[3];
+    }
+    if (s.rr == 0.0) {
+        s.active = 0;
+        s.stop = 1;
+        return;
+    }
+    if (!isfinite(s.delta)) {
+        s.active = 0;
+        s.stop = 2;
+        return;
+    }
+    double d = s.delta + (s.lam - s.lam_bar) * s.pi;
+    if (d <= 0.0) {
+        s.lam_bar = 2.0 * (s.lam - d / s.pi);
+        d = -d + s.lam * s.pi;
+        s.lam = s.lam_bar;
+    }
+    s.delta = d;
+    s.alpha = s.mu / d;
+    if (!isfinite(s.alpha)) {
+        s.active = 0;
+        s.stop = 2;
+        return;
+    }
+    s.alpha_f = (float)s.alpha;
+}
+
+// steps 6-9 of the pass
+__device__ void scg_phase_b(ScgState &s, const double *v, IterRec *trace) {
+    s.do_update = 0;
+    if (!s.active) return;
+    const double Et = v[0] + v[1];
+    s.E_t = Et;
+    if (!isfinite(Et)) {
+        s.active = 0;
+        s.stop = 2;
+        s.Delta = 0.0;
+    } else {
+        const double Delta = 2.0 * s.delta * (s.E - Et) / (s.mu * s.mu);
+        s.Delta = Delta;
+        if (Delta >= 0.0) {
+            const double gg = v[2], ggk = v[3], gp = v[4];
+            s.E = Et;
+            s.lam_bar = 0.0;
+            s.success = 1;
+            s.n_success++;
+            s.beta = (s.k % s.N == 0) ? 0.0 : (gg - ggk) / s.mu;
+            s.rr = gg;
+            s.cur ^= 1;
+            s.upd_src = s.xc;
+            s.xc ^= 1;
+            s.do_update = 1;
+            s.beta_f = (float)s.beta;
+            const double pn = gg - 2.0 * s.beta * gp + s.beta * s.beta * s.pi;
+            s.sigk = (pn > 0.0) ? s.sigma / sqrt(pn) : 0.0;
+            s.sigk_f = (float)s.sigk;
+            if (Delta >= 0.75) s.lam *= 0.25;
+        } else {
+            s.lam_bar = s.lam;
+            s.success = 0;
+        }
+        if (Delta < 0.25) s.lam += s.delta * (1.0 - Delta) / s.pi;
+    }
+    if (trace) {
+        IterRec &r = trace[s.it];
+        r.E = s.E;
+        r.E_t = s.E_t;
+        r.delta = s.delta;
+        r.mu = s.mu;
+        r.alpha = s.alpha;
+        r.Delta = s.Delta;
+        r.lam = s.lam;
+        r.success = (s.do_update != 0);
+        r.pad_ = 0;
+    }
+    s.k++;
+    s.it++;
+    if (s.it >= s.n_iter) s.active = 0;
+}
+
+__global__ void __launch_bounds__(kNT) k_scalar(ScgState *states, const int *n_states,
+                                                const double *__restrict__ partials,
+                                                IterRec *const *traces, int phase) {
+    __shared__ double red[kNV * (kNT / 64)];
+    __shared__ double tot[kNV];
+    const int ns = *n_states;
+    for (int sv = blockIdx.x; sv < ns; sv += gridDim.x) {
+        ScgState &s = states[sv];
+        bool need;
+        if (phase == PH_INIT)
+            need = true;
+        else if (phase == PH_A)
+            need = s.active && s.success;
+        else
+            need = s.active;
+        __syncthreads();   // every thread has read the state before thread 0 writes it
+        if (need) {
+            double v[kNV] = {0, 0, 0, 0, 0, 0};
+            for (int i = s.item0 + threadIdx.x; i < s.item0 + s.nitems; i += kNT)
+#pragma unroll
+                for (int q = 0; q < kNV; ++q) v[q] += partials[(long long)i * kNV + q];
+            block_sum_store<kNV, kNT>(v, tot, red);
+        }
+        if (threadIdx.x == 0) {
+            if (phase == PH_INIT)
+                scg_init(s, tot);
+            else if (phase == PH_A)
+                scg_phase_a(s, tot);
+            else
+                scg_phase_b(s, tot, traces ? traces[sv] : nullptr);
+        }
+        __syncthreads();
+    }
+}
+
+// Sums one solve's partials into out[0..3) = {J, E_data, E_reg} (cost only).
+__global__ void __launch_bounds__(kNT) k_cost_out(const double *__restrict__ partials,
+                                                  int nitems, double *out) {
+    __shared__ double red[kNV * (kNT / 64)];
+    __shared__ double tot[kNV];
+    double v[kNV] = {0, 0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < nitems; i += kNT)
+#pragma unroll
+        for (int q = 0; q < kNV; ++q) v[q] += partials[(long long)i * kNV + q];
+    block_sum_store<kNV, kNT>(v, tot, red);
+    if (threadIdx.x == 0) {
+        out[0] = tot[0] + tot[1];
+        out[1] = tot[0];
+        out[2] = tot[1];
+    }
+}
+
+// ----------------------------------------------------------- small kernels
+__global__ void k_fill_f32(float *p, long long n, float v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Copies x[1] into x[0] for every view whose current iterate sits in the
+// workspace buffer (decided on the device).
+__global__ void k_finalize(const Proj *__restrict__ projs, int nproj,
+                           const ScgState *__restrict__ states, int stype) {
+    for (int j = 0; j < nproj; ++j) {
+        const Proj &P = projs[j];
+        if (states[P.req].xc == 0) continue;
+        const long long n = (long long)P.Hb * P.ld;
+        const int es = (stype == ST_F32) ? 4 : 2;
+        if (es == 4) {
+            const float *a = (const float *)P.x[1];
+            float *b = (float *)P.x[0];
+            for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+                 i += (long long)gridDim.x * blockDim.x)
+                b[i] = a[i];
+        } else {
+            const unsigned short *a = (const unsigned short *)P.x[1];
+            unsigned short *b = (unsigned short *)P.x[0];
+            for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+                 i += (long long)gridDim.x * blockDim.x)
+                b[i] = a[i];
+        }
+    }
+}
+
+// ------------------------------------------------------------- dispatching
+#define MISR_SCALES(X) X(1) X(2) X(3) X(4)
+#define X(s)                                                                                   \
+    int tile_dims_s##s(int Lp, int *th, int *tw);                                              \
+    hipError_t launch_trial_s##s(int Lp, int stype, int grid, hipStream_t st, const Proj *projs, \
+                                 const Item *items, const int *n_items,                        \
+                                 const ScgState *states, double *partials, int mode);          \
+    hipError_t launch_upcurv_s##s(int Lp, int stype, int grid, hipStream_t st,                 \
+                                  const Proj *projs, const Item *items, const int *n_items,    \
+                                  const ScgState *states, double *partials);                   \
+    hipError_t launch_forward_s##s(int Lp, int stype, int grid, hipStream_t st,                \
+                                   const Proj *projs, const Item *items, int n, void *y);      \
+    hipError_t launch_adjoint_s##s(int Lp, int stype, int grid, hipStream_t st,                \
+                                   const Proj *projs, const Item *items, int n, const void *r, \
+                                   float *x);
+MISR_SCALES(X)
+#undef X
+
+// Band lengths instantiated per scale; an operator's L is rounded up to one.
+static const int kBands[5][6] = {{0}, {4, 8, 16, 0}, {6, 8, 9, 12, 16, 0},
+                                 {6, 9, 10, 12, 16, 0}, {12, 16, 0}};
+
+int padded_band(int S, int L) {
+    if (S < 1 || S > 4) return -1;
+    for (int i = 0; kBands[S][i]; ++i)
+        if (kBands[S][i] >= L) return kBands[S][i];
+    return -1;
+}
+
+static int tile_dims(int S, int Lp, int *th, int *tw) {
+    switch (S) {
+    case 1: return tile_dims_s1(Lp, th, tw);
+    case 2: return tile_dims_s2(Lp, th, tw);
+    case 3: return tile_dims_s3(Lp, th, tw);
+    case 4: return tile_dims_s4(Lp, th, tw);
+    }
+    return 0;
+}
+
+int tile_hr(int S, int Lp) {
+    int th = -1, tw = -1;
+    return tile_dims(S, Lp, &th, &tw) ? th : -1;
+}
+
+int tile_wr(int S, int Lp) {
+    int th = -1, tw = -1;
+    return tile_dims(S, Lp, &th, &tw) ? tw : -1;
+}
+
+hipError_t launch_image(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
+                        const Item *items, const int *n_items, const ScgState *states,
+                        double *partials, int kind, int stype) {
+#define X(s)                                                                                  \
+    if (S == s)                                                                               \
+        return kind == 2 ? launch_upcurv_s##s(Lp, stype, grid, stream, projs, items, n_items, \
+                                              states, partials)                               \
+                         : launch_trial_s##s(Lp, stype, grid, stream, projs, items, n_items,  \
+                                             states, partials, kind);
+    MISR_SCALES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_forward(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
+                          const Item *items, int n, int stype, void *y) {
+#define X(s) \
+    if (S == s) return launch_forward_s##s(Lp, stype, grid, stream, projs, items, n, y);
+    MISR_SCALES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
+                          const Item *items, int n, int stype, const void *r, float *x) {
+#define X(s) \
+    if (S == s) return launch_adjoint_s##s(Lp, stype, grid, stream, projs, items, n, r, x);
+    MISR_SCALES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_scalar(int grid, hipStream_t stream, ScgState *states, const int *n_states,
+                         const double *partials, IterRec *const *traces, int phase) {
+    hipLaunchKernelGGL(k_scalar, dim3(grid), dim3(kNT), 0, stream, states, n_states, partials,
+                       traces, phase);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost_out(hipStream_t stream, const double *partials, int nitems,
+                           double *out) {
+    hipLaunchKernelGGL(k_cost_out, dim3(1), dim3(kNT), 0, stream, partials, nitems, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(hipStream_t stream, float *p, long long n, float v) {
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(hipStream_t stream, const Proj *projs, int nproj,
+                           const ScgState *states, int stype) {
+    hipLaunchKernelGGL(k_finalize, dim3(1024), dim3(256), 0, stream, projs, nproj, states,
+                       stype);
+    return hipGetLastError();
+}
+
+}  // namespace misr
