@@ -99,6 +99,10 @@ typedef struct {
                             tile_lr x tile_lr LR pixels held separately in HBM
                             with a halo exchanged every pass */
     int32_t halo_lr;     /* halo width in LR pixels for tile_lr > 0 */
+    int32_t x_rounding;  /* 16-bit x storage: 0 round to nearest even (default),
+                            1 stochastic rounding driven by a counter-based hash of
+                            (pixel, pass), so that it is reproducible */
+    int32_t pad_;
 } misr_params;
 
 /* One SCG pass as recorded on the device. */
@@ -183,6 +187,16 @@ misr_status misr_scg_solve(const misr_op *op, const misr_params *params, const v
 misr_status misr_scg_solve_batch(int n, const misr_op *const *ops,
                                  const misr_params *params, const void *const *y,
                                  void *const *x_inout, misr_scg_trace *traces, void *stream);
+
+/* Measurement aid: times one image pass of the solve in isolation.  Prepares
+ * the state of misr_scg_solve(op, params, y, x) up to the first trial point,
+ * then launches pass `which` (0: fused cost+gradient at x + alpha p,
+ * 1: update + curvature) `reps` times on the library stream between two HIP
+ * events and returns the mean duration in microseconds in *avg_us (host).
+ * Both passes are idempotent at a fixed state, so repeated launches do the
+ * work of one pass each.  x is left unchanged.  Synchronises the stream. */
+misr_status misr_time_pass(const misr_op *op, const misr_params *params, const void *y,
+                           void *x, int which, int reps, double *avg_us, void *stream);
 
 /* ------------------------------------------------------------------ serving */
 /* On-the-fly acquisition (Sec. 2.2): each rotation angle's frames arrive as a

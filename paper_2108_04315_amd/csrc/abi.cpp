@@ -30,7 +30,7 @@ misr_status hip_fail(hipError_t e, const char *what) {
 
 size_t dtype_size(misr_dtype dt) { return dt == MISR_F32 ? 4 : 2; }
 
-hipError_t PlanDev::upload(const Plan &pl, int n_iter, hipStream_t stream) {
+hipError_t PlanDev::upload(Plan &pl, int n_iter, hipStream_t stream) {
     hipError_t e;
     const size_t np = pl.projs.size(), ni = pl.items.size(), ns = pl.states.size();
     if ((e = projs.ensure(np * sizeof(Proj))) != hipSuccess) return e;
@@ -38,25 +38,17 @@ hipError_t PlanDev::upload(const Plan &pl, int n_iter, hipStream_t stream) {
     if ((e = counts.ensure(pl.counts.size() * sizeof(int))) != hipSuccess) return e;
     if ((e = states.ensure(ns * sizeof(ScgState))) != hipSuccess) return e;
     if ((e = partials.ensure(ni * kNV * sizeof(double))) != hipSuccess) return e;
+    if ((e = refs.ensure(ns * sizeof(SolveRef))) != hipSuccess) return e;
     // per-pass records of each solve (only solves write them)
-    const size_t per = (size_t)(n_iter > 0 ? n_iter : 1);
-    const size_t tbytes = ns * per * sizeof(IterRec);
-    const bool new_traces = n_iter > 0 && (traces.n < tbytes ||
-                                           trace_ptrs.n < ns * sizeof(IterRec *) ||
-                                           n_iter_max != (int)per || trace_ns != ns);
-    if (n_iter > 0) {
-        if ((e = traces.ensure(tbytes)) != hipSuccess) return e;
-        if ((e = trace_ptrs.ensure(ns * sizeof(IterRec *))) != hipSuccess) return e;
-    }
-    if (new_traces) {
-        trace_ns = ns;
-        std::vector<IterRec *> tp(ns);
-        for (size_t i = 0; i < ns; ++i) tp[i] = traces.as<IterRec>() + i * per;
-        if ((e = hipMemcpy(trace_ptrs.p, tp.data(), ns * sizeof(IterRec *),
-                           hipMemcpyHostToDevice)) != hipSuccess)
-            return e;
-        n_iter_max = (int)per;
-    }
+    const size_t per = (size_t)(n_iter > 0 ? n_iter : 0);
+    if (per > 0 && (e = traces.ensure(ns * per * sizeof(IterRec))) != hipSuccess) return e;
+    n_iter_max = (int)per;
+    ScgState *sd = states.as<ScgState>();
+    for (size_t j = 0; j < np; ++j) pl.projs[j].st = sd + pl.proj_solve[j];
+    pl.refs.resize(ns);
+    for (size_t i = 0; i < ns; ++i)
+        pl.refs[i] = SolveRef{sd + i, per ? traces.as<IterRec>() + i * per : nullptr,
+                              pl.item0[i], pl.nitems[i]};
     if ((e = hipMemcpyAsync(projs.p, pl.projs.data(), np * sizeof(Proj), hipMemcpyHostToDevice,
                             stream)) != hipSuccess)
         return e;
@@ -64,6 +56,9 @@ hipError_t PlanDev::upload(const Plan &pl, int n_iter, hipStream_t stream) {
                             stream)) != hipSuccess)
         return e;
     if ((e = hipMemcpyAsync(counts.p, pl.counts.data(), pl.counts.size() * sizeof(int),
+                            hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return e;
+    if ((e = hipMemcpyAsync(refs.p, pl.refs.data(), ns * sizeof(SolveRef),
                             hipMemcpyHostToDevice, stream)) != hipSuccess)
         return e;
     return hipMemcpyAsync(states.p, pl.states.data(), ns * sizeof(ScgState),
@@ -162,6 +157,8 @@ extern "C" misr_status misr_params_check(const misr_params *p) {
         return set_error(MISR_E_INVAL, "img_dtype invalid");
     if (p->tile_lr < 0 || p->halo_lr < 0)
         return set_error(MISR_E_INVAL, "tile_lr and halo_lr must be >= 0");
+    if (p->x_rounding != 0 && p->x_rounding != 1)
+        return set_error(MISR_E_INVAL, "x_rounding must be 0 or 1");
     return MISR_OK;
 }
 
@@ -314,6 +311,7 @@ static void init_state(ScgState &s, const misr_params &p, long long N) {
     s.wt.eps = (float)p.eps;
     s.wt.eps_data = (float)p.eps_data;
     s.wt.data_p = p.data_p;
+    s.wt.x_rounding = p.x_rounding;
 }
 
 struct SolveIn {
@@ -332,6 +330,9 @@ static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
     pl.states.clear();
     pl.classes.clear();
     pl.counts.clear();
+    pl.proj_solve.clear();
+    pl.item0.assign(in.size(), 0);
+    pl.nitems.assign(in.size(), 0);
     std::map<std::pair<int, int>, std::vector<int>> groups;
     std::vector<std::pair<int, int>> order;
     for (int i = 0; i < (int)in.size(); ++i) {
@@ -360,17 +361,16 @@ static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
             P.oy1 = op->H;
             P.ox1 = op->W;
             P.ntx = (op->W + op->TW - 1) / op->TW;
-            P.req = i;
             P.op = op->opdev.as<OpDev>();
             const int nty = (op->H + op->TH - 1) / op->TH;
             const int pj = (int)pl.projs.size();
             pl.projs.push_back(P);
-            ScgState &st = pl.states[i];
-            init_state(st, s.prm, (long long)op->H * op->W);
-            st.item0 = (int)pl.items.size();
+            pl.proj_solve.push_back(i);
+            init_state(pl.states[i], s.prm, (long long)op->H * op->W);
+            pl.item0[i] = (int)pl.items.size();
             for (int ty = 0; ty < nty; ++ty)
                 for (int tx = 0; tx < P.ntx; ++tx) pl.items.push_back(Item{pj, ty, tx, 0});
-            st.nitems = (int)pl.items.size() - st.item0;
+            pl.nitems[i] = (int)pl.items.size() - pl.item0[i];
         }
         c.count = (int)pl.items.size() - c.start;
         pl.classes.push_back(c);
@@ -400,7 +400,6 @@ static hipError_t enqueue_solve(const Plan &pl, PlanDev &pd, int n_iter, int sty
             const Plan::Cls &cl = pl.classes[c];
             hipError_t e = launch_image(cl.S, cl.Lp, cl.count, s, pd.projs.as<Proj>(),
                                         pd.items.as<Item>() + cl.start, d_counts + c,
-                                        pd.states.as<ScgState>(),
                                         pd.partials.as<double>() + (size_t)cl.start * kNV, kind,
                                         stype);
             if (e != hipSuccess) return e;
@@ -408,8 +407,8 @@ static hipError_t enqueue_solve(const Plan &pl, PlanDev &pd, int n_iter, int sty
         return hipSuccess;
     };
     auto scalar = [&](int phase) {
-        return launch_scalar(ns, s, pd.states.as<ScgState>(), d_nstates, pd.partials.as<double>(),
-                             pd.trace_ptrs.as<IterRec *>(), phase);
+        return launch_scalar(ns, s, pd.refs.as<SolveRef>(), d_nstates, pd.partials.as<double>(),
+                             phase);
     };
     hipError_t e;
     if ((e = image(KIND_COSTGRAD)) != hipSuccess) return e;
@@ -421,14 +420,13 @@ static hipError_t enqueue_solve(const Plan &pl, PlanDev &pd, int n_iter, int sty
         if ((e = scalar(PHASE_B)) != hipSuccess) return e;
         if ((e = image(KIND_UPCURV)) != hipSuccess) return e;
     }
-    return launch_finalize(s, pd.projs.as<Proj>(), (int)pl.projs.size(), pd.states.as<ScgState>(),
-                           stype);
+    return launch_finalize(s, pd.projs.as<Proj>(), (int)pl.projs.size(), stype);
 }
 
 // Runs a plan on the context's library stream, ordered after the caller's
 // stream and before its later work; the solve is captured into a graph once
 // per plan shape and replayed.
-static misr_status run_plan(misr_ctx *ctx, const Plan &pl, PlanDev &pd, int n_iter, int stype,
+static misr_status run_plan(misr_ctx *ctx, Plan &pl, PlanDev &pd, int n_iter, int stype,
                             hipStream_t user) {
     hipStream_t s = ctx->stream;
     MISR_HIP(hipEventRecord(ctx->ev_in, user));
@@ -437,7 +435,7 @@ static misr_status run_plan(misr_ctx *ctx, const Plan &pl, PlanDev &pd, int n_it
     // the graph bakes in the device addresses of the plan arrays
     char ptrs[160];
     snprintf(ptrs, sizeof ptrs, "|%p,%p,%p,%p,%p,%p", pd.projs.p, pd.items.p, pd.counts.p,
-             pd.states.p, pd.partials.p, pd.trace_ptrs.p);
+             pd.states.p, pd.partials.p, pd.refs.p);
     const std::string key = plan_key(pl, n_iter, stype) + ptrs;
     if (!pd.exec || pd.graph_key != key) {
         if (pd.exec) {
@@ -557,8 +555,8 @@ extern "C" misr_status misr_cost_grad(const misr_op *cop, const misr_params *prm
     MISR_HIP(pd.upload(pl, 0, s));
     const Plan::Cls &cl = pl.classes[0];
     MISR_HIP(launch_image(cl.S, cl.Lp, cl.count, s, pd.projs.as<Proj>(), pd.items.as<Item>(),
-                          pd.counts.as<int>(), pd.states.as<ScgState>(), pd.partials.as<double>(),
-                          KIND_COSTGRAD, (int)prm->img_dtype));
+                          pd.counts.as<int>(), pd.partials.as<double>(), KIND_COSTGRAD,
+                          (int)prm->img_dtype));
     MISR_HIP(launch_cost_out(s, pd.partials.as<double>(), cl.count, cost_dev));
     return MISR_OK;
 }
@@ -645,4 +643,61 @@ extern "C" misr_status misr_scg_solve_batch(int n, const misr_op *const *ops,
             if (t != MISR_OK) worst = t;
         }
     return worst;
+}
+
+// ------------------------------------------------------------- measurement
+extern "C" misr_status misr_time_pass(const misr_op *cop, const misr_params *prm, const void *y,
+                                      void *x, int which, int reps, double *avg_us,
+                                      void *stream) {
+    misr_op *op = const_cast<misr_op *>(cop);
+    if (!op || !y || !x || !avg_us || reps < 1 || (which != 0 && which != 1))
+        return set_error(MISR_E_INVAL, "bad arguments");
+    misr_status st = misr_params_check(prm);
+    if (st != MISR_OK) return st;
+    if (prm->data_p != 2 || prm->tile_lr > 0)
+        return set_error(MISR_E_INVAL, "L2 data term, untiled only");
+    std::lock_guard<std::mutex> lk(op->mu);
+    std::lock_guard<std::mutex> lc(op->ctx->mu);
+    MISR_HIP(set_device(op->ctx->dev));
+    const long long n = (long long)op->H * op->W;
+    MISR_HIP(op->bufs.ensure(n, dtype_size(prm->img_dtype)));
+    Plan &pl = op->plan;
+    misr_params p1 = *prm;
+    p1.n_iter = 1;
+    build_plan(pl, {SolveIn{op, p1, y, x, &op->bufs}});
+    PlanDev &pd = op->pdev;
+    hipStream_t s = op->ctx->stream;
+    MISR_HIP(hipEventRecord(op->ctx->ev_in, (hipStream_t)stream));
+    MISR_HIP(hipStreamWaitEvent(s, op->ctx->ev_in, 0));
+    MISR_HIP(pd.upload(pl, 1, s));
+    const Plan::Cls &cl = pl.classes[0];
+    const int stype = (int)prm->img_dtype;
+    auto image = [&](int kind) {
+        return launch_image(cl.S, cl.Lp, cl.count, s, pd.projs.as<Proj>(), pd.items.as<Item>(),
+                            pd.counts.as<int>(), pd.partials.as<double>(), kind, stype);
+    };
+    auto scalar = [&](int phase) {
+        return launch_scalar(1, s, pd.refs.as<SolveRef>(), pd.counts.as<int>() + 1,
+                             pd.partials.as<double>(), phase);
+    };
+    MISR_HIP(image(KIND_COSTGRAD));
+    MISR_HIP(scalar(PHASE_INIT));
+    MISR_HIP(image(KIND_UPCURV));
+    MISR_HIP(scalar(PHASE_A));
+    hipEvent_t e0, e1;
+    MISR_HIP(hipEventCreate(&e0));
+    MISR_HIP(hipEventCreate(&e1));
+    const int kind = which == 0 ? KIND_TRIAL : KIND_UPCURV;
+    hipError_t e = image(kind);   // warm-up launch
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = image(kind);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "misr_time_pass");
+    *avg_us = 1e3 * ms / reps;
+    return MISR_OK;
 }

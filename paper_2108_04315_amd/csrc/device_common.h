@@ -35,12 +35,29 @@ FI const AS1 T *glb(const T *p) { return (const AS1 T *)p; }
 template <class T>
 FI AS1 T *glbw(T *p) { return (AS1 T *)p; }
 
-// Storage of x and y: float32, IEEE half or bfloat16 (round to nearest even).
+// 32-bit mixing hash (the MurmurHash3 finaliser) of a pixel index and a seed:
+// the counter-based source of the stochastic-rounding bits.
+FI unsigned mix32(unsigned h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+FI unsigned pixel_hash(long long gidx, unsigned seed) {
+    return mix32((unsigned)gidx * 0x9e3779b1u ^ mix32((unsigned)(gidx >> 32) + seed));
+}
+
+// Storage of x and y: float32, IEEE half or bfloat16.  rnd() rounds to the
+// nearest representable value (ties to even); rnd_sr() rounds up with
+// probability equal to the fraction of the spacing, from 16 hash bits.
 struct StF32 {
     using raw = float;
     static constexpr int code = ST_F32;
     static FI float ld(const AS1 raw *p, i64 i) { return p[i]; }
     static FI float rnd(float v) { return v; }
+    static FI float rnd_sr(float v, unsigned) { return v; }
     static FI void st(AS1 raw *p, i64 i, float v) { p[i] = v; }
 };
 struct StF16 {
@@ -48,6 +65,13 @@ struct StF16 {
     static constexpr int code = ST_F16;
     static FI float ld(const AS1 raw *p, i64 i) { return (float)p[i]; }
     static FI float rnd(float v) { return (float)(_Float16)v; }
+    static FI float rnd_sr(float v, unsigned h) {
+        // spacing of half precision at v (subnormal spacing 2^-24 below 2^-14)
+        const int e = (int)((__float_as_uint(v) >> 23) & 0xffu) - 127;
+        const float ulp = __builtin_ldexpf(1.f, (e < -14 ? -14 : e) - 10);
+        const float u = (float)(h & 0xffffu) * (1.f / 65536.f) - 0.5f;
+        return (float)(_Float16)fmaf(u, ulp, v);
+    }
     static FI void st(AS1 raw *p, i64 i, float v) { p[i] = (_Float16)v; }
 };
 struct StBF16 {
@@ -61,6 +85,12 @@ struct StBF16 {
     }
     static FI float ld(const AS1 raw *p, i64 i) { return __uint_as_float((unsigned)p[i] << 16); }
     static FI float rnd(float v) { return __uint_as_float((unsigned)bits(v) << 16); }
+    static FI float rnd_sr(float v, unsigned h) {
+        unsigned u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) >= 0x7f800000u) return rnd(v);
+        u += h & 0xffffu;
+        return __uint_as_float(u & 0xffff0000u);
+    }
     static FI void st(AS1 raw *p, i64 i, float v) { p[i] = bits(v); }
 };
 

@@ -368,6 +368,10 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     const AS1 float *pb = glb(P.p[xc]);
     const float af = (mode == 1) ? st.alpha_f : 0.f;
     const int Hb = P.Hb, Wb = P.Wb, ld = P.ld;
+    const bool sr = st.wt.x_rounding == 1;
+    const unsigned seed = st.rseed;
+    const AS4 OpDev &opg = op;
+    const i64 Wg = opg.W;
     {
         float val[T::NSTAGE];
 #pragma unroll
@@ -379,7 +383,13 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
             if (q < T::WR * T::WC && ub >= 0 && ub < Hb && vb >= 0 && vb < Wb) {
                 const i64 idx = (i64)ub * ld + vb;
                 const float xv = ST::ld(xb, idx);
-                val[s] = (mode == 1) ? ST::rnd(fmaf(af, pb[idx], xv)) : xv;
+                if (mode == 1) {
+                    const float v = fmaf(af, pb[idx], xv);
+                    val[s] = sr ? ST::rnd_sr(v, pixel_hash((i64)(P.gy0 + ub) * Wg + P.gx0 + vb, seed))
+                                : ST::rnd(v);
+                } else {
+                    val[s] = xv;
+                }
             }
         }
 #pragma unroll
@@ -514,6 +524,9 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
     AS1 float *po = glbw(P.p[dst]);
     const float af = st.alpha_f, bf = st.beta_f;
     const int Hb = P.Hb, Wb = P.Wb, ld = P.ld;
+    const bool sr = st.wt.x_rounding == 1;
+    const unsigned seed = st.rseed;
+    const i64 Wg = W;
     double pp = 0.0, pr = 0.0;
     {
         float xv[T::NSTAGE], pv[T::NSTAGE];
@@ -527,7 +540,9 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
             if (q < T::WR * T::WC && ub >= 0 && ub < Hb && vb >= 0 && vb < Wb) {
                 const i64 idx = (i64)ub * ld + vb;
                 const float p0 = pb[idx], g0 = gt[idx];
-                xv[s] = ST::rnd(fmaf(af, p0, ST::ld(xb, idx)));
+                const float v = fmaf(af, p0, ST::ld(xb, idx));
+                xv[s] = sr ? ST::rnd_sr(v, pixel_hash((i64)(P.gy0 + ub) * Wg + P.gx0 + vb, seed))
+                           : ST::rnd(v);
                 pv[s] = fmaf(bf, p0, -g0);
                 if (ub >= o.u0 && ub < o.u1 && vb >= o.v0 && vb < o.v1) {
                     ST::st(xo, idx, xv[s]);
@@ -697,15 +712,15 @@ FI void tile_adjoint(const AS4 Proj &P, int ty, int tx, const void *r, float *xo
 // from device memory so that one captured launch can serve a changing list.
 template <int S, int L, class ST>
 __global__ void __launch_bounds__(kNTI) k_trial(const Proj *projs, const Item *items,
-                                                const int *n_items, const ScgState *states,
-                                                double *partials, int mode) {
+                                                const int *n_items, double *partials,
+                                                int mode) {
     __shared__ float sm[Tile<S, L>::SMEM];
     __shared__ double red[kNV * kNWI];
     const int n = *cst(n_items);
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const AS4 Item &itm = cst(items)[it];
         const AS4 Proj &P = cst(projs)[itm.proj];
-        const AS4 ScgState &st = cst(states)[P.req];
+        const AS4 ScgState &st = *cst(P.st);
         if (mode == 1 && !st.active) continue;
         tile_trial<S, L, ST>(P, st, itm.ty, itm.tx, mode, sm, red, partials + (i64)it * kNV);
         __syncthreads();
@@ -714,15 +729,14 @@ __global__ void __launch_bounds__(kNTI) k_trial(const Proj *projs, const Item *i
 
 template <int S, int L, class ST>
 __global__ void __launch_bounds__(kNTI) k_upcurv(const Proj *projs, const Item *items,
-                                                 const int *n_items, const ScgState *states,
-                                                 double *partials) {
+                                                 const int *n_items, double *partials) {
     __shared__ float sm[Tile<S, L>::SMEM];
     __shared__ double red[kNV * kNWI];
     const int n = *cst(n_items);
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const AS4 Item &itm = cst(items)[it];
         const AS4 Proj &P = cst(projs)[itm.proj];
-        const AS4 ScgState &st = cst(states)[P.req];
+        const AS4 ScgState &st = *cst(P.st);
         if (!st.do_update) continue;
         tile_upcurv<S, L, ST>(P, st, itm.ty, itm.tx, sm, red, partials + (i64)it * kNV);
         __syncthreads();
@@ -781,19 +795,19 @@ int MISR_FN(tile_dims_s)(int Lp, int *th, int *tw) {
 }
 
 hipError_t MISR_FN(launch_trial_s)(int Lp, int stype, int grid, hipStream_t s, const Proj *projs,
-                                   const Item *items, const int *n_items,
-                                   const ScgState *states, double *partials, int mode) {
+                                   const Item *items, const int *n_items, double *partials,
+                                   int mode) {
 #define X(l)                                                                                    \
     if (Lp == l) {                                                                              \
         if (stype == ST_F32)                                                                    \
             hipLaunchKernelGGL((k_trial<MISR_SCALE, l, StF32>), dim3(grid), dim3(kNTI), 0, s,     \
-                               projs, items, n_items, states, partials, mode);                  \
+                               projs, items, n_items, partials, mode);                  \
         else if (stype == ST_F16)                                                               \
             hipLaunchKernelGGL((k_trial<MISR_SCALE, l, StF16>), dim3(grid), dim3(kNTI), 0, s,     \
-                               projs, items, n_items, states, partials, mode);                  \
+                               projs, items, n_items, partials, mode);                  \
         else                                                                                    \
             hipLaunchKernelGGL((k_trial<MISR_SCALE, l, StBF16>), dim3(grid), dim3(kNTI), 0, s,    \
-                               projs, items, n_items, states, partials, mode);                  \
+                               projs, items, n_items, partials, mode);                  \
         return hipGetLastError();                                                               \
     }
     MISR_LIST(X)
@@ -803,18 +817,18 @@ hipError_t MISR_FN(launch_trial_s)(int Lp, int stype, int grid, hipStream_t s, c
 
 hipError_t MISR_FN(launch_upcurv_s)(int Lp, int stype, int grid, hipStream_t s, const Proj *projs,
                                     const Item *items, const int *n_items,
-                                    const ScgState *states, double *partials) {
+                                    double *partials) {
 #define X(l)                                                                                     \
     if (Lp == l) {                                                                               \
         if (stype == ST_F32)                                                                     \
             hipLaunchKernelGGL((k_upcurv<MISR_SCALE, l, StF32>), dim3(grid), dim3(kNTI), 0, s,     \
-                               projs, items, n_items, states, partials);                         \
+                               projs, items, n_items, partials);                         \
         else if (stype == ST_F16)                                                                \
             hipLaunchKernelGGL((k_upcurv<MISR_SCALE, l, StF16>), dim3(grid), dim3(kNTI), 0, s,     \
-                               projs, items, n_items, states, partials);                         \
+                               projs, items, n_items, partials);                         \
         else                                                                                     \
             hipLaunchKernelGGL((k_upcurv<MISR_SCALE, l, StBF16>), dim3(grid), dim3(kNTI), 0, s,    \
-                               projs, items, n_items, states, partials);                         \
+                               projs, items, n_items, partials);                         \
         return hipGetLastError();                                                                \
     }
     MISR_LIST(X)

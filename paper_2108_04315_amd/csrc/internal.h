@@ -42,7 +42,8 @@ struct Proj {
     int gy0, gx0;
     int oy0, oy1, ox0, ox1;
     int ntx;             // tiles per row of the owned rectangle
-    int req;             // index of the solve this view belongs to
+    int pad_;
+    struct ScgState *st; // the solve this view belongs to
     const OpDev *op;
 };
 
@@ -58,6 +59,7 @@ struct Weights {
     float eps;           // prior Charbonnier eps
     float eps_data;      // data Charbonnier eps (p = 1)
     int data_p;
+    int x_rounding;      // 16-bit x storage: 0 nearest even, 1 stochastic (hashed)
 };
 
 // Device-resident SCG state of one solve (Moller's scalars, FP64).
@@ -74,10 +76,17 @@ struct ScgState {
     int active;          // 0 once stopped
     int stop;            // 0 running/complete, 1 ||r|| = 0, 2 non-finite
     int do_update;       // k_upcurv runs this pass
-    int item0, nitems;   // this solve's range of work items (partials)
     float alpha_f, beta_f, sigk_f;
-    int pad_;
+    unsigned rseed;      // per-pass seed of the stochastic rounding hash
     Weights wt;
+};
+
+// A solve as seen by the scalar kernel: its state, its per-pass record and
+// the range of work items (and partial sums) its views occupy.
+struct SolveRef {
+    ScgState *st;
+    struct IterRec *trace;
+    int item0, nitems;
 };
 
 struct IterRec {

@@ -19,19 +19,18 @@ int padded_band(int S, int L);
 int tile_hr(int S, int Lp);
 int tile_wr(int S, int Lp);
 hipError_t launch_image(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
-                        const Item *items, const int *n_items, const ScgState *states,
-                        double *partials, int kind, int stype);
+                        const Item *items, const int *n_items, double *partials, int kind,
+                        int stype);
 hipError_t launch_forward(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
                           const Item *items, int n, int stype, void *y);
 hipError_t launch_adjoint(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
                           const Item *items, int n, int stype, const void *r, float *x);
-hipError_t launch_scalar(int grid, hipStream_t stream, ScgState *states, const int *n_states,
-                         const double *partials, IterRec *const *traces, int phase);
+hipError_t launch_scalar(int grid, hipStream_t stream, const SolveRef *refs, const int *n_refs,
+                         const double *partials, int phase);
 hipError_t launch_cost_out(hipStream_t stream, const double *partials, int nitems,
                            double *out);
 hipError_t launch_fill(hipStream_t stream, float *p, long long n, float v);
-hipError_t launch_finalize(hipStream_t stream, const Proj *projs, int nproj,
-                           const ScgState *states, int stype);
+hipError_t launch_finalize(hipStream_t stream, const Proj *projs, int nproj, int stype);
 
 enum { KIND_COSTGRAD = 0, KIND_TRIAL = 1, KIND_UPCURV = 2 };
 enum { PHASE_INIT = 0, PHASE_A = 1, PHASE_B = 2 };
@@ -81,6 +80,9 @@ struct Plan {
     std::vector<ScgState> states;
     std::vector<Cls> classes;
     std::vector<int> counts;          // per class item count, then n_states
+    std::vector<int> proj_solve;      // solve index of each view
+    std::vector<int> item0, nitems;   // per solve: its range of work items
+    std::vector<SolveRef> refs;       // device-side references (filled by upload)
 };
 
 // Per-solve image buffers owned by the library (x1, p0, p1, g0, g1).
@@ -98,7 +100,7 @@ struct SolveBufs {
 
 // Device mirrors of a Plan plus an instantiated graph of the whole solve.
 struct PlanDev {
-    DevMem projs, items, counts, states, partials, traces, trace_ptrs;
+    DevMem projs, items, counts, states, partials, traces, refs;
     int n_iter_max = 0;
     size_t trace_ns = 0;
     hipGraphExec_t exec = nullptr;
@@ -106,7 +108,7 @@ struct PlanDev {
     ~PlanDev() {
         if (exec) (void)hipGraphExecDestroy(exec);
     }
-    hipError_t upload(const Plan &pl, int n_iter_max, hipStream_t stream);
+    hipError_t upload(Plan &pl, int n_iter_max, hipStream_t stream);
 };
 
 }  // namespace misr

@@ -75,6 +75,7 @@ __device__ void scg_phase_a(ScgState &s, const double *v) {
         return;
     }
     s.alpha_f = (float)s.alpha;
+    s.rseed = mix32(0x51ed270bu + (unsigned)s.it);
 }
 
 // steps 6-9 of the pass
@@ -130,14 +131,14 @@ __device__ void scg_phase_b(ScgState &s, const double *v, IterRec *trace) {
     if (s.it >= s.n_iter) s.active = 0;
 }
 
-__global__ void __launch_bounds__(kNT) k_scalar(ScgState *states, const int *n_states,
-                                                const double *__restrict__ partials,
-                                                IterRec *const *traces, int phase) {
+__global__ void __launch_bounds__(kNT) k_scalar(const SolveRef *refs, const int *n_refs,
+                                                const double *__restrict__ partials, int phase) {
     __shared__ double red[kNV * (kNT / 64)];
     __shared__ double tot[kNV];
-    const int ns = *n_states;
+    const int ns = *n_refs;
     for (int sv = blockIdx.x; sv < ns; sv += gridDim.x) {
-        ScgState &s = states[sv];
+        const SolveRef ref = refs[sv];
+        ScgState &s = *ref.st;
         bool need;
         if (phase == PH_INIT)
             need = true;
@@ -148,7 +149,7 @@ __global__ void __launch_bounds__(kNT) k_scalar(ScgState *states, const int *n_s
         __syncthreads();   // every thread has read the state before thread 0 writes it
         if (need) {
             double v[kNV] = {0, 0, 0, 0, 0, 0};
-            for (int i = s.item0 + threadIdx.x; i < s.item0 + s.nitems; i += kNT)
+            for (int i = ref.item0 + threadIdx.x; i < ref.item0 + ref.nitems; i += kNT)
 #pragma unroll
                 for (int q = 0; q < kNV; ++q) v[q] += partials[(long long)i * kNV + q];
             block_sum_store<kNV, kNT>(v, tot, red);
@@ -159,7 +160,7 @@ __global__ void __launch_bounds__(kNT) k_scalar(ScgState *states, const int *n_s
             else if (phase == PH_A)
                 scg_phase_a(s, tot);
             else
-                scg_phase_b(s, tot, traces ? traces[sv] : nullptr);
+                scg_phase_b(s, tot, ref.trace);
         }
         __syncthreads();
     }
@@ -191,11 +192,10 @@ __global__ void k_fill_f32(float *p, long long n, float v) {
 
 // Copies x[1] into x[0] for every view whose current iterate sits in the
 // workspace buffer (decided on the device).
-__global__ void k_finalize(const Proj *__restrict__ projs, int nproj,
-                           const ScgState *__restrict__ states, int stype) {
+__global__ void k_finalize(const Proj *__restrict__ projs, int nproj, int stype) {
     for (int j = 0; j < nproj; ++j) {
         const Proj &P = projs[j];
-        if (states[P.req].xc == 0) continue;
+        if (P.st->xc == 0) continue;
         const long long n = (long long)P.Hb * P.ld;
         const int es = (stype == ST_F32) ? 4 : 2;
         if (es == 4) {
@@ -219,11 +219,11 @@ __global__ void k_finalize(const Proj *__restrict__ projs, int nproj,
 #define X(s)                                                                                   \
     int tile_dims_s##s(int Lp, int *th, int *tw);                                              \
     hipError_t launch_trial_s##s(int Lp, int stype, int grid, hipStream_t st, const Proj *projs, \
-                                 const Item *items, const int *n_items,                        \
-                                 const ScgState *states, double *partials, int mode);          \
+                                 const Item *items, const int *n_items, double *partials,      \
+                                 int mode);                                                    \
     hipError_t launch_upcurv_s##s(int Lp, int stype, int grid, hipStream_t st,                 \
                                   const Proj *projs, const Item *items, const int *n_items,    \
-                                  const ScgState *states, double *partials);                   \
+                                  double *partials);                                           \
     hipError_t launch_forward_s##s(int Lp, int stype, int grid, hipStream_t st,                \
                                    const Proj *projs, const Item *items, int n, void *y);      \
     hipError_t launch_adjoint_s##s(int Lp, int stype, int grid, hipStream_t st,                \
@@ -264,14 +264,14 @@ int tile_wr(int S, int Lp) {
 }
 
 hipError_t launch_image(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
-                        const Item *items, const int *n_items, const ScgState *states,
-                        double *partials, int kind, int stype) {
+                        const Item *items, const int *n_items, double *partials, int kind,
+                        int stype) {
 #define X(s)                                                                                  \
     if (S == s)                                                                               \
         return kind == 2 ? launch_upcurv_s##s(Lp, stype, grid, stream, projs, items, n_items, \
-                                              states, partials)                               \
+                                              partials)                                       \
                          : launch_trial_s##s(Lp, stype, grid, stream, projs, items, n_items,  \
-                                             states, partials, kind);
+                                             partials, kind);
     MISR_SCALES(X)
 #undef X
     return hipErrorInvalidValue;
@@ -295,10 +295,10 @@ hipError_t launch_adjoint(int S, int Lp, int grid, hipStream_t stream, const Pro
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_scalar(int grid, hipStream_t stream, ScgState *states, const int *n_states,
-                         const double *partials, IterRec *const *traces, int phase) {
-    hipLaunchKernelGGL(k_scalar, dim3(grid), dim3(kNT), 0, stream, states, n_states, partials,
-                       traces, phase);
+hipError_t launch_scalar(int grid, hipStream_t stream, const SolveRef *refs, const int *n_refs,
+                         const double *partials, int phase) {
+    hipLaunchKernelGGL(k_scalar, dim3(grid), dim3(kNT), 0, stream, refs, n_refs, partials,
+                       phase);
     return hipGetLastError();
 }
 
@@ -316,10 +316,8 @@ hipError_t launch_fill(hipStream_t stream, float *p, long long n, float v) {
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(hipStream_t stream, const Proj *projs, int nproj,
-                           const ScgState *states, int stype) {
-    hipLaunchKernelGGL(k_finalize, dim3(1024), dim3(256), 0, stream, projs, nproj, states,
-                       stype);
+hipError_t launch_finalize(hipStream_t stream, const Proj *projs, int nproj, int stype) {
+    hipLaunchKernelGGL(k_finalize, dim3(1024), dim3(256), 0, stream, projs, nproj, stype);
     return hipGetLastError();
 }
 

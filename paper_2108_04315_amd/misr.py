@@ -44,7 +44,8 @@ class misr_params(C.Structure):
     _fields_ = [("lambda_reg", C.c_double), ("alpha_btv", C.c_double), ("eps", C.c_double),
                 ("btv_w", C.c_int32), ("data_p", C.c_int32), ("eps_data", C.c_double),
                 ("scg_sigma", C.c_double), ("scg_lambda1", C.c_double), ("n_iter", C.c_int32),
-                ("img_dtype", C.c_int32), ("tile_lr", C.c_int32), ("halo_lr", C.c_int32)]
+                ("img_dtype", C.c_int32), ("tile_lr", C.c_int32), ("halo_lr", C.c_int32),
+                ("x_rounding", C.c_int32), ("pad_", C.c_int32)]
 
 
 class misr_scg_iter(C.Structure):
@@ -98,6 +99,8 @@ _SIGS = {
     "misr_scg_solve_batch": (C.c_int, [C.c_int, C.POINTER(_vp), C.POINTER(misr_params),
                                        C.POINTER(_vp), C.POINTER(_vp),
                                        C.POINTER(misr_scg_trace), _vp]),
+    "misr_time_pass": (C.c_int, [_vp, C.POINTER(misr_params), _vp, _vp, C.c_int, C.c_int,
+                                 C.POINTER(C.c_double), _vp]),
     "misr_server_create": (C.c_int, [_vp, C.POINTER(misr_server_config), C.POINTER(_vp)]),
     "misr_server_submit": (C.c_int, [_vp, C.POINTER(misr_request), C.POINTER(C.c_uint64)]),
     "misr_server_poll": (C.c_int, [_vp, C.c_uint64, C.POINTER(C.c_int),
@@ -262,6 +265,18 @@ class Operator:
         return _trace_out(tr, recs, st)
 
 
+    def time_pass(self, y, x, which: int, reps: int = 20, params: misr_params | None = None,
+                  stream=None) -> float:
+        """Mean duration (us) of one image pass (0: trial, 1: update) at the
+        solve's first trial point, timed with HIP events."""
+        p = params or default_params()
+        p.img_dtype = dtype_code(x)
+        out = C.c_double()
+        check(lib.misr_time_pass(self.h, C.byref(p), _ptr(y), _ptr(x), which, reps,
+                                 C.byref(out), stream_handle(stream)))
+        return out.value
+
+
 def _new_trace(n: int):
     recs = (misr_scg_iter * max(1, n))()
     tr = misr_scg_trace()
@@ -298,3 +313,56 @@ def scg_solve_batch(ops, ys, xs, params_list, trace: bool = True, stream=None):
     if not trace:
         return None
     return [_trace_out(trs[i], recs[i], st) for i in range(n)]
+
+
+class Server:
+    """Continuous-batching server of SR solves (misr_server_*)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 64,
+                 max_queue: int = 0, fail_alloc_n: int = 0):
+        cfg = misr_server_config(hbm_budget_bytes, max_slots, max_queue, fail_alloc_n, 0)
+        h = C.c_void_p()
+        check(lib.misr_server_create(ctx.h, C.byref(cfg), C.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, H, W, s, shifts, psf, y, x0, x_out, params: misr_params | None = None,
+               on_device: bool = True) -> int:
+        """Queues one solve; y, x0, x_out are device tensors (or host numpy
+        arrays with on_device=False) that must stay alive until it finishes."""
+        g, keep = make_geometry(H, W, s, shifts, psf)
+        p = params or default_params()
+        if on_device:
+            p.img_dtype = dtype_code(x0)
+            ptrs = (y.data_ptr(), x0.data_ptr(), x_out.data_ptr())
+        else:
+            ptrs = (y.ctypes.data, x0.ctypes.data, x_out.ctypes.data)
+        req = misr_request(g, p, ptrs[0], ptrs[1], ptrs[2], 1 if on_device else 0,
+                           DONE_CB(0), None)
+        rid = C.c_uint64()
+        check(lib.misr_server_submit(self.h, C.byref(req), C.byref(rid)))
+        self._keep[rid.value] = (keep, y, x0, x_out)
+        return rid.value
+
+    def poll(self, rid: int):
+        st = C.c_int()
+        stats = misr_req_stats()
+        check(lib.misr_server_poll(self.h, rid, C.byref(st), C.byref(stats)))
+        return st.value, stats
+
+    def wait(self, rid: int, timeout_us: int = -1) -> int:
+        return lib.misr_server_wait(self.h, rid, timeout_us)
+
+    def cancel(self, rid: int) -> int:
+        return lib.misr_server_cancel(self.h, rid)
+
+    def close(self):
+        if self.h:
+            check(lib.misr_server_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

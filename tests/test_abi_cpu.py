@@ -29,11 +29,29 @@ def test_every_declared_symbol_is_exported(misr):
     assert not missing, missing
 
 
-def test_struct_sizes_match_header(misr):
-    # field order and sizes as declared; the ctypes mirrors must agree
-    assert C.sizeof(misr.misr_scg_iter) == 8 * 8
-    assert C.sizeof(misr.misr_params) == 80
-    assert C.sizeof(misr.misr_geometry) == 40
+def test_struct_layouts_match_header(misr, tmp_path):
+    """The ctypes mirrors have the sizes and field offsets a C compiler gives
+    the structs of include/misr.h."""
+    structs = {"misr_geometry": misr.misr_geometry, "misr_params": misr.misr_params,
+               "misr_scg_iter": misr.misr_scg_iter, "misr_scg_trace": misr.misr_scg_trace,
+               "misr_request": misr.misr_request, "misr_server_config": misr.misr_server_config,
+               "misr_req_stats": misr.misr_req_stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "misr.h"', "int main(void){"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(ln.split() for ln in subprocess.check_output([str(exe)], text=True).splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == C.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(got[f"{name}.{fname}"]) == getattr(cls, fname).offset, (name, fname)
 
 
 def test_params_defaults_and_checks(misr):

