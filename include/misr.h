@@ -140,7 +140,9 @@ misr_status misr_params_check(const misr_params *p);
  * next misr_* call on the same thread. */
 const char *misr_last_error(void);
 
-/* Binds a context to HIP device `hip_device` (ordinal). */
+/* Binds a context to HIP device `hip_device` (ordinal).  A context must outlive
+ * the ops and servers created on it: misr_ctx_destroy returns MISR_E_BUSY (and
+ * frees nothing) while any of them is alive. */
 misr_status misr_ctx_create(int hip_device, misr_ctx **out);
 misr_status misr_ctx_destroy(misr_ctx *ctx);
 

@@ -32,13 +32,17 @@ size_t dtype_size(misr_dtype dt) { return dt == MISR_F32 ? 4 : 2; }
 
 hipError_t PlanDev::upload(Plan &pl, int n_iter, hipStream_t stream) {
     hipError_t e;
-    const size_t np = pl.projs.size(), ni = pl.items.size(), ns = pl.states.size();
+    const size_t np = pl.projs.size(), ni = pl.items.size(), nu = pl.items_u.size(),
+                 ns = pl.states.size(), nh = pl.halos.size();
     if ((e = projs.ensure(np * sizeof(Proj))) != hipSuccess) return e;
     if ((e = items.ensure(ni * sizeof(Item))) != hipSuccess) return e;
+    if ((e = items_u.ensure(nu * sizeof(Item))) != hipSuccess) return e;
     if ((e = counts.ensure(pl.counts.size() * sizeof(int))) != hipSuccess) return e;
     if ((e = states.ensure(ns * sizeof(ScgState))) != hipSuccess) return e;
     if ((e = partials.ensure(ni * kNV * sizeof(double))) != hipSuccess) return e;
+    if ((e = partials_u.ensure(nu * kNV * sizeof(double))) != hipSuccess) return e;
     if ((e = refs.ensure(ns * sizeof(SolveRef))) != hipSuccess) return e;
+    if ((e = halos.ensure(nh * sizeof(HaloCopy))) != hipSuccess) return e;
     // per-pass records of each solve (only solves write them)
     const size_t per = (size_t)(n_iter > 0 ? n_iter : 0);
     if (per > 0 && (e = traces.ensure(ns * per * sizeof(IterRec))) != hipSuccess) return e;
@@ -48,21 +52,22 @@ hipError_t PlanDev::upload(Plan &pl, int n_iter, hipStream_t stream) {
     pl.refs.resize(ns);
     for (size_t i = 0; i < ns; ++i)
         pl.refs[i] = SolveRef{sd + i, per ? traces.as<IterRec>() + i * per : nullptr,
-                              pl.item0[i], pl.nitems[i]};
-    if ((e = hipMemcpyAsync(projs.p, pl.projs.data(), np * sizeof(Proj), hipMemcpyHostToDevice,
-                            stream)) != hipSuccess)
-        return e;
-    if ((e = hipMemcpyAsync(items.p, pl.items.data(), ni * sizeof(Item), hipMemcpyHostToDevice,
-                            stream)) != hipSuccess)
-        return e;
-    if ((e = hipMemcpyAsync(counts.p, pl.counts.data(), pl.counts.size() * sizeof(int),
-                            hipMemcpyHostToDevice, stream)) != hipSuccess)
-        return e;
-    if ((e = hipMemcpyAsync(refs.p, pl.refs.data(), ns * sizeof(SolveRef),
-                            hipMemcpyHostToDevice, stream)) != hipSuccess)
-        return e;
-    return hipMemcpyAsync(states.p, pl.states.data(), ns * sizeof(ScgState),
-                          hipMemcpyHostToDevice, stream);
+                              pl.item0[i], pl.nitems[i], pl.item0u[i], pl.nitemsu[i]};
+    struct Up {
+        void *d;
+        const void *h;
+        size_t n;
+    } ups[] = {{projs.p, pl.projs.data(), np * sizeof(Proj)},
+               {items.p, pl.items.data(), ni * sizeof(Item)},
+               {items_u.p, pl.items_u.data(), nu * sizeof(Item)},
+               {counts.p, pl.counts.data(), pl.counts.size() * sizeof(int)},
+               {refs.p, pl.refs.data(), ns * sizeof(SolveRef)},
+               {halos.p, pl.halos.data(), nh * sizeof(HaloCopy)},
+               {states.p, pl.states.data(), ns * sizeof(ScgState)}};
+    for (auto &u : ups)
+        if (u.n && (e = hipMemcpyAsync(u.d, u.h, u.n, hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return e;
+    return hipSuccess;
 }
 
 }  // namespace misr
@@ -188,6 +193,8 @@ extern "C" misr_status misr_ctx_create(int dev, misr_ctx **out) {
 
 extern "C" misr_status misr_ctx_destroy(misr_ctx *c) {
     if (!c) return set_error(MISR_E_INVAL, "ctx is NULL");
+    if (c->users.load() > 0)
+        return set_error(MISR_E_BUSY, "%d ops/servers still use this context", c->users.load());
     (void)hipStreamSynchronize(c->stream);
     (void)hipEventDestroy(c->ev_in);
     (void)hipEventDestroy(c->ev_out);
@@ -279,15 +286,18 @@ extern "C" misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, mis
     hd.K = op->K;
     hd.L = op->Lp;
     MISR_HIP(hipMemcpy(op->opdev.p, &hd, sizeof hd, hipMemcpyHostToDevice));
+    ctx->users++;
     *out = op.release();
     return MISR_OK;
 }
 
 extern "C" misr_status misr_op_destroy(misr_op *op) {
     if (!op) return set_error(MISR_E_INVAL, "op is NULL");
-    (void)set_device(op->ctx->dev);
-    (void)hipStreamSynchronize(op->ctx->stream);
+    misr_ctx *ctx = op->ctx;
+    (void)set_device(ctx->dev);
+    (void)hipStreamSynchronize(ctx->stream);
     delete op;
+    ctx->users--;
     return MISR_OK;
 }
 
@@ -319,108 +329,260 @@ struct SolveIn {
     misr_params prm;
     const void *y;
     void *x;
-    SolveBufs *bufs;
+    SolveBufs *bufs;     // untiled: the view's workspace
+    TileSet *tiles;      // tiled (prm.tile_lr > 0): per-tile buffers
 };
 
-// Builds the work list: solves grouped by kernel class (S, Lp), each solve's
-// tiles contiguous so that its partial sums form one range.
+// Tile grid of a tiled solve: tile t = (a, b) owns HR rows [a T, (a+1) T) and
+// columns [b T, (b+1) T) (clipped); its buffer adds a halo of Hh on interior
+// sides.
+struct TileGrid {
+    int T, Hh, ny, nx;
+};
+static TileGrid tile_grid(const misr_op *op, const misr_params &p) {
+    TileGrid g;
+    g.T = p.tile_lr * op->s;
+    g.Hh = p.halo_lr * op->s;
+    g.ny = (op->H + g.T - 1) / g.T;
+    g.nx = (op->W + g.T - 1) / g.T;
+    return g;
+}
+
+static misr_status check_tiling(const misr_op *op, const misr_params &p) {
+    if (p.tile_lr <= 0) return MISR_OK;
+    const int need = std::max(op->L - 1, 2);
+    if (p.halo_lr * op->s < need)
+        return set_error(MISR_E_INVAL, "halo of %d LR px (%d HR px) is below the %d HR px the "
+                         "operator and prior reach", p.halo_lr, p.halo_lr * op->s, need);
+    return MISR_OK;
+}
+
+static hipError_t ensure_tiles(const misr_op *op, const misr_params &p, TileSet &ts) {
+    const TileGrid g = tile_grid(op, p);
+    const size_t es = dtype_size(p.img_dtype);
+    const int nt = g.ny * g.nx;
+    if (ts.tile_lr != p.tile_lr || ts.halo_lr != p.halo_lr || ts.es != es ||
+        (int)ts.bufs.size() != nt) {
+        ts.bufs.clear();
+        ts.x0.clear();
+        ts.tile_lr = p.tile_lr;
+        ts.halo_lr = p.halo_lr;
+        ts.es = es;
+    }
+    for (int a = 0; a < g.ny; ++a)
+        for (int b = 0; b < g.nx; ++b) {
+            const int t = a * g.nx + b;
+            const int r0 = std::max(0, a * g.T - g.Hh), r1 = std::min(op->H, (a + 1) * g.T + g.Hh);
+            const int c0 = std::max(0, b * g.T - g.Hh), c1 = std::min(op->W, (b + 1) * g.T + g.Hh);
+            const long long n = (long long)(r1 - r0) * (c1 - c0);
+            if ((int)ts.bufs.size() <= t) {
+                ts.bufs.emplace_back(new SolveBufs());
+                ts.x0.emplace_back(new DevMem());
+            }
+            hipError_t e = ts.bufs[t]->ensure(n, es);
+            if (e == hipSuccess) e = ts.x0[t]->ensure(n * es);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
+static void add_items(std::vector<Item> &items, int pj, int rows, int cols, int TH, int TW) {
+    const int nty = (rows + TH - 1) / TH, ntx = (cols + TW - 1) / TW;
+    for (int ty = 0; ty < nty; ++ty)
+        for (int tx = 0; tx < ntx; ++tx) items.push_back(Item{pj, ty, tx, 0});
+}
+
+// Builds the work lists: solves grouped by kernel class (S, Lp), each solve's
+// items contiguous so that its partial sums form one range.
 static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
     pl.projs.clear();
     pl.items.clear();
+    pl.items_u.clear();
     pl.states.clear();
     pl.classes.clear();
-    pl.counts.clear();
+    pl.classes_u.clear();
     pl.proj_solve.clear();
-    pl.item0.assign(in.size(), 0);
-    pl.nitems.assign(in.size(), 0);
+    pl.refs.clear();
+    pl.halos.clear();
+    pl.tiled = false;
+    const size_t ns = in.size();
+    pl.item0.assign(ns, 0);
+    pl.nitems.assign(ns, 0);
+    pl.item0u.assign(ns, 0);
+    pl.nitemsu.assign(ns, 0);
     std::map<std::pair<int, int>, std::vector<int>> groups;
     std::vector<std::pair<int, int>> order;
-    for (int i = 0; i < (int)in.size(); ++i) {
+    for (int i = 0; i < (int)ns; ++i) {
         auto key = std::make_pair(in[i].op->s, in[i].op->Lp);
         if (!groups.count(key)) order.push_back(key);
         groups[key].push_back(i);
     }
-    pl.states.resize(in.size());
+    pl.states.resize(ns);
     for (auto &key : order) {
         Plan::Cls c{key.first, key.second, (int)pl.items.size(), 0};
+        Plan::Cls cu{key.first, key.second, (int)pl.items_u.size(), 0};
         for (int i : groups[key]) {
-            const SolveIn &s = in[i];
-            const misr_op *op = s.op;
+            const SolveIn &si = in[i];
+            const misr_op *op = si.op;
+            init_state(pl.states[i], si.prm, (long long)op->H * op->W);
+            pl.item0[i] = (int)pl.items.size();
+            pl.item0u[i] = (int)pl.items_u.size();
             Proj P;
             std::memset(&P, 0, sizeof P);
-            P.x[0] = s.x;
-            P.x[1] = s.bufs->x1.p;
-            P.p[0] = s.bufs->p0.as<float>();
-            P.p[1] = s.bufs->p1.as<float>();
-            P.g[0] = s.bufs->g0.as<float>();
-            P.g[1] = s.bufs->g1.as<float>();
-            P.y = s.y;
-            P.ld = op->W;
-            P.Hb = op->H;
-            P.Wb = op->W;
-            P.oy1 = op->H;
-            P.ox1 = op->W;
-            P.ntx = (op->W + op->TW - 1) / op->TW;
+            P.y = si.y;
             P.op = op->opdev.as<OpDev>();
-            const int nty = (op->H + op->TH - 1) / op->TH;
-            const int pj = (int)pl.projs.size();
-            pl.projs.push_back(P);
-            pl.proj_solve.push_back(i);
-            init_state(pl.states[i], s.prm, (long long)op->H * op->W);
-            pl.item0[i] = (int)pl.items.size();
-            for (int ty = 0; ty < nty; ++ty)
-                for (int tx = 0; tx < P.ntx; ++tx) pl.items.push_back(Item{pj, ty, tx, 0});
+            if (si.prm.tile_lr <= 0) {
+                P.x[0] = si.x;
+                P.x[1] = si.bufs->x1.p;
+                P.p[0] = si.bufs->p0.as<float>();
+                P.p[1] = si.bufs->p1.as<float>();
+                P.g[0] = si.bufs->g0.as<float>();
+                P.g[1] = si.bufs->g1.as<float>();
+                P.ld = P.Wb = op->W;
+                P.Hb = op->H;
+                P.oy1 = P.uy1 = op->H;
+                P.ox1 = P.ux1 = op->W;
+                P.ntx = (op->W + op->TW - 1) / op->TW;
+                const int pj = (int)pl.projs.size();
+                pl.projs.push_back(P);
+                pl.proj_solve.push_back(i);
+                add_items(pl.items, pj, op->H, op->W, op->TH, op->TW);
+                add_items(pl.items_u, pj, op->H, op->W, op->TH, op->TW);
+            } else {
+                pl.tiled = true;
+                pl.states[i].xglob = si.x;
+                pl.states[i].ldg = op->W;
+                const TileGrid g = tile_grid(op, si.prm);
+                const int v0 = (int)pl.projs.size();
+                for (int a = 0; a < g.ny; ++a)
+                    for (int b = 0; b < g.nx; ++b) {
+                        const int t = a * g.nx + b;
+                        SolveBufs &tb = *si.tiles->bufs[t];
+                        const int R0 = a * g.T, R1 = std::min(op->H, (a + 1) * g.T);
+                        const int C0 = b * g.T, C1 = std::min(op->W, (b + 1) * g.T);
+                        const int r0 = std::max(0, R0 - g.Hh), r1 = std::min(op->H, R1 + g.Hh);
+                        const int c0 = std::max(0, C0 - g.Hh), c1 = std::min(op->W, C1 + g.Hh);
+                        Proj Q = P;
+                        Q.x[0] = si.tiles->x0[t]->p;
+                        Q.x[1] = tb.x1.p;
+                        Q.p[0] = tb.p0.as<float>();
+                        Q.p[1] = tb.p1.as<float>();
+                        Q.g[0] = tb.g0.as<float>();
+                        Q.g[1] = tb.g1.as<float>();
+                        Q.ld = Q.Wb = c1 - c0;
+                        Q.Hb = r1 - r0;
+                        Q.gy0 = r0;
+                        Q.gx0 = c0;
+                        Q.oy0 = R0 - r0;
+                        Q.oy1 = R1 - r0;
+                        Q.ox0 = C0 - c0;
+                        Q.ox1 = C1 - c0;
+                        Q.uy0 = 0;
+                        Q.uy1 = Q.Hb;
+                        Q.ux0 = 0;
+                        Q.ux1 = Q.Wb;
+                        Q.ntx = (C1 - C0 + op->TW - 1) / op->TW;
+                        const int pj = (int)pl.projs.size();
+                        pl.projs.push_back(Q);
+                        pl.proj_solve.push_back(i);
+                        add_items(pl.items, pj, R1 - R0, C1 - C0, op->TH, op->TW);
+                        add_items(pl.items_u, pj, Q.Hb, Q.Wb, op->TH, op->TW);
+                    }
+                // halo exchanges: every view's halo from the views that own it
+                const int v1 = (int)pl.projs.size();
+                for (int bi = v0; bi < v1; ++bi)
+                    for (int ai = v0; ai < v1; ++ai) {
+                        if (ai == bi) continue;
+                        const Proj &A = pl.projs[ai], &B = pl.projs[bi];
+                        const int gy0 = std::max(B.gy0, A.gy0 + A.oy0);
+                        const int gy1 = std::min(B.gy0 + B.Hb, A.gy0 + A.oy1);
+                        const int gx0 = std::max(B.gx0, A.gx0 + A.ox0);
+                        const int gx1 = std::min(B.gx0 + B.Wb, A.gx0 + A.ox1);
+                        if (gy1 > gy0 && gx1 > gx0)
+                            pl.halos.push_back(HaloCopy{ai, bi, gy0, gx0, gy1 - gy0, gx1 - gx0});
+                    }
+            }
             pl.nitems[i] = (int)pl.items.size() - pl.item0[i];
+            pl.nitemsu[i] = (int)pl.items_u.size() - pl.item0u[i];
         }
         c.count = (int)pl.items.size() - c.start;
+        cu.count = (int)pl.items_u.size() - cu.start;
         pl.classes.push_back(c);
+        pl.classes_u.push_back(cu);
     }
-    for (auto &c : pl.classes) pl.counts.push_back(c.count);
-    pl.counts.push_back((int)pl.states.size());
+    pl.finish_counts();
 }
 
 static std::string plan_key(const Plan &pl, int n_iter, int stype) {
     std::string k = std::to_string(n_iter) + "/" + std::to_string(stype) + "/" +
-                     std::to_string(pl.states.size()) + "/" + std::to_string(pl.projs.size());
+                     std::to_string(pl.states.size()) + "/" + std::to_string(pl.projs.size()) +
+                     "/" + std::to_string(pl.halos.size()) + (pl.tiled ? "T" : "U");
     for (auto &c : pl.classes)
         k += ":" + std::to_string(c.S) + "," + std::to_string(c.Lp) + "," +
              std::to_string(c.start) + "," + std::to_string(c.count);
+    for (auto &c : pl.classes_u)
+        k += ";" + std::to_string(c.start) + "," + std::to_string(c.count);
     return k;
 }
 
-// Enqueues the whole solve (init + n_iter passes + final copy) on `s`.
-static hipError_t enqueue_solve(const Plan &pl, PlanDev &pd, int n_iter, int stype,
-                                hipStream_t s) {
-    const int nc = (int)pl.classes.size();
-    const int ns = (int)pl.states.size();
-    const int *d_counts = pd.counts.as<int>();
-    const int *d_nstates = d_counts + nc;
-    auto image = [&](int kind) -> hipError_t {
-        for (int c = 0; c < nc; ++c) {
-            const Plan::Cls &cl = pl.classes[c];
-            hipError_t e = launch_image(cl.S, cl.Lp, cl.count, s, pd.projs.as<Proj>(),
-                                        pd.items.as<Item>() + cl.start, d_counts + c,
-                                        pd.partials.as<double>() + (size_t)cl.start * kNV, kind,
-                                        stype);
+// Launch helpers over a plan's device mirror.
+struct Launcher {
+    const Plan &pl;
+    PlanDev &pd;
+    int stype;
+    hipStream_t s;
+    const int *cnt() const { return pd.counts.as<int>(); }
+    hipError_t image(int kind) const {
+        const bool upd = kind == KIND_UPCURV;
+        const auto &cls = upd ? pl.classes_u : pl.classes;
+        const Item *items = upd ? pd.items_u.as<Item>() : pd.items.as<Item>();
+        double *part = upd ? pd.partials_u.as<double>() : pd.partials.as<double>();
+        const int off = upd ? (int)pl.classes.size() : 0;
+        for (int c = 0; c < (int)cls.size(); ++c) {
+            hipError_t e = launch_image(cls[c].S, cls[c].Lp, cls[c].count, s, pd.projs.as<Proj>(),
+                                        items + cls[c].start, cnt() + off + c,
+                                        part + (size_t)cls[c].start * kNV, kind, stype);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
-    };
-    auto scalar = [&](int phase) {
-        return launch_scalar(ns, s, pd.refs.as<SolveRef>(), d_nstates, pd.partials.as<double>(),
-                             phase);
-    };
-    hipError_t e;
-    if ((e = image(KIND_COSTGRAD)) != hipSuccess) return e;
-    if ((e = scalar(PHASE_INIT)) != hipSuccess) return e;
-    if ((e = image(KIND_UPCURV)) != hipSuccess) return e;
-    for (int it = 0; it < n_iter; ++it) {
-        if ((e = scalar(PHASE_A)) != hipSuccess) return e;
-        if ((e = image(KIND_TRIAL)) != hipSuccess) return e;
-        if ((e = scalar(PHASE_B)) != hipSuccess) return e;
-        if ((e = image(KIND_UPCURV)) != hipSuccess) return e;
     }
-    return launch_finalize(s, pd.projs.as<Proj>(), (int)pl.projs.size(), stype);
+    hipError_t scalar(int phase) const {
+        return launch_scalar((int)pl.states.size(), s, pd.refs.as<SolveRef>(),
+                             cnt() + pl.n_states_idx(), pd.partials.as<double>(),
+                             pd.partials_u.as<double>(), phase);
+    }
+    hipError_t halo() const {
+        if (pl.halos.empty()) return hipSuccess;
+        return launch_halo(s, pd.projs.as<Proj>(), pd.halos.as<HaloCopy>(),
+                           cnt() + pl.n_states_idx() + 1, (int)pl.halos.size());
+    }
+};
+
+// Enqueues the whole solve (init + n_iter passes + result copy) on `s`.
+static hipError_t enqueue_solve(const Plan &pl, PlanDev &pd, int n_iter, int stype,
+                                hipStream_t s) {
+    const Launcher Lr{pl, pd, stype, s};
+    const int np = (int)pl.projs.size();
+    hipError_t e = hipSuccess;
+#define STEP(x)                          \
+    if ((e = (x)) != hipSuccess) return e;
+    if (pl.tiled) STEP(launch_scatter(s, pd.projs.as<Proj>(), np, stype));
+    STEP(Lr.image(KIND_COSTGRAD));
+    STEP(Lr.halo());
+    STEP(Lr.scalar(PHASE_INIT));
+    STEP(Lr.image(KIND_UPCURV));
+    for (int it = 0; it < n_iter; ++it) {
+        STEP(Lr.scalar(PHASE_A));
+        STEP(Lr.image(KIND_TRIAL));
+        STEP(Lr.halo());
+        STEP(Lr.scalar(PHASE_B));
+        STEP(Lr.image(KIND_UPCURV));
+    }
+#undef STEP
+    // tiled views: owned parts back into the caller's image; an untiled view
+    // copies its workspace buffer back when the iterate ended there
+    return pl.tiled ? launch_gather(s, pd.projs.as<Proj>(), np, stype, 0)
+                    : launch_finalize(s, pd.projs.as<Proj>(), np, stype);
 }
 
 // Runs a plan on the context's library stream, ordered after the caller's
@@ -433,9 +595,10 @@ static misr_status run_plan(misr_ctx *ctx, Plan &pl, PlanDev &pd, int n_iter, in
     MISR_HIP(hipStreamWaitEvent(s, ctx->ev_in, 0));
     MISR_HIP(pd.upload(pl, n_iter, s));
     // the graph bakes in the device addresses of the plan arrays
-    char ptrs[160];
-    snprintf(ptrs, sizeof ptrs, "|%p,%p,%p,%p,%p,%p", pd.projs.p, pd.items.p, pd.counts.p,
-             pd.states.p, pd.partials.p, pd.refs.p);
+    char ptrs[256];
+    snprintf(ptrs, sizeof ptrs, "|%p,%p,%p,%p,%p,%p,%p,%p,%p", pd.projs.p, pd.items.p,
+             pd.items_u.p, pd.counts.p, pd.states.p, pd.partials.p, pd.partials_u.p, pd.refs.p,
+             pd.halos.p);
     const std::string key = plan_key(pl, n_iter, stype) + ptrs;
     if (!pd.exec || pd.graph_key != key) {
         if (pd.exec) {
@@ -465,8 +628,7 @@ static misr_status run_plan(misr_ctx *ctx, Plan &pl, PlanDev &pd, int n_iter, in
     return MISR_OK;
 }
 
-static misr_status fetch_trace(const Plan &pl, PlanDev &pd, int idx, misr_scg_trace *tr,
-                               hipStream_t user) {
+static misr_status fetch_trace(PlanDev &pd, int idx, misr_scg_trace *tr, hipStream_t user) {
     ScgState st;
     MISR_HIP(hipMemcpyAsync(&st, pd.states.as<ScgState>() + idx, sizeof st, hipMemcpyDeviceToHost,
                             user));
@@ -482,19 +644,17 @@ static misr_status fetch_trace(const Plan &pl, PlanDev &pd, int idx, misr_scg_tr
         MISR_HIP(hipMemcpy(tr->iters, pd.traces.as<IterRec>() + (size_t)idx * pd.n_iter_max,
                            n * sizeof(IterRec), hipMemcpyDeviceToHost));
     }
-    (void)pl;
     return st.stop == 2 ? set_error(MISR_E_NUMERIC, "non-finite cost or curvature at pass %d",
                                     st.it)
                         : MISR_OK;
 }
 
 // ------------------------------------------------------------ operators
-static misr_status single_view(misr_op *op, const void *x, Plan &pl) {
-    SolveIn si{op, {}, nullptr, const_cast<void *>(x), &op->bufs};
+static void single_view(misr_op *op, const void *x, Plan &pl) {
+    SolveIn si{op, {}, nullptr, const_cast<void *>(x), &op->bufs, nullptr};
     misr_params_default(&si.prm);
     si.prm.n_iter = 0;
     build_plan(pl, {si});
-    return MISR_OK;
 }
 
 extern "C" misr_status misr_forward(const misr_op *cop, misr_dtype dt, const void *x, void *y,
@@ -539,25 +699,30 @@ extern "C" misr_status misr_cost_grad(const misr_op *cop, const misr_params *prm
     if (!op || !x || !y || !g || !cost_dev) return set_error(MISR_E_INVAL, "NULL argument");
     misr_status st = misr_params_check(prm);
     if (st != MISR_OK) return st;
-    if (prm->tile_lr > 0) return set_error(MISR_E_INVAL, "tiled cost_grad not available");
+    if ((st = check_tiling(op, *prm)) != MISR_OK) return st;
     std::lock_guard<std::mutex> lk(op->mu);
     MISR_HIP(set_device(op->ctx->dev));
     const size_t es = dtype_size(prm->img_dtype);
     const long long n = (long long)op->H * op->W;
     MISR_HIP(op->bufs.ensure(n, es));
+    if (prm->tile_lr > 0) MISR_HIP(ensure_tiles(op, *prm, op->tiles));
     Plan &pl = op->plan;
-    SolveIn si{op, *prm, y, const_cast<void *>(x), &op->bufs};
+    SolveIn si{op, *prm, y, const_cast<void *>(x), &op->bufs, &op->tiles};
     si.prm.n_iter = 0;
     build_plan(pl, {si});
-    pl.projs[0].g[1] = g;   // the init pass writes g[cur ^ 1] with cur = 0
+    if (pl.tiled)
+        pl.states[0].gglob = g;
+    else
+        pl.projs[0].g[1] = g;   // the init pass writes g[cur ^ 1] with cur = 0
     PlanDev &pd = op->pdev;
     hipStream_t s = (hipStream_t)stream;
     MISR_HIP(pd.upload(pl, 0, s));
-    const Plan::Cls &cl = pl.classes[0];
-    MISR_HIP(launch_image(cl.S, cl.Lp, cl.count, s, pd.projs.as<Proj>(), pd.items.as<Item>(),
-                          pd.counts.as<int>(), pd.partials.as<double>(), KIND_COSTGRAD,
-                          (int)prm->img_dtype));
-    MISR_HIP(launch_cost_out(s, pd.partials.as<double>(), cl.count, cost_dev));
+    const Launcher Lr{pl, pd, (int)prm->img_dtype, s};
+    const int np = (int)pl.projs.size();
+    if (pl.tiled) MISR_HIP(launch_scatter(s, pd.projs.as<Proj>(), np, (int)prm->img_dtype));
+    MISR_HIP(Lr.image(KIND_COSTGRAD));
+    MISR_HIP(launch_cost_out(s, pd.partials.as<double>(), (int)pl.items.size(), cost_dev));
+    if (pl.tiled) MISR_HIP(launch_gather(s, pd.projs.as<Proj>(), np, (int)prm->img_dtype, 1));
     return MISR_OK;
 }
 
@@ -570,18 +735,19 @@ extern "C" misr_status misr_scg_solve(const misr_op *cop, const misr_params *prm
     if (st != MISR_OK) return st;
     if (prm->data_p != 2)
         return set_error(MISR_E_INVAL, "the SCG solve supports the L2 data term (data_p = 2)");
-    if (prm->tile_lr > 0) return set_error(MISR_E_INVAL, "tiled solve not available");
+    if ((st = check_tiling(op, *prm)) != MISR_OK) return st;
     std::lock_guard<std::mutex> lk(op->mu);
     std::lock_guard<std::mutex> lc(op->ctx->mu);
     MISR_HIP(set_device(op->ctx->dev));
     const long long n = (long long)op->H * op->W;
     MISR_HIP(op->bufs.ensure(n, dtype_size(prm->img_dtype)));
+    if (prm->tile_lr > 0) MISR_HIP(ensure_tiles(op, *prm, op->tiles));
     Plan &pl = op->plan;
-    build_plan(pl, {SolveIn{op, *prm, y, x, &op->bufs}});
+    build_plan(pl, {SolveIn{op, *prm, y, x, &op->bufs, &op->tiles}});
     hipStream_t s = (hipStream_t)stream;
     st = run_plan(op->ctx, pl, op->pdev, prm->n_iter, (int)prm->img_dtype, s);
     if (st != MISR_OK) return st;
-    if (trace) return fetch_trace(pl, op->pdev, 0, trace, s);
+    if (trace) return fetch_trace(op->pdev, 0, trace, s);
     return MISR_OK;
 }
 
@@ -630,7 +796,7 @@ extern "C" misr_status misr_scg_solve_batch(int n, const misr_op *const *ops,
     for (int i = 0; i < n; ++i) {
         if ((int)bc.bufs.size() <= i) bc.bufs.emplace_back(new SolveBufs());
         MISR_HIP(bc.bufs[i]->ensure((long long)ops[i]->H * ops[i]->W, es));
-        in.push_back(SolveIn{ops[i], prm[i], y[i], x[i], bc.bufs[i].get()});
+        in.push_back(SolveIn{ops[i], prm[i], y[i], x[i], bc.bufs[i].get(), nullptr});
     }
     build_plan(bc.plan, in);
     hipStream_t s = (hipStream_t)stream;
@@ -639,7 +805,7 @@ extern "C" misr_status misr_scg_solve_batch(int n, const misr_op *const *ops,
     misr_status worst = MISR_OK;
     if (traces)
         for (int i = 0; i < n; ++i) {
-            misr_status t = fetch_trace(bc.plan, bc.pdev, i, &traces[i], s);
+            misr_status t = fetch_trace(bc.pdev, i, &traces[i], s);
             if (t != MISR_OK) worst = t;
         }
     return worst;
@@ -664,33 +830,24 @@ extern "C" misr_status misr_time_pass(const misr_op *cop, const misr_params *prm
     Plan &pl = op->plan;
     misr_params p1 = *prm;
     p1.n_iter = 1;
-    build_plan(pl, {SolveIn{op, p1, y, x, &op->bufs}});
+    build_plan(pl, {SolveIn{op, p1, y, x, &op->bufs, nullptr}});
     PlanDev &pd = op->pdev;
     hipStream_t s = op->ctx->stream;
     MISR_HIP(hipEventRecord(op->ctx->ev_in, (hipStream_t)stream));
     MISR_HIP(hipStreamWaitEvent(s, op->ctx->ev_in, 0));
     MISR_HIP(pd.upload(pl, 1, s));
-    const Plan::Cls &cl = pl.classes[0];
-    const int stype = (int)prm->img_dtype;
-    auto image = [&](int kind) {
-        return launch_image(cl.S, cl.Lp, cl.count, s, pd.projs.as<Proj>(), pd.items.as<Item>(),
-                            pd.counts.as<int>(), pd.partials.as<double>(), kind, stype);
-    };
-    auto scalar = [&](int phase) {
-        return launch_scalar(1, s, pd.refs.as<SolveRef>(), pd.counts.as<int>() + 1,
-                             pd.partials.as<double>(), phase);
-    };
-    MISR_HIP(image(KIND_COSTGRAD));
-    MISR_HIP(scalar(PHASE_INIT));
-    MISR_HIP(image(KIND_UPCURV));
-    MISR_HIP(scalar(PHASE_A));
+    const Launcher Lr{pl, pd, (int)prm->img_dtype, s};
+    MISR_HIP(Lr.image(KIND_COSTGRAD));
+    MISR_HIP(Lr.scalar(PHASE_INIT));
+    MISR_HIP(Lr.image(KIND_UPCURV));
+    MISR_HIP(Lr.scalar(PHASE_A));
     hipEvent_t e0, e1;
     MISR_HIP(hipEventCreate(&e0));
     MISR_HIP(hipEventCreate(&e1));
     const int kind = which == 0 ? KIND_TRIAL : KIND_UPCURV;
-    hipError_t e = image(kind);   // warm-up launch
+    hipError_t e = Lr.image(kind);   // warm-up launch
     if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = image(kind);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = Lr.image(kind);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;

@@ -253,9 +253,9 @@ __device__ constexpr int kDY[8] = {0, 0, 1, 1, 1, 2, 2, 2};
 // is evaluated once, by the lane of i; the lane of i+d takes its share from
 // its running history (same row) or by a lane shift (rows below).  The
 // gradient accumulates into gs (LDS, row stride GP).
-template <int S, int L, bool EPS0>
+template <int S, int L, bool EPS0, bool CHECK>
 FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, int U0, int V0,
-                  int H, int W, int th_own, int tw_own, float &e_reg) {
+                  int H, int W, int th_own, int tw_own, double &e_reg) {
     using T = Tile<S, L>;
     const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
     const int u = lane - 2;
@@ -263,9 +263,12 @@ FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, 
     const int U = U0 + u;
     const int ur = min(u, T::TH - 1);
     const float e2 = eps * eps;
-    const bool row_in = U >= 0 && U < H;
-    const bool row_own = u >= 0 && u < th_own;
     const bool row_tile = u >= 0 && u < T::TH;
+    const bool own_row = u >= 0 && u < (CHECK ? th_own : T::TH);
+    // pair validity per row offset (both pixels inside the image)
+    bool rok[3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) rok[dy] = !CHECK || (U >= 0 && U + dy < H);
     const float *base = xs + (T::EXT + ur) * T::WCP + T::EXT;
     float *grow = gs + max(u, 0) * T::GP;
     float win[3][3];   // win[dy][dx] = x(u + dy, v + dx)
@@ -276,8 +279,8 @@ FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, 
     float h1[8], h2[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) h1[d] = h2[d] = 0.f;
-    float eacc = 0.f;
-#pragma unroll 2
+    double eacc = 0.0;
+#pragma unroll 1
     for (int vs = -2; vs < T::CV; ++vs) {
         const int v = cv0 + vs, V = V0 + v;
 #pragma unroll
@@ -286,14 +289,15 @@ FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, 
             win[dy][1] = win[dy][2];
             win[dy][2] = base[dy * T::WCP + v + 2];
         }
-        const bool in = row_in && V >= 0 && V < W;
+        bool cok[3];
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) cok[dx] = !CHECK || (V >= 0 && V + dx < W);
         float cur[8];
         float eb = 0.f;
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const int dx = kDX[d], dy = kDY[d];
             const float z = win[0][0] - win[dy][dx];
-            const bool valid = in && (U + dy < H) && (V + dx < W);
             float ps, ph;
             if (EPS0) {
                 ps = (z > 0.f) ? 1.f : ((z < 0.f) ? -1.f : 0.f);
@@ -304,8 +308,14 @@ FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, 
                 ps = z * r;
                 ph = fmaf(dd, r, -eps);
             }
-            cur[d] = valid ? gam[d] * ps : 0.f;
-            eb = fmaf(valid ? gam[d] : 0.f, ph, eb);
+            if (CHECK) {
+                const bool valid = rok[dy] && cok[dx];
+                cur[d] = valid ? gam[d] * ps : 0.f;
+                eb = fmaf(valid ? gam[d] : 0.f, ph, eb);
+            } else {
+                cur[d] = gam[d] * ps;
+                eb = fmaf(gam[d], ph, eb);
+            }
         }
         float gsum = 0.f;
 #pragma unroll
@@ -317,7 +327,7 @@ FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, 
         }
         if (vs >= 0) {
             if (row_tile) grow[v] += gsum;
-            if (row_own && v < tw_own) eacc += eb;
+            if (own_row && (!CHECK || v < tw_own)) eacc += (double)eb;
         }
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
@@ -326,6 +336,65 @@ FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, 
         }
     }
     e_reg += eacc;
+}
+
+// Curvature of the prior along p (Moller's step 2 without forming x + sk p):
+// sum over owned pairs of gamma q^2 Q(z, sk q), z, q the pair differences of
+// x and p.  Same sweep as btv_sweep (lanes on rows, waves on CV columns,
+// sliding 3x3 windows); [ru0,ru1) x [rv0,rv1) is the owned part of the tile.
+template <int S, int L, bool CHECK>
+FI void curv_sweep(const float *xs, const float *ps, const float (&gam)[8], float eps, float sk,
+                   int U0, int V0, int H, int W, int ru0, int ru1, int rv0, int rv1,
+                   double &dreg) {
+    using T = Tile<S, L>;
+    const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
+    const int u = lane;
+    const int cv0 = wv * T::CV;
+    const int U = U0 + u;
+    const int ur = min(u, T::TH - 1);
+    const float e2 = eps * eps;
+    const bool own_row = CHECK ? (u >= ru0 && u < ru1) : (u < T::TH);
+    bool rok[3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) rok[dy] = !CHECK || (U + dy < H);
+    const int off = (T::EXT + ur) * T::WCP + T::EXT;
+    float wx[3][3], wp[3][3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+            wx[dy][dx + 1] = xs[off + dy * T::WCP + cv0 + dx];
+            wp[dy][dx + 1] = ps[off + dy * T::WCP + cv0 + dx];
+        }
+    double acc = 0.0;
+#pragma unroll 2
+    for (int vs = 0; vs < T::CV; ++vs) {
+        const int v = cv0 + vs, V = V0 + v;
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            wx[dy][0] = wx[dy][1];
+            wx[dy][1] = wx[dy][2];
+            wx[dy][2] = xs[off + dy * T::WCP + v + 2];
+            wp[dy][0] = wp[dy][1];
+            wp[dy][1] = wp[dy][2];
+            wp[dy][2] = ps[off + dy * T::WCP + v + 2];
+        }
+        float a = 0.f;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const int dx = kDX[d], dy = kDY[d];
+            const float z = wx[0][0] - wx[dy][dx];
+            const float qd = wp[0][0] - wp[dy][dx];
+            const float t = gam[d] * qd * qd * psi_quot(z, sk * qd, eps, e2);
+            if (CHECK)
+                a += (rok[dy] && V + dx < W) ? t : 0.f;
+            else
+                a += t;
+        }
+        const bool own = own_row && (!CHECK || (v >= rv0 && v < rv1));
+        acc += own ? (double)a : 0.0;
+    }
+    dreg += acc;
 }
 
 // --------------------------------------------------------------- the tiles
@@ -468,13 +537,17 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
 #pragma unroll
     for (int d = 0; d < 8; ++d) gam[d] = st.wt.gam[kDY[d] * 3 + kDX[d]];
     const float eps = st.wt.eps;
-    float e_reg = 0.f;
+    double e_reg = 0.0;
+    // interior tiles: every pair of the sweep lies inside the image, tile owned whole
+    const bool inner = o.U0 >= 2 && o.V0 >= 2 && o.U0 + T::TH + 2 <= H &&
+                       o.V0 + T::TW + 2 <= W && o.u1 - o.u0 == T::TH && o.v1 - o.v0 == T::TW;
+    const int tho = o.u1 - o.u0, two = o.v1 - o.v0;
     if (eps == 0.f)
-        btv_sweep<S, L, true>(xs, gs, gam, eps, o.U0, o.V0, H, W, o.u1 - o.u0, o.v1 - o.v0,
-                              e_reg);
+        btv_sweep<S, L, true, true>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
+    else if (inner)
+        btv_sweep<S, L, false, false>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
     else
-        btv_sweep<S, L, false>(xs, gs, gam, eps, o.U0, o.V0, H, W, o.u1 - o.u0, o.v1 - o.v0,
-                               e_reg);
+        btv_sweep<S, L, false, true>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
     __syncthreads();
     double gg = 0.0, ggk = 0.0, gp = 0.0;
     const int cur = st.cur;
@@ -494,7 +567,7 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
             gp += (double)gv * (double)pb[idx];
         }
     }
-    double v[5] = {e_data, (double)e_reg, gg, ggk, gp};
+    double v[5] = {e_data, e_reg, gg, ggk, gp};
     block_sum_store<5, kNTI>(v, part, red);
 }
 
@@ -510,7 +583,17 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
     using raw = typename ST::raw;
     const AS4 OpDev &op = *cst(P.op);
     const int tid = threadIdx.x;
-    const TileOrigin o = tile_origin<S, L>(P, ty, tx);
+    // update tiles cover the update rectangle (owned plus halo); reductions
+    // count only their intersection with the owned rectangle [ou0,ou1) x [ov0,ov1)
+    TileOrigin o;
+    o.u0 = P.uy0 + ty * T::TH;
+    o.v0 = P.ux0 + tx * T::TW;
+    o.u1 = min(o.u0 + T::TH, P.uy1);
+    o.v1 = min(o.v0 + T::TW, P.ux1);
+    o.U0 = P.gy0 + o.u0;
+    o.V0 = P.gx0 + o.v0;
+    const int ou0 = max(o.u0, P.oy0), ou1 = min(o.u1, P.oy1);
+    const int ov0 = max(o.v0, P.ox0), ov1 = min(o.v1, P.ox1);
     const int H = op.H, W = op.W, h = H / S, w = W / S, K = op.K;
     float *xs = sm;
     float *ps = xs + T::XS;
@@ -547,8 +630,10 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
                 if (ub >= o.u0 && ub < o.u1 && vb >= o.v0 && vb < o.v1) {
                     ST::st(xo, idx, xv[s]);
                     po[idx] = pv[s];
-                    pp += (double)pv[s] * (double)pv[s];
-                    pr -= (double)pv[s] * (double)g0;
+                    if (ub >= ou0 && ub < ou1 && vb >= ov0 && vb < ov1) {
+                        pp += (double)pv[s] * (double)pv[s];
+                        pr -= (double)pv[s] * (double)g0;
+                    }
                 }
             }
         }
@@ -563,17 +648,17 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
         }
     }
     __syncthreads();
-    // data part: |A_k p|^2 over the owned LR pixels
+    // data part: |A_k p|^2 over the owned LR pixels (all edges are multiples of S)
     double ap2 = 0.0;
-    const int NIo = (o.u1 - o.u0) / S, NJo = (o.v1 - o.v0) / S;
-    const int iA = o.U0 / S, jA = o.V0 / S;
+    const int NIo = (ou1 - ou0) / S, NJo = (ov1 - ov0) / S;
+    const int iA = (P.gy0 + ou0) / S, jA = (P.gx0 + ov0) / S;
     if (NIo > 0 && NJo > 0) {
         for (int k = 0; k < K; ++k) {
             const int offy = op.offy[k], offx = op.offx[k];
             const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
             const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
-            pass1<S, L>(ps, offy + T::EXT, offx + T::EXT, S * (NIo - 1) + L, NJo, wxk, jA, w - 1,
-                        hx);
+            pass1<S, L>(ps, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
+                        S * (NIo - 1) + L, NJo, wxk, jA, w - 1, hx);
             __syncthreads();
             pass2<S, L>(hx, NIo, NJo, wyk, iA, h - 1,
                         [&](int i0, int, const float (&av)[T::CI]) {
@@ -585,31 +670,19 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
         }
     }
     // prior part over the owned pairs (i, i+d)
-    const float eps = st.wt.eps, e2 = eps * eps, sk = st.sigk_f;
+    const float eps = st.wt.eps, sk = st.sigk_f;
     float gam[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) gam[d] = st.wt.gam[kDY[d] * 3 + kDX[d]];
-    float dreg = 0.f;
-    for (int q = tid; q < T::TH * T::TW; q += kNTI) {
-        const int uu = q / T::TW, vv = q - uu * T::TW;
-        if (o.u0 + uu >= o.u1 || o.v0 + vv >= o.v1) continue;
-        const int U = o.U0 + uu, V = o.V0 + vv;
-        const int wi = (uu + T::EXT) * T::WCP + vv + T::EXT;
-        const float xi = xs[wi], pi = ps[wi];
-        float acc = 0.f;
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const int dx = kDX[d], dy = kDY[d];
-            const int of = dy * T::WCP + dx;
-            const float z = xi - xs[wi + of];
-            const float qd = pi - ps[wi + of];
-            const bool valid = (U + dy < H) && (V + dx < W);
-            const float t = gam[d] * qd * qd * psi_quot(z, sk * qd, eps, e2);
-            acc += valid ? t : 0.f;
-        }
-        dreg += acc;
-    }
-    double v[4] = {2.0 * ap2, (double)dreg, pp, pr};
+    double dreg = 0.0;
+    const int ru0 = ou0 - o.u0, ru1 = ou1 - o.u0, rv0 = ov0 - o.v0, rv1 = ov1 - o.v0;
+    const bool inner = o.U0 + T::TH + 2 <= H && o.V0 + T::TW + 2 <= W && ru0 == 0 &&
+                       ru1 == T::TH && rv0 == 0 && rv1 == T::TW;
+    if (inner)
+        curv_sweep<S, L, false>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0, rv1, dreg);
+    else
+        curv_sweep<S, L, true>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0, rv1, dreg);
+    double v[4] = {2.0 * ap2, dreg, pp, pr};
     block_sum_store<4, kNTI>(v, part, red);
 }
 
@@ -711,7 +784,7 @@ FI void tile_adjoint(const AS4 Proj &P, int ty, int tx, const void *r, float *xo
 // Each kernel walks the work list with a grid stride; the item count is read
 // from device memory so that one captured launch can serve a changing list.
 template <int S, int L, class ST>
-__global__ void __launch_bounds__(kNTI) k_trial(const Proj *projs, const Item *items,
+__global__ void __launch_bounds__(kNTI, 4) k_trial(const Proj *projs, const Item *items,
                                                 const int *n_items, double *partials,
                                                 int mode) {
     __shared__ float sm[Tile<S, L>::SMEM];
@@ -728,7 +801,7 @@ __global__ void __launch_bounds__(kNTI) k_trial(const Proj *projs, const Item *i
 }
 
 template <int S, int L, class ST>
-__global__ void __launch_bounds__(kNTI) k_upcurv(const Proj *projs, const Item *items,
+__global__ void __launch_bounds__(kNTI, 4) k_upcurv(const Proj *projs, const Item *items,
                                                  const int *n_items, double *partials) {
     __shared__ float sm[Tile<S, L>::SMEM];
     __shared__ double red[kNV * kNWI];

@@ -31,8 +31,10 @@ struct OpDev {
 // One image (or one tile of an image held separately in HBM) in a work list.
 // Buffers are H-major with row stride ld; buffer pixel (u, v) is global
 // pixel (gy0 + u, gx0 + v).  The owned rectangle [oy0,oy1) x [ox0,ox1)
-// (buffer coordinates, multiples of s in global coordinates) is what this
-// view computes, writes and counts in its reductions; the rest is halo.
+// (buffer coordinates, multiples of s in global coordinates) is where this
+// view computes the gradient and what it counts in its reductions; the update
+// rectangle [uy0,uy1) x [ux0,ux1) (owned plus halo) is where it applies the
+// pointwise x, p update, so that halo copies stay identical to their owners.
 struct Proj {
     void *x[2];          // storage type
     float *p[2];
@@ -41,10 +43,17 @@ struct Proj {
     int ld, Hb, Wb;
     int gy0, gx0;
     int oy0, oy1, ox0, ox1;
+    int uy0, uy1, ux0, ux1;
     int ntx;             // tiles per row of the owned rectangle
-    int pad_;
     struct ScgState *st; // the solve this view belongs to
     const OpDev *op;
+};
+
+// Halo exchange: rows x cols pixels at global (gy, gx) of view src's owned
+// gradient copied into view dst's halo.
+struct HaloCopy {
+    int src, dst;
+    int gy, gx, rows, cols;
 };
 
 struct Item {
@@ -78,6 +87,9 @@ struct ScgState {
     int do_update;       // k_upcurv runs this pass
     float alpha_f, beta_f, sigk_f;
     unsigned rseed;      // per-pass seed of the stochastic rounding hash
+    void *xglob;         // tiled solves: the caller's whole-image x (row stride ldg)
+    float *gglob;        // tiled cost_grad: the caller's whole-image gradient
+    int ldg, pad2_;
     Weights wt;
 };
 
@@ -86,7 +98,8 @@ struct ScgState {
 struct SolveRef {
     ScgState *st;
     struct IterRec *trace;
-    int item0, nitems;
+    int item0, nitems;     // trial-pass items (owned tiles)
+    int item0u, nitemsu;   // update-pass items (owned plus halo)
 };
 
 struct IterRec {

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <memory>
 #include <mutex>
@@ -26,7 +27,12 @@ hipError_t launch_forward(int S, int Lp, int grid, hipStream_t stream, const Pro
 hipError_t launch_adjoint(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
                           const Item *items, int n, int stype, const void *r, float *x);
 hipError_t launch_scalar(int grid, hipStream_t stream, const SolveRef *refs, const int *n_refs,
-                         const double *partials, int phase);
+                         const double *partials, const double *partials_u, int phase);
+hipError_t launch_halo(hipStream_t stream, const Proj *projs, const HaloCopy *copies,
+                       const int *n_copies, int grid);
+hipError_t launch_scatter(hipStream_t stream, const Proj *projs, int nproj, int stype);
+hipError_t launch_gather(hipStream_t stream, const Proj *projs, int nproj, int stype,
+                         int which);
 hipError_t launch_cost_out(hipStream_t stream, const double *partials, int nitems,
                            double *out);
 hipError_t launch_fill(hipStream_t stream, float *p, long long n, float v);
@@ -70,19 +76,32 @@ struct DevMem {
     T *as() const { return (T *)p; }
 };
 
-// Work list and device state for a set of solves advanced together.
+// Work list and device state for a set of solves advanced together.  The
+// trial pass walks `items` (owned tiles), the update pass `items_u` (owned
+// plus halo; the same list when no view has a halo).
 struct Plan {
     struct Cls {
         int S, Lp, start, count;
     };
     std::vector<Proj> projs;
-    std::vector<Item> items;
+    std::vector<Item> items, items_u;
     std::vector<ScgState> states;
-    std::vector<Cls> classes;
-    std::vector<int> counts;          // per class item count, then n_states
+    std::vector<Cls> classes, classes_u;
+    std::vector<int> counts;          // trial classes, update classes, then n_states
     std::vector<int> proj_solve;      // solve index of each view
-    std::vector<int> item0, nitems;   // per solve: its range of work items
+    std::vector<int> item0, nitems;   // per solve: its range of trial items
+    std::vector<int> item0u, nitemsu; // per solve: its range of update items
     std::vector<SolveRef> refs;       // device-side references (filled by upload)
+    std::vector<HaloCopy> halos;      // halo exchanges after each trial pass
+    bool tiled = false;
+    void finish_counts() {
+        counts.clear();
+        for (auto &c : classes) counts.push_back(c.count);
+        for (auto &c : classes_u) counts.push_back(c.count);
+        counts.push_back((int)refs.size() > 0 ? (int)refs.size() : (int)states.size());
+        counts.push_back((int)halos.size());
+    }
+    int n_states_idx() const { return (int)(classes.size() + classes_u.size()); }
 };
 
 // Per-solve image buffers owned by the library (x1, p0, p1, g0, g1).
@@ -98,9 +117,17 @@ struct SolveBufs {
     }
 };
 
+// Per-tile buffers of a tiled solve (x pair, p pair, g pair per tile).
+struct TileSet {
+    int tile_lr = 0, halo_lr = 0;
+    size_t es = 0;
+    std::vector<std::unique_ptr<SolveBufs>> bufs;
+    std::vector<std::unique_ptr<DevMem>> x0;
+};
+
 // Device mirrors of a Plan plus an instantiated graph of the whole solve.
 struct PlanDev {
-    DevMem projs, items, counts, states, partials, traces, refs;
+    DevMem projs, items, items_u, counts, states, partials, partials_u, traces, refs, halos;
     int n_iter_max = 0;
     size_t trace_ns = 0;
     hipGraphExec_t exec = nullptr;
@@ -116,6 +143,7 @@ struct PlanDev {
 struct misr_ctx {
     int dev;
     int ncu;
+    std::atomic<int> users{0};   // live ops and servers; the ctx outlives them
     hipStream_t stream;     // library stream that runs captured solves
     hipEvent_t ev_in, ev_out;
     std::mutex mu;
@@ -130,6 +158,7 @@ struct misr_op {
     std::mutex mu;
     // cached workspace of the single-image entry points
     misr::SolveBufs bufs;
+    misr::TileSet tiles;
     misr::PlanDev pdev;
     misr::Plan plan;
 };

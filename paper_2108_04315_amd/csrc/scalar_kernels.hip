@@ -131,8 +131,12 @@ __device__ void scg_phase_b(ScgState &s, const double *v, IterRec *trace) {
     if (s.it >= s.n_iter) s.active = 0;
 }
 
+// partials: per-item sums of the trial pass (init, phase B); partials_u: of
+// the update pass (phase A).
 __global__ void __launch_bounds__(kNT) k_scalar(const SolveRef *refs, const int *n_refs,
-                                                const double *__restrict__ partials, int phase) {
+                                                const double *__restrict__ partials,
+                                                const double *__restrict__ partials_u,
+                                                int phase) {
     __shared__ double red[kNV * (kNT / 64)];
     __shared__ double tot[kNV];
     const int ns = *n_refs;
@@ -148,10 +152,13 @@ __global__ void __launch_bounds__(kNT) k_scalar(const SolveRef *refs, const int 
             need = s.active;
         __syncthreads();   // every thread has read the state before thread 0 writes it
         if (need) {
+            const double *pt = (phase == PH_A) ? partials_u : partials;
+            const int i0 = (phase == PH_A) ? ref.item0u : ref.item0;
+            const int ni = (phase == PH_A) ? ref.nitemsu : ref.nitems;
             double v[kNV] = {0, 0, 0, 0, 0, 0};
-            for (int i = ref.item0 + threadIdx.x; i < ref.item0 + ref.nitems; i += kNT)
+            for (int i = i0 + threadIdx.x; i < i0 + ni; i += kNT)
 #pragma unroll
-                for (int q = 0; q < kNV; ++q) v[q] += partials[(long long)i * kNV + q];
+                for (int q = 0; q < kNV; ++q) v[q] += pt[(long long)i * kNV + q];
             block_sum_store<kNV, kNT>(v, tot, red);
         }
         if (threadIdx.x == 0) {
@@ -210,6 +217,74 @@ __global__ void k_finalize(const Proj *__restrict__ projs, int nproj, int stype)
             for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
                  i += (long long)gridDim.x * blockDim.x)
                 b[i] = a[i];
+        }
+    }
+}
+
+// ---------------------------------------------------- tiled-solve helpers
+// Halo exchange: each copy moves a rectangle of the trial gradient g[cur^1]
+// from the view that owns it into another view's halo.
+__global__ void k_halo(const Proj *__restrict__ projs, const HaloCopy *__restrict__ copies,
+                       const int *n_copies) {
+    const int n = *n_copies;
+    for (int c = blockIdx.x; c < n; c += gridDim.x) {
+        const HaloCopy hc = copies[c];
+        const Proj &A = projs[hc.src];
+        const Proj &B = projs[hc.dst];
+        const int g = A.st->cur ^ 1;
+        const float *src = A.g[g];
+        float *dst = B.g[g];
+        for (int q = threadIdx.x; q < hc.rows * hc.cols; q += blockDim.x) {
+            const int r = q / hc.cols, cc = q - r * hc.cols;
+            const int gy = hc.gy + r, gx = hc.gx + cc;
+            dst[(long long)(gy - B.gy0) * B.ld + gx - B.gx0] =
+                src[(long long)(gy - A.gy0) * A.ld + gx - A.gx0];
+        }
+    }
+}
+
+// Whole-image x (the solve's xglob) into every view's x[0], halo included;
+// p[0] cleared so that the first update starts from a zero direction.
+__global__ void k_scatter(const Proj *__restrict__ projs, int nproj, int stype) {
+    for (int j = blockIdx.y; j < nproj; j += gridDim.y) {
+        const Proj &P = projs[j];
+        const ScgState &st = *P.st;
+        const int es = (stype == ST_F32) ? 4 : 2;
+        const long long n = (long long)P.Hb * P.Wb;
+        for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+             q += (long long)gridDim.x * blockDim.x) {
+            const int r = (int)(q / P.Wb), c = (int)(q - (long long)r * P.Wb);
+            const long long src = (long long)(P.gy0 + r) * st.ldg + P.gx0 + c;
+            const long long dst = (long long)r * P.ld + c;
+            if (es == 4)
+                ((float *)P.x[0])[dst] = ((const float *)st.xglob)[src];
+            else
+                ((unsigned short *)P.x[0])[dst] = ((const unsigned short *)st.xglob)[src];
+            P.p[0][dst] = 0.f;
+        }
+    }
+}
+
+// Owned part of every view's current x (which = 0) or trial gradient g[cur^1]
+// (which = 1) back into the whole-image buffer.
+__global__ void k_gather(const Proj *__restrict__ projs, int nproj, int stype, int which) {
+    for (int j = blockIdx.y; j < nproj; j += gridDim.y) {
+        const Proj &P = projs[j];
+        const ScgState &st = *P.st;
+        const int es = (stype == ST_F32 || which == 1) ? 4 : 2;
+        const int oh = P.oy1 - P.oy0, ow = P.ox1 - P.ox0;
+        const long long n = (long long)oh * ow;
+        const void *srcb = which ? (const void *)P.g[st.cur ^ 1] : P.x[st.xc];
+        void *dstb = which ? (void *)st.gglob : st.xglob;
+        for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+             q += (long long)gridDim.x * blockDim.x) {
+            const int r = (int)(q / ow) + P.oy0, c = (int)(q % ow) + P.ox0;
+            const long long src = (long long)r * P.ld + c;
+            const long long dst = (long long)(P.gy0 + r) * st.ldg + P.gx0 + c;
+            if (es == 4)
+                ((float *)dstb)[dst] = ((const float *)srcb)[src];
+            else
+                ((unsigned short *)dstb)[dst] = ((const unsigned short *)srcb)[src];
         }
     }
 }
@@ -296,9 +371,29 @@ hipError_t launch_adjoint(int S, int Lp, int grid, hipStream_t stream, const Pro
 }
 
 hipError_t launch_scalar(int grid, hipStream_t stream, const SolveRef *refs, const int *n_refs,
-                         const double *partials, int phase) {
+                         const double *partials, const double *partials_u, int phase) {
     hipLaunchKernelGGL(k_scalar, dim3(grid), dim3(kNT), 0, stream, refs, n_refs, partials,
-                       phase);
+                       partials_u, phase);
+    return hipGetLastError();
+}
+
+hipError_t launch_halo(hipStream_t stream, const Proj *projs, const HaloCopy *copies,
+                       const int *n_copies, int grid) {
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_halo, dim3(grid), dim3(256), 0, stream, projs, copies, n_copies);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(hipStream_t stream, const Proj *projs, int nproj, int stype) {
+    hipLaunchKernelGGL(k_scatter, dim3(256, nproj < 65535 ? nproj : 65535), dim3(256), 0, stream,
+                       projs, nproj, stype);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(hipStream_t stream, const Proj *projs, int nproj, int stype,
+                         int which) {
+    hipLaunchKernelGGL(k_gather, dim3(256, nproj < 65535 ? nproj : 65535), dim3(256), 0, stream,
+                       projs, nproj, stype, which);
     return hipGetLastError();
 }
 

@@ -79,17 +79,23 @@ struct misr_server {
     size_t used = 0;
     int alloc_count = 0;
     std::map<OpKey, misr_op *> ops;
-    // work lists: all active solves, and the newly admitted ones (init)
+    // work list of all active solves; per class, the running solves' items
+    // come first and the newly admitted ones' after, so that the init passes
+    // of the new solves run over a sub-range and leave their partial sums where
+    // the next pass of the whole list reads them
     struct List {
         Plan pl;
-        DevMem projs, items, counts, refs, partials;
-    } all, init;
+        std::vector<int> new_begin;          // per class: first item of the new solves
+        std::vector<SolveRef> refs_new;      // the new solves only
+        DevMem projs, items, counts, refs, drefs_new, partials;
+    } all;
     std::string last_error;
 
     void run();
     bool setup(SReq *r);
     void release(SReq *r);
     void build_list(List &L, const std::vector<SReq *> &rs);
+    hipError_t enqueue_init(List &L);
     hipError_t enqueue_image(List &L, int kind);
     void finish(SReq *r, misr_req_state st, misr_status code);
 };
@@ -182,16 +188,22 @@ void misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
     pl.classes.clear();
     pl.counts.clear();
     pl.refs.clear();
+    L.new_begin.clear();
+    L.refs_new.clear();
     std::map<std::pair<int, int>, std::vector<SReq *>> groups;
     std::vector<std::pair<int, int>> order;
-    for (SReq *r : rs) {
-        auto key = std::make_pair(r->op->s, r->op->Lp);
-        if (!groups.count(key)) order.push_back(key);
-        groups[key].push_back(r);
-    }
+    for (int pass = 0; pass < 2; ++pass)       // running solves first, then new ones
+        for (SReq *r : rs) {
+            if (r->fresh != (pass == 1)) continue;
+            auto key = std::make_pair(r->op->s, r->op->Lp);
+            if (!groups.count(key)) order.push_back(key);
+            groups[key].push_back(r);
+        }
     for (auto &key : order) {
         Plan::Cls c{key.first, key.second, (int)pl.items.size(), 0};
+        int nb = -1;
         for (SReq *r : groups[key]) {
+            if (r->fresh && nb < 0) nb = (int)pl.items.size();
             const misr_op *op = r->op;
             Proj P;
             std::memset(&P, 0, sizeof P);
@@ -205,8 +217,8 @@ void misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
             P.ld = op->W;
             P.Hb = op->H;
             P.Wb = op->W;
-            P.oy1 = op->H;
-            P.ox1 = op->W;
+            P.oy1 = P.uy1 = op->H;
+            P.ox1 = P.ux1 = op->W;
             P.ntx = (op->W + op->TW - 1) / op->TW;
             P.st = r->st_dev;
             P.op = op->opdev.as<OpDev>();
@@ -216,18 +228,27 @@ void misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
             const int i0 = (int)pl.items.size();
             for (int ty = 0; ty < nty; ++ty)
                 for (int tx = 0; tx < P.ntx; ++tx) pl.items.push_back(Item{pj, ty, tx, 0});
-            pl.refs.push_back(SolveRef{r->st_dev, r->trace_dev, i0, (int)pl.items.size() - i0});
+            // untiled views: the update pass walks the same items as the trial pass
+            const int ni = (int)pl.items.size() - i0;
+            pl.refs.push_back(SolveRef{r->st_dev, r->trace_dev, i0, ni, i0, ni});
+            if (r->fresh) L.refs_new.push_back(pl.refs.back());
         }
         c.count = (int)pl.items.size() - c.start;
         pl.classes.push_back(c);
+        L.new_begin.push_back(nb < 0 ? (int)pl.items.size() : nb);
     }
+    // counts: per class items, n solves, per class new items, n new solves
     for (auto &c : pl.classes) pl.counts.push_back(c.count);
     pl.counts.push_back((int)pl.refs.size());
+    for (size_t c = 0; c < pl.classes.size(); ++c)
+        pl.counts.push_back(pl.classes[c].start + pl.classes[c].count - L.new_begin[c]);
+    pl.counts.push_back((int)L.refs_new.size());
     const size_t np = pl.projs.size(), ni = pl.items.size(), ns = pl.refs.size();
     bool ok = L.projs.ensure(np * sizeof(Proj)) == hipSuccess &&
               L.items.ensure(ni * sizeof(Item)) == hipSuccess &&
               L.counts.ensure(pl.counts.size() * sizeof(int)) == hipSuccess &&
               L.refs.ensure(ns * sizeof(SolveRef)) == hipSuccess &&
+              L.drefs_new.ensure((L.refs_new.size() + 1) * sizeof(SolveRef)) == hipSuccess &&
               L.partials.ensure(ni * kNV * sizeof(double)) == hipSuccess;
     if (ok) {
         (void)hipMemcpyAsync(L.projs.p, pl.projs.data(), np * sizeof(Proj),
@@ -238,7 +259,39 @@ void misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
                              hipMemcpyHostToDevice, stream);
         (void)hipMemcpyAsync(L.refs.p, pl.refs.data(), ns * sizeof(SolveRef),
                              hipMemcpyHostToDevice, stream);
+        if (!L.refs_new.empty())
+            (void)hipMemcpyAsync(L.drefs_new.p, L.refs_new.data(),
+                                 L.refs_new.size() * sizeof(SolveRef), hipMemcpyHostToDevice,
+                                 stream);
     }
+}
+
+// Init of the newly admitted solves over their sub-range of the list: cost
+// and gradient at x0, Moller's init, update pass (p = -g0) with curvature.
+hipError_t misr_server::enqueue_init(List &L) {
+    const int nc = (int)L.pl.classes.size();
+    const int *cnt = L.counts.as<int>();
+    const misr_dtype dt = active.empty() ? MISR_F32 : active[0]->req.params.img_dtype;
+    auto image = [&](int kind) {
+        for (int c = 0; c < nc; ++c) {
+            const Plan::Cls &cl = L.pl.classes[c];
+            const int nb = L.new_begin[c], n = cl.start + cl.count - nb;
+            if (n <= 0) continue;
+            hipError_t e = launch_image(cl.S, cl.Lp, n, stream, L.projs.as<Proj>(),
+                                        L.items.as<Item>() + nb, cnt + nc + 1 + c,
+                                        L.partials.as<double>() + (size_t)nb * kNV, kind,
+                                        (int)dt);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    hipError_t e = image(KIND_COSTGRAD);
+    if (e == hipSuccess)
+        e = launch_scalar((int)L.refs_new.size(), stream, L.drefs_new.as<SolveRef>(),
+                          cnt + 2 * nc + 1, L.partials.as<double>(), L.partials.as<double>(),
+                          PHASE_INIT);
+    if (e == hipSuccess) e = image(KIND_UPCURV);
+    return e;
 }
 
 hipError_t misr_server::enqueue_image(List &L, int kind) {
@@ -321,26 +374,20 @@ void misr_server::run() {
         for (SReq *r : active) n_ep = std::min(n_ep, r->req.params.n_iter - r->passes);
         n_ep = std::max(n_ep, 0);
         hipError_t e = hipSuccess;
+        build_list(all, active);
         if (!fresh.empty()) {
-            build_list(init, fresh);
-            e = enqueue_image(init, KIND_COSTGRAD);
-            if (e == hipSuccess)
-                e = launch_scalar((int)init.pl.refs.size(), stream, init.refs.as<SolveRef>(),
-                                  init.counts.as<int>() + init.pl.classes.size(),
-                                  init.partials.as<double>(), PHASE_INIT);
-            if (e == hipSuccess) e = enqueue_image(init, KIND_UPCURV);
+            e = enqueue_init(all);
             for (SReq *r : fresh) r->fresh = false;
         }
-        build_list(all, active);
         const int ns = (int)all.pl.refs.size();
         const int *d_ns = all.counts.as<int>() + all.pl.classes.size();
         for (int ep = 0; ep < n_ep && e == hipSuccess; ++ep) {
             e = launch_scalar(ns, stream, all.refs.as<SolveRef>(), d_ns, all.partials.as<double>(),
-                              PHASE_A);
+                              all.partials.as<double>(), PHASE_A);
             if (e == hipSuccess) e = enqueue_image(all, KIND_TRIAL);
             if (e == hipSuccess)
                 e = launch_scalar(ns, stream, all.refs.as<SolveRef>(), d_ns,
-                                  all.partials.as<double>(), PHASE_B);
+                                  all.partials.as<double>(), all.partials.as<double>(), PHASE_B);
             if (e == hipSuccess) e = enqueue_image(all, KIND_UPCURV);
         }
         std::vector<SReq *> done;
@@ -402,6 +449,7 @@ extern "C" misr_status misr_server_create(misr_ctx *ctx, const misr_server_confi
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
         return set_error(MISR_E_HIP, "stream creation failed");
     misr_server *raw = s.release();
+    ctx->users++;
     raw->th = std::thread([raw] { raw->run(); });
     *out = raw;
     return MISR_OK;
@@ -509,6 +557,8 @@ extern "C" misr_status misr_server_destroy(misr_server *s) {
     if (s->th.joinable()) s->th.join();
     for (auto &kv : s->ops) misr_op_destroy(kv.second);
     (void)hipStreamDestroy(s->stream);
+    misr_ctx *ctx = s->ctx;
     delete s;
+    ctx->users--;
     return MISR_OK;
 }

@@ -181,8 +181,9 @@ class Context:
         self.device = device
 
     def close(self):
-        if self.h:
-            lib.misr_ctx_destroy(self.h)
+        # the C context refuses to go while ops or servers still use it; then
+        # it stays alive (the objects using it keep this wrapper referenced)
+        if self.h and lib.misr_ctx_destroy(self.h) == OK:
             self.h = None
 
     def __del__(self):

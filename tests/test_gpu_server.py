@@ -85,8 +85,10 @@ def test_admission_by_budget(misr, ctx, probs):
     larger than the whole budget fails with E_NOMEM and does not block others."""
     import torch
     p_small, p_big = probs[3], probs[2]
-    n_small = p_small.H * p_small.W
-    budget = n_small * 40 + 200_000          # room for about one small request
+    # device bytes of one request: x pair + p pair + g pair, state and records
+    need = lambda p, n_iter: p.H * p.W * (2 * 4 + 16) + 512 + n_iter * 64   # noqa: E731
+    budget = int(1.5 * need(p_small, 4))      # one small request at a time, never the big one
+    assert need(p_big, 4) > budget
     srv = misr.Server(ctx, hbm_budget_bytes=budget)
     ids, outs = [], []
     for p in (p_small, p_big, p_small):
