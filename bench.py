@@ -34,12 +34,16 @@ WORKLOAD = ("plain2048: 4 LR frames 1024x1024 f32 -> 2048x2048 HR (x2), {0,1/2}^
             "lambda 0.01 alpha 0.4, 100 SCG passes")
 
 
+KERNEL_SOURCES = ("image_kernels.hip", "device_common.h", "internal.h")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_trial_plain2048_hbm_traffic.md")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the sources the image kernels are compiled from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2108_04315_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -59,18 +63,139 @@ def make_inputs(misr, ctx):
 
 
 def traffic_from_profile(src_hash: str):
-    """HBM bytes per trial launch from the committed counter summary, if it was
-    taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "k_trial_plain2048_traffic.json")
-    if not os.path.exists(path):
+    """HBM bytes per trial launch (FETCH_SIZE + WRITE_SIZE, scaled by the copy
+    calibration) from the committed counter summary, if it was taken on the
+    current kernel sources; else None."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
         return None
-    try:
-        d = json.load(open(path))
-    except Exception:
+    vals = {}
+    for ln in open(TRAFFIC_SUMMARY):
+        if ln.startswith("traffic:"):
+            for kv in ln.split()[1:]:
+                k, _, v = kv.partition("=")
+                vals[k] = v
+    if vals.get("kernel_source_hash") != src_hash or "bytes_per_launch" not in vals:
         return None
-    if d.get("kernel_source_hash") != src_hash:
-        return None
-    return d.get("bytes_per_launch")
+    return float(vals["bytes_per_launch"])
+
+
+def copy_probe(mib: int, reps: int = 3):
+    """Plain device copy of a known size: the calibration kernel for the HBM
+    byte counters (run under rocprofv3 --pmc)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.rand(n, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                      "reps": reps}), flush=True)
+
+
+# ------------------------------------------------------------------ serving
+SERVE_SIZES = (512, 768, 1024, 1536, 2048)
+SERVE_ITERS = 80
+
+
+def _serve_problem(misr, ctx, L, s, seed):
+    """One synthetic projection: LR L x L, scale s (4 frames on the {0,1/2}^2
+    grid at s=2, 9 frames on the 3x3 grid at s=3), jittered shifts, 7x7 PSF
+    sigma 0.8, Poisson 1e4 counts; y and x0 (bicubic of frame 0) on the device."""
+    import torch
+    from paper_2108_04315_amd import synth
+    Hh = L * s
+    K = s * s
+    shifts = synth.frame_shifts(s, K, 0.05, seed)
+    psf = synth.psf_taps(0.8)
+    op = misr.Operator(ctx, Hh, Hh, s, shifts, psf)
+    clean = op.forward(torch.from_numpy(synth.phantom(Hh, Hh, seed)).float().cuda())
+    torch.cuda.synchronize()
+    y_np = synth.add_poisson_noise(clean.double().cpu().numpy(), 1e4, seed + 1)
+    y = torch.from_numpy(y_np).float().cuda()
+    x0 = torch.from_numpy(synth.bicubic_upsample(y_np[0], s)).float().cuda()
+    return dict(op=op, y=y, x0=x0, shifts=shifts, psf=psf, H=Hh, s=s)
+
+
+def serving_leg(misr, ctx, n_req: int = 48, load: float = 0.8, seed: int = 7):
+    """Poisson stream of SR requests (LR 512^2..2048^2, scale 2 or 3, 80 SCG
+    passes each) at a rate that loads the plain path to `load`; the same
+    stream solved (a) plain: one solve at a time in arrival order, (b) served:
+    misr_server continuous batching.  Latency = completion - arrival."""
+    import torch
+    rng = np.random.default_rng(seed)
+    geoms = [(int(rng.choice(SERVE_SIZES)), int(rng.choice([2, 3]))) for _ in range(n_req)]
+    probs = {g: _serve_problem(misr, ctx, g[0], g[1], 100 + i)
+             for i, g in enumerate(sorted(set(geoms)))}
+    prm = misr.default_params(n_iter=SERVE_ITERS)
+    # service time of each geometry on the plain path (after a warm-up solve)
+    t_serv = {}
+    for g, pb in probs.items():
+        for rep in range(2):
+            x = pb["x0"].clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pb["op"].scg_solve(pb["y"], x, prm, trace=False)
+            torch.cuda.synchronize()
+            t_serv[g] = time.perf_counter() - t0
+    mean_s = float(np.mean([t_serv[g] for g in geoms]))
+    rate = load / mean_s
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    hr_px = sum(g[0] * g[0] * g[1] * g[1] for g in geoms)
+
+    # (a) plain
+    outs_plain = [probs[g]["x0"].clone() for g in geoms]
+    torch.cuda.synchronize()
+    lat_p, t_end = [], 0.0
+    t0 = time.perf_counter()
+    for i, g in enumerate(geoms):
+        while time.perf_counter() - t0 < arrivals[i]:
+            time.sleep(2e-5)
+        probs[g]["op"].scg_solve(probs[g]["y"], outs_plain[i], prm, trace=False)
+        torch.cuda.synchronize()
+        t_end = time.perf_counter() - t0
+        lat_p.append(t_end - arrivals[i])
+    span_p = t_end
+
+    # (b) served
+    srv = misr.Server(ctx, hbm_budget_bytes=64 << 30)
+    outs_srv = [torch.empty_like(probs[g]["x0"]) for g in geoms]
+    torch.cuda.synchronize()
+    ids = []
+    t0 = time.perf_counter()
+    for i, g in enumerate(geoms):
+        while time.perf_counter() - t0 < arrivals[i]:
+            time.sleep(2e-5)
+        pb = probs[g]
+        ids.append(srv.submit(pb["H"], pb["H"], pb["s"], pb["shifts"], pb["psf"], pb["y"],
+                              pb["x0"], outs_srv[i], prm))
+    stats = []
+    for rid in ids:
+        if srv.wait(rid, 600_000_000) != misr.OK:
+            raise RuntimeError("served request did not finish")
+        st, stt = srv.poll(rid)
+        if st != misr.REQ_DONE:
+            raise RuntimeError(f"served request failed: status {stt.status}")
+        stats.append(stt)
+    srv.close()
+    lat_s = [(st.t_done_us - st.t_submit_us) * 1e-6 for st in stats]
+    span_s = (max(st.t_done_us for st in stats) - min(st.t_submit_us for st in stats)) * 1e-6
+    span_s += arrivals[0]       # measured from t0 like the plain run
+    equal = all(torch.equal(a, b) for a, b in zip(outs_plain, outs_srv))
+
+    def pct(v, q):
+        return float(np.percentile(np.asarray(v) * 1e3, q))
+    return {
+        "workload": (f"{n_req} requests, Poisson arrivals at {rate:.1f}/s ({load:.0%} of plain "
+                     f"capacity), LR {{512..2048}}^2, scale 2 (4 frames) or 3 (9 frames), "
+                     f"{SERVE_ITERS} SCG passes, f32"),
+        "plain": {"p50_ms": pct(lat_p, 50), "p99_ms": pct(lat_p, 99),
+                  "hr_mpx_per_s": hr_px / span_p / 1e6},
+        "served": {"p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99),
+                   "hr_mpx_per_s": hr_px / span_s / 1e6},
+        "served_equals_plain_bitwise": bool(equal),
+    }
 
 
 def cpu_baseline(y_np, shifts, psf, x0_np, budget_s: float = 15.0):
@@ -101,9 +226,16 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        sys.exit("bench.py: this build runs on one GPU; --gpus N > 1 is not supported")
+        sys.exit("bench.py: one GPU only; --gpus N > 1 is not supported (the multi-GPU "
+                 "decomposition is a design, not an implementation)")
+    if args.copy_probe_mib > 0:
+        copy_probe(args.copy_probe_mib)
+        return
 
     import torch
     from paper_2108_04315_amd import misr
@@ -159,6 +291,8 @@ def main():
         "update_pass": {"kernel": "k_upcurv (update + curvature)", "avg_us": us_update,
                         "achieved_GBs": BYTES_UPDATE * H * W / (us_update * 1e-6) / 1e9},
     }
+    if not args.no_serve:
+        out["serving"] = serving_leg(misr, ctx)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(y_np, shifts, psf, x0.double().cpu().numpy())
     print(json.dumps(out), flush=True)

@@ -304,7 +304,7 @@ extern "C" misr_status misr_op_destroy(misr_op *op) {
 extern "C" int misr_op_band(const misr_op *op) { return op ? op->L : -1; }
 
 // ------------------------------------------------------------- plan build
-static void init_state(ScgState &s, const misr_params &p, long long N) {
+void misr::init_state(ScgState &s, const misr_params &p, long long N) {
     std::memset(&s, 0, sizeof s);
     s.lam = p.scg_lambda1;
     s.lam_bar = 0.0;
@@ -333,13 +333,7 @@ struct SolveIn {
     TileSet *tiles;      // tiled (prm.tile_lr > 0): per-tile buffers
 };
 
-// Tile grid of a tiled solve: tile t = (a, b) owns HR rows [a T, (a+1) T) and
-// columns [b T, (b+1) T) (clipped); its buffer adds a halo of Hh on interior
-// sides.
-struct TileGrid {
-    int T, Hh, ny, nx;
-};
-static TileGrid tile_grid(const misr_op *op, const misr_params &p) {
+TileGrid misr::tile_grid(const misr_op *op, const misr_params &p) {
     TileGrid g;
     g.T = p.tile_lr * op->s;
     g.Hh = p.halo_lr * op->s;
@@ -348,7 +342,7 @@ static TileGrid tile_grid(const misr_op *op, const misr_params &p) {
     return g;
 }
 
-static misr_status check_tiling(const misr_op *op, const misr_params &p) {
+misr_status misr::check_tiling(const misr_op *op, const misr_params &p) {
     if (p.tile_lr <= 0) return MISR_OK;
     const int need = std::max(op->L - 1, 2);
     if (p.halo_lr * op->s < need)
@@ -357,7 +351,7 @@ static misr_status check_tiling(const misr_op *op, const misr_params &p) {
     return MISR_OK;
 }
 
-static hipError_t ensure_tiles(const misr_op *op, const misr_params &p, TileSet &ts) {
+hipError_t misr::ensure_tiles(const misr_op *op, const misr_params &p, TileSet &ts) {
     const TileGrid g = tile_grid(op, p);
     const size_t es = dtype_size(p.img_dtype);
     const int nt = g.ny * g.nx;
@@ -390,6 +384,82 @@ static void add_items(std::vector<Item> &items, int pj, int rows, int cols, int 
     const int nty = (rows + TH - 1) / TH, ntx = (cols + TW - 1) / TW;
     for (int ty = 0; ty < nty; ++ty)
         for (int tx = 0; tx < ntx; ++tx) items.push_back(Item{pj, ty, tx, 0});
+}
+
+void misr::add_views(const misr_op *op, const misr_params &prm, const void *y, void *x,
+                     SolveBufs *bufs, TileSet *tiles, std::vector<Proj> &projs,
+                     std::vector<Item> &items, std::vector<Item> &items_u,
+                     std::vector<HaloCopy> &halos) {
+    Proj P;
+    std::memset(&P, 0, sizeof P);
+    P.y = y;
+    P.op = op->opdev.as<OpDev>();
+    if (prm.tile_lr <= 0) {
+        P.x[0] = x;
+        P.x[1] = bufs->x1.p;
+        P.p[0] = bufs->p0.as<float>();
+        P.p[1] = bufs->p1.as<float>();
+        P.g[0] = bufs->g0.as<float>();
+        P.g[1] = bufs->g1.as<float>();
+        P.ld = P.Wb = op->W;
+        P.Hb = op->H;
+        P.oy1 = P.uy1 = op->H;
+        P.ox1 = P.ux1 = op->W;
+        P.ntx = (op->W + op->TW - 1) / op->TW;
+        const int pj = (int)projs.size();
+        projs.push_back(P);
+        add_items(items, pj, op->H, op->W, op->TH, op->TW);
+        add_items(items_u, pj, op->H, op->W, op->TH, op->TW);
+        return;
+    }
+    const TileGrid g = tile_grid(op, prm);
+    const int v0 = (int)projs.size();
+    for (int a = 0; a < g.ny; ++a)
+        for (int b = 0; b < g.nx; ++b) {
+            const int t = a * g.nx + b;
+            SolveBufs &tb = *tiles->bufs[t];
+            const int R0 = a * g.T, R1 = std::min(op->H, (a + 1) * g.T);
+            const int C0 = b * g.T, C1 = std::min(op->W, (b + 1) * g.T);
+            const int r0 = std::max(0, R0 - g.Hh), r1 = std::min(op->H, R1 + g.Hh);
+            const int c0 = std::max(0, C0 - g.Hh), c1 = std::min(op->W, C1 + g.Hh);
+            Proj Q = P;
+            Q.x[0] = tiles->x0[t]->p;
+            Q.x[1] = tb.x1.p;
+            Q.p[0] = tb.p0.as<float>();
+            Q.p[1] = tb.p1.as<float>();
+            Q.g[0] = tb.g0.as<float>();
+            Q.g[1] = tb.g1.as<float>();
+            Q.ld = Q.Wb = c1 - c0;
+            Q.Hb = r1 - r0;
+            Q.gy0 = r0;
+            Q.gx0 = c0;
+            Q.oy0 = R0 - r0;
+            Q.oy1 = R1 - r0;
+            Q.ox0 = C0 - c0;
+            Q.ox1 = C1 - c0;
+            Q.uy0 = 0;
+            Q.uy1 = Q.Hb;
+            Q.ux0 = 0;
+            Q.ux1 = Q.Wb;
+            Q.ntx = (C1 - C0 + op->TW - 1) / op->TW;
+            const int pj = (int)projs.size();
+            projs.push_back(Q);
+            add_items(items, pj, R1 - R0, C1 - C0, op->TH, op->TW);
+            add_items(items_u, pj, Q.Hb, Q.Wb, op->TH, op->TW);
+        }
+    // halo exchanges: every view's halo from the views that own it
+    const int v1 = (int)projs.size();
+    for (int bi = v0; bi < v1; ++bi)
+        for (int ai = v0; ai < v1; ++ai) {
+            if (ai == bi) continue;
+            const Proj &A = projs[ai], &B = projs[bi];
+            const int gy0 = std::max(B.gy0, A.gy0 + A.oy0);
+            const int gy1 = std::min(B.gy0 + B.Hb, A.gy0 + A.oy1);
+            const int gx0 = std::max(B.gx0, A.gx0 + A.ox0);
+            const int gx1 = std::min(B.gx0 + B.Wb, A.gx0 + A.ox1);
+            if (gy1 > gy0 && gx1 > gx0)
+                halos.push_back(HaloCopy{ai, bi, gy0, gx0, gy1 - gy0, gx1 - gx0});
+        }
 }
 
 // Builds the work lists: solves grouped by kernel class (S, Lp), each solve's
@@ -427,81 +497,14 @@ static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
             init_state(pl.states[i], si.prm, (long long)op->H * op->W);
             pl.item0[i] = (int)pl.items.size();
             pl.item0u[i] = (int)pl.items_u.size();
-            Proj P;
-            std::memset(&P, 0, sizeof P);
-            P.y = si.y;
-            P.op = op->opdev.as<OpDev>();
-            if (si.prm.tile_lr <= 0) {
-                P.x[0] = si.x;
-                P.x[1] = si.bufs->x1.p;
-                P.p[0] = si.bufs->p0.as<float>();
-                P.p[1] = si.bufs->p1.as<float>();
-                P.g[0] = si.bufs->g0.as<float>();
-                P.g[1] = si.bufs->g1.as<float>();
-                P.ld = P.Wb = op->W;
-                P.Hb = op->H;
-                P.oy1 = P.uy1 = op->H;
-                P.ox1 = P.ux1 = op->W;
-                P.ntx = (op->W + op->TW - 1) / op->TW;
-                const int pj = (int)pl.projs.size();
-                pl.projs.push_back(P);
-                pl.proj_solve.push_back(i);
-                add_items(pl.items, pj, op->H, op->W, op->TH, op->TW);
-                add_items(pl.items_u, pj, op->H, op->W, op->TH, op->TW);
-            } else {
+            if (si.prm.tile_lr > 0) {
                 pl.tiled = true;
                 pl.states[i].xglob = si.x;
                 pl.states[i].ldg = op->W;
-                const TileGrid g = tile_grid(op, si.prm);
-                const int v0 = (int)pl.projs.size();
-                for (int a = 0; a < g.ny; ++a)
-                    for (int b = 0; b < g.nx; ++b) {
-                        const int t = a * g.nx + b;
-                        SolveBufs &tb = *si.tiles->bufs[t];
-                        const int R0 = a * g.T, R1 = std::min(op->H, (a + 1) * g.T);
-                        const int C0 = b * g.T, C1 = std::min(op->W, (b + 1) * g.T);
-                        const int r0 = std::max(0, R0 - g.Hh), r1 = std::min(op->H, R1 + g.Hh);
-                        const int c0 = std::max(0, C0 - g.Hh), c1 = std::min(op->W, C1 + g.Hh);
-                        Proj Q = P;
-                        Q.x[0] = si.tiles->x0[t]->p;
-                        Q.x[1] = tb.x1.p;
-                        Q.p[0] = tb.p0.as<float>();
-                        Q.p[1] = tb.p1.as<float>();
-                        Q.g[0] = tb.g0.as<float>();
-                        Q.g[1] = tb.g1.as<float>();
-                        Q.ld = Q.Wb = c1 - c0;
-                        Q.Hb = r1 - r0;
-                        Q.gy0 = r0;
-                        Q.gx0 = c0;
-                        Q.oy0 = R0 - r0;
-                        Q.oy1 = R1 - r0;
-                        Q.ox0 = C0 - c0;
-                        Q.ox1 = C1 - c0;
-                        Q.uy0 = 0;
-                        Q.uy1 = Q.Hb;
-                        Q.ux0 = 0;
-                        Q.ux1 = Q.Wb;
-                        Q.ntx = (C1 - C0 + op->TW - 1) / op->TW;
-                        const int pj = (int)pl.projs.size();
-                        pl.projs.push_back(Q);
-                        pl.proj_solve.push_back(i);
-                        add_items(pl.items, pj, R1 - R0, C1 - C0, op->TH, op->TW);
-                        add_items(pl.items_u, pj, Q.Hb, Q.Wb, op->TH, op->TW);
-                    }
-                // halo exchanges: every view's halo from the views that own it
-                const int v1 = (int)pl.projs.size();
-                for (int bi = v0; bi < v1; ++bi)
-                    for (int ai = v0; ai < v1; ++ai) {
-                        if (ai == bi) continue;
-                        const Proj &A = pl.projs[ai], &B = pl.projs[bi];
-                        const int gy0 = std::max(B.gy0, A.gy0 + A.oy0);
-                        const int gy1 = std::min(B.gy0 + B.Hb, A.gy0 + A.oy1);
-                        const int gx0 = std::max(B.gx0, A.gx0 + A.ox0);
-                        const int gx1 = std::min(B.gx0 + B.Wb, A.gx0 + A.ox1);
-                        if (gy1 > gy0 && gx1 > gx0)
-                            pl.halos.push_back(HaloCopy{ai, bi, gy0, gx0, gy1 - gy0, gx1 - gx0});
-                    }
             }
+            add_views(op, si.prm, si.y, si.x, si.bufs, si.tiles, pl.projs, pl.items, pl.items_u,
+                      pl.halos);
+            pl.proj_solve.resize(pl.projs.size(), i);
             pl.nitems[i] = (int)pl.items.size() - pl.item0[i];
             pl.nitemsu[i] = (int)pl.items_u.size() - pl.item0u[i];
         }

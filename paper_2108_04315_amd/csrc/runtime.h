@@ -162,3 +162,29 @@ struct misr_op {
     misr::PlanDev pdev;
     misr::Plan plan;
 };
+
+namespace misr {
+
+// SCG state of a new solve from its parameters (N = HR pixels).
+void init_state(ScgState &s, const misr_params &p, long long N);
+
+// Tile grid of a tiled solve: tile t = (a, b) owns HR rows [a T, (a+1) T) and
+// columns [b T, (b+1) T) (clipped); its buffer adds a halo of Hh on interior
+// sides.
+struct TileGrid {
+    int T, Hh, ny, nx;
+};
+TileGrid tile_grid(const misr_op *op, const misr_params &p);
+// E_INVAL when the halo is below the reach of the operator and the prior.
+misr_status check_tiling(const misr_op *op, const misr_params &p);
+// Per-tile buffers (halo included) of a tiled solve.
+hipError_t ensure_tiles(const misr_op *op, const misr_params &p, TileSet &ts);
+// Appends one solve's views (one untiled view, or one per tile plus the halo
+// copies between them) with their trial and update items; Proj::st is left
+// for the caller.
+void add_views(const misr_op *op, const misr_params &prm, const void *y, void *x,
+               SolveBufs *bufs, TileSet *tiles, std::vector<Proj> &projs,
+               std::vector<Item> &items, std::vector<Item> &items_u,
+               std::vector<HaloCopy> &halos);
+
+}  // namespace misr

@@ -56,6 +56,9 @@ struct SReq {
     // device memory owned by the server for this request
     DevMem xwork, ydev, dstate;
     SolveBufs bufs;
+    TileSet tiles;        // tiled requests (params.tile_lr > 0): per-tile buffers
+    bool tiled = false;
+    int view0 = 0, nviews = 0;   // its views in the current work list
     void *x0dev = nullptr;
     const void *ydev_ptr = nullptr;
     ScgState *st_dev = nullptr;
@@ -81,13 +84,20 @@ struct misr_server {
     std::map<OpKey, misr_op *> ops;
     // work list of all active solves; per class, the running solves' items
     // come first and the newly admitted ones' after, so that the init passes
-    // of the new solves run over a sub-range and leave their partial sums where
-    // the next pass of the whole list reads them
+    // of the new solves run over a sub-range of each class.
+    // Device counts: [0,nc) trial items per class, [nc,2nc) update items per
+    // class, 2nc solves, 2nc+1 halo copies, then the same four for the new
+    // solves only at offset 2nc+2.
     struct List {
         Plan pl;
-        std::vector<int> new_begin;          // per class: first item of the new solves
+        std::vector<int> nb, nbu;            // per class: first trial / update item of the new solves
         std::vector<SolveRef> refs_new;      // the new solves only
-        DevMem projs, items, counts, refs, drefs_new, partials;
+        std::vector<HaloCopy> halos_new;     // halo copies of the new solves only
+        std::vector<int> counts;
+        DevMem projs, items, items_u, counts_d, refs, drefs_new, partials, partials_u, halos,
+            halos_new_d;
+        int nc() const { return (int)pl.classes.size(); }
+        const int *cnt(int off) const { return counts_d.as<int>() + off; }
     } all;
     std::string last_error;
 
@@ -96,12 +106,28 @@ struct misr_server {
     void release(SReq *r);
     void build_list(List &L, const std::vector<SReq *> &rs);
     hipError_t enqueue_init(List &L);
-    hipError_t enqueue_image(List &L, int kind);
+    hipError_t enqueue_image(List &L, int kind, bool fresh);
+    hipError_t enqueue_scalar(List &L, int phase, bool fresh);
+    hipError_t enqueue_halo(List &L, bool fresh);
     void finish(SReq *r, misr_req_state st, misr_status code);
 };
 
+// Device bytes a request holds while admitted.  A tiled request keeps every
+// tile (halo included) with its own x pair, p pair and g pair.
 static size_t request_bytes(const misr_request &q, long long n, size_t es, int K, long long m) {
-    size_t b = (size_t)n * es * 2 + (size_t)n * 16;           // x pair, p pair, g pair
+    size_t b = 0;
+    if (q.params.tile_lr > 0) {
+        const int s = q.geom.scale, H = q.geom.hr_h, W = q.geom.hr_w;
+        const int T = q.params.tile_lr * s, Hh = q.params.halo_lr * s;
+        for (int a = 0; a * T < H; ++a)
+            for (int c = 0; c * T < W; ++c) {
+                const long long rows = std::min(H, (a + 1) * T + Hh) - std::max(0, a * T - Hh);
+                const long long cols = std::min(W, (c + 1) * T + Hh) - std::max(0, c * T - Hh);
+                b += (size_t)(rows * cols) * (es * 2 + 16);
+            }
+    } else {
+        b = (size_t)n * es * 2 + (size_t)n * 16;           // x pair, p pair, g pair
+    }
     if (!q.on_device) b += (size_t)K * m * es + (size_t)n * es;  // y and x staged on device
     b += sizeof(ScgState) + (size_t)std::max(1, q.params.n_iter) * sizeof(IterRec);
     return b;
@@ -121,8 +147,11 @@ bool misr_server::setup(SReq *r) {
         it = ops.emplace(key, op).first;
     }
     r->op = it->second;
+    if (r->tiled && (check_tiling(r->op, q.params) != MISR_OK ||
+                     ensure_tiles(r->op, q.params, r->tiles) != hipSuccess))
+        return false;
     const long long m = (long long)(g.hr_h / g.scale) * (g.hr_w / g.scale) * g.n_frames;
-    if (r->bufs.ensure(r->n, r->es) != hipSuccess) return false;
+    if (!r->tiled && r->bufs.ensure(r->n, r->es) != hipSuccess) return false;
     const size_t per = (size_t)std::max(1, q.params.n_iter);
     if (r->dstate.ensure(sizeof(ScgState) + per * sizeof(IterRec)) != hipSuccess) return false;
     r->st_dev = r->dstate.as<ScgState>();
@@ -146,23 +175,11 @@ bool misr_server::setup(SReq *r) {
             return false;
     }
     ScgState st;
-    std::memset(&st, 0, sizeof st);
-    st.lam = q.params.scg_lambda1;
-    st.sigma = q.params.scg_sigma;
-    st.N = r->n;
-    st.n_iter = q.params.n_iter;
-    st.success = 1;
-    st.active = 1;
-    for (int dy = 0; dy < 3; ++dy)
-        for (int dx = 0; dx < 3; ++dx)
-            st.wt.gam[dy * 3 + dx] =
-                (dx == 0 && dy == 0) || dx >= q.params.btv_w || dy >= q.params.btv_w
-                    ? 0.f
-                    : (float)(q.params.lambda_reg * std::pow(q.params.alpha_btv, dx + dy));
-    st.wt.eps = (float)q.params.eps;
-    st.wt.eps_data = (float)q.params.eps_data;
-    st.wt.data_p = q.params.data_p;
-    st.wt.x_rounding = q.params.x_rounding;
+    init_state(st, q.params, r->n);
+    if (r->tiled) {
+        st.xglob = r->x0dev;     // scattered into the tiles at init, gathered at the end
+        st.ldg = g.hr_w;
+    }
     return hipMemcpyAsync(r->st_dev, &st, sizeof st, hipMemcpyHostToDevice, stream) ==
                hipSuccess &&
            hipStreamSynchronize(stream) == hipSuccess;   // st lives on this stack frame
@@ -177,6 +194,8 @@ void misr_server::release(SReq *r) {
     r->bufs.p1.release();
     r->bufs.g0.release();
     r->bufs.g1.release();
+    r->tiles.bufs.clear();
+    r->tiles.x0.clear();
     std::lock_guard<std::mutex> lk(mu);
     used -= std::min(used, r->bytes);
 }
@@ -185,11 +204,15 @@ void misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
     Plan &pl = L.pl;
     pl.projs.clear();
     pl.items.clear();
+    pl.items_u.clear();
     pl.classes.clear();
-    pl.counts.clear();
+    pl.classes_u.clear();
     pl.refs.clear();
-    L.new_begin.clear();
+    pl.halos.clear();
+    L.nb.clear();
+    L.nbu.clear();
     L.refs_new.clear();
+    L.halos_new.clear();
     std::map<std::pair<int, int>, std::vector<SReq *>> groups;
     std::vector<std::pair<int, int>> order;
     for (int pass = 0; pass < 2; ++pass)       // running solves first, then new ones
@@ -201,111 +224,124 @@ void misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
         }
     for (auto &key : order) {
         Plan::Cls c{key.first, key.second, (int)pl.items.size(), 0};
-        int nb = -1;
+        Plan::Cls cu{key.first, key.second, (int)pl.items_u.size(), 0};
+        int nb = -1, nbu = -1;
         for (SReq *r : groups[key]) {
-            if (r->fresh && nb < 0) nb = (int)pl.items.size();
-            const misr_op *op = r->op;
-            Proj P;
-            std::memset(&P, 0, sizeof P);
-            P.x[0] = r->x0dev;
-            P.x[1] = r->bufs.x1.p;
-            P.p[0] = r->bufs.p0.as<float>();
-            P.p[1] = r->bufs.p1.as<float>();
-            P.g[0] = r->bufs.g0.as<float>();
-            P.g[1] = r->bufs.g1.as<float>();
-            P.y = r->ydev_ptr;
-            P.ld = op->W;
-            P.Hb = op->H;
-            P.Wb = op->W;
-            P.oy1 = P.uy1 = op->H;
-            P.ox1 = P.ux1 = op->W;
-            P.ntx = (op->W + op->TW - 1) / op->TW;
-            P.st = r->st_dev;
-            P.op = op->opdev.as<OpDev>();
-            const int nty = (op->H + op->TH - 1) / op->TH;
-            const int pj = (int)pl.projs.size();
-            pl.projs.push_back(P);
-            const int i0 = (int)pl.items.size();
-            for (int ty = 0; ty < nty; ++ty)
-                for (int tx = 0; tx < P.ntx; ++tx) pl.items.push_back(Item{pj, ty, tx, 0});
-            // untiled views: the update pass walks the same items as the trial pass
-            const int ni = (int)pl.items.size() - i0;
-            pl.refs.push_back(SolveRef{r->st_dev, r->trace_dev, i0, ni, i0, ni});
-            if (r->fresh) L.refs_new.push_back(pl.refs.back());
+            if (r->fresh && nb < 0) {
+                nb = (int)pl.items.size();
+                nbu = (int)pl.items_u.size();
+            }
+            const int i0 = (int)pl.items.size(), iu0 = (int)pl.items_u.size();
+            const size_t h0 = pl.halos.size();
+            r->view0 = (int)pl.projs.size();
+            add_views(r->op, r->req.params, r->ydev_ptr, r->x0dev, &r->bufs, &r->tiles, pl.projs,
+                      pl.items, pl.items_u, pl.halos);
+            r->nviews = (int)pl.projs.size() - r->view0;
+            for (int j = r->view0; j < (int)pl.projs.size(); ++j) pl.projs[j].st = r->st_dev;
+            pl.refs.push_back(SolveRef{r->st_dev, r->trace_dev, i0, (int)pl.items.size() - i0,
+                                       iu0, (int)pl.items_u.size() - iu0});
+            if (r->fresh) {
+                L.refs_new.push_back(pl.refs.back());
+                L.halos_new.insert(L.halos_new.end(), pl.halos.begin() + h0, pl.halos.end());
+            }
         }
         c.count = (int)pl.items.size() - c.start;
+        cu.count = (int)pl.items_u.size() - cu.start;
         pl.classes.push_back(c);
-        L.new_begin.push_back(nb < 0 ? (int)pl.items.size() : nb);
+        pl.classes_u.push_back(cu);
+        L.nb.push_back(nb < 0 ? (int)pl.items.size() : nb);
+        L.nbu.push_back(nbu < 0 ? (int)pl.items_u.size() : nbu);
     }
-    // counts: per class items, n solves, per class new items, n new solves
-    for (auto &c : pl.classes) pl.counts.push_back(c.count);
-    pl.counts.push_back((int)pl.refs.size());
-    for (size_t c = 0; c < pl.classes.size(); ++c)
-        pl.counts.push_back(pl.classes[c].start + pl.classes[c].count - L.new_begin[c]);
-    pl.counts.push_back((int)L.refs_new.size());
-    const size_t np = pl.projs.size(), ni = pl.items.size(), ns = pl.refs.size();
-    bool ok = L.projs.ensure(np * sizeof(Proj)) == hipSuccess &&
-              L.items.ensure(ni * sizeof(Item)) == hipSuccess &&
-              L.counts.ensure(pl.counts.size() * sizeof(int)) == hipSuccess &&
-              L.refs.ensure(ns * sizeof(SolveRef)) == hipSuccess &&
-              L.drefs_new.ensure((L.refs_new.size() + 1) * sizeof(SolveRef)) == hipSuccess &&
-              L.partials.ensure(ni * kNV * sizeof(double)) == hipSuccess;
-    if (ok) {
-        (void)hipMemcpyAsync(L.projs.p, pl.projs.data(), np * sizeof(Proj),
-                             hipMemcpyHostToDevice, stream);
-        (void)hipMemcpyAsync(L.items.p, pl.items.data(), ni * sizeof(Item),
-                             hipMemcpyHostToDevice, stream);
-        (void)hipMemcpyAsync(L.counts.p, pl.counts.data(), pl.counts.size() * sizeof(int),
-                             hipMemcpyHostToDevice, stream);
-        (void)hipMemcpyAsync(L.refs.p, pl.refs.data(), ns * sizeof(SolveRef),
-                             hipMemcpyHostToDevice, stream);
-        if (!L.refs_new.empty())
-            (void)hipMemcpyAsync(L.drefs_new.p, L.refs_new.data(),
-                                 L.refs_new.size() * sizeof(SolveRef), hipMemcpyHostToDevice,
-                                 stream);
+    const int nc = L.nc();
+    L.counts.clear();
+    for (auto &c : pl.classes) L.counts.push_back(c.count);
+    for (auto &c : pl.classes_u) L.counts.push_back(c.count);
+    L.counts.push_back((int)pl.refs.size());
+    L.counts.push_back((int)pl.halos.size());
+    for (int c = 0; c < nc; ++c)
+        L.counts.push_back(pl.classes[c].start + pl.classes[c].count - L.nb[c]);
+    for (int c = 0; c < nc; ++c)
+        L.counts.push_back(pl.classes_u[c].start + pl.classes_u[c].count - L.nbu[c]);
+    L.counts.push_back((int)L.refs_new.size());
+    L.counts.push_back((int)L.halos_new.size());
+    const size_t np = pl.projs.size(), ni = pl.items.size(), nu = pl.items_u.size(),
+                 ns = pl.refs.size(), nh = pl.halos.size(), nhn = L.halos_new.size();
+    struct Up {
+        DevMem *d;
+        const void *h;
+        size_t n;
+    } ups[] = {{&L.projs, pl.projs.data(), np * sizeof(Proj)},
+               {&L.items, pl.items.data(), ni * sizeof(Item)},
+               {&L.items_u, pl.items_u.data(), nu * sizeof(Item)},
+               {&L.counts_d, L.counts.data(), L.counts.size() * sizeof(int)},
+               {&L.refs, pl.refs.data(), ns * sizeof(SolveRef)},
+               {&L.drefs_new, L.refs_new.data(), L.refs_new.size() * sizeof(SolveRef)},
+               {&L.halos, pl.halos.data(), nh * sizeof(HaloCopy)},
+               {&L.halos_new_d, L.halos_new.data(), nhn * sizeof(HaloCopy)}};
+    for (auto &u : ups) {
+        if (u.d->ensure(std::max<size_t>(u.n, 16)) != hipSuccess) continue;
+        if (u.n) (void)hipMemcpyAsync(u.d->p, u.h, u.n, hipMemcpyHostToDevice, stream);
     }
+    (void)L.partials.ensure(std::max<size_t>(ni, 1) * kNV * sizeof(double));
+    (void)L.partials_u.ensure(std::max<size_t>(nu, 1) * kNV * sizeof(double));
 }
 
-// Init of the newly admitted solves over their sub-range of the list: cost
-// and gradient at x0, Moller's init, update pass (p = -g0) with curvature.
-hipError_t misr_server::enqueue_init(List &L) {
-    const int nc = (int)L.pl.classes.size();
-    const int *cnt = L.counts.as<int>();
+// Image pass over the whole list (fresh = false) or over the new solves' tail
+// of each class (fresh = true).
+hipError_t misr_server::enqueue_image(List &L, int kind, bool fresh) {
+    const int nc = L.nc();
+    const bool upd = kind == KIND_UPCURV;
+    const auto &cls = upd ? L.pl.classes_u : L.pl.classes;
+    const Item *items = upd ? L.items_u.as<Item>() : L.items.as<Item>();
+    double *part = upd ? L.partials_u.as<double>() : L.partials.as<double>();
     const misr_dtype dt = active.empty() ? MISR_F32 : active[0]->req.params.img_dtype;
-    auto image = [&](int kind) {
-        for (int c = 0; c < nc; ++c) {
-            const Plan::Cls &cl = L.pl.classes[c];
-            const int nb = L.new_begin[c], n = cl.start + cl.count - nb;
-            if (n <= 0) continue;
-            hipError_t e = launch_image(cl.S, cl.Lp, n, stream, L.projs.as<Proj>(),
-                                        L.items.as<Item>() + nb, cnt + nc + 1 + c,
-                                        L.partials.as<double>() + (size_t)nb * kNV, kind,
-                                        (int)dt);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
-    };
-    hipError_t e = image(KIND_COSTGRAD);
-    if (e == hipSuccess)
-        e = launch_scalar((int)L.refs_new.size(), stream, L.drefs_new.as<SolveRef>(),
-                          cnt + 2 * nc + 1, L.partials.as<double>(), L.partials.as<double>(),
-                          PHASE_INIT);
-    if (e == hipSuccess) e = image(KIND_UPCURV);
-    return e;
-}
-
-hipError_t misr_server::enqueue_image(List &L, int kind) {
-    const int nc = (int)L.pl.classes.size();
     for (int c = 0; c < nc; ++c) {
-        const Plan::Cls &cl = L.pl.classes[c];
-        const misr_dtype dt = active.empty() ? MISR_F32 : active[0]->req.params.img_dtype;
-        hipError_t e = launch_image(cl.S, cl.Lp, cl.count, stream, L.projs.as<Proj>(),
-                                    L.items.as<Item>() + cl.start, L.counts.as<int>() + c,
-                                    L.partials.as<double>() + (size_t)cl.start * kNV, kind,
+        const int first = fresh ? (upd ? L.nbu[c] : L.nb[c]) : cls[c].start;
+        const int n = cls[c].start + cls[c].count - first;
+        if (n <= 0) continue;
+        const int cidx = (fresh ? 2 * nc + 2 : 0) + (upd ? nc : 0) + c;
+        hipError_t e = launch_image(cls[c].S, cls[c].Lp, n, stream, L.projs.as<Proj>(),
+                                    items + first, L.cnt(cidx), part + (size_t)first * kNV, kind,
                                     (int)dt);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t misr_server::enqueue_scalar(List &L, int phase, bool fresh) {
+    const int nc = L.nc();
+    const int n = fresh ? (int)L.refs_new.size() : (int)L.pl.refs.size();
+    if (n == 0) return hipSuccess;
+    return launch_scalar(n, stream, fresh ? L.drefs_new.as<SolveRef>() : L.refs.as<SolveRef>(),
+                         L.cnt((fresh ? 2 * nc + 2 : 0) + 2 * nc), L.partials.as<double>(),
+                         L.partials_u.as<double>(), phase);
+}
+
+hipError_t misr_server::enqueue_halo(List &L, bool fresh) {
+    const int nc = L.nc();
+    const size_t n = fresh ? L.halos_new.size() : L.pl.halos.size();
+    if (n == 0) return hipSuccess;
+    return launch_halo(stream, L.projs.as<Proj>(),
+                       fresh ? L.halos_new_d.as<HaloCopy>() : L.halos.as<HaloCopy>(),
+                       L.cnt((fresh ? 2 * nc + 2 : 0) + 2 * nc + 1), (int)n);
+}
+
+// Init of the newly admitted solves over their sub-range of the list: tiled
+// ones scatter x0 into their tiles; cost and gradient at x0 (and its halo
+// exchange), Moller's init, update pass (p = -g0) with curvature, then steps
+// 1-5 of their first pass.
+hipError_t misr_server::enqueue_init(List &L) {
+    const misr_dtype dt = active.empty() ? MISR_F32 : active[0]->req.params.img_dtype;
+    hipError_t e = hipSuccess;
+    for (SReq *r : active)
+        if (e == hipSuccess && r->fresh && r->tiled)
+            e = launch_scatter(stream, L.projs.as<Proj>() + r->view0, r->nviews, (int)dt);
+    if (e == hipSuccess) e = enqueue_image(L, KIND_COSTGRAD, true);
+    if (e == hipSuccess) e = enqueue_halo(L, true);
+    if (e == hipSuccess) e = enqueue_scalar(L, PHASE_INIT, true);
+    if (e == hipSuccess) e = enqueue_image(L, KIND_UPCURV, true);
+    if (e == hipSuccess) e = enqueue_scalar(L, PHASE_A, true);
+    return e;
 }
 
 void misr_server::finish(SReq *r, misr_req_state st, misr_status code) {
@@ -379,16 +415,16 @@ void misr_server::run() {
             e = enqueue_init(all);
             for (SReq *r : fresh) r->fresh = false;
         }
-        const int ns = (int)all.pl.refs.size();
-        const int *d_ns = all.counts.as<int>() + all.pl.classes.size();
+        // Each pass ends with steps 1-5 of the next one (phase A), so that no
+        // partial sums outlive a cycle: the next cycle's list may place a
+        // running solve's items elsewhere.  After a solve's last pass phase A
+        // finds it inactive and changes nothing.
         for (int ep = 0; ep < n_ep && e == hipSuccess; ++ep) {
-            e = launch_scalar(ns, stream, all.refs.as<SolveRef>(), d_ns, all.partials.as<double>(),
-                              all.partials.as<double>(), PHASE_A);
-            if (e == hipSuccess) e = enqueue_image(all, KIND_TRIAL);
-            if (e == hipSuccess)
-                e = launch_scalar(ns, stream, all.refs.as<SolveRef>(), d_ns,
-                                  all.partials.as<double>(), all.partials.as<double>(), PHASE_B);
-            if (e == hipSuccess) e = enqueue_image(all, KIND_UPCURV);
+            e = enqueue_image(all, KIND_TRIAL, false);
+            if (e == hipSuccess) e = enqueue_halo(all, false);
+            if (e == hipSuccess) e = enqueue_scalar(all, PHASE_B, false);
+            if (e == hipSuccess) e = enqueue_image(all, KIND_UPCURV, false);
+            if (e == hipSuccess) e = enqueue_scalar(all, PHASE_A, false);
         }
         std::vector<SReq *> done;
         for (SReq *r : active) {
@@ -398,12 +434,10 @@ void misr_server::run() {
         // results of finished solves: current iterate into the caller's buffer
         for (SReq *r : done) {
             if (e != hipSuccess) break;
-            const int idx = (int)(std::find(active.begin(), active.end(), r) - active.begin());
-            (void)idx;
-            for (size_t j = 0; j < all.pl.projs.size(); ++j)
-                if (all.pl.projs[j].st == r->st_dev)
-                    e = launch_finalize(stream, all.projs.as<Proj>() + j, 1,
-                                        (int)r->req.params.img_dtype);
+            const Proj *pv = all.projs.as<Proj>() + r->view0;
+            const int dt = (int)r->req.params.img_dtype;
+            e = r->tiled ? launch_gather(stream, pv, r->nviews, dt, 0)
+                         : launch_finalize(stream, pv, r->nviews, dt);
             if (e == hipSuccess && !r->req.on_device)
                 e = hipMemcpyAsync(r->req.x_out, r->xwork.p, r->n * r->es, hipMemcpyDeviceToHost,
                                    stream);
@@ -461,14 +495,15 @@ extern "C" misr_status misr_server_submit(misr_server *s, const misr_request *re
     misr_status st = misr_geometry_check(&req->geom);
     if (st != MISR_OK) return st;
     if ((st = misr_params_check(&req->params)) != MISR_OK) return st;
-    if (req->params.data_p != 2 || req->params.tile_lr > 0)
-        return set_error(MISR_E_INVAL, "served solves: L2 data term, untiled");
+    if (req->params.data_p != 2)
+        return set_error(MISR_E_INVAL, "served solves use the L2 data term (data_p = 2)");
     if (!req->y || !req->x0 || !req->x_out) return set_error(MISR_E_INVAL, "NULL buffer");
     auto r = std::make_unique<SReq>();
     r->req = *req;
     r->shifts.assign(req->geom.shifts_lr, req->geom.shifts_lr + 2 * req->geom.n_frames);
     r->psf.assign(req->geom.psf_1d, req->geom.psf_1d + req->geom.psf_size);
     r->n = (long long)req->geom.hr_h * req->geom.hr_w;
+    r->tiled = req->params.tile_lr > 0;
     r->es = dtype_size(req->params.img_dtype);
     const long long m = (long long)(req->geom.hr_h / req->geom.scale) *
                         (req->geom.hr_w / req->geom.scale);

@@ -151,3 +151,32 @@ def test_cancel_and_fault_hook(misr, ctx, probs):
     with pytest.raises(misr.MisrError):
         srv.poll(987654)
     srv.close()
+
+
+def test_tiled_request_in_mix(misr, ctx, probs):
+    """A request split into tiles (device halo exchange after every trial
+    pass), served beside untiled ones of another scale, equals its plain tiled
+    solve bit for bit."""
+    import torch
+    pt = problem(60, 2, 0.8, None, jitter=0.05, n_iter=14, seeds=(21, 22, 23))   # HR 120
+    prm_t = misr.default_params(n_iter=14, tile_lr=24, halo_lr=8)
+    op = misr.Operator(ctx, pt.H, pt.W, pt.s, pt.shifts, pt.psf)
+    yt = to_dev(_f32(pt.y))
+    x_plain = to_dev(_f32(pt.x0))
+    op.scg_solve(yt, x_plain, prm_t)
+    solo1 = _solo(misr, ctx, probs[1], SPECS[1][3])
+    srv = misr.Server(ctx, hbm_budget_bytes=1 << 30)
+    x1 = to_dev(_f32(probs[1].x0))
+    o1 = torch.empty_like(x1)
+    r1 = srv.submit(probs[1].H, probs[1].W, probs[1].s, probs[1].shifts, probs[1].psf,
+                    to_dev(_f32(probs[1].y)), x1, o1, misr.default_params(n_iter=SPECS[1][3]))
+    xt = to_dev(_f32(pt.x0))
+    ot = torch.empty_like(xt)
+    rt = srv.submit(pt.H, pt.W, pt.s, pt.shifts, pt.psf, yt, xt, ot, prm_t)
+    for rid in (r1, rt):
+        assert srv.wait(rid, 60_000_000) == misr.OK
+        st, stats = srv.poll(rid)
+        assert st == misr.REQ_DONE and stats.status == misr.OK, stats.status
+    assert torch.equal(o1, solo1)
+    assert torch.equal(ot, x_plain), f"max diff {float((ot - x_plain).abs().max())}"
+    srv.close()
