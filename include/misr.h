@@ -99,10 +99,16 @@ typedef struct {
                             tile_lr x tile_lr LR pixels held separately in HBM
                             with a halo exchanged every pass */
     int32_t halo_lr;     /* halo width in LR pixels for tile_lr > 0 */
-    int32_t x_rounding;  /* 16-bit x storage: 0 round to nearest even (default),
-                            1 stochastic rounding driven by a counter-based hash of
-                            (pixel, pass), so that it is reproducible */
-    int32_t pad_;
+    int32_t x_rounding;  /* x_work = 1 with a 16-bit img_dtype: rounding of each
+                            x update, 0 to nearest even (default), 1 stochastic,
+                            driven by a counter-based hash of (pixel, pass) so
+                            that it is reproducible */
+    int32_t x_work;      /* SCG iterate with a 16-bit img_dtype: 0 (default) FP32
+                            in library buffers (x is widened on entry and rounded
+                            to nearest even on exit; y stays 16-bit); 1 held in
+                            img_dtype itself (half the x traffic, but steps below
+                            half a unit in the last place are lost, so the solve
+                            stalls once steps get small) */
 } misr_params;
 
 /* One SCG pass as recorded on the device. */

@@ -164,6 +164,7 @@ extern "C" misr_status misr_params_check(const misr_params *p) {
         return set_error(MISR_E_INVAL, "tile_lr and halo_lr must be >= 0");
     if (p->x_rounding != 0 && p->x_rounding != 1)
         return set_error(MISR_E_INVAL, "x_rounding must be 0 or 1");
+    if (p->x_work != 0 && p->x_work != 1) return set_error(MISR_E_INVAL, "x_work must be 0 or 1");
     return MISR_OK;
 }
 
@@ -353,7 +354,7 @@ misr_status misr::check_tiling(const misr_op *op, const misr_params &p) {
 
 hipError_t misr::ensure_tiles(const misr_op *op, const misr_params &p, TileSet &ts) {
     const TileGrid g = tile_grid(op, p);
-    const size_t es = dtype_size(p.img_dtype);
+    const size_t es = view_esize(p);
     const int nt = g.ny * g.nx;
     if (ts.tile_lr != p.tile_lr || ts.halo_lr != p.halo_lr || ts.es != es ||
         (int)ts.bufs.size() != nt) {
@@ -395,7 +396,7 @@ void misr::add_views(const misr_op *op, const misr_params &prm, const void *y, v
     P.y = y;
     P.op = op->opdev.as<OpDev>();
     if (prm.tile_lr <= 0) {
-        P.x[0] = x;
+        P.x[0] = iterate_fp32(prm) ? bufs->x0w.p : x;
         P.x[1] = bufs->x1.p;
         P.p[0] = bufs->p0.as<float>();
         P.p[1] = bufs->p1.as<float>();
@@ -475,6 +476,9 @@ static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
     pl.refs.clear();
     pl.halos.clear();
     pl.tiled = false;
+    pl.staged = false;
+    pl.vt = in.empty() ? (int)ST_F32 : view_stype(in[0].prm);
+    pl.gt = in.empty() ? (int)ST_F32 : (int)in[0].prm.img_dtype;
     const size_t ns = in.size();
     pl.item0.assign(ns, 0);
     pl.nitems.assign(ns, 0);
@@ -497,8 +501,9 @@ static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
             init_state(pl.states[i], si.prm, (long long)op->H * op->W);
             pl.item0[i] = (int)pl.items.size();
             pl.item0u[i] = (int)pl.items_u.size();
-            if (si.prm.tile_lr > 0) {
-                pl.tiled = true;
+            if (si.prm.tile_lr > 0 || iterate_fp32(si.prm)) {
+                pl.tiled |= si.prm.tile_lr > 0;
+                pl.staged = true;
                 pl.states[i].xglob = si.x;
                 pl.states[i].ldg = op->W;
             }
@@ -516,10 +521,10 @@ static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
     pl.finish_counts();
 }
 
-static std::string plan_key(const Plan &pl, int n_iter, int stype) {
-    std::string k = std::to_string(n_iter) + "/" + std::to_string(stype) + "/" +
+static std::string plan_key(const Plan &pl, int n_iter) {
+    std::string k = std::to_string(n_iter) + "/" + std::to_string(pl.code()) + "/" +
                      std::to_string(pl.states.size()) + "/" + std::to_string(pl.projs.size()) +
-                     "/" + std::to_string(pl.halos.size()) + (pl.tiled ? "T" : "U");
+                     "/" + std::to_string(pl.halos.size()) + (pl.staged ? "S" : "U");
     for (auto &c : pl.classes)
         k += ":" + std::to_string(c.S) + "," + std::to_string(c.Lp) + "," +
              std::to_string(c.start) + "," + std::to_string(c.count);
@@ -532,7 +537,6 @@ static std::string plan_key(const Plan &pl, int n_iter, int stype) {
 struct Launcher {
     const Plan &pl;
     PlanDev &pd;
-    int stype;
     hipStream_t s;
     const int *cnt() const { return pd.counts.as<int>(); }
     hipError_t image(int kind) const {
@@ -544,7 +548,8 @@ struct Launcher {
         for (int c = 0; c < (int)cls.size(); ++c) {
             hipError_t e = launch_image(cls[c].S, cls[c].Lp, cls[c].count, s, pd.projs.as<Proj>(),
                                         items + cls[c].start, cnt() + off + c,
-                                        part + (size_t)cls[c].start * kNV, kind, stype);
+                                        part + (size_t)cls[c].start * kNV, kind,
+                                        pl.code());
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -562,14 +567,13 @@ struct Launcher {
 };
 
 // Enqueues the whole solve (init + n_iter passes + result copy) on `s`.
-static hipError_t enqueue_solve(const Plan &pl, PlanDev &pd, int n_iter, int stype,
-                                hipStream_t s) {
-    const Launcher Lr{pl, pd, stype, s};
+static hipError_t enqueue_solve(const Plan &pl, PlanDev &pd, int n_iter, hipStream_t s) {
+    const Launcher Lr{pl, pd, s};
     const int np = (int)pl.projs.size();
     hipError_t e = hipSuccess;
 #define STEP(x)                          \
     if ((e = (x)) != hipSuccess) return e;
-    if (pl.tiled) STEP(launch_scatter(s, pd.projs.as<Proj>(), np, stype));
+    if (pl.staged) STEP(launch_scatter(s, pd.projs.as<Proj>(), np, pl.vt, pl.gt));
     STEP(Lr.image(KIND_COSTGRAD));
     STEP(Lr.halo());
     STEP(Lr.scalar(PHASE_INIT));
@@ -582,16 +586,17 @@ static hipError_t enqueue_solve(const Plan &pl, PlanDev &pd, int n_iter, int sty
         STEP(Lr.image(KIND_UPCURV));
     }
 #undef STEP
-    // tiled views: owned parts back into the caller's image; an untiled view
-    // copies its workspace buffer back when the iterate ended there
-    return pl.tiled ? launch_gather(s, pd.projs.as<Proj>(), np, stype, 0)
-                    : launch_finalize(s, pd.projs.as<Proj>(), np, stype);
+    // staged views: owned parts back into the caller's image (rounded to its
+    // storage); an unstaged view copies its workspace buffer back when the
+    // iterate ended there
+    return pl.staged ? launch_gather(s, pd.projs.as<Proj>(), np, pl.vt, pl.gt, 0)
+                     : launch_finalize(s, pd.projs.as<Proj>(), np, pl.vt);
 }
 
 // Runs a plan on the context's library stream, ordered after the caller's
 // stream and before its later work; the solve is captured into a graph once
 // per plan shape and replayed.
-static misr_status run_plan(misr_ctx *ctx, Plan &pl, PlanDev &pd, int n_iter, int stype,
+static misr_status run_plan(misr_ctx *ctx, Plan &pl, PlanDev &pd, int n_iter,
                             hipStream_t user) {
     hipStream_t s = ctx->stream;
     MISR_HIP(hipEventRecord(ctx->ev_in, user));
@@ -602,7 +607,7 @@ static misr_status run_plan(misr_ctx *ctx, Plan &pl, PlanDev &pd, int n_iter, in
     snprintf(ptrs, sizeof ptrs, "|%p,%p,%p,%p,%p,%p,%p,%p,%p", pd.projs.p, pd.items.p,
              pd.items_u.p, pd.counts.p, pd.states.p, pd.partials.p, pd.partials_u.p, pd.refs.p,
              pd.halos.p);
-    const std::string key = plan_key(pl, n_iter, stype) + ptrs;
+    const std::string key = plan_key(pl, n_iter) + ptrs;
     if (!pd.exec || pd.graph_key != key) {
         if (pd.exec) {
             (void)hipGraphExecDestroy(pd.exec);
@@ -610,7 +615,7 @@ static misr_status run_plan(misr_ctx *ctx, Plan &pl, PlanDev &pd, int n_iter, in
         }
         hipGraph_t graph = nullptr;
         MISR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_solve(pl, pd, n_iter, stype, s);
+        hipError_t e = enqueue_solve(pl, pd, n_iter, s);
         hipError_t e2 = hipStreamEndCapture(s, &graph);
         if (e != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -712,6 +717,7 @@ extern "C" misr_status misr_cost_grad(const misr_op *cop, const misr_params *prm
     Plan &pl = op->plan;
     SolveIn si{op, *prm, y, const_cast<void *>(x), &op->bufs, &op->tiles};
     si.prm.n_iter = 0;
+    si.prm.x_work = 1;   // evaluated at x as stored: no FP32 copy
     build_plan(pl, {si});
     if (pl.tiled)
         pl.states[0].gglob = g;
@@ -720,12 +726,12 @@ extern "C" misr_status misr_cost_grad(const misr_op *cop, const misr_params *prm
     PlanDev &pd = op->pdev;
     hipStream_t s = (hipStream_t)stream;
     MISR_HIP(pd.upload(pl, 0, s));
-    const Launcher Lr{pl, pd, (int)prm->img_dtype, s};
+    const Launcher Lr{pl, pd, s};
     const int np = (int)pl.projs.size();
-    if (pl.tiled) MISR_HIP(launch_scatter(s, pd.projs.as<Proj>(), np, (int)prm->img_dtype));
+    if (pl.staged) MISR_HIP(launch_scatter(s, pd.projs.as<Proj>(), np, pl.vt, pl.gt));
     MISR_HIP(Lr.image(KIND_COSTGRAD));
     MISR_HIP(launch_cost_out(s, pd.partials.as<double>(), (int)pl.items.size(), cost_dev));
-    if (pl.tiled) MISR_HIP(launch_gather(s, pd.projs.as<Proj>(), np, (int)prm->img_dtype, 1));
+    if (pl.staged) MISR_HIP(launch_gather(s, pd.projs.as<Proj>(), np, pl.vt, pl.gt, 1));
     return MISR_OK;
 }
 
@@ -743,12 +749,14 @@ extern "C" misr_status misr_scg_solve(const misr_op *cop, const misr_params *prm
     std::lock_guard<std::mutex> lc(op->ctx->mu);
     MISR_HIP(set_device(op->ctx->dev));
     const long long n = (long long)op->H * op->W;
-    MISR_HIP(op->bufs.ensure(n, dtype_size(prm->img_dtype)));
-    if (prm->tile_lr > 0) MISR_HIP(ensure_tiles(op, *prm, op->tiles));
+    if (prm->tile_lr > 0)
+        MISR_HIP(ensure_tiles(op, *prm, op->tiles));
+    else
+        MISR_HIP(op->bufs.ensure_view(n, *prm));
     Plan &pl = op->plan;
     build_plan(pl, {SolveIn{op, *prm, y, x, &op->bufs, &op->tiles}});
     hipStream_t s = (hipStream_t)stream;
-    st = run_plan(op->ctx, pl, op->pdev, prm->n_iter, (int)prm->img_dtype, s);
+    st = run_plan(op->ctx, pl, op->pdev, prm->n_iter, s);
     if (st != MISR_OK) return st;
     if (trace) return fetch_trace(op->pdev, 0, trace, s);
     return MISR_OK;
@@ -777,8 +785,8 @@ extern "C" misr_status misr_scg_solve_batch(int n, const misr_op *const *ops,
         if (st != MISR_OK) return st;
         if (prm[i].data_p != 2 || prm[i].tile_lr > 0)
             return set_error(MISR_E_INVAL, "batch entry %d: L2 data term, untiled only", i);
-        if (prm[i].img_dtype != prm[0].img_dtype)
-            return set_error(MISR_E_INVAL, "batch entries must share img_dtype");
+        if (prm[i].img_dtype != prm[0].img_dtype || prm[i].x_work != prm[0].x_work)
+            return set_error(MISR_E_INVAL, "batch entries must share img_dtype and x_work");
         if (ctx && ops[i]->ctx != ctx) return set_error(MISR_E_INVAL, "ops span contexts");
         ctx = ops[i]->ctx;
     }
@@ -795,15 +803,14 @@ extern "C" misr_status misr_scg_solve_batch(int n, const misr_op *const *ops,
     int n_iter = 0;
     for (int i = 0; i < n; ++i) n_iter = std::max(n_iter, prm[i].n_iter);
     std::vector<SolveIn> in;
-    const size_t es = dtype_size(prm[0].img_dtype);
     for (int i = 0; i < n; ++i) {
         if ((int)bc.bufs.size() <= i) bc.bufs.emplace_back(new SolveBufs());
-        MISR_HIP(bc.bufs[i]->ensure((long long)ops[i]->H * ops[i]->W, es));
+        MISR_HIP(bc.bufs[i]->ensure_view((long long)ops[i]->H * ops[i]->W, prm[i]));
         in.push_back(SolveIn{ops[i], prm[i], y[i], x[i], bc.bufs[i].get(), nullptr});
     }
     build_plan(bc.plan, in);
     hipStream_t s = (hipStream_t)stream;
-    misr_status st = run_plan(ctx, bc.plan, bc.pdev, n_iter, (int)prm[0].img_dtype, s);
+    misr_status st = run_plan(ctx, bc.plan, bc.pdev, n_iter, s);
     if (st != MISR_OK) return st;
     misr_status worst = MISR_OK;
     if (traces)
@@ -833,13 +840,14 @@ extern "C" misr_status misr_time_pass(const misr_op *cop, const misr_params *prm
     Plan &pl = op->plan;
     misr_params p1 = *prm;
     p1.n_iter = 1;
+    p1.x_work = 1;   // the passes over x as stored
     build_plan(pl, {SolveIn{op, p1, y, x, &op->bufs, nullptr}});
     PlanDev &pd = op->pdev;
     hipStream_t s = op->ctx->stream;
     MISR_HIP(hipEventRecord(op->ctx->ev_in, (hipStream_t)stream));
     MISR_HIP(hipStreamWaitEvent(s, op->ctx->ev_in, 0));
     MISR_HIP(pd.upload(pl, 1, s));
-    const Launcher Lr{pl, pd, (int)prm->img_dtype, s};
+    const Launcher Lr{pl, pd, s};
     MISR_HIP(Lr.image(KIND_COSTGRAD));
     MISR_HIP(Lr.scalar(PHASE_INIT));
     MISR_HIP(Lr.image(KIND_UPCURV));

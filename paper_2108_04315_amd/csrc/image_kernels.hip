@@ -419,11 +419,12 @@ FI TileOrigin tile_origin(const AS4 Proj &P, int ty, int tx) {
 // every frame's forward, residual, data cost and adjoint, then the BTV cost
 // and gradient; writes g_t = grad J(x_t) to g[cur^1] for the owned pixels and
 // the partial sums {E_data, E_reg, |g_t|^2, g_t.g_k, g_t.p}.
-template <int S, int L, class ST>
+template <int S, int L, class ST, class SY>
 FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, int mode,
                    float *sm, double *red, double *part) {
     using T = Tile<S, L>;
     using raw = typename ST::raw;
+    using rawy = typename SY::raw;
     const AS4 OpDev &op = *cst(P.op);
     const int tid = threadIdx.x;
     const TileOrigin o = tile_origin<S, L>(P, ty, tx);
@@ -474,7 +475,7 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     double e_data = 0.0;
     const int data_p = st.wt.data_p;
     const float epsd = st.wt.eps_data, e2d = epsd * epsd;
-    const AS1 raw *yb = glb((const raw *)P.y);
+    const AS1 rawy *yb = glb((const rawy *)P.y);
     __syncthreads();
 
     for (int k = 0; k < K; ++k) {
@@ -490,13 +491,13 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
         pass1<S, L>(xs, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
                     S * (NI - 1) + L, NJ, wxk, jA, w - 1, hx);
         __syncthreads();
-        const AS1 raw *yk = yb + (i64)k * h * w;
+        const AS1 rawy *yk = yb + (i64)k * h * w;
         pass2<S, L>(hx, NI, NJ, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
             const int gj = jA + j;
             float yv[T::CI];
 #pragma unroll
             for (int c = 0; c < T::CI; ++c)
-                yv[c] = ST::ld(yk, (i64)min(iA + i0 + c, h - 1) * w + gj);
+                yv[c] = SY::ld(yk, (i64)min(iA + i0 + c, h - 1) * w + gj);
             const bool own_j = (S * gj >= o.V0) && (S * gj < P.gx0 + o.v1);
 #pragma unroll
             for (int c = 0; c < T::CI; ++c) {
@@ -783,7 +784,7 @@ FI void tile_adjoint(const AS4 Proj &P, int ty, int tx, const void *r, float *xo
 // -------------------------------------------------------------- the kernels
 // Each kernel walks the work list with a grid stride; the item count is read
 // from device memory so that one captured launch can serve a changing list.
-template <int S, int L, class ST>
+template <int S, int L, class ST, class SY>
 __global__ void __launch_bounds__(kNTI, 4) k_trial(const Proj *projs, const Item *items,
                                                 const int *n_items, double *partials,
                                                 int mode) {
@@ -795,7 +796,7 @@ __global__ void __launch_bounds__(kNTI, 4) k_trial(const Proj *projs, const Item
         const AS4 Proj &P = cst(projs)[itm.proj];
         const AS4 ScgState &st = *cst(P.st);
         if (mode == 1 && !st.active) continue;
-        tile_trial<S, L, ST>(P, st, itm.ty, itm.tx, mode, sm, red, partials + (i64)it * kNV);
+        tile_trial<S, L, ST, SY>(P, st, itm.ty, itm.tx, mode, sm, red, partials + (i64)it * kNV);
         __syncthreads();
     }
 }
@@ -867,30 +868,40 @@ int MISR_FN(tile_dims_s)(int Lp, int *th, int *tw) {
     return 0;
 }
 
-hipError_t MISR_FN(launch_trial_s)(int Lp, int stype, int grid, hipStream_t s, const Proj *projs,
+// code = st_code(x storage, y storage): the frames share the iterate's
+// storage, or the iterate is FP32 over 16-bit frames.
+hipError_t MISR_FN(launch_trial_s)(int Lp, int code, int grid, hipStream_t s, const Proj *projs,
                                    const Item *items, const int *n_items, double *partials,
                                    int mode) {
-#define X(l)                                                                                    \
-    if (Lp == l) {                                                                              \
-        if (stype == ST_F32)                                                                    \
-            hipLaunchKernelGGL((k_trial<MISR_SCALE, l, StF32>), dim3(grid), dim3(kNTI), 0, s,     \
-                               projs, items, n_items, partials, mode);                  \
-        else if (stype == ST_F16)                                                               \
-            hipLaunchKernelGGL((k_trial<MISR_SCALE, l, StF16>), dim3(grid), dim3(kNTI), 0, s,     \
-                               projs, items, n_items, partials, mode);                  \
-        else                                                                                    \
-            hipLaunchKernelGGL((k_trial<MISR_SCALE, l, StBF16>), dim3(grid), dim3(kNTI), 0, s,    \
-                               projs, items, n_items, partials, mode);                  \
-        return hipGetLastError();                                                               \
+#define LAUNCH(l, SX, SY)                                                                     \
+    hipLaunchKernelGGL((k_trial<MISR_SCALE, l, SX, SY>), dim3(grid), dim3(kNTI), 0, s, projs, \
+                       items, n_items, partials, mode)
+#define X(l)                                                                                  \
+    if (Lp == l) {                                                                            \
+        if (code == st_code(ST_F32, ST_F32))                                                  \
+            LAUNCH(l, StF32, StF32);                                                          \
+        else if (code == st_code(ST_F16, ST_F16))                                             \
+            LAUNCH(l, StF16, StF16);                                                          \
+        else if (code == st_code(ST_BF16, ST_BF16))                                           \
+            LAUNCH(l, StBF16, StBF16);                                                        \
+        else if (code == st_code(ST_F32, ST_F16))                                             \
+            LAUNCH(l, StF32, StF16);                                                          \
+        else if (code == st_code(ST_F32, ST_BF16))                                            \
+            LAUNCH(l, StF32, StBF16);                                                         \
+        else                                                                                  \
+            return hipErrorInvalidValue;                                                      \
+        return hipGetLastError();                                                             \
     }
     MISR_LIST(X)
 #undef X
+#undef LAUNCH
     return hipErrorInvalidValue;
 }
 
-hipError_t MISR_FN(launch_upcurv_s)(int Lp, int stype, int grid, hipStream_t s, const Proj *projs,
+hipError_t MISR_FN(launch_upcurv_s)(int Lp, int code, int grid, hipStream_t s, const Proj *projs,
                                     const Item *items, const int *n_items,
                                     double *partials) {
+    const int stype = st_x(code);
 #define X(l)                                                                                     \
     if (Lp == l) {                                                                               \
         if (stype == ST_F32)                                                                     \

@@ -14,6 +14,11 @@ constexpr int kMaxL = 16;    // band length
 constexpr int kPadRows = 16; // zero weight rows before and after each frame's table
 
 enum StorageType : int { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+// Launch code of the image kernels: storage of the views' iterate x (low
+// nibble) and of the frames y (high nibble).
+constexpr int st_code(int sx, int sy) { return sx | (sy << 4); }
+constexpr int st_x(int code) { return code & 15; }
+constexpr int st_y(int code) { return code >> 4; }
 
 // Operator of one geometry: per frame the two 1-D factors of A_k.
 // Row factor: LR row i reads HR rows s*i + offy[k] + l, l in [0, L), with

@@ -19,9 +19,10 @@ namespace misr {
 int padded_band(int S, int L);
 int tile_hr(int S, int Lp);
 int tile_wr(int S, int Lp);
+// code = st_code(storage of the views' x, storage of y)
 hipError_t launch_image(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
                         const Item *items, const int *n_items, double *partials, int kind,
-                        int stype);
+                        int code);
 hipError_t launch_forward(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
                           const Item *items, int n, int stype, void *y);
 hipError_t launch_adjoint(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
@@ -30,8 +31,8 @@ hipError_t launch_scalar(int grid, hipStream_t stream, const SolveRef *refs, con
                          const double *partials, const double *partials_u, int phase);
 hipError_t launch_halo(hipStream_t stream, const Proj *projs, const HaloCopy *copies,
                        const int *n_copies, int grid);
-hipError_t launch_scatter(hipStream_t stream, const Proj *projs, int nproj, int stype);
-hipError_t launch_gather(hipStream_t stream, const Proj *projs, int nproj, int stype,
+hipError_t launch_scatter(hipStream_t stream, const Proj *projs, int nproj, int vt, int gt);
+hipError_t launch_gather(hipStream_t stream, const Proj *projs, int nproj, int vt, int gt,
                          int which);
 hipError_t launch_cost_out(hipStream_t stream, const double *partials, int nitems,
                            double *out);
@@ -93,7 +94,11 @@ struct Plan {
     std::vector<int> item0u, nitemsu; // per solve: its range of update items
     std::vector<SolveRef> refs;       // device-side references (filled by upload)
     std::vector<HaloCopy> halos;      // halo exchanges after each trial pass
-    bool tiled = false;
+    bool tiled = false;               // some solve is split into tiles
+    bool staged = false;              // some solve's iterate lives in library views
+                                      // (tiled, or FP32 over a 16-bit caller image)
+    int vt = ST_F32, gt = ST_F32;     // storage of the views' x and of the caller's x and y
+    int code() const { return st_code(vt, gt); }
     void finish_counts() {
         counts.clear();
         for (auto &c : classes) counts.push_back(c.count);
@@ -104,9 +109,21 @@ struct Plan {
     int n_states_idx() const { return (int)(classes.size() + classes_u.size()); }
 };
 
-// Per-solve image buffers owned by the library (x1, p0, p1, g0, g1).
+// The iterate is FP32 in library buffers while the caller's x is 16-bit.
+inline bool iterate_fp32(const misr_params &p) {
+    return p.img_dtype != MISR_F32 && p.x_work == 0;
+}
+// Storage type of the views' x.
+inline int view_stype(const misr_params &p) {
+    return iterate_fp32(p) ? (int)ST_F32 : (int)p.img_dtype;
+}
+inline size_t view_esize(const misr_params &p) { return view_stype(p) == ST_F32 ? 4 : 2; }
+
+// Per-solve image buffers owned by the library (x1, p0, p1, g0, g1; x0w is
+// the FP32 copy of x0 when a 16-bit caller image is solved with an FP32
+// iterate).
 struct SolveBufs {
-    DevMem x1, p0, p1, g0, g1;
+    DevMem x1, p0, p1, g0, g1, x0w;
     hipError_t ensure(long long n, size_t es) {
         hipError_t e;
         if ((e = x1.ensure(n * es)) != hipSuccess) return e;
@@ -114,6 +131,12 @@ struct SolveBufs {
         if ((e = p1.ensure(n * 4)) != hipSuccess) return e;
         if ((e = g0.ensure(n * 4)) != hipSuccess) return e;
         return g1.ensure(n * 4);
+    }
+    // an untiled solve with parameters p over n HR pixels
+    hipError_t ensure_view(long long n, const misr_params &p) {
+        hipError_t e = ensure(n, view_esize(p));
+        if (e == hipSuccess && iterate_fp32(p)) e = x0w.ensure(n * 4);
+        return e;
     }
 };
 
@@ -167,6 +190,7 @@ namespace misr {
 
 // SCG state of a new solve from its parameters (N = HR pixels).
 void init_state(ScgState &s, const misr_params &p, long long N);
+
 
 // Tile grid of a tiled solve: tile t = (a, b) owns HR rows [a T, (a+1) T) and
 // columns [b T, (b+1) T) (clipped); its buffer adds a halo of Hh on interior

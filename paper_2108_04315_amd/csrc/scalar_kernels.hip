@@ -243,48 +243,66 @@ __global__ void k_halo(const Proj *__restrict__ projs, const HaloCopy *__restric
     }
 }
 
-// Whole-image x (the solve's xglob) into every view's x[0], halo included;
-// p[0] cleared so that the first update starts from a zero direction.
-__global__ void k_scatter(const Proj *__restrict__ projs, int nproj, int stype) {
+// Element conversions between the storage types (round to nearest even
+// into 16-bit; widening is exact).
+__device__ __forceinline__ float ld_any(const void *b, long long i, int t) {
+    if (t == ST_F32) return ((const float *)b)[i];
+    if (t == ST_BF16) return __uint_as_float((unsigned)((const unsigned short *)b)[i] << 16);
+    return (float)((const _Float16 *)b)[i];
+}
+__device__ __forceinline__ void st_any(void *b, long long i, int t, float v) {
+    if (t == ST_F32) {
+        ((float *)b)[i] = v;
+    } else if (t == ST_BF16) {
+        unsigned u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) {
+            u = 0x7fc00000u;
+        } else {
+            u += 0x7fffu + ((u >> 16) & 1u);
+        }
+        ((unsigned short *)b)[i] = (unsigned short)(u >> 16);
+    } else {
+        ((_Float16 *)b)[i] = (_Float16)v;
+    }
+}
+
+// Whole-image x (the solve's xglob, storage gt) into every view's x[0]
+// (storage vt), halo included; p[0] cleared so that the first update starts
+// from a zero direction.
+__global__ void k_scatter(const Proj *__restrict__ projs, int nproj, int vt, int gt) {
     for (int j = blockIdx.y; j < nproj; j += gridDim.y) {
         const Proj &P = projs[j];
         const ScgState &st = *P.st;
-        const int es = (stype == ST_F32) ? 4 : 2;
         const long long n = (long long)P.Hb * P.Wb;
         for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
              q += (long long)gridDim.x * blockDim.x) {
             const int r = (int)(q / P.Wb), c = (int)(q - (long long)r * P.Wb);
             const long long src = (long long)(P.gy0 + r) * st.ldg + P.gx0 + c;
             const long long dst = (long long)r * P.ld + c;
-            if (es == 4)
-                ((float *)P.x[0])[dst] = ((const float *)st.xglob)[src];
-            else
-                ((unsigned short *)P.x[0])[dst] = ((const unsigned short *)st.xglob)[src];
+            st_any(P.x[0], dst, vt, ld_any(st.xglob, src, gt));
             P.p[0][dst] = 0.f;
         }
     }
 }
 
-// Owned part of every view's current x (which = 0) or trial gradient g[cur^1]
-// (which = 1) back into the whole-image buffer.
-__global__ void k_gather(const Proj *__restrict__ projs, int nproj, int stype, int which) {
+// Owned part of every view's current x (which = 0; storage vt, written as
+// gt) or trial gradient g[cur^1] (which = 1; FP32) back into the whole-image
+// buffer.
+__global__ void k_gather(const Proj *__restrict__ projs, int nproj, int vt, int gt, int which) {
     for (int j = blockIdx.y; j < nproj; j += gridDim.y) {
         const Proj &P = projs[j];
         const ScgState &st = *P.st;
-        const int es = (stype == ST_F32 || which == 1) ? 4 : 2;
         const int oh = P.oy1 - P.oy0, ow = P.ox1 - P.ox0;
         const long long n = (long long)oh * ow;
         const void *srcb = which ? (const void *)P.g[st.cur ^ 1] : P.x[st.xc];
         void *dstb = which ? (void *)st.gglob : st.xglob;
+        const int ts = which ? (int)ST_F32 : vt, td = which ? (int)ST_F32 : gt;
         for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
              q += (long long)gridDim.x * blockDim.x) {
             const int r = (int)(q / ow) + P.oy0, c = (int)(q % ow) + P.ox0;
             const long long src = (long long)r * P.ld + c;
             const long long dst = (long long)(P.gy0 + r) * st.ldg + P.gx0 + c;
-            if (es == 4)
-                ((float *)dstb)[dst] = ((const float *)srcb)[src];
-            else
-                ((unsigned short *)dstb)[dst] = ((const unsigned short *)srcb)[src];
+            st_any(dstb, dst, td, ld_any(srcb, src, ts));
         }
     }
 }
@@ -384,16 +402,16 @@ hipError_t launch_halo(hipStream_t stream, const Proj *projs, const HaloCopy *co
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(hipStream_t stream, const Proj *projs, int nproj, int stype) {
+hipError_t launch_scatter(hipStream_t stream, const Proj *projs, int nproj, int vt, int gt) {
     hipLaunchKernelGGL(k_scatter, dim3(256, nproj < 65535 ? nproj : 65535), dim3(256), 0, stream,
-                       projs, nproj, stype);
+                       projs, nproj, vt, gt);
     return hipGetLastError();
 }
 
-hipError_t launch_gather(hipStream_t stream, const Proj *projs, int nproj, int stype,
+hipError_t launch_gather(hipStream_t stream, const Proj *projs, int nproj, int vt, int gt,
                          int which) {
     hipLaunchKernelGGL(k_gather, dim3(256, nproj < 65535 ? nproj : 65535), dim3(256), 0, stream,
-                       projs, nproj, stype, which);
+                       projs, nproj, vt, gt, which);
     return hipGetLastError();
 }
 

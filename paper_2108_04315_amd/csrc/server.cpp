@@ -58,6 +58,7 @@ struct SReq {
     SolveBufs bufs;
     TileSet tiles;        // tiled requests (params.tile_lr > 0): per-tile buffers
     bool tiled = false;
+    bool staged = false;  // iterate in library views: tiled, or FP32 over a 16-bit x
     int view0 = 0, nviews = 0;   // its views in the current work list
     void *x0dev = nullptr;
     const void *ydev_ptr = nullptr;
@@ -109,12 +110,21 @@ struct misr_server {
     hipError_t enqueue_image(List &L, int kind, bool fresh);
     hipError_t enqueue_scalar(List &L, int phase, bool fresh);
     hipError_t enqueue_halo(List &L, bool fresh);
+    // storage code of the image launches (every admitted request shares
+    // img_dtype and x_work)
+    int launch_code() const {
+        if (active.empty()) return st_code(ST_F32, ST_F32);
+        const misr_params &p = active[0]->req.params;
+        return st_code(view_stype(p), (int)p.img_dtype);
+    }
     void finish(SReq *r, misr_req_state st, misr_status code);
 };
 
 // Device bytes a request holds while admitted.  A tiled request keeps every
-// tile (halo included) with its own x pair, p pair and g pair.
+// tile (halo included) with its own x pair, p pair and g pair; an FP32
+// iterate over a 16-bit image adds an FP32 copy of x0.
 static size_t request_bytes(const misr_request &q, long long n, size_t es, int K, long long m) {
+    const size_t ev = view_esize(q.params);
     size_t b = 0;
     if (q.params.tile_lr > 0) {
         const int s = q.geom.scale, H = q.geom.hr_h, W = q.geom.hr_w;
@@ -123,10 +133,10 @@ static size_t request_bytes(const misr_request &q, long long n, size_t es, int K
             for (int c = 0; c * T < W; ++c) {
                 const long long rows = std::min(H, (a + 1) * T + Hh) - std::max(0, a * T - Hh);
                 const long long cols = std::min(W, (c + 1) * T + Hh) - std::max(0, c * T - Hh);
-                b += (size_t)(rows * cols) * (es * 2 + 16);
+                b += (size_t)(rows * cols) * (ev * 2 + 16);
             }
     } else {
-        b = (size_t)n * es * 2 + (size_t)n * 16;           // x pair, p pair, g pair
+        b = (size_t)n * ev * 2 + (size_t)n * 16;           // x pair, p pair, g pair
     }
     if (!q.on_device) b += (size_t)K * m * es + (size_t)n * es;  // y and x staged on device
     b += sizeof(ScgState) + (size_t)std::max(1, q.params.n_iter) * sizeof(IterRec);
@@ -151,7 +161,7 @@ bool misr_server::setup(SReq *r) {
                      ensure_tiles(r->op, q.params, r->tiles) != hipSuccess))
         return false;
     const long long m = (long long)(g.hr_h / g.scale) * (g.hr_w / g.scale) * g.n_frames;
-    if (!r->tiled && r->bufs.ensure(r->n, r->es) != hipSuccess) return false;
+    if (!r->tiled && r->bufs.ensure_view(r->n, q.params) != hipSuccess) return false;
     const size_t per = (size_t)std::max(1, q.params.n_iter);
     if (r->dstate.ensure(sizeof(ScgState) + per * sizeof(IterRec)) != hipSuccess) return false;
     r->st_dev = r->dstate.as<ScgState>();
@@ -176,8 +186,8 @@ bool misr_server::setup(SReq *r) {
     }
     ScgState st;
     init_state(st, q.params, r->n);
-    if (r->tiled) {
-        st.xglob = r->x0dev;     // scattered into the tiles at init, gathered at the end
+    if (r->staged) {
+        st.xglob = r->x0dev;     // scattered into the views at init, gathered at the end
         st.ldg = g.hr_w;
     }
     return hipMemcpyAsync(r->st_dev, &st, sizeof st, hipMemcpyHostToDevice, stream) ==
@@ -194,6 +204,7 @@ void misr_server::release(SReq *r) {
     r->bufs.p1.release();
     r->bufs.g0.release();
     r->bufs.g1.release();
+    r->bufs.x0w.release();
     r->tiles.bufs.clear();
     r->tiles.x0.clear();
     std::lock_guard<std::mutex> lk(mu);
@@ -294,7 +305,7 @@ hipError_t misr_server::enqueue_image(List &L, int kind, bool fresh) {
     const auto &cls = upd ? L.pl.classes_u : L.pl.classes;
     const Item *items = upd ? L.items_u.as<Item>() : L.items.as<Item>();
     double *part = upd ? L.partials_u.as<double>() : L.partials.as<double>();
-    const misr_dtype dt = active.empty() ? MISR_F32 : active[0]->req.params.img_dtype;
+    const int code = launch_code();
     for (int c = 0; c < nc; ++c) {
         const int first = fresh ? (upd ? L.nbu[c] : L.nb[c]) : cls[c].start;
         const int n = cls[c].start + cls[c].count - first;
@@ -302,7 +313,7 @@ hipError_t misr_server::enqueue_image(List &L, int kind, bool fresh) {
         const int cidx = (fresh ? 2 * nc + 2 : 0) + (upd ? nc : 0) + c;
         hipError_t e = launch_image(cls[c].S, cls[c].Lp, n, stream, L.projs.as<Proj>(),
                                     items + first, L.cnt(cidx), part + (size_t)first * kNV, kind,
-                                    (int)dt);
+                                    code);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -331,11 +342,11 @@ hipError_t misr_server::enqueue_halo(List &L, bool fresh) {
 // exchange), Moller's init, update pass (p = -g0) with curvature, then steps
 // 1-5 of their first pass.
 hipError_t misr_server::enqueue_init(List &L) {
-    const misr_dtype dt = active.empty() ? MISR_F32 : active[0]->req.params.img_dtype;
     hipError_t e = hipSuccess;
     for (SReq *r : active)
-        if (e == hipSuccess && r->fresh && r->tiled)
-            e = launch_scatter(stream, L.projs.as<Proj>() + r->view0, r->nviews, (int)dt);
+        if (e == hipSuccess && r->fresh && r->staged)
+            e = launch_scatter(stream, L.projs.as<Proj>() + r->view0, r->nviews,
+                               view_stype(r->req.params), (int)r->req.params.img_dtype);
     if (e == hipSuccess) e = enqueue_image(L, KIND_COSTGRAD, true);
     if (e == hipSuccess) e = enqueue_halo(L, true);
     if (e == hipSuccess) e = enqueue_scalar(L, PHASE_INIT, true);
@@ -435,9 +446,9 @@ void misr_server::run() {
         for (SReq *r : done) {
             if (e != hipSuccess) break;
             const Proj *pv = all.projs.as<Proj>() + r->view0;
-            const int dt = (int)r->req.params.img_dtype;
-            e = r->tiled ? launch_gather(stream, pv, r->nviews, dt, 0)
-                         : launch_finalize(stream, pv, r->nviews, dt);
+            const int vt = view_stype(r->req.params), gt = (int)r->req.params.img_dtype;
+            e = r->staged ? launch_gather(stream, pv, r->nviews, vt, gt, 0)
+                          : launch_finalize(stream, pv, r->nviews, vt);
             if (e == hipSuccess && !r->req.on_device)
                 e = hipMemcpyAsync(r->req.x_out, r->xwork.p, r->n * r->es, hipMemcpyDeviceToHost,
                                    stream);
@@ -504,6 +515,7 @@ extern "C" misr_status misr_server_submit(misr_server *s, const misr_request *re
     r->psf.assign(req->geom.psf_1d, req->geom.psf_1d + req->geom.psf_size);
     r->n = (long long)req->geom.hr_h * req->geom.hr_w;
     r->tiled = req->params.tile_lr > 0;
+    r->staged = r->tiled || iterate_fp32(req->params);
     r->es = dtype_size(req->params.img_dtype);
     const long long m = (long long)(req->geom.hr_h / req->geom.scale) *
                         (req->geom.hr_w / req->geom.scale);
@@ -516,8 +528,9 @@ extern "C" misr_status misr_server_submit(misr_server *s, const misr_request *re
     // every admitted request shares one storage type (one launch per class)
     for (auto &kv : s->reqs)
         if ((kv.second->state == MISR_REQ_QUEUED || kv.second->state == MISR_REQ_RUNNING) &&
-            kv.second->req.params.img_dtype != req->params.img_dtype)
-            return set_error(MISR_E_INVAL, "requests in flight use another img_dtype");
+            (kv.second->req.params.img_dtype != req->params.img_dtype ||
+             view_stype(kv.second->req.params) != view_stype(req->params)))
+            return set_error(MISR_E_INVAL, "requests in flight use another img_dtype or x_work");
     r->id = s->next_id++;
     *id = r->id;
     s->queue.push_back(r.get());

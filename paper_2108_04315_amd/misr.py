@@ -45,7 +45,7 @@ class misr_params(C.Structure):
                 ("btv_w", C.c_int32), ("data_p", C.c_int32), ("eps_data", C.c_double),
                 ("scg_sigma", C.c_double), ("scg_lambda1", C.c_double), ("n_iter", C.c_int32),
                 ("img_dtype", C.c_int32), ("tile_lr", C.c_int32), ("halo_lr", C.c_int32),
-                ("x_rounding", C.c_int32), ("pad_", C.c_int32)]
+                ("x_rounding", C.c_int32), ("x_work", C.c_int32)]
 
 
 class misr_scg_iter(C.Structure):

@@ -61,7 +61,8 @@ def test_params_defaults_and_checks(misr):
     assert misr.lib.misr_params_check(C.byref(p)) == misr.OK
     for field, bad in [("alpha_btv", 1.0), ("alpha_btv", 0.0), ("lambda_reg", -1.0),
                        ("btv_w", 4), ("data_p", 3), ("scg_sigma", 0.0), ("scg_lambda1", -1.0),
-                       ("n_iter", -1), ("eps", float("nan")), ("img_dtype", 7)]:
+                       ("n_iter", -1), ("eps", float("nan")), ("img_dtype", 7),
+                       ("x_work", 2), ("x_rounding", 3)]:
         q = misr.default_params(**{field: bad})
         assert misr.lib.misr_params_check(C.byref(q)) == misr.E_INVAL, field
         assert misr.last_error()

@@ -102,17 +102,58 @@ def test_one_pass_closed_form(misr, ctx):
     assert np.max(np.abs(to_np(x) - ref)) <= 1e-6
 
 
-@pytest.mark.parametrize("dtype_name,tol", [("float16", TOL_LOWP), ("bfloat16", TOL_LOWP)])
-def test_lowp_storage_solve(misr, ctx, dtype_name, tol):
+@pytest.mark.parametrize("dtype_name", ["float16", "bfloat16"])
+def test_lowp_storage_solve(misr, ctx, dtype_name):
+    """Frames and image stored in 16 bits, FP32 iterate (x_work = 0): within
+    1e-2 of the FP64 oracle solve on the FP32 inputs, so the bound covers the
+    rounding of y and x0 to 16 bits as well as of the result."""
     import torch
     dt = getattr(torch, dtype_name)
-    prob = problem(48, 3, 1.0, 7, noise=("poisson", 1e4), jitter=0.05, n_iter=30,
+    prob = problem(48, 3, 1.0, 7, noise=("poisson", 1e4), jitter=0.05, n_iter=60,
                    seeds=(3, 4, 5))
-    x_o, _, _ = _oracle_solve(prob, 30)
-    x_g, its, info = _gpu_solve(misr, ctx, prob, 30, dtype=dt)
+    x_o, _, _ = _oracle_solve(prob, 60)
+    x_g, its, info = _gpu_solve(misr, ctx, prob, 60, dtype=dt)
     err = rel_l2(x_g, x_o)
-    print(f"{dtype_name}: rel-L2 {err:.3e}, PSNR vs oracle {psnr(x_g, x_o):.2f} dB")
-    assert err <= tol
+    print(f"{dtype_name} storage, FP32 iterate: rel-L2 {err:.3e}, PSNR vs oracle "
+          f"{psnr(x_g, x_o):.2f} dB")
+    assert err <= TOL_LOWP
+
+
+@pytest.mark.parametrize("dtype_name", ["float16", "bfloat16"])
+def test_lowp_fp32_iterate_is_rounded_fp32_solve(misr, ctx, dtype_name):
+    """With x_work = 0 a 16-bit solve is the FP32 solve of the widened inputs,
+    rounded to nearest even once at the end: bit for bit."""
+    import torch
+    dt = getattr(torch, dtype_name)
+    prob = problem(40, 2, 0.8, None, noise=("poisson", 1e4), jitter=0.05, n_iter=20,
+                   seeds=(7, 8, 9))
+    op = misr.Operator(ctx, prob.H, prob.W, prob.s, prob.shifts, prob.psf)
+    y16, x16 = to_dev(_f32(prob.y), dt), to_dev(_f32(prob.x0), dt)
+    y32, x32 = y16.float(), x16.float()
+    op.scg_solve(y32, x32, misr.default_params(n_iter=20))
+    op.scg_solve(y16, x16, misr.default_params(n_iter=20))
+    assert torch.equal(x16, x32.to(dt))
+
+
+@pytest.mark.parametrize("dtype_name,x_rounding", [("float16", 0), ("float16", 1),
+                                                   ("bfloat16", 0), ("bfloat16", 1)])
+def test_lowp_iterate_in_storage(misr, ctx, dtype_name, x_rounding):
+    """x_work = 1 keeps the iterate itself in 16 bits (x updates rounded on
+    store, the trial point rounded the same way).  Steps below half a unit in
+    the last place are lost, so the solve stalls short of the FP64 result;
+    the error is reported, and bounded only loosely."""
+    import torch
+    dt = getattr(torch, dtype_name)
+    prob = problem(48, 3, 1.0, 7, noise=("poisson", 1e4), jitter=0.05, n_iter=60,
+                   seeds=(3, 4, 5))
+    x_o, _, _ = _oracle_solve(prob, 60)
+    x_g, its, info = _gpu_solve(misr, ctx, prob, 60, dtype=dt, x_work=1, x_rounding=x_rounding)
+    err = rel_l2(x_g, x_o)
+    print(f"{dtype_name} iterate in storage ({'stochastic' if x_rounding else 'nearest'}): "
+          f"rel-L2 {err:.3e}, PSNR vs oracle {psnr(x_g, x_o):.2f} dB, "
+          f"{info['n_success']} accepted")
+    assert np.isfinite(x_g).all() and info["stop"] == 0
+    assert err <= 0.2
 
 
 def test_batch_equals_solo_and_oracle(misr, ctx):

@@ -180,3 +180,28 @@ def test_tiled_request_in_mix(misr, ctx, probs):
     assert torch.equal(o1, solo1)
     assert torch.equal(ot, x_plain), f"max diff {float((ot - x_plain).abs().max())}"
     srv.close()
+
+
+def test_bf16_requests_match_plain(misr, ctx, probs):
+    """bf16 frames and image with the FP32 iterate (staged through library
+    buffers, rounded once at the end): served equals plain, bit for bit."""
+    import torch
+    srv = misr.Server(ctx, hbm_budget_bytes=1 << 30)
+    outs, refs, ids = [], [], []
+    for i in (0, 1):
+        p, n = probs[i], SPECS[i][3]
+        op = misr.Operator(ctx, p.H, p.W, p.s, p.shifts, p.psf)
+        y = to_dev(_f32(p.y), torch.bfloat16)
+        xr = to_dev(_f32(p.x0), torch.bfloat16)
+        op.scg_solve(y, xr, misr.default_params(n_iter=n))
+        refs.append(xr)
+        x0 = to_dev(_f32(p.x0), torch.bfloat16)
+        out = torch.empty_like(x0)
+        outs.append(out)
+        ids.append(srv.submit(p.H, p.W, p.s, p.shifts, p.psf, y, x0, out,
+                              misr.default_params(n_iter=n)))
+    for rid, out, ref in zip(ids, outs, refs):
+        assert srv.wait(rid, 60_000_000) == misr.OK
+        assert srv.poll(rid)[0] == misr.REQ_DONE
+        assert torch.equal(out, ref)
+    srv.close()
