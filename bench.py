@@ -1,6 +1,6 @@
 """Benchmark of the MISR SCG hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload plain2048]
 
 Workload (one step = one whole solve): 4 synthetic LR frames of 1024x1024
 (x2 super-resolution to 2048x2048 HR), shifts on the {0, 1/2}^2 LR-pixel grid
@@ -220,6 +220,98 @@ def cpu_baseline(y_np, shifts, psf, x0_np, budget_s: float = 15.0):
                        f"({t_pass:.2f} s/pass), extrapolated to {N_ITER} passes")
 
 
+# ------------------------------------------------------- other workloads
+def _base_line(metric_value, K, Wm, dt, dtype, config):
+    return {"metric": "HR Mpixel/s at fixed SCG iters + p50/p99 latency, served vs plain, 1 GPU",
+            "value": metric_value, "unit": "HR Mpixel/s", "n_gpus": 1, "steps": K,
+            "warmup": Wm, "ms_per_step": dt / K * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": config}
+
+
+def bench_batched(misr, ctx, K, Wm, n_proj=64, n_iter=60, seed=11):
+    """64 independent projections advanced together (one work list, shared
+    launches, one captured graph): LR sizes uniform in {512,...,2048}^2,
+    scale 2 (4 frames) or 3 (9 frames on the 3x3 grid), 60 SCG passes."""
+    import torch
+    rng = np.random.default_rng(seed)
+    geoms = [(int(rng.choice(SERVE_SIZES)), int(rng.choice([2, 3]))) for _ in range(n_proj)]
+    probs = {g: _serve_problem(misr, ctx, g[0], g[1], 200 + i)
+             for i, g in enumerate(sorted(set(geoms)))}
+    ops = [probs[g]["op"] for g in geoms]
+    ys = [probs[g]["y"].clone() for g in geoms]     # every projection its own frames
+    prms = [misr.default_params(n_iter=n_iter) for _ in geoms]
+    hr_px = sum(g[0] * g[0] * g[1] * g[1] for g in geoms)
+    sets = [[probs[g]["x0"].clone() for g in geoms] for _ in range(K + Wm)]
+    torch.cuda.synchronize()
+    for i in range(Wm):
+        misr.scg_solve_batch(ops, ys, sets[i], prms, trace=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(Wm, Wm + K):
+        misr.scg_solve_batch(ops, ys, sets[i], prms, trace=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = _base_line(hr_px * K / dt / 1e6, K, Wm, dt, "f32",
+                     {"workload": f"batched64: {n_proj} projections, LR {{512..2048}}^2, "
+                                  f"scale 2 (4 frames) or 3 (9 frames), {n_iter} SCG passes, "
+                                  f"one shared work list", "hr_pixels": hr_px,
+                      "scg_passes": n_iter, "parallelism": "1 GPU"})
+    out["scg_passes_per_s"] = n_iter * K / dt
+    return out
+
+
+def bench_precision(misr, ctx, K, Wm, L=2048, s=3, n_iter=100):
+    """One 2048^2-LR projection, 9 frames at scale 3 (HR 6144^2), PSF sigma 1.0,
+    100 SCG passes, frames and image stored in FP32, FP16 and BF16 (FP32
+    iterate, x_work = 0) and in 16 bits with the iterate itself 16-bit
+    (x_work = 1).  Each mode's result is compared with the FP32 solve (the
+    FP32 path is checked against the FP64 oracle at sizes the oracle
+    finishes)."""
+    import torch
+    from paper_2108_04315_amd import synth
+    Hh = L * s
+    shifts = synth.frame_shifts(s, s * s, 0.05, 5)
+    psf = synth.psf_taps(1.0)
+    op = misr.Operator(ctx, Hh, Hh, s, shifts, psf)
+    clean = op.forward(torch.from_numpy(synth.phantom(Hh, Hh, 5)).float().cuda())
+    torch.cuda.synchronize()
+    y_np = synth.add_poisson_noise(clean.double().cpu().numpy(), 1e4, 6)
+    y32 = torch.from_numpy(y_np).float().cuda()
+    x032 = torch.from_numpy(synth.bicubic_upsample(y_np[0], s)).float().cuda()
+    modes = [("f32", torch.float32, 0), ("f16", torch.float16, 0), ("bf16", torch.bfloat16, 0),
+             ("f16-iterate16", torch.float16, 1), ("bf16-iterate16", torch.bfloat16, 1)]
+    res, x_ref, dt_f32 = {}, None, None
+    for name, dt, xw in modes:
+        y = y32.to(dt)
+        prm = misr.default_params(n_iter=n_iter, x_work=xw)
+        xs = [x032.to(dt) for _ in range(K + Wm)]
+        torch.cuda.synchronize()
+        for i in range(Wm):
+            op.scg_solve(y, xs[i], prm, trace=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(Wm, Wm + K):
+            op.scg_solve(y, xs[i], prm, trace=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        x = xs[-1].double()
+        if x_ref is None:
+            x_ref, dt_f32 = x, el
+        err = float(torch.linalg.vector_norm(x - x_ref) / torch.linalg.vector_norm(x_ref))
+        mse = float(torch.mean((x - x_ref) ** 2))
+        res[name] = {"hr_mpx_per_s": Hh * Hh * K / el / 1e6,
+                     "rel_l2_vs_f32_solve": err,
+                     "psnr_vs_f32_solve_db": (10 * np.log10(1.0 / mse)) if mse > 0 else None}
+    out = _base_line(Hh * Hh * K / dt_f32 / 1e6, K, Wm, dt_f32, "f32",
+                     {"workload": f"precision6144: 9 LR frames {L}x{L} -> {Hh}x{Hh} HR (x3), "
+                                  f"PSF sigma 1.0, {n_iter} SCG passes; storage modes",
+                      "hr": [Hh, Hh], "scale": s, "frames": s * s, "scg_passes": n_iter,
+                      "parallelism": "1 GPU"})
+    out["modes"] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +319,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--workload", default="plain2048",
+                    choices=["plain2048", "batched64", "precision6144"],
+                    help="plain2048 (default: the headline line), batched64, precision6144")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -241,9 +336,13 @@ def main():
     from paper_2108_04315_amd import misr
 
     ctx = misr.Context(0)
+    K, Wm = max(1, args.steps), max(0, args.warmup)
+    if args.workload != "plain2048":
+        fn = bench_batched if args.workload == "batched64" else bench_precision
+        print(json.dumps(fn(misr, ctx, K, Wm)), flush=True)
+        return
     op, shifts, psf, y, x0, y_np = make_inputs(misr, ctx)
     prm = misr.default_params(n_iter=N_ITER)
-    K, Wm = max(1, args.steps), max(0, args.warmup)
     xs = [x0.clone() for _ in range(K + Wm)]
     torch.cuda.synchronize()
     for i in range(Wm):

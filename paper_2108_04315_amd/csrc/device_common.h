@@ -27,6 +27,12 @@ FI int pmod(int a, int b) {
 }
 FI int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 FI float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// v from the lane below: lane i receives lane i-1's value, lane 0 receives 0
+// (a DPP wave shift right by one, full rate, no LDS traffic).
+FI float wave_shr1(float v) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
 
 template <class T>
 FI const AS4 T *cst(const T *p) { return (const AS4 T *)p; }

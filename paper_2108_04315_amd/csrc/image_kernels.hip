@@ -18,6 +18,8 @@
 // wave-uniform (scalar) loads: every pass maps one weight row to one wave.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 
 #ifndef MISR_SCALE
@@ -250,13 +252,18 @@ __device__ constexpr int kDY[8] = {0, 0, 1, 1, 1, 2, 2, 2};
 
 // BTV prior on the window, swept left to right over the wave's CV columns
 // with lanes on rows (u = lane - 2, two rows of halo).  Each pair (i, i+d)
-// is evaluated once, by the lane of i; the lane of i+d takes its share from
-// its running history (same row) or by a lane shift (rows below).  The
-// gradient accumulates into gs (LDS, row stride GP).
+// is evaluated once, by the lane of i; the pixel i+d takes the share back
+// from the same lane's history (same row, dx columns earlier) or, for rows
+// below, from the lane dy above through DPP lane shifts of the per-dy sums.
+// The 3-column window and the 2-step history rotate through three register
+// slots, so the loop is unrolled by three and nothing is moved.  Steps 0
+// and 1 (columns cv0-2, cv0-1) only fill the history.  The gradient
+// accumulates into gs (LDS, row stride GP).
 template <int S, int L, bool EPS0, bool CHECK>
 FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, int U0, int V0,
                   int H, int W, int th_own, int tw_own, double &e_reg) {
     using T = Tile<S, L>;
+    constexpr int NSTEP = T::CV + 2;
     const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
     const int u = lane - 2;
     const int cv0 = wv * T::CV;
@@ -269,35 +276,36 @@ FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, 
     bool rok[3];
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) rok[dy] = !CHECK || (U >= 0 && U + dy < H);
-    const float *base = xs + (T::EXT + ur) * T::WCP + T::EXT;
-    float *grow = gs + max(u, 0) * T::GP;
-    float win[3][3];   // win[dy][dx] = x(u + dy, v + dx)
+    const float *base = xs + (T::EXT + ur) * T::WCP + T::EXT + cv0 - 2;
+    float *grow = gs + max(u, 0) * T::GP + cv0 - 2;
+    float win[3][3];    // win[dy][slot]: window column c (from cv0 - 2) sits in slot (c + 1) % 3
+    float hist[3][8];   // hist[slot][d]: the step's lambda gamma_d psi(z_d), slot t % 3
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
+    for (int dy = 0; dy < 3; ++dy) {
+        win[dy][1] = base[dy * T::WCP + 0];
+        win[dy][2] = base[dy * T::WCP + 1];
+    }
 #pragma unroll
-        for (int dx = 0; dx < 2; ++dx) win[dy][dx + 1] = base[dy * T::WCP + cv0 - 2 + dx];
-    float h1[8], h2[8];
+    for (int q = 0; q < 3; ++q)
 #pragma unroll
-    for (int d = 0; d < 8; ++d) h1[d] = h2[d] = 0.f;
+        for (int d = 0; d < 8; ++d) hist[q][d] = 0.f;
     double eacc = 0.0;
-#pragma unroll 1
-    for (int vs = -2; vs < T::CV; ++vs) {
-        const int v = cv0 + vs, V = V0 + v;
+    // step t handles column cv0 + t - 2 and loads window column t + 2 (slot t % 3)
+    auto step = [&](auto slot_c, auto out_c, int t) {
+        constexpr int Q = decltype(slot_c)::value;
+        constexpr bool OUT = decltype(out_c)::value;
 #pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-            win[dy][0] = win[dy][1];
-            win[dy][1] = win[dy][2];
-            win[dy][2] = base[dy * T::WCP + v + 2];
-        }
+        for (int dy = 0; dy < 3; ++dy) win[dy][Q] = base[dy * T::WCP + t + 2];
+        const int v = cv0 + t - 2, V = V0 + v;
         bool cok[3];
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) cok[dx] = !CHECK || (V >= 0 && V + dx < W);
-        float cur[8];
+        const float x0 = win[0][(Q + 1) % 3];
         float eb = 0.f;
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const int dx = kDX[d], dy = kDY[d];
-            const float z = win[0][0] - win[dy][dx];
+            const float z = x0 - win[dy][(Q + 1 + dx) % 3];
             float ps, ph;
             if (EPS0) {
                 ps = (z > 0.f) ? 1.f : ((z < 0.f) ? -1.f : 0.f);
@@ -310,43 +318,59 @@ FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, 
             }
             if (CHECK) {
                 const bool valid = rok[dy] && cok[dx];
-                cur[d] = valid ? gam[d] * ps : 0.f;
+                hist[Q][d] = valid ? gam[d] * ps : 0.f;
                 eb = fmaf(valid ? gam[d] : 0.f, ph, eb);
             } else {
-                cur[d] = gam[d] * ps;
+                hist[Q][d] = gam[d] * ps;
                 eb = fmaf(gam[d], ph, eb);
             }
         }
-        float gsum = 0.f;
+        if (OUT) {
+            // shares of the pairs (i - d, i): from dx steps back, dy lanes up
+            float own = 0.f, back[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const int dx = kDX[d], dy = kDY[d];
-            const float src = (dx == 0) ? cur[d] : ((dx == 1) ? h1[d] : h2[d]);
-            const float bk = (dy == 0) ? src : __shfl_up(src, dy, 64);
-            gsum += cur[d] - bk;
-        }
-        if (vs >= 0) {
-            if (row_tile) grow[v] += gsum;
+            for (int d = 0; d < 8; ++d) {
+                const int dx = kDX[d], dy = kDY[d];
+                own += hist[Q][d];
+                back[dy] += hist[(Q + 3 - dx) % 3][d];
+            }
+            const float up = wave_shr1(back[1] + wave_shr1(back[2]));
+            const float gsum = own - back[0] - up;
+            if (row_tile) grow[t] += gsum;
             if (own_row && (!CHECK || v < tw_own)) eacc += (double)eb;
         }
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            h2[d] = h1[d];
-            h1[d] = cur[d];
-        }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using F = std::false_type;
+    using Tr = std::true_type;
+    step(I0{}, F{}, 0);
+    step(I1{}, F{}, 1);
+    step(I2{}, Tr{}, 2);
+#pragma unroll 1
+    for (int t = 3; t + 2 < NSTEP; t += 3) {
+        step(I0{}, Tr{}, t);
+        step(I1{}, Tr{}, t + 1);
+        step(I2{}, Tr{}, t + 2);
     }
+    constexpr int REM = NSTEP % 3;   // steps after the last full group of three
+    if constexpr (REM >= 1) step(I0{}, Tr{}, NSTEP - REM);
+    if constexpr (REM >= 2) step(I1{}, Tr{}, NSTEP - REM + 1);
     e_reg += eacc;
 }
 
 // Curvature of the prior along p (Moller's step 2 without forming x + sk p):
 // sum over owned pairs of gamma q^2 Q(z, sk q), z, q the pair differences of
 // x and p.  Same sweep as btv_sweep (lanes on rows, waves on CV columns,
-// sliding 3x3 windows); [ru0,ru1) x [rv0,rv1) is the owned part of the tile.
+// 3-slot rotating windows, unrolled by three); [ru0,ru1) x [rv0,rv1) is the
+// owned part of the tile.
 template <int S, int L, bool CHECK>
 FI void curv_sweep(const float *xs, const float *ps, const float (&gam)[8], float eps, float sk,
                    int U0, int V0, int H, int W, int ru0, int ru1, int rv0, int rv1,
                    double &dreg) {
     using T = Tile<S, L>;
+    constexpr int NSTEP = T::CV;
     const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
     const int u = lane;
     const int cv0 = wv * T::CV;
@@ -357,47 +381,80 @@ FI void curv_sweep(const float *xs, const float *ps, const float (&gam)[8], floa
     bool rok[3];
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) rok[dy] = !CHECK || (U + dy < H);
-    const int off = (T::EXT + ur) * T::WCP + T::EXT;
-    float wx[3][3], wp[3][3];
+    const int off = (T::EXT + ur) * T::WCP + T::EXT + cv0;
+    float wx[3][3], wp[3][3];   // [dy][slot]: window column c in slot c % 3
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
         for (int dx = 0; dx < 2; ++dx) {
-            wx[dy][dx + 1] = xs[off + dy * T::WCP + cv0 + dx];
-            wp[dy][dx + 1] = ps[off + dy * T::WCP + cv0 + dx];
+            wx[dy][dx] = xs[off + dy * T::WCP + dx];
+            wp[dy][dx] = ps[off + dy * T::WCP + dx];
         }
     double acc = 0.0;
-#pragma unroll 2
-    for (int vs = 0; vs < T::CV; ++vs) {
-        const int v = cv0 + vs, V = V0 + v;
+    // step t handles column cv0 + t and loads window column t + 2 (slot (t+2) % 3)
+    auto step = [&](auto slot_c, int t) {
+        constexpr int Q = decltype(slot_c)::value;   // slot of column t
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
-            wx[dy][0] = wx[dy][1];
-            wx[dy][1] = wx[dy][2];
-            wx[dy][2] = xs[off + dy * T::WCP + v + 2];
-            wp[dy][0] = wp[dy][1];
-            wp[dy][1] = wp[dy][2];
-            wp[dy][2] = ps[off + dy * T::WCP + v + 2];
+            wx[dy][(Q + 2) % 3] = xs[off + dy * T::WCP + t + 2];
+            wp[dy][(Q + 2) % 3] = ps[off + dy * T::WCP + t + 2];
         }
+        const int v = cv0 + t, V = V0 + v;
         float a = 0.f;
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const int dx = kDX[d], dy = kDY[d];
-            const float z = wx[0][0] - wx[dy][dx];
-            const float qd = wp[0][0] - wp[dy][dx];
-            const float t = gam[d] * qd * qd * psi_quot(z, sk * qd, eps, e2);
+            const float z = wx[0][Q] - wx[dy][(Q + dx) % 3];
+            const float qd = wp[0][Q] - wp[dy][(Q + dx) % 3];
+            const float tq = gam[d] * qd * qd * psi_quot(z, sk * qd, eps, e2);
             if (CHECK)
-                a += (rok[dy] && V + dx < W) ? t : 0.f;
+                a += (rok[dy] && V + dx < W) ? tq : 0.f;
             else
-                a += t;
+                a += tq;
         }
         const bool own = own_row && (!CHECK || (v >= rv0 && v < rv1));
         acc += own ? (double)a : 0.0;
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+#pragma unroll 1
+    for (int t = 0; t + 2 < NSTEP; t += 3) {
+        step(I0{}, t);
+        step(I1{}, t + 1);
+        step(I2{}, t + 2);
     }
+    constexpr int REM = NSTEP % 3;
+    if constexpr (REM >= 1) step(I0{}, NSTEP - REM);
+    if constexpr (REM >= 2) step(I1{}, NSTEP - REM + 1);
     dreg += acc;
 }
 
 // --------------------------------------------------------------- the tiles
+// Window element s of this thread (q = tid + s * kNTI, row-major over the
+// WR x WC window whose corner is (u0 - EXT, v0 - EXT) in view coordinates):
+// its LDS slot (-1 past the window), a source index clamped into the view so
+// that every load is issued unconditionally, and whether the element is
+// inside the view (outside it reads as zero).
+struct StageAt {
+    int lds, ub, vb;
+    i64 idx;
+    bool in;
+};
+template <class T>
+FI StageAt stage_at(int tid, int s, int u0, int v0, int Hb, int Wb, int ld) {
+    const int q = tid + s * kNTI;
+    const int qq = min(q, T::WR * T::WC - 1);
+    const int r = qq / T::WC, c = qq - r * T::WC;
+    StageAt a;
+    a.ub = u0 - T::EXT + r;
+    a.vb = v0 - T::EXT + c;
+    a.in = q < T::WR * T::WC && a.ub >= 0 && a.ub < Hb && a.vb >= 0 && a.vb < Wb;
+    a.idx = (i64)min(max(a.ub, 0), Hb - 1) * ld + min(max(a.vb, 0), Wb - 1);
+    a.lds = (q < T::WR * T::WC) ? r * T::WCP + c : -1;
+    return a;
+}
+
 struct TileOrigin {
     int u0, v0, u1, v1, U0, V0;
 };
@@ -426,7 +483,10 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     using raw = typename ST::raw;
     using rawy = typename SY::raw;
     const AS4 OpDev &op = *cst(P.op);
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    // per-tile index arithmetic is recomputed rather than kept live across the
+    // work-list loop (where it would be spilled)
+    asm volatile("" : "+v"(tid));
     const TileOrigin o = tile_origin<S, L>(P, ty, tx);
     const int H = op.H, W = op.W, h = H / S, w = W / S, K = op.K;
     float *xs = sm;
@@ -442,31 +502,34 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     const unsigned seed = st.rseed;
     const AS4 OpDev &opg = op;
     const i64 Wg = opg.W;
-    {
-        float val[T::NSTAGE];
+    // window of x_t into LDS: every load first (clamped, unconditional), then
+    // the arithmetic, so that the loads are in flight together
+    if (mode == 1) {
+        float xr[T::NSTAGE], pr[T::NSTAGE];
 #pragma unroll
         for (int s = 0; s < T::NSTAGE; ++s) {
-            const int q = tid + s * kNTI;
-            const int r = q / T::WC, c = q - r * T::WC;
-            const int ub = o.u0 - T::EXT + r, vb = o.v0 - T::EXT + c;
-            val[s] = 0.f;
-            if (q < T::WR * T::WC && ub >= 0 && ub < Hb && vb >= 0 && vb < Wb) {
-                const i64 idx = (i64)ub * ld + vb;
-                const float xv = ST::ld(xb, idx);
-                if (mode == 1) {
-                    const float v = fmaf(af, pb[idx], xv);
-                    val[s] = sr ? ST::rnd_sr(v, pixel_hash((i64)(P.gy0 + ub) * Wg + P.gx0 + vb, seed))
-                                : ST::rnd(v);
-                } else {
-                    val[s] = xv;
-                }
-            }
+            const StageAt a = stage_at<T>(tid, s, o.u0, o.v0, Hb, Wb, ld);
+            xr[s] = ST::ld(xb, a.idx);
+            pr[s] = pb[a.idx];
         }
 #pragma unroll
         for (int s = 0; s < T::NSTAGE; ++s) {
-            const int q = tid + s * kNTI;
-            const int r = q / T::WC, c = q - r * T::WC;
-            if (q < T::WR * T::WC) xs[r * T::WCP + c] = val[s];
+            const StageAt a = stage_at<T>(tid, s, o.u0, o.v0, Hb, Wb, ld);
+            const float v = fmaf(af, pr[s], xr[s]);
+            const float vr =
+                sr ? ST::rnd_sr(v, pixel_hash((i64)(P.gy0 + a.ub) * Wg + P.gx0 + a.vb, seed))
+                   : ST::rnd(v);
+            if (a.lds >= 0) xs[a.lds] = a.in ? vr : 0.f;
+        }
+    } else {
+        float xr[T::NSTAGE];
+#pragma unroll
+        for (int s = 0; s < T::NSTAGE; ++s)
+            xr[s] = ST::ld(xb, stage_at<T>(tid, s, o.u0, o.v0, Hb, Wb, ld).idx);
+#pragma unroll
+        for (int s = 0; s < T::NSTAGE; ++s) {
+            const StageAt a = stage_at<T>(tid, s, o.u0, o.v0, Hb, Wb, ld);
+            if (a.lds >= 0) xs[a.lds] = a.in ? xr[s] : 0.f;
         }
     }
     float gacc[T::CV];
@@ -555,17 +618,34 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     AS1 float *gout = glbw(P.g[cur ^ 1]);
     const AS1 float *gk = glb(P.g[cur]);
     AS1 float *pz = glbw(P.p[xc]);
-    for (int q = tid; q < T::TH * T::TW; q += kNTI) {
-        const int uu = q / T::TW, vv = q - uu * T::TW;
-        if (o.u0 + uu >= o.u1 || o.v0 + vv >= o.v1) continue;
-        const float gv = gs[uu * T::GP + vv];
-        const i64 idx = (i64)(o.u0 + uu) * ld + o.v0 + vv;
-        gout[idx] = gv;
-        gg += (double)gv * (double)gv;
-        if (mode == 0) pz[idx] = 0.f;   // start direction buffer for the init pass
+    // owned gradient out, with its inner products (loads first, as above)
+    constexpr int NOUT = (T::TH * T::TW + kNTI - 1) / kNTI;
+    float gvs[NOUT], gkv[NOUT], pv[NOUT];
+    i64 oidx[NOUT];
+    bool ook[NOUT];
+#pragma unroll
+    for (int j = 0; j < NOUT; ++j) {
+        const int q = tid + j * kNTI;
+        const int qq = min(q, T::TH * T::TW - 1);
+        const int uu = qq / T::TW, vv = qq - uu * T::TW;
+        ook[j] = q < T::TH * T::TW && o.u0 + uu < o.u1 && o.v0 + vv < o.v1;
+        oidx[j] = (i64)min(o.u0 + uu, o.u1 - 1) * ld + min(o.v0 + vv, o.v1 - 1);
+        gvs[j] = gs[uu * T::GP + vv];
         if (mode == 1) {
-            ggk += (double)gv * (double)gk[idx];
-            gp += (double)gv * (double)pb[idx];
+            gkv[j] = gk[oidx[j]];
+            pv[j] = pb[oidx[j]];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NOUT; ++j) {
+        if (!ook[j]) continue;
+        const float gv = gvs[j];
+        gout[oidx[j]] = gv;
+        gg += (double)gv * (double)gv;
+        if (mode == 0) pz[oidx[j]] = 0.f;   // start direction buffer for the init pass
+        if (mode == 1) {
+            ggk += (double)gv * (double)gkv[j];
+            gp += (double)gv * (double)pv[j];
         }
     }
     double v[5] = {e_data, e_reg, gg, ggk, gp};
@@ -583,7 +663,10 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
     using T = Tile<S, L>;
     using raw = typename ST::raw;
     const AS4 OpDev &op = *cst(P.op);
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    // per-tile index arithmetic is recomputed rather than kept live across the
+    // work-list loop (where it would be spilled)
+    asm volatile("" : "+v"(tid));
     // update tiles cover the update rectangle (owned plus halo); reductions
     // count only their intersection with the owned rectangle [ou0,ou1) x [ov0,ov1)
     TileOrigin o;
@@ -613,38 +696,35 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
     const i64 Wg = W;
     double pp = 0.0, pr = 0.0;
     {
-        float xv[T::NSTAGE], pv[T::NSTAGE];
+        // every load first (clamped, unconditional), then the update
+        float xr[T::NSTAGE], pr0[T::NSTAGE], gr[T::NSTAGE];
 #pragma unroll
         for (int s = 0; s < T::NSTAGE; ++s) {
-            const int q = tid + s * kNTI;
-            const int r = q / T::WC, c = q - r * T::WC;
-            const int ub = o.u0 - T::EXT + r, vb = o.v0 - T::EXT + c;
-            xv[s] = 0.f;
-            pv[s] = 0.f;
-            if (q < T::WR * T::WC && ub >= 0 && ub < Hb && vb >= 0 && vb < Wb) {
-                const i64 idx = (i64)ub * ld + vb;
-                const float p0 = pb[idx], g0 = gt[idx];
-                const float v = fmaf(af, p0, ST::ld(xb, idx));
-                xv[s] = sr ? ST::rnd_sr(v, pixel_hash((i64)(P.gy0 + ub) * Wg + P.gx0 + vb, seed))
-                           : ST::rnd(v);
-                pv[s] = fmaf(bf, p0, -g0);
-                if (ub >= o.u0 && ub < o.u1 && vb >= o.v0 && vb < o.v1) {
-                    ST::st(xo, idx, xv[s]);
-                    po[idx] = pv[s];
-                    if (ub >= ou0 && ub < ou1 && vb >= ov0 && vb < ov1) {
-                        pp += (double)pv[s] * (double)pv[s];
-                        pr -= (double)pv[s] * (double)g0;
-                    }
-                }
-            }
+            const StageAt a = stage_at<T>(tid, s, o.u0, o.v0, Hb, Wb, ld);
+            xr[s] = ST::ld(xb, a.idx);
+            pr0[s] = pb[a.idx];
+            gr[s] = gt[a.idx];
         }
 #pragma unroll
         for (int s = 0; s < T::NSTAGE; ++s) {
-            const int q = tid + s * kNTI;
-            const int r = q / T::WC, c = q - r * T::WC;
-            if (q < T::WR * T::WC) {
-                xs[r * T::WCP + c] = xv[s];
-                ps[r * T::WCP + c] = pv[s];
+            const StageAt a = stage_at<T>(tid, s, o.u0, o.v0, Hb, Wb, ld);
+            const float v = fmaf(af, pr0[s], xr[s]);
+            float xv = sr ? ST::rnd_sr(v, pixel_hash((i64)(P.gy0 + a.ub) * Wg + P.gx0 + a.vb, seed))
+                          : ST::rnd(v);
+            float pv = fmaf(bf, pr0[s], -gr[s]);
+            xv = a.in ? xv : 0.f;
+            pv = a.in ? pv : 0.f;
+            if (a.in && a.ub >= o.u0 && a.ub < o.u1 && a.vb >= o.v0 && a.vb < o.v1) {
+                ST::st(xo, a.idx, xv);
+                po[a.idx] = pv;
+                if (a.ub >= ou0 && a.ub < ou1 && a.vb >= ov0 && a.vb < ov1) {
+                    pp += (double)pv * (double)pv;
+                    pr -= (double)pv * (double)gr[s];
+                }
+            }
+            if (a.lds >= 0) {
+                xs[a.lds] = xv;
+                ps[a.lds] = pv;
             }
         }
     }
@@ -693,7 +773,10 @@ FI void tile_forward(const AS4 Proj &P, int ty, int tx, void *yout, float *sm) {
     using T = Tile<S, L>;
     using raw = typename ST::raw;
     const AS4 OpDev &op = *cst(P.op);
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    // per-tile index arithmetic is recomputed rather than kept live across the
+    // work-list loop (where it would be spilled)
+    asm volatile("" : "+v"(tid));
     const TileOrigin o = tile_origin<S, L>(P, ty, tx);
     const int h = op.H / S, w = op.W / S, K = op.K;
     float *xs = sm;
@@ -734,7 +817,10 @@ FI void tile_adjoint(const AS4 Proj &P, int ty, int tx, const void *r, float *xo
     using T = Tile<S, L>;
     using raw = typename ST::raw;
     const AS4 OpDev &op = *cst(P.op);
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    // per-tile index arithmetic is recomputed rather than kept live across the
+    // work-list loop (where it would be spilled)
+    asm volatile("" : "+v"(tid));
     const TileOrigin o = tile_origin<S, L>(P, ty, tx);
     const int h = op.H / S, w = op.W / S, K = op.K;
     float *gs = sm;
