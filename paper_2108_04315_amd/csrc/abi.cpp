@@ -373,6 +373,8 @@ hipError_t misr::ensure_tiles(const misr_op *op, const misr_params &p, TileSet &
             if ((int)ts.bufs.size() <= t) {
                 ts.bufs.emplace_back(new SolveBufs());
                 ts.x0.emplace_back(new DevMem());
+                ts.bufs.back()->set_pool(ts.pool);
+                ts.x0.back()->pool = ts.pool;
             }
             hipError_t e = ts.bufs[t]->ensure(n, es);
             if (e == hipSuccess) e = ts.x0[t]->ensure(n * es);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <iterator>
+#include <map>
 #include <cstdarg>
 #include <memory>
 #include <mutex>
@@ -53,23 +55,72 @@ misr_status hip_fail(hipError_t e, const char *what);
 size_t dtype_size(misr_dtype dt);
 
 // A device allocation owned by the library.
+// Cache of device blocks for a stream-ordered user (the server): blocks are
+// handed back instead of freed, so that requests of recurring sizes reuse
+// them without hipMalloc / hipFree (hipFree waits for the whole device).
+// Reuse is safe because every user of a pool enqueues on one stream.
+struct MemPool {
+    std::multimap<size_t, void *> free_;
+    size_t held = 0;
+    size_t limit = 0;   // bytes kept beyond which the largest blocks are freed
+    static size_t round(size_t n) { return ((n ? n : 16) + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1); }
+    hipError_t get(void **p, size_t n) {
+        n = round(n);
+        auto it = free_.find(n);
+        if (it != free_.end()) {
+            *p = it->second;
+            free_.erase(it);
+            held -= n;
+            return hipSuccess;
+        }
+        hipError_t e = hipMalloc(p, n);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trim(0);
+            e = hipMalloc(p, n);
+        }
+        return e;
+    }
+    void put(void *p, size_t n) {
+        n = round(n);
+        free_.emplace(n, p);
+        held += n;
+        if (held > limit) trim(limit);
+    }
+    void trim(size_t to) {
+        while (held > to && !free_.empty()) {
+            auto it = std::prev(free_.end());
+            (void)hipFree(it->second);
+            held -= it->first;
+            free_.erase(it);
+        }
+    }
+    ~MemPool() { trim(0); }
+};
+
 struct DevMem {
     void *p = nullptr;
     size_t n = 0;
+    MemPool *pool = nullptr;   // blocks come from / go back to this cache if set
     DevMem() = default;
     DevMem(const DevMem &) = delete;
     DevMem &operator=(const DevMem &) = delete;
     ~DevMem() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (pool)
+                pool->put(p, n);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
         n = 0;
     }
     hipError_t ensure(size_t bytes) {
         if (bytes <= n && p) return hipSuccess;
         release();
-        hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
-        if (e == hipSuccess) n = bytes;
+        hipError_t e = pool ? pool->get(&p, bytes) : hipMalloc(&p, bytes ? bytes : 16);
+        if (e == hipSuccess) n = pool ? MemPool::round(bytes) : bytes;
         else p = nullptr;
         return e;
     }
@@ -124,6 +175,7 @@ inline size_t view_esize(const misr_params &p) { return view_stype(p) == ST_F32 
 // iterate).
 struct SolveBufs {
     DevMem x1, p0, p1, g0, g1, x0w;
+    void set_pool(MemPool *pl) { x1.pool = p0.pool = p1.pool = g0.pool = g1.pool = x0w.pool = pl; }
     hipError_t ensure(long long n, size_t es) {
         hipError_t e;
         if ((e = x1.ensure(n * es)) != hipSuccess) return e;
@@ -144,6 +196,7 @@ struct SolveBufs {
 struct TileSet {
     int tile_lr = 0, halo_lr = 0;
     size_t es = 0;
+    MemPool *pool = nullptr;   // for the tile buffers, if set
     std::vector<std::unique_ptr<SolveBufs>> bufs;
     std::vector<std::unique_ptr<DevMem>> x0;
 };

@@ -64,6 +64,33 @@ struct SReq {
     const void *ydev_ptr = nullptr;
     ScgState *st_dev = nullptr;
     IterRec *trace_dev = nullptr;
+    ScgState *h_st = nullptr;     // pinned host slot: initial state up, final state down
+    // outcome for a request retired without a result (cancelled, failed set-up)
+    misr_req_state drop_state = MISR_REQ_FAILED;
+    misr_status drop_code = MISR_E_HIP;
+    void set_pool(MemPool *pl) {
+        xwork.pool = ydev.pool = dstate.pool = pl;
+        bufs.set_pool(pl);
+        tiles.pool = pl;
+    }
+};
+
+// Pinned host staging buffer (grown on demand).
+struct Pinned {
+    void *h = nullptr;
+    size_t cap = 0;
+    ~Pinned() {
+        if (h) (void)hipHostFree(h);
+    }
+    bool ensure(size_t n) {
+        if (n <= cap && h) return true;
+        if (h) (void)hipHostFree(h);
+        h = nullptr;
+        cap = 0;
+        if (hipHostMalloc(&h, n, hipHostMallocDefault) != hipSuccess) return false;
+        cap = n;
+        return true;
+    }
 };
 
 }  // namespace
@@ -97,12 +124,32 @@ struct misr_server {
         std::vector<int> counts;
         DevMem projs, items, items_u, counts_d, refs, drefs_new, partials, partials_u, halos,
             halos_new_d;
+        Pinned stage;                        // the arrays above, packed for upload
         int nc() const { return (int)pl.classes.size(); }
         const int *cnt(int off) const { return counts_d.as<int>() + off; }
-    } all;
+    };
+    // A cycle: the passes enqueued for the admitted solves in one scheduler
+    // step.  Two cycles alternate: while one runs on the device the scheduler
+    // builds and enqueues the next, then retires the first; so the device
+    // does not idle at cycle boundaries and a cycle's buffers are rewritten
+    // only after it has completed.
+    struct Cycle {
+        List list;
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;   // start and end of its work
+        bool pending = false;
+        hipError_t err = hipSuccess;
+        int n_ep = 0;
+        double mpx = 0;                            // HR Mpx advanced per pass
+        std::vector<SReq *> done, dropped;
+    } cyc[2];
+    MemPool pool;                 // request buffers, reused across requests
+    Pinned slots_mem;             // pinned ScgState slots, one per admitted request
+    std::vector<ScgState *> free_slots;
+    double us_per_mpx_pass = 40.0;   // running estimate of the device time per pass
     std::string last_error;
 
     void run();
+    void retire(Cycle &C);
     bool setup(SReq *r);
     void release(SReq *r);
     void build_list(List &L, const std::vector<SReq *> &rs);
@@ -184,18 +231,23 @@ bool misr_server::setup(SReq *r) {
                 hipSuccess)
             return false;
     }
-    ScgState st;
+    if (free_slots.empty()) return false;
+    r->h_st = free_slots.back();
+    free_slots.pop_back();
+    ScgState &st = *r->h_st;
     init_state(st, q.params, r->n);
     if (r->staged) {
         st.xglob = r->x0dev;     // scattered into the views at init, gathered at the end
         st.ldg = g.hr_w;
     }
-    return hipMemcpyAsync(r->st_dev, &st, sizeof st, hipMemcpyHostToDevice, stream) ==
-               hipSuccess &&
-           hipStreamSynchronize(stream) == hipSuccess;   // st lives on this stack frame
+    // the slot stays untouched until the final state comes back into it
+    return hipMemcpyAsync(r->st_dev, r->h_st, sizeof st, hipMemcpyHostToDevice, stream) ==
+           hipSuccess;
 }
 
 void misr_server::release(SReq *r) {
+    if (r->h_st) free_slots.push_back(r->h_st);
+    r->h_st = nullptr;
     r->xwork.release();
     r->ydev.release();
     r->dstate.release();
@@ -289,9 +341,17 @@ void misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
                {&L.drefs_new, L.refs_new.data(), L.refs_new.size() * sizeof(SolveRef)},
                {&L.halos, pl.halos.data(), nh * sizeof(HaloCopy)},
                {&L.halos_new_d, L.halos_new.data(), nhn * sizeof(HaloCopy)}};
+    size_t total = 0;
+    for (auto &u : ups) total += (u.n + 255) & ~(size_t)255;
+    if (!L.stage.ensure(std::max<size_t>(total, 256))) return;
+    char *hp = (char *)L.stage.h;
     for (auto &u : ups) {
         if (u.d->ensure(std::max<size_t>(u.n, 16)) != hipSuccess) continue;
-        if (u.n) (void)hipMemcpyAsync(u.d->p, u.h, u.n, hipMemcpyHostToDevice, stream);
+        if (u.n) {
+            std::memcpy(hp, u.h, u.n);
+            (void)hipMemcpyAsync(u.d->p, hp, u.n, hipMemcpyHostToDevice, stream);
+        }
+        hp += (u.n + 255) & ~(size_t)255;
     }
     (void)L.partials.ensure(std::max<size_t>(ni, 1) * kNV * sizeof(double));
     (void)L.partials_u.ensure(std::max<size_t>(nu, 1) * kNV * sizeof(double));
@@ -367,20 +427,63 @@ void misr_server::finish(SReq *r, misr_req_state st, misr_status code) {
     if (r->req.done_cb) r->req.done_cb(r->id, code, r->req.user);
 }
 
+// Completion of a cycle: finished requests report their final state (copied
+// into their pinned slot by the cycle), dropped ones their outcome; all give
+// their buffers back.  The cycle's device time updates the pass estimate.
+void misr_server::retire(Cycle &C) {
+    const hipError_t e = C.err != hipSuccess ? C.err : hipEventSynchronize(C.ev1);
+    if (e == hipSuccess && C.n_ep > 0 && C.mpx > 0) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, C.ev0, C.ev1) == hipSuccess && ms > 0.f) {
+            const double est = ms * 1e3 / (C.n_ep * C.mpx);
+            us_per_mpx_pass = 0.7 * us_per_mpx_pass + 0.3 * est;
+        }
+    }
+    for (SReq *r : C.done) {
+        misr_status code = MISR_E_HIP;
+        if (e == hipSuccess) {
+            const ScgState &st = *r->h_st;
+            code = st.stop == 2 ? MISR_E_NUMERIC : MISR_OK;
+            r->stats.n_passes = st.it;
+            r->stats.n_success = st.n_success;
+            r->stats.E_final = st.E;
+        }
+        release(r);
+        finish(r, code == MISR_OK ? MISR_REQ_DONE : MISR_REQ_FAILED, code);
+    }
+    for (SReq *r : C.dropped) {
+        release(r);
+        finish(r, r->drop_state, r->drop_code);
+    }
+    C.done.clear();
+    C.dropped.clear();
+    C.pending = false;
+    C.err = hipSuccess;
+    C.n_ep = 0;
+    C.mpx = 0;
+}
+
 void misr_server::run() {
     (void)hipSetDevice(ctx->dev);
+    int cur = 0;
     for (;;) {
-        std::vector<SReq *> admitted, cancelled;
+        std::vector<SReq *> admitted;
+        Cycle &C = cyc[cur];          // retired: free to rebuild
+        Cycle &P = cyc[cur ^ 1];      // possibly still on the device
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv.wait(lk, [&] { return closing || !queue.empty() || !active.empty(); });
-            if (closing && queue.empty() && active.empty()) break;
-            // admission by free device memory and slots, first come first served
-            while (!queue.empty() &&
-                   (int)(active.size() + admitted.size()) < std::max(1, cfg.max_slots)) {
+            cv.wait(lk, [&] {
+                return closing || !queue.empty() || !active.empty() || P.pending;
+            });
+            if (closing && queue.empty() && active.empty() && !P.pending) break;
+            // admission by free device memory, slots and host state slots,
+            // first come first served
+            const int cap = std::min<int>(std::max(1, cfg.max_slots), (int)free_slots.size() +
+                                                                           (int)active.size());
+            while (!queue.empty() && (int)(active.size() + admitted.size()) < cap) {
                 SReq *r = queue.front();
                 if (used + r->bytes > cfg.hbm_budget_bytes) {
-                    if (active.empty() && admitted.empty()) {
+                    if (active.empty() && admitted.empty() && !P.pending) {
                         queue.pop_front();
                         r->state = MISR_REQ_FAILED;
                         r->stats.status = MISR_E_NOMEM;
@@ -397,87 +500,96 @@ void misr_server::run() {
                 admitted.push_back(r);
             }
             for (SReq *r : active)
-                if (r->cancel) cancelled.push_back(r);
+                if (r->cancel) {
+                    r->drop_state = MISR_REQ_CANCELLED;
+                    r->drop_code = MISR_E_CANCELLED;
+                    C.dropped.push_back(r);
+                }
         }
-        for (SReq *r : cancelled) {
-            active.erase(std::find(active.begin(), active.end(), r));
-            release(r);
-            finish(r, MISR_REQ_CANCELLED, MISR_E_CANCELLED);
-        }
-        std::vector<SReq *> fresh;
+        for (SReq *r : C.dropped) active.erase(std::find(active.begin(), active.end(), r));
         for (SReq *r : admitted) {
+            r->set_pool(&pool);
             if (!setup(r)) {
-                (void)hipStreamSynchronize(stream);
-                release(r);
-                finish(r, MISR_REQ_FAILED, MISR_E_NOMEM);
+                r->drop_state = MISR_REQ_FAILED;
+                r->drop_code = MISR_E_NOMEM;
+                C.dropped.push_back(r);
                 continue;
             }
             active.push_back(r);
-            fresh.push_back(r);
         }
-        if (active.empty()) continue;
-        // passes this cycle: up to the earliest completion (at most 8)
-        int n_ep = 8;
-        for (SReq *r : active) n_ep = std::min(n_ep, r->req.params.n_iter - r->passes);
-        n_ep = std::max(n_ep, 0);
         hipError_t e = hipSuccess;
-        build_list(all, active);
-        if (!fresh.empty()) {
-            e = enqueue_init(all);
-            for (SReq *r : fresh) r->fresh = false;
-        }
-        // Each pass ends with steps 1-5 of the next one (phase A), so that no
-        // partial sums outlive a cycle: the next cycle's list may place a
-        // running solve's items elsewhere.  After a solve's last pass phase A
-        // finds it inactive and changes nothing.
-        for (int ep = 0; ep < n_ep && e == hipSuccess; ++ep) {
-            e = enqueue_image(all, KIND_TRIAL, false);
-            if (e == hipSuccess) e = enqueue_halo(all, false);
-            if (e == hipSuccess) e = enqueue_scalar(all, PHASE_B, false);
-            if (e == hipSuccess) e = enqueue_image(all, KIND_UPCURV, false);
-            if (e == hipSuccess) e = enqueue_scalar(all, PHASE_A, false);
-        }
-        std::vector<SReq *> done;
-        for (SReq *r : active) {
-            r->passes += n_ep;
-            if (r->passes >= r->req.params.n_iter) done.push_back(r);
-        }
-        // results of finished solves: current iterate into the caller's buffer
-        for (SReq *r : done) {
-            if (e != hipSuccess) break;
-            const Proj *pv = all.projs.as<Proj>() + r->view0;
-            const int vt = view_stype(r->req.params), gt = (int)r->req.params.img_dtype;
-            e = r->staged ? launch_gather(stream, pv, r->nviews, vt, gt, 0)
-                          : launch_finalize(stream, pv, r->nviews, vt);
-            if (e == hipSuccess && !r->req.on_device)
-                e = hipMemcpyAsync(r->req.x_out, r->xwork.p, r->n * r->es, hipMemcpyDeviceToHost,
-                                   stream);
-        }
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        for (SReq *r : done) {
-            ScgState st;
-            misr_status code = MISR_E_HIP;
-            if (e == hipSuccess &&
-                hipMemcpy(&st, r->st_dev, sizeof st, hipMemcpyDeviceToHost) == hipSuccess) {
-                code = st.stop == 2 ? MISR_E_NUMERIC : MISR_OK;
-                r->stats.n_passes = st.it;
-                r->stats.n_success = st.n_success;
-                r->stats.E_final = st.E;
+        if (!active.empty()) {
+            // passes this cycle: about 3 ms of device time, at most 8, and no
+            // further than the earliest completion
+            double mpx = 0;
+            for (SReq *r : active) mpx += r->n * 1e-6;
+            int n_ep = (int)(3000.0 / std::max(1e-3, us_per_mpx_pass * mpx));
+            n_ep = std::max(1, std::min(8, n_ep));
+            for (SReq *r : active) n_ep = std::min(n_ep, r->req.params.n_iter - r->passes);
+            n_ep = std::max(n_ep, 0);
+            build_list(C.list, active);
+            e = hipEventRecord(C.ev0, stream);
+            bool any_fresh = false;
+            for (SReq *r : active) any_fresh |= r->fresh;
+            if (e == hipSuccess && any_fresh) e = enqueue_init(C.list);
+            for (SReq *r : active) r->fresh = false;
+            // Each pass ends with steps 1-5 of the next one (phase A), so that
+            // no partial sums outlive a cycle: the next cycle's list may place
+            // a running solve's items elsewhere.  After a solve's last pass
+            // phase A finds it inactive and changes nothing.
+            List &L = C.list;
+            for (int ep = 0; ep < n_ep && e == hipSuccess; ++ep) {
+                e = enqueue_image(L, KIND_TRIAL, false);
+                if (e == hipSuccess) e = enqueue_halo(L, false);
+                if (e == hipSuccess) e = enqueue_scalar(L, PHASE_B, false);
+                if (e == hipSuccess) e = enqueue_image(L, KIND_UPCURV, false);
+                if (e == hipSuccess) e = enqueue_scalar(L, PHASE_A, false);
             }
-            active.erase(std::find(active.begin(), active.end(), r));
-            release(r);
-            finish(r, code == MISR_OK ? MISR_REQ_DONE : MISR_REQ_FAILED, code);
+            // finished solves: current iterate into the caller's buffer and the
+            // final state into the request's pinned slot
+            std::vector<SReq *> still;
+            for (SReq *r : active) {
+                r->passes += n_ep;
+                if (r->passes < r->req.params.n_iter) {
+                    still.push_back(r);
+                    continue;
+                }
+                const Proj *pv = L.projs.as<Proj>() + r->view0;
+                const int vt = view_stype(r->req.params), gt = (int)r->req.params.img_dtype;
+                if (e == hipSuccess)
+                    e = r->staged ? launch_gather(stream, pv, r->nviews, vt, gt, 0)
+                                  : launch_finalize(stream, pv, r->nviews, vt);
+                if (e == hipSuccess && !r->req.on_device)
+                    e = hipMemcpyAsync(r->req.x_out, r->xwork.p, r->n * r->es,
+                                       hipMemcpyDeviceToHost, stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(r->h_st, r->st_dev, sizeof(ScgState),
+                                       hipMemcpyDeviceToHost, stream);
+                C.done.push_back(r);
+            }
+            active.swap(still);
+            C.n_ep = n_ep;
+            C.mpx = mpx;
         }
+        if (e == hipSuccess && (!C.done.empty() || !C.dropped.empty() || C.n_ep > 0))
+            e = hipEventRecord(C.ev1, stream);
         if (e != hipSuccess) {
-            // a device error fails every running request
-            std::vector<SReq *> rs = active;
-            active.clear();
-            for (SReq *r : rs) {
-                release(r);
-                finish(r, MISR_REQ_FAILED, MISR_E_HIP);
+            // a device error fails every request of this cycle and every running one
+            C.err = e;
+            for (SReq *r : active) {
+                r->drop_state = MISR_REQ_FAILED;
+                r->drop_code = MISR_E_HIP;
+                C.dropped.push_back(r);
             }
+            active.clear();
         }
+        C.pending = !C.done.empty() || !C.dropped.empty() || C.n_ep > 0 || C.err != hipSuccess;
+        if (P.pending) retire(P);
+        if (C.pending && active.empty()) retire(C);   // nothing follows: finish now
+        cur ^= 1;
     }
+    if (cyc[0].pending) retire(cyc[0]);
+    if (cyc[1].pending) retire(cyc[1]);
 }
 
 // ---------------------------------------------------------------- C ABI
@@ -491,8 +603,28 @@ extern "C" misr_status misr_server_create(misr_ctx *ctx, const misr_server_confi
     auto s = std::make_unique<misr_server>();
     s->ctx = ctx;
     s->cfg = *cfg;
+    auto undo = [&] {
+        for (auto &c : s->cyc) {
+            if (c.ev0) (void)hipEventDestroy(c.ev0);
+            if (c.ev1) (void)hipEventDestroy(c.ev1);
+        }
+        if (s->stream) (void)hipStreamDestroy(s->stream);
+    };
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
         return set_error(MISR_E_HIP, "stream creation failed");
+    for (auto &c : s->cyc)
+        if (hipEventCreate(&c.ev0) != hipSuccess || hipEventCreate(&c.ev1) != hipSuccess) {
+            undo();
+            return set_error(MISR_E_HIP, "event creation failed");
+        }
+    const int nslots = std::max(1, cfg->max_slots);
+    if (!s->slots_mem.ensure((size_t)nslots * sizeof(ScgState))) {
+        undo();
+        return set_error(MISR_E_NOMEM, "pinned host memory for %d solve states", nslots);
+    }
+    for (int i = nslots - 1; i >= 0; --i)
+        s->free_slots.push_back((ScgState *)s->slots_mem.h + i);
+    s->pool.limit = cfg->hbm_budget_bytes;
     misr_server *raw = s.release();
     ctx->users++;
     raw->th = std::thread([raw] { raw->run(); });
@@ -603,7 +735,13 @@ extern "C" misr_status misr_server_destroy(misr_server *s) {
     }
     s->cv.notify_all();
     if (s->th.joinable()) s->th.join();
+    (void)hipStreamSynchronize(s->stream);
+    s->reqs.clear();   // their buffers went back to the pool when they retired
     for (auto &kv : s->ops) misr_op_destroy(kv.second);
+    for (auto &c : s->cyc) {
+        if (c.ev0) (void)hipEventDestroy(c.ev0);
+        if (c.ev1) (void)hipEventDestroy(c.ev1);
+    }
     (void)hipStreamDestroy(s->stream);
     misr_ctx *ctx = s->ctx;
     delete s;
