@@ -12,6 +12,10 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch first: libmisr.so must bind to the HIP runtime torch has loaded (its
+# streams and device pointers are the ones passed in); loading the library
+# first would bring a second HIP runtime into the process.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmisr.so")
