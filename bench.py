@@ -118,13 +118,20 @@ def _serve_problem(misr, ctx, L, s, seed):
     return dict(op=op, y=y, x0=x0, shifts=shifts, psf=psf, H=Hh, s=s)
 
 
-def serving_leg(misr, ctx, n_req: int = 48, loads=(0.8, 1.0), seed: int = 7):
+SERVE_FILL_MPX = 8   # about two waves of 48 x 96 tiles over the 256 CUs
+
+
+def serving_leg(misr, ctx, n_req: int = 48, loads=(0.8, 1.0), seed: int = 7,
+                fill_mpx: int = SERVE_FILL_MPX):
     """A stream of SR requests (LR 512^2..2048^2, scale 2 or 3, 80 SCG passes
     each) solved (a) plain: one solve at a time in arrival order, each solve
     one captured graph, synchronised; (b) served: misr_server continuous
     batching.  Capacity: every request submitted at t = 0.  Latency
     (completion - arrival): Poisson arrivals at `load` x the plain capacity
-    (in requests/s).  Served results must equal plain ones bit for bit."""
+    (in requests/s).  The server admits in arrival order while the admitted
+    solves hold fewer than fill_mpx million HR pixels (0: no cap), so small
+    requests share the device and large ones keep first-come order.  Served
+    results must equal plain ones bit for bit."""
     import torch
     rng = np.random.default_rng(seed)
     geoms = [(int(rng.choice(SERVE_SIZES)), int(rng.choice([2, 3]))) for _ in range(n_req)]
@@ -132,7 +139,7 @@ def serving_leg(misr, ctx, n_req: int = 48, loads=(0.8, 1.0), seed: int = 7):
              for i, g in enumerate(sorted(set(geoms)))}
     prm = misr.default_params(n_iter=SERVE_ITERS)
     hr_px = sum(g[0] * g[0] * g[1] * g[1] for g in geoms)
-    srv = misr.Server(ctx, hbm_budget_bytes=64 << 30)
+    srv = misr.Server(ctx, hbm_budget_bytes=64 << 30, fill_mpx=fill_mpx)
 
     def run_plain(arrivals):
         outs = [probs[g]["x0"].clone() for g in geoms]
@@ -188,6 +195,7 @@ def serving_leg(misr, ctx, n_req: int = 48, loads=(0.8, 1.0), seed: int = 7):
     res = {"workload": (f"{n_req} requests, LR {{512..2048}}^2, scale 2 (4 frames) or 3 "
                         f"(9 frames), {SERVE_ITERS} SCG passes, f32; latency runs: Poisson "
                         f"arrivals at a fraction of the plain capacity"),
+           "server_fill_mpx": fill_mpx,
            "capacity": {"plain_hr_mpx_per_s": hr_px / span_p / 1e6,
                         "served_hr_mpx_per_s": hr_px / span_s / 1e6,
                         "plain_requests_per_s": cap_plain,

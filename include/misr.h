@@ -236,7 +236,13 @@ typedef struct {
     int32_t max_slots;        /* cap on concurrently admitted requests */
     int32_t max_queue;        /* submit returns MISR_E_BUSY beyond this */
     int32_t fail_alloc_n;     /* fault hook: the n-th slot allocation fails (0 off) */
-    int32_t pad_;
+    int32_t fill_mpx;         /* 0: admit whatever memory and slots allow (every
+                                 admitted solve advances in every pass); > 0:
+                                 admit in arrival order only while the admitted
+                                 solves hold fewer than fill_mpx million HR
+                                 pixels (a request is always admitted when none
+                                 runs), so small requests are batched to fill the
+                                 device and large ones keep first-come order */
 } misr_server_config;
 
 typedef struct {

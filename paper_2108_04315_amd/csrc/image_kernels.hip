@@ -364,8 +364,12 @@ FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, 
 // sum over owned pairs of gamma q^2 Q(z, sk q), z, q the pair differences of
 // x and p.  Same sweep as btv_sweep (lanes on rows, waves on CV columns,
 // 3-slot rotating windows, unrolled by three); [ru0,ru1) x [rv0,rv1) is the
-// owned part of the tile.
-template <int S, int L, bool CHECK>
+// owned part of the tile.  With eps > 0 every pair first takes the series
+// form of psi_quot (eps^2 / B^3 times 1 - 3/2 t b + t^2 (2 b^2 - eps^2 / 2),
+// t = h / B^2); a lane that has a pair outside the series' range
+// (|h| >= 1e-3 B) recomputes those pairs with the closed form, so the common
+// case takes one branch per column instead of one per pair.
+template <int S, int L, bool CHECK, bool EPS0>
 FI void curv_sweep(const float *xs, const float *ps, const float (&gam)[8], float eps, float sk,
                    int U0, int V0, int H, int W, int ru0, int ru1, int rv0, int rv1,
                    double &dreg) {
@@ -390,6 +394,9 @@ FI void curv_sweep(const float *xs, const float *ps, const float (&gam)[8], floa
             wx[dy][dx] = xs[off + dy * T::WCP + dx];
             wp[dy][dx] = ps[off + dy * T::WCP + dx];
         }
+    float gq[8];   // gamma_d eps^2
+#pragma unroll
+    for (int d = 0; d < 8; ++d) gq[d] = gam[d] * e2;
     double acc = 0.0;
     // step t handles column cv0 + t and loads window column t + 2 (slot (t+2) % 3)
     auto step = [&](auto slot_c, int t) {
@@ -400,17 +407,50 @@ FI void curv_sweep(const float *xs, const float *ps, const float (&gam)[8], floa
             wp[dy][(Q + 2) % 3] = ps[off + dy * T::WCP + t + 2];
         }
         const int v = cv0 + t, V = V0 + v;
+        float tq[8];
+        if (EPS0) {
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                const int dx = kDX[d], dy = kDY[d];
+                const float z = wx[0][Q] - wx[dy][(Q + dx) % 3];
+                const float qd = wp[0][Q] - wp[dy][(Q + dx) % 3];
+                tq[d] = gam[d] * qd * qd * psi_quot(z, sk * qd, eps, e2);
+            }
+        } else {
+            bool slow = false;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                const int dx = kDX[d], dy = kDY[d];
+                const float z = wx[0][Q] - wx[dy][(Q + dx) % 3];
+                const float qd = wp[0][Q] - wp[dy][(Q + dx) % 3];
+                const float h = sk * qd;
+                const float rB = rsq(fmaf(z, z, e2));
+                const float rB2 = rB * rB;
+                const float tt = h * rB2;
+                slow |= fabsf(h * rB) >= 1e-3f;
+                const float poly = fmaf(tt, fmaf(tt, fmaf(2.f * z, z, -0.5f * e2), -1.5f * z), 1.f);
+                tq[d] = gq[d] * (qd * qd) * (rB * rB2) * poly;
+            }
+            if (slow) {
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    const int dx = kDX[d], dy = kDY[d];
+                    const float z = wx[0][Q] - wx[dy][(Q + dx) % 3];
+                    const float qd = wp[0][Q] - wp[dy][(Q + dx) % 3];
+                    const float h = sk * qd;
+                    if (fabsf(h * rsq(fmaf(z, z, e2))) >= 1e-3f)
+                        tq[d] = gam[d] * qd * qd * psi_quot(z, h, eps, e2);
+                }
+            }
+        }
         float a = 0.f;
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const int dx = kDX[d], dy = kDY[d];
-            const float z = wx[0][Q] - wx[dy][(Q + dx) % 3];
-            const float qd = wp[0][Q] - wp[dy][(Q + dx) % 3];
-            const float tq = gam[d] * qd * qd * psi_quot(z, sk * qd, eps, e2);
             if (CHECK)
-                a += (rok[dy] && V + dx < W) ? tq : 0.f;
+                a += (rok[dy] && V + dx < W) ? tq[d] : 0.f;
             else
-                a += tq;
+                a += tq[d];
         }
         const bool own = own_row && (!CHECK || (v >= rv0 && v < rv1));
         acc += own ? (double)a : 0.0;
@@ -597,6 +637,30 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
 #pragma unroll
             for (int c = 0; c < T::CV; ++c) gs[u * T::GP + wv * T::CV + c] = gacc[c];
     }
+    // the output pass's loads of g_k are issued here, so that they are in
+    // flight during the prior's sweep (those of p just after it)
+    const int cur = st.cur;
+    AS1 float *gout = glbw(P.g[cur ^ 1]);
+    const AS1 float *gk = glb(P.g[cur]);
+    AS1 float *pz = glbw(P.p[xc]);
+    constexpr int NOUT = (T::TH * T::TW + kNTI - 1) / kNTI;
+    auto out_at = [&](int j, i64 &idx) {
+        const int q = tid + j * kNTI;
+        const int qq = min(q, T::TH * T::TW - 1);
+        const int uu = qq / T::TW, vv = qq - uu * T::TW;
+        idx = (i64)min(o.u0 + uu, o.u1 - 1) * ld + min(o.v0 + vv, o.v1 - 1);
+        return (q < T::TH * T::TW && o.u0 + uu < o.u1 && o.v0 + vv < o.v1) ? uu * T::GP + vv
+                                                                           : -1;
+    };
+    float gkv[NOUT], pv[NOUT];
+    if (mode == 1) {
+#pragma unroll
+        for (int j = 0; j < NOUT; ++j) {
+            i64 idx;
+            (void)out_at(j, idx);
+            gkv[j] = gk[idx];
+        }
+    }
     float gam[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) gam[d] = st.wt.gam[kDY[d] * 3 + kDX[d]];
@@ -612,37 +676,26 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
         btv_sweep<S, L, false, false>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
     else
         btv_sweep<S, L, false, true>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
-    __syncthreads();
-    double gg = 0.0, ggk = 0.0, gp = 0.0;
-    const int cur = st.cur;
-    AS1 float *gout = glbw(P.g[cur ^ 1]);
-    const AS1 float *gk = glb(P.g[cur]);
-    AS1 float *pz = glbw(P.p[xc]);
-    // owned gradient out, with its inner products (loads first, as above)
-    constexpr int NOUT = (T::TH * T::TW + kNTI - 1) / kNTI;
-    float gvs[NOUT], gkv[NOUT], pv[NOUT];
-    i64 oidx[NOUT];
-    bool ook[NOUT];
+    if (mode == 1) {
 #pragma unroll
-    for (int j = 0; j < NOUT; ++j) {
-        const int q = tid + j * kNTI;
-        const int qq = min(q, T::TH * T::TW - 1);
-        const int uu = qq / T::TW, vv = qq - uu * T::TW;
-        ook[j] = q < T::TH * T::TW && o.u0 + uu < o.u1 && o.v0 + vv < o.v1;
-        oidx[j] = (i64)min(o.u0 + uu, o.u1 - 1) * ld + min(o.v0 + vv, o.v1 - 1);
-        gvs[j] = gs[uu * T::GP + vv];
-        if (mode == 1) {
-            gkv[j] = gk[oidx[j]];
-            pv[j] = pb[oidx[j]];
+        for (int j = 0; j < NOUT; ++j) {
+            i64 idx;
+            (void)out_at(j, idx);
+            pv[j] = pb[idx];
         }
     }
+    __syncthreads();
+    // owned gradient out, with its inner products
+    double gg = 0.0, ggk = 0.0, gp = 0.0;
 #pragma unroll
     for (int j = 0; j < NOUT; ++j) {
-        if (!ook[j]) continue;
-        const float gv = gvs[j];
-        gout[oidx[j]] = gv;
+        i64 idx;
+        const int at = out_at(j, idx);
+        if (at < 0) continue;
+        const float gv = gs[at];
+        gout[idx] = gv;
         gg += (double)gv * (double)gv;
-        if (mode == 0) pz[oidx[j]] = 0.f;   // start direction buffer for the init pass
+        if (mode == 0) pz[idx] = 0.f;   // start direction buffer for the init pass
         if (mode == 1) {
             ggk += (double)gv * (double)gkv[j];
             gp += (double)gv * (double)pv[j];
@@ -759,10 +812,15 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
     const int ru0 = ou0 - o.u0, ru1 = ou1 - o.u0, rv0 = ov0 - o.v0, rv1 = ov1 - o.v0;
     const bool inner = o.U0 + T::TH + 2 <= H && o.V0 + T::TW + 2 <= W && ru0 == 0 &&
                        ru1 == T::TH && rv0 == 0 && rv1 == T::TW;
-    if (inner)
-        curv_sweep<S, L, false>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0, rv1, dreg);
+    if (eps == 0.f)
+        curv_sweep<S, L, true, true>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0, rv1,
+                                     dreg);
+    else if (inner)
+        curv_sweep<S, L, false, false>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0,
+                                       rv1, dreg);
     else
-        curv_sweep<S, L, true>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0, rv1, dreg);
+        curv_sweep<S, L, true, false>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0,
+                                      rv1, dreg);
     double v[4] = {2.0 * ap2, dreg, pp, pr};
     block_sum_store<4, kNTI>(v, part, red);
 }

@@ -480,8 +480,13 @@ void misr_server::run() {
             // first come first served
             const int cap = std::min<int>(std::max(1, cfg.max_slots), (int)free_slots.size() +
                                                                            (int)active.size());
+            double held_mpx = 0;   // HR pixels of the solves that will run next cycle
+            for (SReq *r : active) held_mpx += r->n * 1e-6;
             while (!queue.empty() && (int)(active.size() + admitted.size()) < cap) {
                 SReq *r = queue.front();
+                if (cfg.fill_mpx > 0 && !(active.empty() && admitted.empty()) &&
+                    held_mpx + r->n * 1e-6 > cfg.fill_mpx)
+                    break;
                 if (used + r->bytes > cfg.hbm_budget_bytes) {
                     if (active.empty() && admitted.empty() && !P.pending) {
                         queue.pop_front();
@@ -495,6 +500,7 @@ void misr_server::run() {
                 }
                 queue.pop_front();
                 used += r->bytes;
+                held_mpx += r->n * 1e-6;
                 r->state = MISR_REQ_RUNNING;
                 r->stats.t_admit_us = now_us();
                 admitted.push_back(r);
@@ -596,8 +602,9 @@ void misr_server::run() {
 extern "C" misr_status misr_server_create(misr_ctx *ctx, const misr_server_config *cfg,
                                           misr_server **out) {
     if (!ctx || !cfg || !out) return set_error(MISR_E_INVAL, "NULL argument");
-    if (cfg->max_slots < 1 || cfg->hbm_budget_bytes == 0)
-        return set_error(MISR_E_INVAL, "max_slots >= 1 and hbm_budget_bytes > 0 required");
+    if (cfg->max_slots < 1 || cfg->hbm_budget_bytes == 0 || cfg->fill_mpx < 0)
+        return set_error(MISR_E_INVAL,
+                         "max_slots >= 1, hbm_budget_bytes > 0 and fill_mpx >= 0 required");
     *out = nullptr;
     if (hipSetDevice(ctx->dev) != hipSuccess) return set_error(MISR_E_HIP, "hipSetDevice");
     auto s = std::make_unique<misr_server>();

@@ -205,3 +205,33 @@ def test_bf16_requests_match_plain(misr, ctx, probs):
         assert srv.poll(rid)[0] == misr.REQ_DONE
         assert torch.equal(out, ref)
     srv.close()
+
+
+def test_fill_admission_keeps_arrival_order(misr, ctx):
+    """With fill_mpx set, a request that would push the admitted pixels past
+    the fill waits for the running ones: three 768^2 requests (0.59 Mpx each)
+    under a 1 Mpx fill run one after another, in arrival order, with results
+    equal to their solo solves."""
+    import torch
+    p = problem(384, 2, 0.8, None, jitter=0.05, n_iter=5, seeds=(31, 32, 33))
+    solo = _solo(misr, ctx, p, 5)
+    srv = misr.Server(ctx, hbm_budget_bytes=1 << 30, fill_mpx=1)
+    ids, outs = [], []
+    for _ in range(3):
+        x0 = to_dev(_f32(p.x0))
+        out = torch.empty_like(x0)
+        outs.append(out)
+        ids.append(srv.submit(p.H, p.W, p.s, p.shifts, p.psf, to_dev(_f32(p.y)), x0, out,
+                              misr.default_params(n_iter=5)))
+    stats = []
+    for rid, out in zip(ids, outs):
+        assert srv.wait(rid, 60_000_000) == misr.OK
+        st, stt = srv.poll(rid)
+        assert st == misr.REQ_DONE
+        assert torch.equal(out, solo)
+        stats.append(stt)
+    admits = [s_.t_admit_us for s_ in stats]
+    dones = [s_.t_done_us for s_ in stats]
+    assert admits == sorted(admits) and dones == sorted(dones)
+    assert admits[1] > admits[0] and admits[2] > admits[1]
+    srv.close()
