@@ -122,7 +122,7 @@ SERVE_FILL_MPX = 8   # about two waves of 48 x 96 tiles over the 256 CUs
 
 
 def serving_leg(misr, ctx, n_req: int = 48, loads=(0.8, 1.0), seed: int = 7,
-                fill_mpx: int = SERVE_FILL_MPX):
+                fill_mpx: int = SERVE_FILL_MPX, sizes=SERVE_SIZES):
     """A stream of SR requests (LR 512^2..2048^2, scale 2 or 3, 80 SCG passes
     each) solved (a) plain: one solve at a time in arrival order, each solve
     one captured graph, synchronised; (b) served: misr_server continuous
@@ -134,7 +134,7 @@ def serving_leg(misr, ctx, n_req: int = 48, loads=(0.8, 1.0), seed: int = 7,
     results must equal plain ones bit for bit."""
     import torch
     rng = np.random.default_rng(seed)
-    geoms = [(int(rng.choice(SERVE_SIZES)), int(rng.choice([2, 3]))) for _ in range(n_req)]
+    geoms = [(int(rng.choice(sizes)), int(rng.choice([2, 3]))) for _ in range(n_req)]
     probs = {g: _serve_problem(misr, ctx, g[0], g[1], 100 + i)
              for i, g in enumerate(sorted(set(geoms)))}
     prm = misr.default_params(n_iter=SERVE_ITERS)
@@ -192,7 +192,8 @@ def serving_leg(misr, ctx, n_req: int = 48, loads=(0.8, 1.0), seed: int = 7,
     outs_s, _, span_s = run_served(zeros)
     equal = all(torch.equal(a, b) for a, b in zip(outs_p, outs_s))
     cap_plain = n_req / span_p
-    res = {"workload": (f"{n_req} requests, LR {{512..2048}}^2, scale 2 (4 frames) or 3 "
+    res = {"workload": (f"{n_req} requests, LR {'/'.join(str(v) for v in sizes)}^2, scale 2 "
+                        f"(4 frames) or 3 "
                         f"(9 frames), {SERVE_ITERS} SCG passes, f32; latency runs: Poisson "
                         f"arrivals at a fraction of the plain capacity"),
            "server_fill_mpx": fill_mpx,
@@ -392,6 +393,7 @@ def main():
     }
     if not args.no_serve:
         out["serving"] = serving_leg(misr, ctx)
+        out["serving_small"] = serving_leg(misr, ctx, sizes=(512,), seed=8)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(y_np, shifts, psf, x0.double().cpu().numpy())
     print(json.dumps(out), flush=True)

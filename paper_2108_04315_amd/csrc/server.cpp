@@ -122,9 +122,14 @@ struct misr_server {
         std::vector<SolveRef> refs_new;      // the new solves only
         std::vector<HaloCopy> halos_new;     // halo copies of the new solves only
         std::vector<int> counts;
-        DevMem projs, items, items_u, counts_d, refs, drefs_new, partials, partials_u, halos,
-            halos_new_d;
-        Pinned stage;                        // the arrays above, packed for upload
+        // device copies of the arrays above, all in one block (one upload)
+        struct View {
+            void *p = nullptr;
+            template <typename T>
+            T *as() const { return (T *)p; }
+        } projs, items, items_u, counts_d, refs, drefs_new, halos, halos_new_d;
+        DevMem blob, partials, partials_u;
+        Pinned stage;                        // the packed arrays, pinned for the upload
         int nc() const { return (int)pl.classes.size(); }
         const int *cnt(int off) const { return counts_d.as<int>() + off; }
     };
@@ -330,7 +335,7 @@ void misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
     const size_t np = pl.projs.size(), ni = pl.items.size(), nu = pl.items_u.size(),
                  ns = pl.refs.size(), nh = pl.halos.size(), nhn = L.halos_new.size();
     struct Up {
-        DevMem *d;
+        List::View *d;
         const void *h;
         size_t n;
     } ups[] = {{&L.projs, pl.projs.data(), np * sizeof(Proj)},
@@ -343,16 +348,18 @@ void misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
                {&L.halos_new_d, L.halos_new.data(), nhn * sizeof(HaloCopy)}};
     size_t total = 0;
     for (auto &u : ups) total += (u.n + 255) & ~(size_t)255;
-    if (!L.stage.ensure(std::max<size_t>(total, 256))) return;
-    char *hp = (char *)L.stage.h;
+    total = std::max<size_t>(total, 256);
+    if (!L.stage.ensure(total) || L.blob.ensure(total) != hipSuccess) return;
+    char *hp = (char *)L.stage.h, *dp = L.blob.as<char>();
     for (auto &u : ups) {
-        if (u.d->ensure(std::max<size_t>(u.n, 16)) != hipSuccess) continue;
-        if (u.n) {
-            std::memcpy(hp, u.h, u.n);
-            (void)hipMemcpyAsync(u.d->p, hp, u.n, hipMemcpyHostToDevice, stream);
-        }
-        hp += (u.n + 255) & ~(size_t)255;
+        if (u.n) std::memcpy(hp, u.h, u.n);
+        u.d->p = dp;
+        const size_t step = (u.n + 255) & ~(size_t)255;
+        hp += step;
+        dp += step;
     }
+    (void)hipMemcpyAsync(L.blob.p, L.stage.h, (size_t)(hp - (char *)L.stage.h),
+                         hipMemcpyHostToDevice, stream);
     (void)L.partials.ensure(std::max<size_t>(ni, 1) * kNV * sizeof(double));
     (void)L.partials_u.ensure(std::max<size_t>(nu, 1) * kNV * sizeof(double));
 }
@@ -525,12 +532,12 @@ void misr_server::run() {
         }
         hipError_t e = hipSuccess;
         if (!active.empty()) {
-            // passes this cycle: about 3 ms of device time, at most 8, and no
+            // passes this cycle: about 3 ms of device time, at most 64, and no
             // further than the earliest completion
             double mpx = 0;
             for (SReq *r : active) mpx += r->n * 1e-6;
             int n_ep = (int)(3000.0 / std::max(1e-3, us_per_mpx_pass * mpx));
-            n_ep = std::max(1, std::min(8, n_ep));
+            n_ep = std::max(1, std::min(64, n_ep));
             for (SReq *r : active) n_ep = std::min(n_ep, r->req.params.n_iter - r->passes);
             n_ep = std::max(n_ep, 0);
             build_list(C.list, active);
