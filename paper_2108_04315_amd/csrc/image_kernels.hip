@@ -55,7 +55,7 @@ struct Tile {
         const int hx = NRM * njp + S * CI * njp;
         const int hr = hx + NIM * njp;
         const int gs = TH * (tw + 1);
-        const int trial = xs + (hr > gs ? hr : gs);
+        const int trial = xs + (hr > gs ? hr : gs) + TH * tw;   // + the owned p
         const int upd = 2 * xs + hx;
         return trial > upd ? trial : upd;
     }
@@ -78,7 +78,9 @@ struct Tile {
     static constexpr int NSTAGE = (WR * WC + kNTI - 1) / kNTI;
     static_assert(NRM <= 64 && TH + 2 <= 64 && NJM <= 64, "a wave spans a tile dimension");
     static_assert(CV % S == 0 && CU % S == 0, "phase-aligned groups");
+    static constexpr int PO = XS + ((HXS + RSS > TH * GP) ? HXS + RSS : TH * GP);
     static_assert(TH * GP <= SMEM - XS && TH <= NRM, "LDS aliasing");
+    static_assert(PO + TH * TW <= SMEM, "LDS: owned p of the trial pass");
 };
 
 // pass 1: hx[r][j] = sum_l wx[jA+j][l] win[wr0+r][wc0+S j+l], r < NR, j < NJ.
@@ -532,6 +534,7 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     float *xs = sm;
     float *hx = xs + T::XS;
     float *rs = hx + T::HXS;
+    float *po = sm + T::PO;     // p at the owned pixels, for g_t . p
 
     const int xc = st.xc;
     const AS1 raw *xb = glb((const raw *)P.x[xc]);
@@ -560,6 +563,9 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
                 sr ? ST::rnd_sr(v, pixel_hash((i64)(P.gy0 + a.ub) * Wg + P.gx0 + a.vb, seed))
                    : ST::rnd(v);
             if (a.lds >= 0) xs[a.lds] = a.in ? vr : 0.f;
+            const int ou = a.ub - o.u0, ov = a.vb - o.v0;
+            if (a.lds >= 0 && ou >= 0 && ou < T::TH && ov >= 0 && ov < T::TW)
+                po[ou * T::TW + ov] = pr[s];
         }
     } else {
         float xr[T::NSTAGE];
@@ -638,7 +644,7 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
             for (int c = 0; c < T::CV; ++c) gs[u * T::GP + wv * T::CV + c] = gacc[c];
     }
     // the output pass's loads of g_k are issued here, so that they are in
-    // flight during the prior's sweep (those of p just after it)
+    // flight during the prior's sweep (p at the owned pixels is in LDS)
     const int cur = st.cur;
     AS1 float *gout = glbw(P.g[cur ^ 1]);
     const AS1 float *gk = glb(P.g[cur]);
@@ -652,7 +658,7 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
         return (q < T::TH * T::TW && o.u0 + uu < o.u1 && o.v0 + vv < o.v1) ? uu * T::GP + vv
                                                                            : -1;
     };
-    float gkv[NOUT], pv[NOUT];
+    float gkv[NOUT];
     if (mode == 1) {
 #pragma unroll
         for (int j = 0; j < NOUT; ++j) {
@@ -676,14 +682,6 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
         btv_sweep<S, L, false, false>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
     else
         btv_sweep<S, L, false, true>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
-    if (mode == 1) {
-#pragma unroll
-        for (int j = 0; j < NOUT; ++j) {
-            i64 idx;
-            (void)out_at(j, idx);
-            pv[j] = pb[idx];
-        }
-    }
     __syncthreads();
     // owned gradient out, with its inner products
     double gg = 0.0, ggk = 0.0, gp = 0.0;
@@ -697,8 +695,9 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
         gg += (double)gv * (double)gv;
         if (mode == 0) pz[idx] = 0.f;   // start direction buffer for the init pass
         if (mode == 1) {
+            const int q = min(tid + j * kNTI, T::TH * T::TW - 1);
             ggk += (double)gv * (double)gkv[j];
-            gp += (double)gv * (double)pv[j];
+            gp += (double)gv * (double)po[q];
         }
     }
     double v[5] = {e_data, e_reg, gg, ggk, gp};
@@ -928,6 +927,16 @@ FI void tile_adjoint(const AS4 Proj &P, int ty, int tx, const void *r, float *xo
 // -------------------------------------------------------------- the kernels
 // Each kernel walks the work list with a grid stride; the item count is read
 // from device memory so that one captured launch can serve a changing list.
+//
+// Workgroups are dispatched to the 8 XCDs round-robin in blockIdx order, and
+// each XCD has its own L2.  With one workgroup per item, workgroup b takes
+// item xcd_item(b, n): XCD b % 8 gets one contiguous run of the list (a band
+// of neighbouring tiles), so the halos neighbouring tiles share are re-read
+// from that XCD's L2 rather than fetched again.
+FI int xcd_item(int b, int n) {
+    const int q = n >> 3, r = n & 7, x = b & 7, j = b >> 3;
+    return x * q + min(x, r) + j;
+}
 template <int S, int L, class ST, class SY>
 __global__ void __launch_bounds__(kNTI, 4) k_trial(const Proj *projs, const Item *items,
                                                 const int *n_items, double *partials,
@@ -935,7 +944,9 @@ __global__ void __launch_bounds__(kNTI, 4) k_trial(const Proj *projs, const Item
     __shared__ float sm[Tile<S, L>::SMEM];
     __shared__ double red[kNV * kNWI];
     const int n = *cst(n_items);
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const bool remap = (int)gridDim.x == n;
+    for (int b = blockIdx.x; b < n; b += gridDim.x) {
+        const int it = remap ? xcd_item(b, n) : b;
         const AS4 Item &itm = cst(items)[it];
         const AS4 Proj &P = cst(projs)[itm.proj];
         const AS4 ScgState &st = *cst(P.st);
@@ -951,7 +962,9 @@ __global__ void __launch_bounds__(kNTI, 4) k_upcurv(const Proj *projs, const Ite
     __shared__ float sm[Tile<S, L>::SMEM];
     __shared__ double red[kNV * kNWI];
     const int n = *cst(n_items);
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const bool remap = (int)gridDim.x == n;
+    for (int b = blockIdx.x; b < n; b += gridDim.x) {
+        const int it = remap ? xcd_item(b, n) : b;
         const AS4 Item &itm = cst(items)[it];
         const AS4 Proj &P = cst(projs)[itm.proj];
         const AS4 ScgState &st = *cst(P.st);
