@@ -89,7 +89,8 @@ typedef struct {
     double alpha_btv;    /* alpha in (0, 1) (default 0.4) */
     double eps;          /* Charbonnier eps of the prior >= 0 (default 1e-3) */
     int32_t btv_w;       /* window w in [1, 3] (default 3) */
-    int32_t data_p;      /* data norm p in {1, 2} (default 2) */
+    int32_t data_p;      /* data norm p in {1, 2} (default 2); p = 1 is the
+                            Charbonnier-smoothed L1 norm with eps_data */
     double eps_data;     /* Charbonnier eps of the L1 data term (p = 1) >= 0 */
     double scg_sigma;    /* SCG sigma > 0 (default 1e-4) */
     double scg_lambda1;  /* SCG initial scale lambda_1 > 0 (default 1e-6) */

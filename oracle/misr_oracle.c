@@ -304,6 +304,27 @@ double orc_curv_exact(int H, int W, int s, int K, const double *shifts, int P,
     return dd + dr;
 }
 
+/* Data part of delta for the Charbonnier L1 data term (Eq. misr, p = 1):
+ *   sum_k sum_i (A_k p)_i^2 Q(r_i, sk (A_k p)_i),  r = A_k x - y_k,
+ * Q the psi quotient above with eps_data.  Equal in exact arithmetic to
+ * p^T (grad E_data(x + sk p) - grad E_data(x)) / sk. */
+double orc_curv_data_l1(int H, int W, int s, int K, const double *shifts, int P,
+                        const double *psf, double eps_data, double sk, const double *x,
+                        const double *p, const double *y) {
+    const i64 m = (i64)(H / s) * (W / s) * K;
+    double *ap = (double *)malloc(sizeof(double) * m);
+    double *ax = (double *)malloc(sizeof(double) * m);
+    orc_forward(H, W, s, K, shifts, P, psf, p, ap);
+    orc_forward(H, W, s, K, shifts, P, psf, x, ax);
+    double dd = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : dd)
+    for (i64 i = 0; i < m; ++i)
+        dd += ap[i] * ap[i] * orc_psi_quotient(ax[i] - y[i], sk * ap[i], eps_data);
+    free(ap);
+    free(ax);
+    return dd;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

@@ -55,6 +55,7 @@ def _load():
                           _P, _P],
         "orc_psi_quotient": [_D, _D, _D],
         "orc_curv_exact": [_I, _I, _I, _I, _P, _I, _P, _D, _D, _D, _I, _D, _P, _P, _P],
+        "orc_curv_data_l1": [_I, _I, _I, _I, _P, _I, _P, _D, _D, _P, _P, _P],
         "orc_num_threads": [],
         "orc_set_threads": [_I],
     }
@@ -66,6 +67,7 @@ def _load():
     lib.orc_cost_grad.restype = _D
     lib.orc_psi_quotient.restype = _D
     lib.orc_curv_exact.restype = _D
+    lib.orc_curv_data_l1.restype = _D
     lib.orc_num_threads.restype = _I
     _lib = lib
     return lib
@@ -171,6 +173,15 @@ def cost_grad(x, y, shifts, psf, s, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3, w=
 
 def psi_quotient(b, h, eps):
     return _load().orc_psi_quotient(float(b), float(h), float(eps))
+
+
+def curvature_data_l1(x, p, y, shifts, psf, s, sk, eps_data=1e-3):
+    """Data part of p^T (grad J(x + sk p) - grad J(x)) / sk for the
+    Charbonnier L1 data term, closed form."""
+    x, p, y, shifts, psf = _f64(x), _f64(p), _f64(y), _f64(shifts), _f64(psf)
+    H, W = x.shape
+    return _load().orc_curv_data_l1(H, W, s, shifts.shape[0], _p(shifts), psf.size, _p(psf),
+                                    eps_data, sk, _p(x), _p(p), _p(y))
 
 
 def curvature_exact(x, p, shifts, psf, s, sk, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3,

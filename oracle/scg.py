@@ -140,9 +140,13 @@ def misr_curvature_exact(shifts, psf, s, lambda_reg=0.01, alpha_btv=0.4, eps=1e-
 
 
 def solve(prob_y, shifts, psf, s, x0, n_iter, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3,
-          w=3, sigma=1e-4, lam1=1e-6, exact_curvature=False):
-    """SCG solve of the MISR objective (L2 data term)."""
-    f = misr_objective(prob_y, shifts, psf, s, lambda_reg, alpha_btv, eps, w)
+          w=3, sigma=1e-4, lam1=1e-6, exact_curvature=False, data_p=2, eps_data=1e-3):
+    """SCG solve of the MISR objective (Eq. misr: L2 data term, or the
+    Charbonnier-smoothed L1 term for data_p = 1), Moller's finite-difference
+    curvature unless exact_curvature (L2 only)."""
+    if exact_curvature and data_p != 2:
+        raise ValueError("the closed-form curvature here covers the L2 data term")
+    f = misr_objective(prob_y, shifts, psf, s, lambda_reg, alpha_btv, eps, w, data_p, eps_data)
     curv = misr_curvature_exact(shifts, psf, s, lambda_reg, alpha_btv, eps, w) \
         if exact_curvature else None
     return scg_minimize(f, x0, n_iter, sigma, lam1, curvature=curv)

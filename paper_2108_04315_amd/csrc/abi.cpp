@@ -744,8 +744,6 @@ extern "C" misr_status misr_scg_solve(const misr_op *cop, const misr_params *prm
     if (!op || !y || !x) return set_error(MISR_E_INVAL, "NULL argument");
     misr_status st = misr_params_check(prm);
     if (st != MISR_OK) return st;
-    if (prm->data_p != 2)
-        return set_error(MISR_E_INVAL, "the SCG solve supports the L2 data term (data_p = 2)");
     if ((st = check_tiling(op, *prm)) != MISR_OK) return st;
     std::lock_guard<std::mutex> lk(op->mu);
     std::lock_guard<std::mutex> lc(op->ctx->mu);
@@ -785,8 +783,8 @@ extern "C" misr_status misr_scg_solve_batch(int n, const misr_op *const *ops,
         if (!ops[i] || !y[i] || !x[i]) return set_error(MISR_E_INVAL, "NULL entry %d", i);
         misr_status st = misr_params_check(&prm[i]);
         if (st != MISR_OK) return st;
-        if (prm[i].data_p != 2 || prm[i].tile_lr > 0)
-            return set_error(MISR_E_INVAL, "batch entry %d: L2 data term, untiled only", i);
+        if (prm[i].tile_lr > 0)
+            return set_error(MISR_E_INVAL, "batch entry %d: batched solves are untiled", i);
         if (prm[i].img_dtype != prm[0].img_dtype || prm[i].x_work != prm[0].x_work)
             return set_error(MISR_E_INVAL, "batch entries must share img_dtype and x_work");
         if (ctx && ops[i]->ctx != ctx) return set_error(MISR_E_INVAL, "ops span contexts");
@@ -832,8 +830,7 @@ extern "C" misr_status misr_time_pass(const misr_op *cop, const misr_params *prm
         return set_error(MISR_E_INVAL, "bad arguments");
     misr_status st = misr_params_check(prm);
     if (st != MISR_OK) return st;
-    if (prm->data_p != 2 || prm->tile_lr > 0)
-        return set_error(MISR_E_INVAL, "L2 data term, untiled only");
+    if (prm->tile_lr > 0) return set_error(MISR_E_INVAL, "timing runs untiled");
     std::lock_guard<std::mutex> lk(op->mu);
     std::lock_guard<std::mutex> lc(op->ctx->mu);
     MISR_HIP(set_device(op->ctx->dev));

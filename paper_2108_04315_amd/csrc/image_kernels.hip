@@ -56,7 +56,7 @@ struct Tile {
         const int hr = hx + NIM * njp;
         const int gs = TH * (tw + 1);
         const int trial = xs + (hr > gs ? hr : gs) + TH * tw;   // + the owned p
-        const int upd = 2 * xs + hx;
+        const int upd = 2 * xs + hx + NIM * njp;                // + A_k x for p = 1
         return trial > upd ? trial : upd;
     }
     static constexpr int calc_tw() {
@@ -704,12 +704,65 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     block_sum_store<5, kNTI>(v, part, red);
 }
 
+// Data part of the curvature over the owned LR pixels (all edges are
+// multiples of S): L2 (DP = 2), 2 |A_k p|^2, exact since the term is
+// quadratic; L1 (DP = 1, Charbonnier), the sum of (A_k p)^2 Q(r, sk A_k p) with
+// r = A_k x - y_k and Q the quotient the prior's pairs use.
+template <int S, int L, class SY, int DP>
+FI double upd_data_part(const AS4 Proj &P, const AS4 ScgState &st, const TileOrigin &o,
+                        const float *xs, const float *ps, float *hx, float *ax, int NIo,
+                        int NJo, int iA, int jA) {
+    using T = Tile<S, L>;
+    using rawy = typename SY::raw;
+    const AS4 OpDev &op = *cst(P.op);
+    const int h = op.H / S, w = op.W / S, K = op.K;
+    const float skd = st.sigk_f, epsd = st.wt.eps_data, e2d = epsd * epsd;
+    const AS1 rawy *yb = glb((const rawy *)P.y);
+    double ap2 = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const int offy = op.offy[k], offx = op.offx[k];
+        const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
+        const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
+        if (DP == 1) {
+            pass1<S, L>(xs, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
+                        S * (NIo - 1) + L, NJo, wxk, jA, w - 1, hx);
+            __syncthreads();
+            pass2<S, L>(hx, NIo, NJo, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
+#pragma unroll
+                for (int c = 0; c < T::CI; ++c)
+                    if (i0 + c < NIo) ax[(i0 + c) * T::NJP + j] = av[c];
+            });
+            __syncthreads();
+        }
+        pass1<S, L>(ps, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
+                    S * (NIo - 1) + L, NJo, wxk, jA, w - 1, hx);
+        __syncthreads();
+        const AS1 rawy *yk = yb + (i64)k * h * w;
+        pass2<S, L>(hx, NIo, NJo, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
+#pragma unroll
+            for (int c = 0; c < T::CI; ++c) {
+                if (i0 + c >= NIo) break;
+                if (DP == 2) {
+                    ap2 += (double)av[c] * (double)av[c];
+                } else {
+                    const float r = ax[(i0 + c) * T::NJP + j] -
+                                    SY::ld(yk, (i64)(iA + i0 + c) * w + jA + j);
+                    ap2 += (double)(av[c] * av[c] * psi_quot(r, skd * av[c], epsd, e2d));
+                }
+            }
+        });
+        __syncthreads();
+    }
+    return DP == 2 ? 2.0 * ap2 : ap2;
+}
+
 // Accepted step: x <- x + alpha p, p <- -g_t + beta p (into the other buffer
 // of each pair), then Moller's curvature at the new (x, p) without forming
-// x + sigma_k p: data part 2 sum_k |A_k p|^2 (exact: the data term is
-// quadratic), prior part lambda sum gamma q^2 Q(z, sigma_k q).  Partial sums
-// {2 |A p|^2, prior part, |p|^2, p.r}.
-template <int S, int L, class ST>
+// x + sigma_k p: data part 2 sum_k |A_k p|^2 for the L2 term (exact: it is
+// quadratic) or sum_k (A_k p)^2 Q(A_k x - y_k, sigma_k A_k p) for the L1
+// (Charbonnier) term, prior part lambda sum gamma q^2 Q(z, sigma_k q).
+// Partial sums {data part, prior part, |p|^2, p.r}.
+template <int S, int L, class ST, class SY>
 FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, float *sm,
                     double *red, double *part) {
     using T = Tile<S, L>;
@@ -734,6 +787,7 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
     float *xs = sm;
     float *ps = xs + T::XS;
     float *hx = ps + T::XS;
+    float *ax = hx + T::HXS;    // A_k x at the owned LR pixels (L1 data term)
 
     const int src = st.upd_src, dst = src ^ 1;
     const AS1 raw *xb = glb((const raw *)P.x[src]);
@@ -781,26 +835,19 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
         }
     }
     __syncthreads();
-    // data part: |A_k p|^2 over the owned LR pixels (all edges are multiples of S)
+    // data part over the owned LR pixels (all edges are multiples of S): L2,
+    // 2 |A_k p|^2 (exact, the term is quadratic); L1 (Charbonnier), the sum of
+    // (A_k p)^2 Q(r, sk A_k p) with r = A_k x - y_k, the same quotient as the
+    // prior's pairs
     double ap2 = 0.0;
     const int NIo = (ou1 - ou0) / S, NJo = (ov1 - ov0) / S;
     const int iA = (P.gy0 + ou0) / S, jA = (P.gx0 + ov0) / S;
+    const int data_p = st.wt.data_p;
     if (NIo > 0 && NJo > 0) {
-        for (int k = 0; k < K; ++k) {
-            const int offy = op.offy[k], offx = op.offx[k];
-            const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
-            const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
-            pass1<S, L>(ps, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
-                        S * (NIo - 1) + L, NJo, wxk, jA, w - 1, hx);
-            __syncthreads();
-            pass2<S, L>(hx, NIo, NJo, wyk, iA, h - 1,
-                        [&](int i0, int, const float (&av)[T::CI]) {
-#pragma unroll
-                            for (int c = 0; c < T::CI; ++c)
-                                if (i0 + c < NIo) ap2 += (double)av[c] * (double)av[c];
-                        });
-            __syncthreads();
-        }
+        if (data_p == 2)
+            ap2 = upd_data_part<S, L, SY, 2>(P, st, o, xs, ps, hx, ax, NIo, NJo, iA, jA);
+        else
+            ap2 = upd_data_part<S, L, SY, 1>(P, st, o, xs, ps, hx, ax, NIo, NJo, iA, jA);
     }
     // prior part over the owned pairs (i, i+d)
     const float eps = st.wt.eps, sk = st.sigk_f;
@@ -820,7 +867,7 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
     else
         curv_sweep<S, L, true, false>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0,
                                       rv1, dreg);
-    double v[4] = {2.0 * ap2, dreg, pp, pr};
+    double v[4] = {ap2, dreg, pp, pr};
     block_sum_store<4, kNTI>(v, part, red);
 }
 
@@ -956,7 +1003,7 @@ __global__ void __launch_bounds__(kNTI, 4) k_trial(const Proj *projs, const Item
     }
 }
 
-template <int S, int L, class ST>
+template <int S, int L, class ST, class SY>
 __global__ void __launch_bounds__(kNTI, 4) k_upcurv(const Proj *projs, const Item *items,
                                                  const int *n_items, double *partials) {
     __shared__ float sm[Tile<S, L>::SMEM];
@@ -969,7 +1016,7 @@ __global__ void __launch_bounds__(kNTI, 4) k_upcurv(const Proj *projs, const Ite
         const AS4 Proj &P = cst(projs)[itm.proj];
         const AS4 ScgState &st = *cst(P.st);
         if (!st.do_update) continue;
-        tile_upcurv<S, L, ST>(P, st, itm.ty, itm.tx, sm, red, partials + (i64)it * kNV);
+        tile_upcurv<S, L, ST, SY>(P, st, itm.ty, itm.tx, sm, red, partials + (i64)it * kNV);
         __syncthreads();
     }
 }
@@ -1058,22 +1105,28 @@ hipError_t MISR_FN(launch_trial_s)(int Lp, int code, int grid, hipStream_t s, co
 hipError_t MISR_FN(launch_upcurv_s)(int Lp, int code, int grid, hipStream_t s, const Proj *projs,
                                     const Item *items, const int *n_items,
                                     double *partials) {
-    const int stype = st_x(code);
-#define X(l)                                                                                     \
-    if (Lp == l) {                                                                               \
-        if (stype == ST_F32)                                                                     \
-            hipLaunchKernelGGL((k_upcurv<MISR_SCALE, l, StF32>), dim3(grid), dim3(kNTI), 0, s,     \
-                               projs, items, n_items, partials);                         \
-        else if (stype == ST_F16)                                                                \
-            hipLaunchKernelGGL((k_upcurv<MISR_SCALE, l, StF16>), dim3(grid), dim3(kNTI), 0, s,     \
-                               projs, items, n_items, partials);                         \
-        else                                                                                     \
-            hipLaunchKernelGGL((k_upcurv<MISR_SCALE, l, StBF16>), dim3(grid), dim3(kNTI), 0, s,    \
-                               projs, items, n_items, partials);                         \
-        return hipGetLastError();                                                                \
+#define LAUNCH(l, SX, SY)                                                                      \
+    hipLaunchKernelGGL((k_upcurv<MISR_SCALE, l, SX, SY>), dim3(grid), dim3(kNTI), 0, s, projs, \
+                       items, n_items, partials)
+#define X(l)                                                                                   \
+    if (Lp == l) {                                                                             \
+        if (code == st_code(ST_F32, ST_F32))                                                   \
+            LAUNCH(l, StF32, StF32);                                                           \
+        else if (code == st_code(ST_F16, ST_F16))                                              \
+            LAUNCH(l, StF16, StF16);                                                           \
+        else if (code == st_code(ST_BF16, ST_BF16))                                            \
+            LAUNCH(l, StBF16, StBF16);                                                         \
+        else if (code == st_code(ST_F32, ST_F16))                                              \
+            LAUNCH(l, StF32, StF16);                                                           \
+        else if (code == st_code(ST_F32, ST_BF16))                                             \
+            LAUNCH(l, StF32, StBF16);                                                          \
+        else                                                                                   \
+            return hipErrorInvalidValue;                                                       \
+        return hipGetLastError();                                                              \
     }
     MISR_LIST(X)
 #undef X
+#undef LAUNCH
     return hipErrorInvalidValue;
 }
 

@@ -652,8 +652,6 @@ extern "C" misr_status misr_server_submit(misr_server *s, const misr_request *re
     misr_status st = misr_geometry_check(&req->geom);
     if (st != MISR_OK) return st;
     if ((st = misr_params_check(&req->params)) != MISR_OK) return st;
-    if (req->params.data_p != 2)
-        return set_error(MISR_E_INVAL, "served solves use the L2 data term (data_p = 2)");
     if (!req->y || !req->x0 || !req->x_out) return set_error(MISR_E_INVAL, "NULL buffer");
     auto r = std::make_unique<SReq>();
     r->req = *req;

@@ -200,3 +200,20 @@ def test_nonfinite_input_stops_with_numeric(misr, ctx):
     its, info = op.scg_solve(to_dev(y), x, misr.default_params(n_iter=10))
     assert info["stop"] == 2 and info["status"] == "E_NUMERIC"
     assert np.all(np.isfinite(to_np(x)))
+
+
+@pytest.mark.parametrize("eps_data", [1e-2, 1e-3])
+def test_l1_data_solve_matches_oracle(misr, ctx, eps_data):
+    """Eq. misr with p = 1 (Charbonnier-smoothed L1 data term): the device
+    solve, whose update pass takes the closed-form L1 curvature, against the
+    oracle's literal SCG (finite-difference curvature): image, success
+    sequence and cost per pass."""
+    n = 20
+    prob = problem(40, 2, 0.8, None, noise=("poisson", 1e4), jitter=0.05, n_iter=n,
+                   seeds=(11, 12, 13))
+    x_o, tr_o, _ = _oracle_solve(prob, n, data_p=1, eps_data=eps_data)
+    x_g, its, info = _gpu_solve(misr, ctx, prob, n, data_p=1, eps_data=eps_data)
+    err = rel_l2(x_g, x_o)
+    print(f"L1 data term, eps_data {eps_data}: rel-L2 {err:.3e}, {info['n_success']} accepted")
+    assert err <= TOL_SCG
+    _compare_traces(its, tr_o)

@@ -235,3 +235,29 @@ def test_fill_admission_keeps_arrival_order(misr, ctx):
     assert admits == sorted(admits) and dones == sorted(dones)
     assert admits[1] > admits[0] and admits[2] > admits[1]
     srv.close()
+
+
+def test_l1_requests_match_plain(misr, ctx, probs):
+    """Requests with the L1 data term, served beside L2 ones: each equals its
+    plain solve bit for bit."""
+    import torch
+    srv = misr.Server(ctx, hbm_budget_bytes=1 << 30)
+    cases = [(probs[0], SPECS[0][3], 1), (probs[1], SPECS[1][3], 2), (probs[4], SPECS[4][3], 1)]
+    ids, outs, refs = [], [], []
+    for p, n, dp in cases:
+        prm = misr.default_params(n_iter=n, data_p=dp, eps_data=1e-2)
+        op = misr.Operator(ctx, p.H, p.W, p.s, p.shifts, p.psf)
+        xr = to_dev(_f32(p.x0))
+        y = to_dev(_f32(p.y))
+        op.scg_solve(y, xr, prm)
+        refs.append(xr)
+        x0 = to_dev(_f32(p.x0))
+        out = torch.empty_like(x0)
+        outs.append(out)
+        ids.append(srv.submit(p.H, p.W, p.s, p.shifts, p.psf, y, x0, out,
+                              misr.default_params(n_iter=n, data_p=dp, eps_data=1e-2)))
+    for rid, out, ref in zip(ids, outs, refs):
+        assert srv.wait(rid, 60_000_000) == misr.OK
+        assert srv.poll(rid)[0] == misr.REQ_DONE
+        assert torch.equal(out, ref)
+    srv.close()

@@ -503,3 +503,33 @@ def test_psf_sizes_and_shift_order():
     sh3 = synth.frame_shifts(3, jitter=0.05, seed=1)
     assert sh3.shape == (9, 2) and np.all(sh3[0] == 0)
     assert np.all(np.abs(sh3[1:] - synth.frame_shifts(3)[1:]) <= 0.05)
+
+
+def test_l1_data_curvature_closed_form():
+    """Eq. misr with p = 1 (Charbonnier): the closed-form data curvature
+    sum (A p)^2 Q(A x - y, sk A p) equals p^T (grad E_data(x + sk p) -
+    grad E_data(x)) / sk taken literally (prior switched off), and tends to
+    p^T H_data p, H_data = A^T diag(psi'(r)) A, as sk -> 0."""
+    rng = np.random.default_rng(12)
+    H = W = 8
+    s, K = 2, 4
+    shifts = synth.frame_shifts(s, K, 0.05, 2)
+    psf = synth.psf_taps(0.6)
+    x = rng.uniform(0, 1, (H, W))
+    y = rng.uniform(0, 1, (K, 4, 4))
+    p = rng.standard_normal((H, W))
+    eps_d = 1e-2
+    for sk in (1e-4 / np.linalg.norm(p), 3e-2):
+        kw = dict(lambda_reg=0.0, data_p=1, eps_data=eps_d)
+        _, g0, _ = oracle.cost_grad(x, y, shifts, psf, s, **kw)
+        _, g1, _ = oracle.cost_grad(x + sk * p, y, shifts, psf, s, **kw)
+        d_fd = float(np.sum(p * (g1 - g0))) / sk
+        d_ex = oracle.curvature_data_l1(x, p, y, shifts, psf, s, sk, eps_d)
+        assert abs(d_fd - d_ex) <= 1e-9 * abs(d_ex) + 1e-12 / sk
+    # the limit from a dense system matrix and the Charbonnier second derivative
+    A = dense_A(H, W, shifts, psf, s)
+    r = A @ x.ravel() - y.ravel()
+    psi_p = eps_d ** 2 / (r * r + eps_d ** 2) ** 1.5
+    d_h = float((A @ p.ravel()) @ (psi_p * (A @ p.ravel())))
+    d_lim = oracle.curvature_data_l1(x, p, y, shifts, psf, s, 1e-12, eps_d)
+    assert abs(d_h - d_lim) <= 1e-9 * abs(d_h)
