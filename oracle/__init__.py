@@ -10,11 +10,12 @@ product.
 ``scg``  -- Moller's scaled conjugate gradient, step by step, in numpy.
 """
 from .ops import (build, forward, adjoint, cost_grad, btv, curvature_exact, curvature_data_l1,
+                  interpolate, upsample,
                   psi_quotient, num_threads, set_threads, warp, warp_T, blur, blur_T,
                   bin_, bin_T)
 from .scg import scg_minimize, solve, moller_scale_delta, moller_update_lambda
 
 __all__ = ["build", "forward", "adjoint", "cost_grad", "btv", "curvature_exact",
-           "curvature_data_l1",
+           "curvature_data_l1", "interpolate", "upsample",
            "psi_quotient", "num_threads", "set_threads", "warp", "warp_T", "blur",
            "blur_T", "bin_", "bin_T", "scg_minimize", "solve", "moller_scale_delta", "moller_update_lambda"]

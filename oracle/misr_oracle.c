@@ -325,6 +325,70 @@ double orc_curv_data_l1(int H, int W, int s, int K, const double *shifts, int P,
     return dd;
 }
 
+/* Multi-image interpolation, the paper's non-iterative fusion baseline
+ * (Sec. 3: LR pixel values inserted at their integer HR positions).  Frame
+ * k's pixel (i, j) lands on HR (s i + ty_k, s j + tx_k), t_k = round(s d_k)
+ * (halves away from zero); an HR pixel takes the mean of the samples landing
+ * on it, in frame order; one that receives none takes frame 0's pixel
+ * (floor(u / s), floor(v / s)). */
+void orc_interpolate(int H, int W, int s, int K, const double *shifts, const double *y,
+                     double *x) {
+    const int h = H / s, w = W / s;
+    int *ty = (int *)malloc(sizeof(int) * K), *tx = (int *)malloc(sizeof(int) * K);
+    for (int k = 0; k < K; ++k) {
+        tx[k] = (int)lround(s * shifts[2 * k + 0]);
+        ty[k] = (int)lround(s * shifts[2 * k + 1]);
+    }
+#pragma omp parallel for schedule(static)
+    for (int u = 0; u < H; ++u)
+        for (int v = 0; v < W; ++v) {
+            double acc = 0.0;
+            int n = 0;
+            for (int k = 0; k < K; ++k) {
+                const int a = u - ty[k], b = v - tx[k];
+                if (a < 0 || b < 0 || a % s != 0 || b % s != 0) continue;
+                const int i = a / s, j = b / s;
+                if (i >= h || j >= w) continue;
+                acc += y[((i64)k * h + i) * w + j];
+                ++n;
+            }
+            x[(i64)u * W + v] = n ? acc / n : y[(i64)(u / s) * w + v / s];
+        }
+    free(ty);
+    free(tx);
+}
+
+/* Keys cubic convolution kernel with a = -1/2. */
+static double keys(double t) {
+    t = fabs(t);
+    if (t <= 1.0) return (1.5 * t - 2.5) * t * t + 1.0;
+    if (t < 2.0) return ((-0.5 * t + 2.5) * t - 4.0) * t + 2.0;
+    return 0.0;
+}
+
+/* Bicubic upsampling of one LR frame by s (the solver's start point): HR
+ * sample u sits at LR coordinate (u + 1/2) / s - 1/2; the 4 x 4 taps around
+ * it take Keys weights, indices clamped to the frame.  Evaluated as the full
+ * 2-D sum (no separable passes). */
+void orc_upsample(int H, int W, int s, const double *lr, double *x) {
+    const int h = H / s, w = W / s;
+#pragma omp parallel for schedule(static)
+    for (int u = 0; u < H; ++u)
+        for (int v = 0; v < W; ++v) {
+            const double cy = (u + 0.5) / s - 0.5, cx = (v + 0.5) / s - 0.5;
+            const int iy = (int)floor(cy), ix = (int)floor(cx);
+            double acc = 0.0;
+            for (int a = -1; a <= 2; ++a)
+                for (int b = -1; b <= 2; ++b) {
+                    int i = iy + a, j = ix + b;
+                    i = i < 0 ? 0 : (i >= h ? h - 1 : i);
+                    j = j < 0 ? 0 : (j >= w ? w - 1 : j);
+                    acc += keys(cy - (iy + a)) * keys(cx - (ix + b)) * lr[(i64)i * w + j];
+                }
+            x[(i64)u * W + v] = acc;
+        }
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

@@ -56,6 +56,8 @@ def _load():
         "orc_psi_quotient": [_D, _D, _D],
         "orc_curv_exact": [_I, _I, _I, _I, _P, _I, _P, _D, _D, _D, _I, _D, _P, _P, _P],
         "orc_curv_data_l1": [_I, _I, _I, _I, _P, _I, _P, _D, _D, _P, _P, _P],
+        "orc_interpolate": [_I, _I, _I, _I, _P, _P, _P],
+        "orc_upsample": [_I, _I, _I, _P, _P],
         "orc_num_threads": [],
         "orc_set_threads": [_I],
     }
@@ -173,6 +175,24 @@ def cost_grad(x, y, shifts, psf, s, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3, w=
 
 def psi_quotient(b, h, eps):
     return _load().orc_psi_quotient(float(b), float(h), float(eps))
+
+
+def interpolate(y, shifts, s):
+    """Multi-image interpolation of the K frames y (K, h, w) onto the HR grid."""
+    y, shifts = _f64(y), _f64(shifts)
+    K, h, w = y.shape
+    x = np.empty((h * s, w * s))
+    _load().orc_interpolate(h * s, w * s, s, K, _p(shifts), _p(y), _p(x))
+    return x
+
+
+def upsample(lr, s):
+    """Keys bicubic upsampling (a = -1/2) of one LR frame by s."""
+    lr = _f64(lr)
+    h, w = lr.shape
+    x = np.empty((h * s, w * s))
+    _load().orc_upsample(h * s, w * s, s, _p(lr), _p(x))
+    return x
 
 
 def curvature_data_l1(x, p, y, shifts, psf, s, sk, eps_data=1e-3):

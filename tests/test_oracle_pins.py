@@ -533,3 +533,53 @@ def test_l1_data_curvature_closed_form():
     d_h = float((A @ p.ravel()) @ (psi_p * (A @ p.ravel())))
     d_lim = oracle.curvature_data_l1(x, p, y, shifts, psf, s, 1e-12, eps_d)
     assert abs(d_h - d_lim) <= 1e-9 * abs(d_h)
+
+
+@pytest.mark.parametrize("s,jitter", [(2, 0.0), (2, 0.05), (3, 0.04)])
+def test_interpolation_inverts_grid_sampling(s, jitter):
+    """Multi-image interpolation (Sec. 3): frames that sample an HR image at
+    every integer offset of the s x s grid are put back together exactly,
+    whatever jitter below half an HR pixel does to the shifts."""
+    rng = np.random.default_rng(20 + s)
+    H, W = 6 * s, 4 * s
+    x = rng.uniform(0, 1, (H, W))
+    shifts = synth.frame_shifts(s, s * s, jitter, 3)
+    t = np.rint(s * shifts).astype(int)          # (tx, ty) per frame
+    y = np.stack([x[t[k, 1]::s, t[k, 0]::s][:H // s, :W // s] for k in range(s * s)])
+    assert np.array_equal(oracle.interpolate(y, shifts, s), x)
+
+
+def test_interpolation_holes_and_collisions():
+    rng = np.random.default_rng(31)
+    y0 = rng.uniform(0, 1, (5, 7))
+    # one frame: every HR pixel is a hole but (2i, 2j): nearest upsampling
+    assert np.array_equal(oracle.interpolate(y0[None], np.zeros((1, 2)), 2),
+                          np.kron(y0, np.ones((2, 2))))
+    # two frames on the same offset: their mean there, frame 0 elsewhere
+    y1 = y0 + 0.25
+    xi = oracle.interpolate(np.stack([y0, y1]), np.zeros((2, 2)), 2)
+    assert np.allclose(xi[::2, ::2], y0 + 0.125, rtol=0, atol=1e-15)
+    assert np.array_equal(xi[1::2, 1::2], y0)
+
+
+def test_bicubic_start_point():
+    """Keys cubic convolution (a = -1/2): constants and linear ramps are
+    reproduced away from the clamped border, LR samples are hit exactly where
+    an HR centre falls on them (s = 3), and it agrees with the input
+    generator's separable implementation."""
+    rng = np.random.default_rng(41)
+    for s in (2, 3):
+        assert np.allclose(oracle.upsample(np.full((6, 5), 0.7), s), 0.7, rtol=0, atol=1e-15)
+        h, w = 9, 8
+        ii, jj = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+        ramp = 0.3 * ii - 0.2 * jj + 1.0
+        up = oracle.upsample(ramp, s)
+        uu, vv = np.meshgrid(np.arange(h * s), np.arange(w * s), indexing="ij")
+        want = 0.3 * ((uu + 0.5) / s - 0.5) - 0.2 * ((vv + 0.5) / s - 0.5) + 1.0
+        inner = (slice(2 * s, (h - 2) * s), slice(2 * s, (w - 2) * s))
+        assert np.allclose(up[inner], want[inner], rtol=0, atol=1e-12)
+        lr = rng.uniform(0, 1, (h, w))
+        assert np.allclose(oracle.upsample(lr, s), synth.bicubic_upsample(lr, s), rtol=0,
+                           atol=1e-12)
+    lr = rng.uniform(0, 1, (7, 6))
+    assert np.allclose(oracle.upsample(lr, 3)[1::3, 1::3], lr, rtol=0, atol=1e-14)
