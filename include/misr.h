@@ -110,6 +110,12 @@ typedef struct {
                             img_dtype itself (half the x traffic, but steps below
                             half a unit in the last place are lost, so the solve
                             stalls once steps get small) */
+    int32_t x_init;      /* start point of misr_scg_solve and served requests:
+                            0 the caller's x (default); 1 bicubic upsampling of
+                            frame 0 (misr_upsample); 2 multi-image interpolation
+                            (misr_interpolate); computed on the device into x,
+                            so served requests may pass x0 = NULL */
+    int32_t pad_;
 } misr_params;
 
 /* One SCG pass as recorded on the device. */
@@ -173,6 +179,23 @@ misr_status misr_forward(const misr_op *op, misr_dtype dt, const void *x, void *
 misr_status misr_adjoint(const misr_op *op, misr_dtype dt, const void *r, float *x,
                          void *stream);
 
+/* Multi-image interpolation, the paper's non-iterative fusion baseline
+ * (Sec. 3: LR pixel values inserted at their integer HR positions).  Frame
+ * k's pixel (i, j) is written to HR (s i + ty_k, s j + tx_k) with
+ * t_k = round(s d_k) (halves away from zero); an HR pixel that receives
+ * several samples takes their mean (frame order), one that receives none
+ * frame 0's pixel (floor(u/s), floor(v/s)).  y: device, K*(H/s)*(W/s) of
+ * dtype dt; x: device H*W of dtype dt (overwritten, rounded to nearest even
+ * for 16-bit dtypes). */
+misr_status misr_interpolate(const misr_op *op, misr_dtype dt, const void *y, void *x,
+                             void *stream);
+
+/* Bicubic upsampling of frame 0 by s (the solver's usual start point): Keys
+ * cubic convolution (a = -1/2), HR pixel u at LR coordinate (u + 1/2)/s - 1/2,
+ * taps clamped to the frame.  y, x as for misr_interpolate. */
+misr_status misr_upsample(const misr_op *op, misr_dtype dt, const void *y, void *x,
+                          void *stream);
+
 /* J(x) and grad J(x) (Eq. objective).  x, y: device, params->img_dtype.
  * g: device float32 H*W (overwritten).  cost_dev: device double[3] receiving
  * {J, data term, lambda * prior}.  Honours params->tile_lr. */
@@ -225,7 +248,7 @@ typedef struct {
     misr_geometry geom;       /* host arrays read during submit */
     misr_params params;       /* tile_lr > 0 splits a large request into tiles */
     const void *y;            /* K frames (device or host, see below) */
-    const void *x0;           /* initial HR image */
+    const void *x0;           /* initial HR image; NULL with params.x_init > 0 */
     void *x_out;              /* result (device or host) */
     int32_t on_device;        /* 1: y, x0, x_out are device pointers; 0: host */
     misr_done_cb done_cb;     /* nullable; called from the scheduler thread */

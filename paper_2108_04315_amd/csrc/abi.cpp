@@ -165,6 +165,7 @@ extern "C" misr_status misr_params_check(const misr_params *p) {
     if (p->x_rounding != 0 && p->x_rounding != 1)
         return set_error(MISR_E_INVAL, "x_rounding must be 0 or 1");
     if (p->x_work != 0 && p->x_work != 1) return set_error(MISR_E_INVAL, "x_work must be 0 or 1");
+    if (p->x_init < 0 || p->x_init > 2) return set_error(MISR_E_INVAL, "x_init must be 0, 1 or 2");
     return MISR_OK;
 }
 
@@ -479,6 +480,7 @@ static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
     pl.halos.clear();
     pl.tiled = false;
     pl.staged = false;
+    pl.inits.clear();
     pl.vt = in.empty() ? (int)ST_F32 : view_stype(in[0].prm);
     pl.gt = in.empty() ? (int)ST_F32 : (int)in[0].prm.img_dtype;
     const size_t ns = in.size();
@@ -509,6 +511,9 @@ static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
                 pl.states[i].xglob = si.x;
                 pl.states[i].ldg = op->W;
             }
+            if (si.prm.x_init > 0)
+                pl.inits.push_back(Plan::Init{si.prm.x_init, init_args(op), si.y, si.x,
+                                              (int)si.prm.img_dtype});
             add_views(op, si.prm, si.y, si.x, si.bufs, si.tiles, pl.projs, pl.items, pl.items_u,
                       pl.halos);
             pl.proj_solve.resize(pl.projs.size(), i);
@@ -524,7 +529,13 @@ static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
 }
 
 static std::string plan_key(const Plan &pl, int n_iter) {
-    std::string k = std::to_string(n_iter) + "/" + std::to_string(pl.code()) + "/" +
+    std::string k = std::to_string(n_iter) + "/" + std::to_string(pl.code()) + "/i";
+    for (auto &it : pl.inits) {
+        char b[64];
+        snprintf(b, sizeof b, "%d,%p,%p;", it.kind, it.y, it.x);
+        k += b;
+    }
+    k += "/" +
                      std::to_string(pl.states.size()) + "/" + std::to_string(pl.projs.size()) +
                      "/" + std::to_string(pl.halos.size()) + (pl.staged ? "S" : "U");
     for (auto &c : pl.classes)
@@ -575,6 +586,7 @@ static hipError_t enqueue_solve(const Plan &pl, PlanDev &pd, int n_iter, hipStre
     hipError_t e = hipSuccess;
 #define STEP(x)                          \
     if ((e = (x)) != hipSuccess) return e;
+    for (auto &it : pl.inits) STEP(launch_init(s, it.kind, it.a, it.y, it.x, it.st));
     if (pl.staged) STEP(launch_scatter(s, pd.projs.as<Proj>(), np, pl.vt, pl.gt));
     STEP(Lr.image(KIND_COSTGRAD));
     STEP(Lr.halo());
@@ -703,6 +715,40 @@ extern "C" misr_status misr_adjoint(const misr_op *cop, misr_dtype dt, const voi
     return MISR_OK;
 }
 
+InitArgs misr::init_args(const misr_op *op) {
+    InitArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.H = op->H;
+    a.W = op->W;
+    a.s = op->s;
+    a.K = op->K;
+    for (int k = 0; k < op->K; ++k) {
+        a.tx[k] = (int)std::lround(op->s * op->shifts[2 * k + 0]);
+        a.ty[k] = (int)std::lround(op->s * op->shifts[2 * k + 1]);
+    }
+    return a;
+}
+
+static misr_status start_point(const misr_op *op, int kind, misr_dtype dt, const void *y,
+                               void *x, void *stream) {
+    if (!op || !y || !x) return set_error(MISR_E_INVAL, "NULL argument");
+    if (dt != MISR_F32 && dt != MISR_F16 && dt != MISR_BF16)
+        return set_error(MISR_E_INVAL, "dtype invalid");
+    MISR_HIP(set_device(op->ctx->dev));
+    MISR_HIP(launch_init((hipStream_t)stream, kind, init_args(op), y, x, (int)dt));
+    return MISR_OK;
+}
+
+extern "C" misr_status misr_interpolate(const misr_op *op, misr_dtype dt, const void *y, void *x,
+                                        void *stream) {
+    return start_point(op, 2, dt, y, x, stream);
+}
+
+extern "C" misr_status misr_upsample(const misr_op *op, misr_dtype dt, const void *y, void *x,
+                                     void *stream) {
+    return start_point(op, 1, dt, y, x, stream);
+}
+
 extern "C" misr_status misr_cost_grad(const misr_op *cop, const misr_params *prm, const void *x,
                                       const void *y, float *g, double *cost_dev, void *stream) {
     misr_op *op = const_cast<misr_op *>(cop);
@@ -720,6 +766,7 @@ extern "C" misr_status misr_cost_grad(const misr_op *cop, const misr_params *prm
     SolveIn si{op, *prm, y, const_cast<void *>(x), &op->bufs, &op->tiles};
     si.prm.n_iter = 0;
     si.prm.x_work = 1;   // evaluated at x as stored: no FP32 copy
+    si.prm.x_init = 0;
     build_plan(pl, {si});
     if (pl.tiled)
         pl.states[0].gglob = g;
@@ -840,6 +887,7 @@ extern "C" misr_status misr_time_pass(const misr_op *cop, const misr_params *prm
     misr_params p1 = *prm;
     p1.n_iter = 1;
     p1.x_work = 1;   // the passes over x as stored
+    p1.x_init = 0;
     build_plan(pl, {SolveIn{op, p1, y, x, &op->bufs, nullptr}});
     PlanDev &pd = op->pdev;
     hipStream_t s = op->ctx->stream;

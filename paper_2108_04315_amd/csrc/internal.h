@@ -107,6 +107,13 @@ struct SolveRef {
     int item0u, nitemsu;   // update-pass items (owned plus halo)
 };
 
+// Start-point kernels (interpolation, bicubic): grid and per-frame integer
+// HR offsets t = round(s d).
+struct InitArgs {
+    int H, W, s, K;
+    int ty[kMaxK], tx[kMaxK];
+};
+
 struct IterRec {
     double E, E_t, delta, mu, alpha, Delta, lam;
     int success, pad_;

@@ -40,6 +40,10 @@ hipError_t launch_cost_out(hipStream_t stream, const double *partials, int nitem
                            double *out);
 hipError_t launch_fill(hipStream_t stream, float *p, long long n, float v);
 hipError_t launch_finalize(hipStream_t stream, const Proj *projs, int nproj, int stype);
+// start point into x (caller storage st): kind 1 bicubic of frame 0, 2 multi-image
+// interpolation
+hipError_t launch_init(hipStream_t stream, int kind, const InitArgs &a, const void *y, void *x,
+                       int st);
 
 enum { KIND_COSTGRAD = 0, KIND_TRIAL = 1, KIND_UPCURV = 2 };
 enum { PHASE_INIT = 0, PHASE_A = 1, PHASE_B = 2 };
@@ -145,6 +149,14 @@ struct Plan {
     std::vector<int> item0u, nitemsu; // per solve: its range of update items
     std::vector<SolveRef> refs;       // device-side references (filled by upload)
     std::vector<HaloCopy> halos;      // halo exchanges after each trial pass
+    struct Init {                     // start points computed on the device
+        int kind;
+        InitArgs a;
+        const void *y;
+        void *x;
+        int st;
+    };
+    std::vector<Init> inits;
     bool tiled = false;               // some solve is split into tiles
     bool staged = false;              // some solve's iterate lives in library views
                                       // (tiled, or FP32 over a 16-bit caller image)
@@ -256,6 +268,9 @@ TileGrid tile_grid(const misr_op *op, const misr_params &p);
 misr_status check_tiling(const misr_op *op, const misr_params &p);
 // Per-tile buffers (halo included) of a tiled solve.
 hipError_t ensure_tiles(const misr_op *op, const misr_params &p, TileSet &ts);
+// Grid and integer HR frame offsets of an operator for the start-point kernels.
+InitArgs init_args(const misr_op *op);
+
 // Appends one solve's views (one untiled view, or one per tile plus the halo
 // copies between them) with their trial and update items; Proj::st is left
 // for the caller.

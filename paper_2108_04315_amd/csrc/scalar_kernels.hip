@@ -307,6 +307,71 @@ __global__ void k_gather(const Proj *__restrict__ projs, int nproj, int vt, int 
     }
 }
 
+// ------------------------------------------------------- start points
+// Multi-image interpolation: frame k's pixel (i, j) lands on HR
+// (s i + ty_k, s j + tx_k); mean of the samples landing on a pixel, in frame
+// order; frame 0's covering pixel where none lands.
+__global__ void k_interpolate(InitArgs a, const void *y, void *x, int st) {
+    const int h = a.H / a.s, w = a.W / a.s;
+    const long long n = (long long)a.H * a.W;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int u = (int)(q / a.W), v = (int)(q - (long long)u * a.W);
+        float acc = 0.f;
+        int cnt = 0;
+        for (int k = 0; k < a.K; ++k) {
+            const int r = u - a.ty[k], c = v - a.tx[k];
+            if (r < 0 || c < 0 || r % a.s != 0 || c % a.s != 0) continue;
+            const int i = r / a.s, j = c / a.s;
+            if (i >= h || j >= w) continue;
+            acc += ld_any(y, ((long long)k * h + i) * w + j, st);
+            ++cnt;
+        }
+        st_any(x, q, st, cnt ? acc / (float)cnt : ld_any(y, (long long)(u / a.s) * w + v / a.s, st));
+    }
+}
+
+// Keys cubic convolution weight (a = -1/2).
+__device__ __forceinline__ float keys_w(float t) {
+    t = fabsf(t);
+    if (t <= 1.f) return (1.5f * t - 2.5f) * t * t + 1.f;
+    if (t < 2.f) return ((-0.5f * t + 2.5f) * t - 4.f) * t + 2.f;
+    return 0.f;
+}
+
+// Bicubic upsampling of frame 0: HR pixel u at LR coordinate (u + 1/2)/s - 1/2,
+// 4 x 4 taps clamped to the frame.
+__global__ void k_upsample(InitArgs a, const void *y, void *x, int st) {
+    const int h = a.H / a.s, w = a.W / a.s;
+    const long long n = (long long)a.H * a.W;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int u = (int)(q / a.W), v = (int)(q - (long long)u * a.W);
+        const double cy = (u + 0.5) / a.s - 0.5, cx = (v + 0.5) / a.s - 0.5;
+        const int iy = (int)floor(cy), ix = (int)floor(cx);
+        const float fy = (float)(cy - iy), fx = (float)(cx - ix);
+        float wy[4], wx[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            wy[t] = keys_w(fy - (t - 1));
+            wx[t] = keys_w(fx - (t - 1));
+        }
+        float acc = 0.f;
+#pragma unroll
+        for (int ta = 0; ta < 4; ++ta) {
+            const int i = min(max(iy + ta - 1, 0), h - 1);
+            float row = 0.f;
+#pragma unroll
+            for (int tb = 0; tb < 4; ++tb) {
+                const int j = min(max(ix + tb - 1, 0), w - 1);
+                row = fmaf(wx[tb], ld_any(y, (long long)i * w + j, st), row);
+            }
+            acc = fmaf(wy[ta], row, acc);
+        }
+        st_any(x, q, st, acc);
+    }
+}
+
 // ------------------------------------------------------------- dispatching
 #define MISR_SCALES(X) X(1) X(2) X(3) X(4)
 #define X(s)                                                                                   \
@@ -426,6 +491,19 @@ hipError_t launch_fill(hipStream_t stream, float *p, long long n, float v) {
     long long blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(hipStream_t stream, int kind, const InitArgs &a, const void *y, void *x,
+                       int st) {
+    const long long n = (long long)a.H * a.W;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (kind == 1)
+        hipLaunchKernelGGL(k_upsample, dim3((unsigned)blocks), dim3(256), 0, stream, a, y, x, st);
+    else
+        hipLaunchKernelGGL(k_interpolate, dim3((unsigned)blocks), dim3(256), 0, stream, a, y, x,
+                           st);
     return hipGetLastError();
 }
 

@@ -221,7 +221,7 @@ bool misr_server::setup(SReq *r) {
     if (q.on_device) {
         r->x0dev = q.x_out;
         r->ydev_ptr = q.y;
-        if (q.x0 != q.x_out &&
+        if (q.x0 && q.x0 != q.x_out &&
             hipMemcpyAsync(q.x_out, q.x0, r->n * r->es, hipMemcpyDeviceToDevice, stream) !=
                 hipSuccess)
             return false;
@@ -230,8 +230,8 @@ bool misr_server::setup(SReq *r) {
         if (r->ydev.ensure(m * r->es) != hipSuccess) return false;
         r->x0dev = r->xwork.p;
         r->ydev_ptr = r->ydev.p;
-        if (hipMemcpyAsync(r->xwork.p, q.x0, r->n * r->es, hipMemcpyHostToDevice, stream) !=
-                hipSuccess ||
+        if ((q.x0 && hipMemcpyAsync(r->xwork.p, q.x0, r->n * r->es, hipMemcpyHostToDevice,
+                                    stream) != hipSuccess) ||
             hipMemcpyAsync(r->ydev.p, q.y, m * r->es, hipMemcpyHostToDevice, stream) !=
                 hipSuccess)
             return false;
@@ -404,12 +404,17 @@ hipError_t misr_server::enqueue_halo(List &L, bool fresh) {
                        L.cnt((fresh ? 2 * nc + 2 : 0) + 2 * nc + 1), (int)n);
 }
 
-// Init of the newly admitted solves over their sub-range of the list: tiled
-// ones scatter x0 into their tiles; cost and gradient at x0 (and its halo
+// Init of the newly admitted solves over their sub-range of the list: start
+// points computed on the device where asked for; tiled ones scatter x0 into
+// their tiles; cost and gradient at x0 (and its halo
 // exchange), Moller's init, update pass (p = -g0) with curvature, then steps
 // 1-5 of their first pass.
 hipError_t misr_server::enqueue_init(List &L) {
     hipError_t e = hipSuccess;
+    for (SReq *r : active)   // start points computed on the device
+        if (e == hipSuccess && r->fresh && r->req.params.x_init > 0)
+            e = launch_init(stream, r->req.params.x_init, init_args(r->op), r->ydev_ptr,
+                            r->x0dev, (int)r->req.params.img_dtype);
     for (SReq *r : active)
         if (e == hipSuccess && r->fresh && r->staged)
             e = launch_scatter(stream, L.projs.as<Proj>() + r->view0, r->nviews,
@@ -652,7 +657,8 @@ extern "C" misr_status misr_server_submit(misr_server *s, const misr_request *re
     misr_status st = misr_geometry_check(&req->geom);
     if (st != MISR_OK) return st;
     if ((st = misr_params_check(&req->params)) != MISR_OK) return st;
-    if (!req->y || !req->x0 || !req->x_out) return set_error(MISR_E_INVAL, "NULL buffer");
+    if (!req->y || !req->x_out || (!req->x0 && req->params.x_init == 0))
+        return set_error(MISR_E_INVAL, "NULL buffer (x0 may be NULL only with x_init > 0)");
     auto r = std::make_unique<SReq>();
     r->req = *req;
     r->shifts.assign(req->geom.shifts_lr, req->geom.shifts_lr + 2 * req->geom.n_frames);

@@ -49,7 +49,8 @@ class misr_params(C.Structure):
                 ("btv_w", C.c_int32), ("data_p", C.c_int32), ("eps_data", C.c_double),
                 ("scg_sigma", C.c_double), ("scg_lambda1", C.c_double), ("n_iter", C.c_int32),
                 ("img_dtype", C.c_int32), ("tile_lr", C.c_int32), ("halo_lr", C.c_int32),
-                ("x_rounding", C.c_int32), ("x_work", C.c_int32)]
+                ("x_rounding", C.c_int32), ("x_work", C.c_int32), ("x_init", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 class misr_scg_iter(C.Structure):
@@ -96,6 +97,8 @@ _SIGS = {
     "misr_op_destroy": (C.c_int, [_vp]),
     "misr_op_band": (C.c_int, [_vp]),
     "misr_forward": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "misr_interpolate": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "misr_upsample": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "misr_adjoint": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "misr_cost_grad": (C.c_int, [_vp, C.POINTER(misr_params), _vp, _vp, _vp, _vp, _vp]),
     "misr_scg_solve": (C.c_int, [_vp, C.POINTER(misr_params), _vp, _vp,
@@ -234,6 +237,23 @@ class Operator:
         check(lib.misr_forward(self.h, dtype_code(x), _ptr(x), _ptr(y), stream_handle(stream)))
         return y
 
+    def interpolate(self, y, x=None, stream=None):
+        """Multi-image interpolation of the frames y onto the HR grid."""
+        torch = _torch()
+        if x is None:
+            x = torch.empty((self.H, self.W), dtype=y.dtype, device=y.device)
+        check(lib.misr_interpolate(self.h, dtype_code(y), _ptr(y), _ptr(x),
+                                   stream_handle(stream)))
+        return x
+
+    def upsample(self, y, x=None, stream=None):
+        """Bicubic upsampling of frame 0 (the solver's start point)."""
+        torch = _torch()
+        if x is None:
+            x = torch.empty((self.H, self.W), dtype=y.dtype, device=y.device)
+        check(lib.misr_upsample(self.h, dtype_code(y), _ptr(y), _ptr(x), stream_handle(stream)))
+        return x
+
     def adjoint(self, r, x=None, stream=None):
         torch = _torch()
         if x is None:
@@ -334,14 +354,16 @@ class Server:
     def submit(self, H, W, s, shifts, psf, y, x0, x_out, params: misr_params | None = None,
                on_device: bool = True) -> int:
         """Queues one solve; y, x0, x_out are device tensors (or host numpy
-        arrays with on_device=False) that must stay alive until it finishes."""
+        arrays with on_device=False) that must stay alive until it finishes;
+        x0 may be None with params.x_init > 0 (start point computed on the
+        device)."""
         g, keep = make_geometry(H, W, s, shifts, psf)
         p = params or default_params()
         if on_device:
-            p.img_dtype = dtype_code(x0)
-            ptrs = (y.data_ptr(), x0.data_ptr(), x_out.data_ptr())
+            p.img_dtype = dtype_code(x_out)
+            ptrs = (y.data_ptr(), x0.data_ptr() if x0 is not None else None, x_out.data_ptr())
         else:
-            ptrs = (y.ctypes.data, x0.ctypes.data, x_out.ctypes.data)
+            ptrs = (y.ctypes.data, x0.ctypes.data if x0 is not None else None, x_out.ctypes.data)
         req = misr_request(g, p, ptrs[0], ptrs[1], ptrs[2], 1 if on_device else 0,
                            DONE_CB(0), None)
         rid = C.c_uint64()

@@ -1,0 +1,103 @@
+"""Start points on the device (through the C ABI) against the oracle: the
+paper's multi-image interpolation (Sec. 3 fusion baseline) and the bicubic
+upsampling of frame 0; solves and served requests that compute their start
+point on the device."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import scg as oscg
+from paper_2108_04315_amd import synth
+from gpu_common import TOL_OP, TOL_SCG, problem, rel_l2, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def misr():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2108_04315_amd import misr as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(misr):
+    c = misr.Context(0)
+    yield c
+    c.close()
+
+
+def _f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+# (h, w, s, K, jitter): LR frame size, scale, frames
+CASES = [(64, 48, 2, 4, 0.05), (30, 41, 3, 9, 0.04), (17, 23, 2, 1, 0.0), (40, 40, 2, 2, 0.0),
+         (12, 20, 4, 16, 0.03)]
+
+
+@pytest.mark.parametrize("h,w,s,K,jit", CASES)
+def test_interpolate_and_upsample_parity(misr, ctx, h, w, s, K, jit):
+    rng = np.random.default_rng(h + w)
+    shifts = synth.frame_shifts(s, K, jit, 5)
+    psf = synth.psf_taps(0.8)
+    op = misr.Operator(ctx, h * s, w * s, s, shifts, psf)
+    y = _f32(rng.uniform(0, 1, (K, h, w)))
+    xi = to_np(op.interpolate(to_dev(y)))
+    assert rel_l2(xi, oracle.interpolate(y, shifts, s)) <= TOL_OP
+    xu = to_np(op.upsample(to_dev(y)))
+    assert rel_l2(xu, oracle.upsample(y[0], s)) <= TOL_OP
+
+
+def test_interpolate_bf16_storage(misr, ctx):
+    """16-bit frames in, 16-bit image out: the oracle's result on the stored
+    frames, rounded to bfloat16, to within one unit in the last place."""
+    import torch
+    s, K, h, w = 2, 4, 32, 40
+    shifts = synth.frame_shifts(s, K, 0.05, 2)
+    op = misr.Operator(ctx, h * s, w * s, s, shifts, synth.psf_taps(0.8))
+    yh = torch.from_numpy(np.random.default_rng(3).uniform(0, 1, (K, h, w))).to(torch.bfloat16)
+    xg = op.interpolate(yh.cuda()).cpu().double().numpy()
+    xo = torch.from_numpy(oracle.interpolate(yh.double().numpy(), shifts, s))
+    ulp = 2.0 ** -7 * np.abs(xo.numpy())
+    assert np.all(np.abs(xg - xo.to(torch.bfloat16).double().numpy()) <= ulp)
+
+
+def test_solve_from_device_start_point(misr, ctx):
+    """x_init = 1: the solve starts from the bicubic upsample computed on the
+    device (inside the captured solve); it equals the solve started from
+    misr_upsample's output bit for bit, and the oracle's solve from its own
+    bicubic start within the SCG bound."""
+    import torch
+    n = 25
+    p = problem(48, 2, 0.8, None, jitter=0.05, n_iter=n, seeds=(4, 5, 6))
+    op = misr.Operator(ctx, p.H, p.W, p.s, p.shifts, p.psf)
+    y = to_dev(_f32(p.y))
+    xa = torch.full((p.H, p.W), float("nan"), device="cuda")   # overwritten by the start point
+    op.scg_solve(y, xa, misr.default_params(n_iter=n, x_init=1))
+    xb = op.upsample(y)
+    op.scg_solve(y, xb, misr.default_params(n_iter=n))
+    assert torch.equal(xa, xb)
+    x0_o = oracle.upsample(_f32(p.y)[0], p.s)
+    x_o, _, _ = oscg.solve(_f32(p.y), p.shifts, p.psf, p.s, x0_o, n)
+    assert rel_l2(to_np(xa), x_o) <= TOL_SCG
+
+
+@pytest.mark.parametrize("x_init", [1, 2])
+def test_served_request_without_x0(misr, ctx, x_init):
+    import torch
+    n = 12
+    p = problem(40, 2, 0.8, None, jitter=0.05, n_iter=n, seeds=(7, 8, 9))
+    op = misr.Operator(ctx, p.H, p.W, p.s, p.shifts, p.psf)
+    y = to_dev(_f32(p.y))
+    ref = torch.empty((p.H, p.W), device="cuda")
+    op.scg_solve(y, ref, misr.default_params(n_iter=n, x_init=x_init))
+    srv = misr.Server(ctx, hbm_budget_bytes=1 << 30)
+    out = torch.empty_like(ref)
+    rid = srv.submit(p.H, p.W, p.s, p.shifts, p.psf, y, None, out,
+                     misr.default_params(n_iter=n, x_init=x_init))
+    assert srv.wait(rid, 60_000_000) == misr.OK
+    assert srv.poll(rid)[0] == misr.REQ_DONE
+    assert torch.equal(out, ref)
+    srv.close()
