@@ -972,8 +972,10 @@ FI void tile_adjoint(const AS4 Proj &P, int ty, int tx, const void *r, float *xo
 }
 
 // -------------------------------------------------------------- the kernels
-// Each kernel walks the work list with a grid stride; the item count is read
-// from device memory so that one captured launch can serve a changing list.
+// The item count is read from device memory so that one captured launch can
+// serve a changing list; the trial and update kernels are launched with one
+// workgroup per item, the standalone operators walk the list with a grid
+// stride.
 //
 // Workgroups are dispatched to the 8 XCDs round-robin in blockIdx order, and
 // each XCD has its own L2.  With one workgroup per item, workgroup b takes
@@ -990,17 +992,17 @@ __global__ void __launch_bounds__(kNTI, 4) k_trial(const Proj *projs, const Item
                                                 int mode) {
     __shared__ float sm[Tile<S, L>::SMEM];
     __shared__ double red[kNV * kNWI];
+    // one workgroup per item (the launch grid is the item count): no loop, so
+    // nothing is hoisted out of one and kept live through the tile
     const int n = *cst(n_items);
-    const bool remap = (int)gridDim.x == n;
-    for (int b = blockIdx.x; b < n; b += gridDim.x) {
-        const int it = remap ? xcd_item(b, n) : b;
-        const AS4 Item &itm = cst(items)[it];
-        const AS4 Proj &P = cst(projs)[itm.proj];
-        const AS4 ScgState &st = *cst(P.st);
-        if (mode == 1 && !st.active) continue;
-        tile_trial<S, L, ST, SY>(P, st, itm.ty, itm.tx, mode, sm, red, partials + (i64)it * kNV);
-        __syncthreads();
-    }
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int it = (int)gridDim.x == n ? xcd_item(b, n) : b;
+    const AS4 Item &itm = cst(items)[it];
+    const AS4 Proj &P = cst(projs)[itm.proj];
+    const AS4 ScgState &st = *cst(P.st);
+    if (mode == 1 && !st.active) return;
+    tile_trial<S, L, ST, SY>(P, st, itm.ty, itm.tx, mode, sm, red, partials + (i64)it * kNV);
 }
 
 template <int S, int L, class ST, class SY>
@@ -1009,16 +1011,14 @@ __global__ void __launch_bounds__(kNTI, 4) k_upcurv(const Proj *projs, const Ite
     __shared__ float sm[Tile<S, L>::SMEM];
     __shared__ double red[kNV * kNWI];
     const int n = *cst(n_items);
-    const bool remap = (int)gridDim.x == n;
-    for (int b = blockIdx.x; b < n; b += gridDim.x) {
-        const int it = remap ? xcd_item(b, n) : b;
-        const AS4 Item &itm = cst(items)[it];
-        const AS4 Proj &P = cst(projs)[itm.proj];
-        const AS4 ScgState &st = *cst(P.st);
-        if (!st.do_update) continue;
-        tile_upcurv<S, L, ST, SY>(P, st, itm.ty, itm.tx, sm, red, partials + (i64)it * kNV);
-        __syncthreads();
-    }
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int it = (int)gridDim.x == n ? xcd_item(b, n) : b;
+    const AS4 Item &itm = cst(items)[it];
+    const AS4 Proj &P = cst(projs)[itm.proj];
+    const AS4 ScgState &st = *cst(P.st);
+    if (!st.do_update) return;
+    tile_upcurv<S, L, ST, SY>(P, st, itm.ty, itm.tx, sm, red, partials + (i64)it * kNV);
 }
 
 template <int S, int L, class ST>

@@ -21,7 +21,9 @@ namespace misr {
 int padded_band(int S, int L);
 int tile_hr(int S, int Lp);
 int tile_wr(int S, int Lp);
-// code = st_code(storage of the views' x, storage of y)
+// code = st_code(storage of the views' x, storage of y).  grid must equal the
+// item count (*n_items): the trial and update kernels run one workgroup per
+// item.
 hipError_t launch_image(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
                         const Item *items, const int *n_items, double *partials, int kind,
                         int code);
