@@ -77,16 +77,10 @@ void orc_warp_T(int H, int W, double tx, double ty, const double *z, double *out
 }
 
 /* ---------------------------------------------------------------- blur B */
-static double *psf2d(int P, const double *psf) {
-    double *h = (double *)malloc(sizeof(double) * P * P);
-    for (int a = 0; a < P; ++a)
-        for (int b = 0; b < P; ++b) h[a * P + b] = psf[a] * psf[b];
-    return h;
-}
-
-void orc_blur(int H, int W, int P, const double *psf, const double *z, double *out) {
+/* h: the P x P PSF (row-major, h[(a+R) P + (b+R)] weights the sample at
+ * offset (-a, -b)); "same" convolution with zero padding. */
+void orc_blur(int H, int W, int P, const double *h, const double *z, double *out) {
     const int R = (P - 1) / 2;
-    double *h = psf2d(P, psf);
 #pragma omp parallel for schedule(static)
     for (i64 u = 0; u < H; ++u)
         for (i64 v = 0; v < W; ++v) {
@@ -96,12 +90,10 @@ void orc_blur(int H, int W, int P, const double *psf, const double *z, double *o
                     acc += h[(a + R) * P + (b + R)] * at(z, H, W, u - a, v - b);
             out[u * W + v] = acc;
         }
-    free(h);
 }
 
-void orc_blur_T(int H, int W, int P, const double *psf, const double *w, double *out) {
+void orc_blur_T(int H, int W, int P, const double *h, const double *w, double *out) {
     const int R = (P - 1) / 2;
-    double *h = psf2d(P, psf);
 #pragma omp parallel for schedule(static)
     for (i64 u = 0; u < H; ++u)
         for (i64 v = 0; v < W; ++v) {
@@ -111,7 +103,6 @@ void orc_blur_T(int H, int W, int P, const double *psf, const double *w, double 
                     acc += h[(a + R) * P + (b + R)] * at(w, H, W, u + a, v + b);
             out[u * W + v] = acc;
         }
-    free(h);
 }
 
 /* ---------------------------------------------------------------- bin D */
@@ -137,7 +128,8 @@ void orc_bin_T(int H, int W, int s, const double *r, double *out) {
 }
 
 /* ------------------------------------------------------ A_k and sum A_k^T */
-/* y has K frames of (H/s) x (W/s); shifts is K x 2 as (dx, dy) in LR px. */
+/* y has K frames of (H/s) x (W/s); shifts is K x 2 as (dx, dy) in LR px;
+ * psf holds each frame's P x P PSF (K of them: B_k may differ per frame). */
 void orc_forward(int H, int W, int s, int K, const double *shifts, int P,
                  const double *psf, const double *x, double *y) {
     const i64 n = (i64)H * W, m = (i64)(H / s) * (W / s);
@@ -145,7 +137,7 @@ void orc_forward(int H, int W, int s, int K, const double *shifts, int P,
     double *t2 = (double *)malloc(sizeof(double) * n);
     for (int k = 0; k < K; ++k) {
         orc_warp(H, W, s * shifts[2 * k], s * shifts[2 * k + 1], x, t1);
-        orc_blur(H, W, P, psf, t1, t2);
+        orc_blur(H, W, P, psf + (i64)k * P * P, t1, t2);
         orc_bin(H, W, s, t2, y + k * m);
     }
     free(t1);
@@ -160,7 +152,7 @@ void orc_adjoint(int H, int W, int s, int K, const double *shifts, int P,
     memset(x, 0, sizeof(double) * n);
     for (int k = 0; k < K; ++k) {
         orc_bin_T(H, W, s, r + k * m, t1);
-        orc_blur_T(H, W, P, psf, t1, t2);
+        orc_blur_T(H, W, P, psf + (i64)k * P * P, t1, t2);
         orc_warp_T(H, W, s * shifts[2 * k], s * shifts[2 * k + 1], t2, t1);
 #pragma omp parallel for schedule(static)
         for (i64 i = 0; i < n; ++i) x[i] += t1[i];

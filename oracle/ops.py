@@ -3,7 +3,7 @@
 Each function takes and returns float64 numpy arrays and forwards to the plain
 C definitions in ``misr_oracle.c``.  Shapes: HR images (H, W); LR frames
 (K, H//s, W//s); shifts (K, 2) as (dx, dy) in LR pixels; psf the 1-D taps whose
-outer product is the 2-D PSF.
+outer product is the 2-D PSF, or per-frame PSFs (see psf_frames).
 """
 from __future__ import annotations
 
@@ -75,6 +75,21 @@ def _load():
     return lib
 
 
+def psf_frames(psf, K):
+    """Each frame's P x P PSF as a (K, P, P) array (the blur B_k of frame k,
+    Eq. sisr with A_k = D B_k M_k).  psf: (P,) taps shared by both axes and
+    all frames (2-D PSF = outer product); (P, P) one 2-D PSF for all frames;
+    (K, 2, P) per frame, row taps then column taps; (K, P, P) per frame."""
+    psf = np.asarray(psf, dtype=np.float64)
+    if psf.ndim == 1:
+        return np.ascontiguousarray(np.broadcast_to(np.outer(psf, psf), (K,) + (psf.size,) * 2))
+    if psf.ndim == 2:
+        return np.ascontiguousarray(np.broadcast_to(psf, (K,) + psf.shape))
+    if psf.shape[1] == 2 and psf.shape[2] != 2:
+        return np.ascontiguousarray(np.einsum("ka,kb->kab", psf[:, 0], psf[:, 1]))
+    return np.ascontiguousarray(psf)
+
+
 def _p(a):
     return None if a is None else a.ctypes.data_as(_P)
 
@@ -106,16 +121,16 @@ def warp_T(z, tx, ty):
 
 
 def blur(z, psf):
-    z, psf = _f64(z), _f64(psf)
+    z, psf = _f64(z), psf_frames(psf, 1)[0]
     out = np.empty_like(z)
-    _load().orc_blur(z.shape[0], z.shape[1], psf.size, _p(psf), _p(z), _p(out))
+    _load().orc_blur(z.shape[0], z.shape[1], psf.shape[0], _p(psf), _p(z), _p(out))
     return out
 
 
 def blur_T(w, psf):
-    w, psf = _f64(w), _f64(psf)
+    w, psf = _f64(w), psf_frames(psf, 1)[0]
     out = np.empty_like(w)
-    _load().orc_blur_T(w.shape[0], w.shape[1], psf.size, _p(psf), _p(w), _p(out))
+    _load().orc_blur_T(w.shape[0], w.shape[1], psf.shape[0], _p(psf), _p(w), _p(out))
     return out
 
 
@@ -135,20 +150,22 @@ def bin_T(r, s, H, W):
 
 def forward(x, shifts, psf, s):
     """y_k = D B M_k x for every frame; returns (K, H//s, W//s)."""
-    x, shifts, psf = _f64(x), _f64(shifts), _f64(psf)
+    x, shifts = _f64(x), _f64(shifts)
     H, W = x.shape
     K = shifts.shape[0]
+    psf = psf_frames(psf, K)
     y = np.empty((K, H // s, W // s))
-    _load().orc_forward(H, W, s, K, _p(shifts), psf.size, _p(psf), _p(x), _p(y))
+    _load().orc_forward(H, W, s, K, _p(shifts), psf.shape[1], _p(psf), _p(x), _p(y))
     return y
 
 
 def adjoint(r, shifts, psf, s, H, W):
     """sum_k A_k^T r_k; returns (H, W)."""
-    r, shifts, psf = _f64(r), _f64(shifts), _f64(psf)
+    r, shifts = _f64(r), _f64(shifts)
     K = shifts.shape[0]
+    psf = psf_frames(psf, K)
     x = np.empty((H, W))
-    _load().orc_adjoint(H, W, s, K, _p(shifts), psf.size, _p(psf), _p(r), _p(x))
+    _load().orc_adjoint(H, W, s, K, _p(shifts), psf.shape[1], _p(psf), _p(r), _p(x))
     return x
 
 
@@ -162,12 +179,13 @@ def btv(x, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3, w=3, grad=True):
 def cost_grad(x, y, shifts, psf, s, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3, w=3,
               data_p=2, eps_data=1e-3, grad=True):
     """Returns (J, grad J or None, (E_data, E_reg))."""
-    x, y, shifts, psf = _f64(x), _f64(y), _f64(shifts), _f64(psf)
+    x, y, shifts = _f64(x), _f64(y), _f64(shifts)
     H, W = x.shape
     K = shifts.shape[0]
+    psf = psf_frames(psf, K)
     g = np.empty_like(x) if grad else None
     parts = np.zeros(2)
-    J = _load().orc_cost_grad(H, W, s, K, _p(shifts), psf.size, _p(psf), lambda_reg,
+    J = _load().orc_cost_grad(H, W, s, K, _p(shifts), psf.shape[1], _p(psf), lambda_reg,
                               alpha_btv, eps, w, data_p, eps_data, _p(x), _p(y), _p(g),
                               _p(parts))
     return J, g, (float(parts[0]), float(parts[1]))
@@ -198,9 +216,10 @@ def upsample(lr, s):
 def curvature_data_l1(x, p, y, shifts, psf, s, sk, eps_data=1e-3):
     """Data part of p^T (grad J(x + sk p) - grad J(x)) / sk for the
     Charbonnier L1 data term, closed form."""
-    x, p, y, shifts, psf = _f64(x), _f64(p), _f64(y), _f64(shifts), _f64(psf)
+    x, p, y, shifts = _f64(x), _f64(p), _f64(y), _f64(shifts)
     H, W = x.shape
-    return _load().orc_curv_data_l1(H, W, s, shifts.shape[0], _p(shifts), psf.size, _p(psf),
+    psf = psf_frames(psf, shifts.shape[0])
+    return _load().orc_curv_data_l1(H, W, s, shifts.shape[0], _p(shifts), psf.shape[1], _p(psf),
                                     eps_data, sk, _p(x), _p(p), _p(y))
 
 
@@ -209,9 +228,10 @@ def curvature_exact(x, p, shifts, psf, s, sk, lambda_reg=0.01, alpha_btv=0.4, ep
     """p^T (grad J(x + sk p) - grad J(x)) / sk for the L2 data term, closed form.
 
     Returns (delta, (data part, BTV part))."""
-    x, p, shifts, psf = _f64(x), _f64(p), _f64(shifts), _f64(psf)
+    x, p, shifts = _f64(x), _f64(p), _f64(shifts)
     H, W = x.shape
+    psf = psf_frames(psf, shifts.shape[0])
     parts = np.zeros(2)
-    d = _load().orc_curv_exact(H, W, s, shifts.shape[0], _p(shifts), psf.size, _p(psf),
+    d = _load().orc_curv_exact(H, W, s, shifts.shape[0], _p(shifts), psf.shape[1], _p(psf),
                                lambda_reg, alpha_btv, eps, w, sk, _p(x), _p(p), _p(parts))
     return d, (float(parts[0]), float(parts[1]))
