@@ -81,6 +81,9 @@ typedef struct {
     const double *shifts_lr;  /* [K][2] = (dx, dy) in LR pixels, |dx|,|dy| <= 1 */
     int32_t psf_size;         /* P, odd, 1 <= P <= 15 */
     const double *psf_1d;     /* [P] taps; the 2-D PSF is their outer product */
+    const double *psf_frames; /* NULL, or [K][2][P]: frame k's own blur B_k (A_k =
+                                 D B_k M_k), vertical taps then horizontal taps,
+                                 B_k their outer product; overrides psf_1d */
 } misr_geometry;
 
 /* Objective and solver settings (Eq. objective, Eq. prior, Algorithm 1). */

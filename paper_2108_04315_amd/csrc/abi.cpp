@@ -126,6 +126,10 @@ extern "C" misr_status misr_geometry_check(const misr_geometry *g) {
     for (int i = 0; i < g->psf_size; ++i)
         if (!std::isfinite(g->psf_1d[i]))
             return set_error(MISR_E_INVAL, "psf tap %d not finite", i);
+    if (g->psf_frames)
+        for (int i = 0; i < 2 * g->n_frames * g->psf_size; ++i)
+            if (!std::isfinite(g->psf_frames[i]))
+                return set_error(MISR_E_INVAL, "psf_frames tap %d not finite", i);
     const int L = band_length(g);
     const int Lp = padded_band(g->scale, L);
     if (Lp < 0)
@@ -260,7 +264,14 @@ extern "C" misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, mis
     op->TH = tile_hr(op->s, op->Lp);
     op->TW = tile_wr(op->s, op->Lp);
     op->shifts.assign(g->shifts_lr, g->shifts_lr + 2 * g->n_frames);
-    op->psf.assign(g->psf_1d, g->psf_1d + g->psf_size);
+    // taps per frame and axis: [K][2][P], vertical then horizontal
+    if (g->psf_frames) {
+        op->psf.assign(g->psf_frames, g->psf_frames + 2 * (size_t)op->K * op->P);
+    } else {
+        op->psf.clear();
+        for (int k = 0; k < 2 * op->K; ++k)
+            op->psf.insert(op->psf.end(), g->psf_1d, g->psf_1d + g->psf_size);
+    }
     const int h = op->H / op->s, w = op->W / op->s, R = (op->P - 1) / 2;
     const size_t fy = (size_t)(h + 2 * kPadRows) * op->Lp, fx = (size_t)(w + 2 * kPadRows) * op->Lp;
     std::vector<float> wy((size_t)op->K * fy, 0.f), wx((size_t)op->K * fx, 0.f);
@@ -270,9 +281,10 @@ extern "C" misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, mis
         const double tx = op->s * op->shifts[2 * k], ty = op->s * op->shifts[2 * k + 1];
         hd.offy[k] = (int)std::floor(ty) - R;
         hd.offx[k] = (int)std::floor(tx) - R;
-        band_weights(op->H, op->s, ty, op->P, op->psf.data(), op->Lp, hd.offy[k],
+        const double *taps = op->psf.data() + (size_t)k * 2 * op->P;
+        band_weights(op->H, op->s, ty, op->P, taps, op->Lp, hd.offy[k],
                      wy.data() + k * fy + (size_t)kPadRows * op->Lp);
-        band_weights(op->W, op->s, tx, op->P, op->psf.data(), op->Lp, hd.offx[k],
+        band_weights(op->W, op->s, tx, op->P, taps + op->P, op->Lp, hd.offx[k],
                      wx.data() + k * fx + (size_t)kPadRows * op->Lp);
     }
     MISR_HIP(op->wy.ensure(wy.size() * 4));

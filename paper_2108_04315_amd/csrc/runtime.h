@@ -242,7 +242,8 @@ struct misr_ctx {
 struct misr_op {
     misr_ctx *ctx;
     int H, W, s, K, P, L, Lp, TH, TW;  // TH x TW: HR tile of the image kernels
-    std::vector<double> shifts, psf;
+    std::vector<double> shifts;
+    std::vector<double> psf;           // [K][2][P]: each frame's vertical, horizontal taps
     misr::DevMem wy, wx, opdev;
     misr::OpDev host;
     std::mutex mu;

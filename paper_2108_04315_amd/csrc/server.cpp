@@ -33,17 +33,17 @@ double now_us() {
 
 struct OpKey {
     int H, W, s, K, P;
-    std::vector<double> shifts, psf;
+    std::vector<double> shifts, psf, psf_frames;
     bool operator<(const OpKey &o) const {
-        return std::tie(H, W, s, K, P, shifts, psf) <
-               std::tie(o.H, o.W, o.s, o.K, o.P, o.shifts, o.psf);
+        return std::tie(H, W, s, K, P, shifts, psf, psf_frames) <
+               std::tie(o.H, o.W, o.s, o.K, o.P, o.shifts, o.psf, o.psf_frames);
     }
 };
 
 struct SReq {
     uint64_t id = 0;
     misr_request req{};
-    std::vector<double> shifts, psf;
+    std::vector<double> shifts, psf, psf_frames;
     misr_req_state state = MISR_REQ_QUEUED;
     misr_req_stats stats{};
     bool cancel = false;
@@ -201,7 +201,8 @@ bool misr_server::setup(SReq *r) {
     misr_geometry g = q.geom;
     g.shifts_lr = r->shifts.data();
     g.psf_1d = r->psf.data();
-    OpKey key{g.hr_h, g.hr_w, g.scale, g.n_frames, g.psf_size, r->shifts, r->psf};
+    g.psf_frames = r->psf_frames.empty() ? nullptr : r->psf_frames.data();
+    OpKey key{g.hr_h, g.hr_w, g.scale, g.n_frames, g.psf_size, r->shifts, r->psf, r->psf_frames};
     auto it = ops.find(key);
     if (it == ops.end()) {
         misr_op *op = nullptr;
@@ -663,6 +664,10 @@ extern "C" misr_status misr_server_submit(misr_server *s, const misr_request *re
     r->req = *req;
     r->shifts.assign(req->geom.shifts_lr, req->geom.shifts_lr + 2 * req->geom.n_frames);
     r->psf.assign(req->geom.psf_1d, req->geom.psf_1d + req->geom.psf_size);
+    if (req->geom.psf_frames)
+        r->psf_frames.assign(req->geom.psf_frames,
+                             req->geom.psf_frames + 2 * (size_t)req->geom.n_frames *
+                                                        req->geom.psf_size);
     r->n = (long long)req->geom.hr_h * req->geom.hr_w;
     r->tiled = req->params.tile_lr > 0;
     r->staged = r->tiled || iterate_fp32(req->params);

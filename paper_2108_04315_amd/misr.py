@@ -41,7 +41,8 @@ class MisrError(RuntimeError):
 class misr_geometry(C.Structure):
     _fields_ = [("hr_h", C.c_int32), ("hr_w", C.c_int32), ("scale", C.c_int32),
                 ("n_frames", C.c_int32), ("shifts_lr", C.POINTER(C.c_double)),
-                ("psf_size", C.c_int32), ("psf_1d", C.POINTER(C.c_double))]
+                ("psf_size", C.c_int32), ("psf_1d", C.POINTER(C.c_double)),
+                ("psf_frames", C.POINTER(C.c_double))]
 
 
 class misr_params(C.Structure):
@@ -170,11 +171,21 @@ def default_params(**kw) -> misr_params:
 
 
 def make_geometry(H: int, W: int, s: int, shifts, psf):
-    """Returns (misr_geometry, keepalive arrays)."""
+    """Returns (misr_geometry, keepalive arrays).  psf: (P,) taps shared by
+    all frames and both axes, or (K, 2, P) per frame (vertical taps, then
+    horizontal taps)."""
     sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64).reshape(-1, 2))
-    ps = np.ascontiguousarray(np.asarray(psf, dtype=np.float64).ravel())
-    g = misr_geometry(H, W, s, sh.shape[0], sh.ctypes.data_as(C.POINTER(C.c_double)),
-                      ps.size, ps.ctypes.data_as(C.POINTER(C.c_double)))
+    pa = np.asarray(psf, dtype=np.float64)
+    dp = C.POINTER(C.c_double)
+    if pa.ndim == 3:
+        pf = np.ascontiguousarray(pa)
+        ps = np.ascontiguousarray(pf[0, 0])
+        g = misr_geometry(H, W, s, sh.shape[0], sh.ctypes.data_as(dp), pf.shape[2],
+                          ps.ctypes.data_as(dp), pf.ctypes.data_as(dp))
+        return g, (sh, ps, pf)
+    ps = np.ascontiguousarray(pa.ravel())
+    g = misr_geometry(H, W, s, sh.shape[0], sh.ctypes.data_as(dp), ps.size,
+                      ps.ctypes.data_as(dp), None)
     return g, (sh, ps)
 
 
@@ -201,7 +212,8 @@ class Context:
 
 
 class Operator:
-    """Observation model A_k = D B M_k of one geometry (built once, reused)."""
+    """Observation model A_k = D B_k M_k of one geometry (built once, reused);
+    psf: (P,) taps for every frame and axis, or (K, 2, P) per frame."""
 
     def __init__(self, ctx: Context, H: int, W: int, s: int, shifts, psf):
         self.ctx = ctx
