@@ -118,7 +118,11 @@ typedef struct {
                             frame 0 (misr_upsample); 2 multi-image interpolation
                             (misr_interpolate); computed on the device into x,
                             so served requests may pass x0 = NULL */
-    int32_t pad_;
+    int32_t y_u16;       /* 0: y stored in img_dtype (default); 1: y holds the
+                            detector's uint16 counts and frame values are
+                            y_scale * count (the paper's 16-bit input images,
+                            Sec. 3); cost/gradient, solves and served requests */
+    double y_scale;      /* > 0 with y_u16 = 1 */
 } misr_params;
 
 /* One SCG pass as recorded on the device. */

@@ -170,6 +170,13 @@ extern "C" misr_status misr_params_check(const misr_params *p) {
         return set_error(MISR_E_INVAL, "x_rounding must be 0 or 1");
     if (p->x_work != 0 && p->x_work != 1) return set_error(MISR_E_INVAL, "x_work must be 0 or 1");
     if (p->x_init < 0 || p->x_init > 2) return set_error(MISR_E_INVAL, "x_init must be 0, 1 or 2");
+    if (p->y_u16 != 0 && p->y_u16 != 1) return set_error(MISR_E_INVAL, "y_u16 must be 0 or 1");
+    if (p->y_u16 && !(std::isfinite(p->y_scale) && p->y_scale > 0))
+        return set_error(MISR_E_INVAL, "y_scale must be finite and > 0 with y_u16");
+    if (p->y_u16 && p->img_dtype != MISR_F32)
+        return set_error(MISR_E_INVAL, "uint16 frames go with an FP32 image (img_dtype F32)");
+    if (p->y_u16 && p->x_init != 0)
+        return set_error(MISR_E_INVAL, "x_init reads frames stored in img_dtype (y_u16 = 0)");
     return MISR_OK;
 }
 
@@ -336,6 +343,7 @@ void misr::init_state(ScgState &s, const misr_params &p, long long N) {
     s.wt.eps_data = (float)p.eps_data;
     s.wt.data_p = p.data_p;
     s.wt.x_rounding = p.x_rounding;
+    s.wt.y_scale = p.y_u16 ? (float)p.y_scale : 1.f;
 }
 
 struct SolveIn {
@@ -495,6 +503,7 @@ static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
     pl.inits.clear();
     pl.vt = in.empty() ? (int)ST_F32 : view_stype(in[0].prm);
     pl.gt = in.empty() ? (int)ST_F32 : (int)in[0].prm.img_dtype;
+    pl.yt = in.empty() ? (int)ST_F32 : frame_stype(in[0].prm);
     const size_t ns = in.size();
     pl.item0.assign(ns, 0);
     pl.nitems.assign(ns, 0);
@@ -844,8 +853,9 @@ extern "C" misr_status misr_scg_solve_batch(int n, const misr_op *const *ops,
         if (st != MISR_OK) return st;
         if (prm[i].tile_lr > 0)
             return set_error(MISR_E_INVAL, "batch entry %d: batched solves are untiled", i);
-        if (prm[i].img_dtype != prm[0].img_dtype || prm[i].x_work != prm[0].x_work)
-            return set_error(MISR_E_INVAL, "batch entries must share img_dtype and x_work");
+        if (prm[i].img_dtype != prm[0].img_dtype || prm[i].x_work != prm[0].x_work ||
+            prm[i].y_u16 != prm[0].y_u16)
+            return set_error(MISR_E_INVAL, "batch entries must share img_dtype, x_work, y_u16");
         if (ctx && ops[i]->ctx != ctx) return set_error(MISR_E_INVAL, "ops span contexts");
         ctx = ops[i]->ctx;
     }

@@ -80,6 +80,13 @@ struct StF16 {
     }
     static FI void st(AS1 raw *p, i64 i, float v) { p[i] = (_Float16)v; }
 };
+// Detector counts: frames only (read, never written); the frame value is the
+// count times the solve's y_scale, applied by the reader.
+struct StU16 {
+    using raw = unsigned short;
+    static constexpr int code = ST_U16;
+    static FI float ld(const AS1 raw *p, i64 i) { return (float)p[i]; }
+};
 struct StBF16 {
     using raw = unsigned short;
     static constexpr int code = ST_BF16;

@@ -585,6 +585,7 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     const int data_p = st.wt.data_p;
     const float epsd = st.wt.eps_data, e2d = epsd * epsd;
     const AS1 rawy *yb = glb((const rawy *)P.y);
+    const float yscale = st.wt.y_scale;
     __syncthreads();
 
     for (int k = 0; k < K; ++k) {
@@ -606,7 +607,7 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
             float yv[T::CI];
 #pragma unroll
             for (int c = 0; c < T::CI; ++c)
-                yv[c] = SY::ld(yk, (i64)min(iA + i0 + c, h - 1) * w + gj);
+                yv[c] = SY::ld(yk, (i64)min(iA + i0 + c, h - 1) * w + gj) * yscale;
             const bool own_j = (S * gj >= o.V0) && (S * gj < P.gx0 + o.v1);
 #pragma unroll
             for (int c = 0; c < T::CI; ++c) {
@@ -746,7 +747,8 @@ FI double upd_data_part(const AS4 Proj &P, const AS4 ScgState &st, const TileOri
                     ap2 += (double)av[c] * (double)av[c];
                 } else {
                     const float r = ax[(i0 + c) * T::NJP + j] -
-                                    SY::ld(yk, (i64)(iA + i0 + c) * w + jA + j);
+                                    SY::ld(yk, (i64)(iA + i0 + c) * w + jA + j) *
+                                        st.wt.y_scale;
                     ap2 += (double)(av[c] * av[c] * psi_quot(r, skd * av[c], epsd, e2d));
                 }
             }
@@ -1092,6 +1094,8 @@ hipError_t MISR_FN(launch_trial_s)(int Lp, int code, int grid, hipStream_t s, co
             LAUNCH(l, StF32, StF16);                                                          \
         else if (code == st_code(ST_F32, ST_BF16))                                            \
             LAUNCH(l, StF32, StBF16);                                                         \
+        else if (code == st_code(ST_F32, ST_U16))                                             \
+            LAUNCH(l, StF32, StU16);                                                          \
         else                                                                                  \
             return hipErrorInvalidValue;                                                      \
         return hipGetLastError();                                                             \
@@ -1120,6 +1124,8 @@ hipError_t MISR_FN(launch_upcurv_s)(int Lp, int code, int grid, hipStream_t s, c
             LAUNCH(l, StF32, StF16);                                                           \
         else if (code == st_code(ST_F32, ST_BF16))                                             \
             LAUNCH(l, StF32, StBF16);                                                          \
+        else if (code == st_code(ST_F32, ST_U16))                                              \
+            LAUNCH(l, StF32, StU16);                                                           \
         else                                                                                   \
             return hipErrorInvalidValue;                                                       \
         return hipGetLastError();                                                              \

@@ -13,7 +13,7 @@ constexpr int kMaxK = 16;    // frames per projection
 constexpr int kMaxL = 16;    // band length
 constexpr int kPadRows = 16; // zero weight rows before and after each frame's table
 
-enum StorageType : int { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+enum StorageType : int { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2, ST_U16 = 3 };
 // Launch code of the image kernels: storage of the views' iterate x (low
 // nibble) and of the frames y (high nibble).
 constexpr int st_code(int sx, int sy) { return sx | (sy << 4); }
@@ -74,6 +74,8 @@ struct Weights {
     float eps_data;      // data Charbonnier eps (p = 1)
     int data_p;
     int x_rounding;      // 16-bit x storage: 0 nearest even, 1 stochastic (hashed)
+    float y_scale;       // frame value = y_scale * stored value (1 unless uint16 counts)
+    int pad_;
 };
 
 // Device-resident SCG state of one solve (Moller's scalars, FP64).

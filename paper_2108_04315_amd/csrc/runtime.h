@@ -162,8 +162,9 @@ struct Plan {
     bool tiled = false;               // some solve is split into tiles
     bool staged = false;              // some solve's iterate lives in library views
                                       // (tiled, or FP32 over a 16-bit caller image)
-    int vt = ST_F32, gt = ST_F32;     // storage of the views' x and of the caller's x and y
-    int code() const { return st_code(vt, gt); }
+    int vt = ST_F32, gt = ST_F32;     // storage of the views' x and of the caller's x
+    int yt = ST_F32;                  // storage of the frames
+    int code() const { return st_code(vt, yt); }
     void finish_counts() {
         counts.clear();
         for (auto &c : classes) counts.push_back(c.count);
@@ -183,6 +184,10 @@ inline int view_stype(const misr_params &p) {
     return iterate_fp32(p) ? (int)ST_F32 : (int)p.img_dtype;
 }
 inline size_t view_esize(const misr_params &p) { return view_stype(p) == ST_F32 ? 4 : 2; }
+// Storage type of the frames y.
+inline int frame_stype(const misr_params &p) {
+    return p.y_u16 ? (int)ST_U16 : (int)p.img_dtype;
+}
 
 // Per-solve image buffers owned by the library (x1, p0, p1, g0, g1; x0w is
 // the FP32 copy of x0 when a 16-bit caller image is solved with an FP32

@@ -167,7 +167,7 @@ struct misr_server {
     int launch_code() const {
         if (active.empty()) return st_code(ST_F32, ST_F32);
         const misr_params &p = active[0]->req.params;
-        return st_code(view_stype(p), (int)p.img_dtype);
+        return st_code(view_stype(p), frame_stype(p));
     }
     void finish(SReq *r, misr_req_state st, misr_status code);
 };
@@ -190,7 +190,8 @@ static size_t request_bytes(const misr_request &q, long long n, size_t es, int K
     } else {
         b = (size_t)n * ev * 2 + (size_t)n * 16;           // x pair, p pair, g pair
     }
-    if (!q.on_device) b += (size_t)K * m * es + (size_t)n * es;  // y and x staged on device
+    if (!q.on_device)   // y and x staged on device
+        b += (size_t)K * m * (q.params.y_u16 ? 2 : es) + (size_t)n * es;
     b += sizeof(ScgState) + (size_t)std::max(1, q.params.n_iter) * sizeof(IterRec);
     return b;
 }
@@ -228,12 +229,13 @@ bool misr_server::setup(SReq *r) {
             return false;
     } else {
         if (r->xwork.ensure(r->n * r->es) != hipSuccess) return false;
-        if (r->ydev.ensure(m * r->es) != hipSuccess) return false;
+        const size_t ye = q.params.y_u16 ? 2 : r->es;   // frame element size
+        if (r->ydev.ensure(m * ye) != hipSuccess) return false;
         r->x0dev = r->xwork.p;
         r->ydev_ptr = r->ydev.p;
         if ((q.x0 && hipMemcpyAsync(r->xwork.p, q.x0, r->n * r->es, hipMemcpyHostToDevice,
                                     stream) != hipSuccess) ||
-            hipMemcpyAsync(r->ydev.p, q.y, m * r->es, hipMemcpyHostToDevice, stream) !=
+            hipMemcpyAsync(r->ydev.p, q.y, m * ye, hipMemcpyHostToDevice, stream) !=
                 hipSuccess)
             return false;
     }
@@ -684,8 +686,10 @@ extern "C" misr_status misr_server_submit(misr_server *s, const misr_request *re
     for (auto &kv : s->reqs)
         if ((kv.second->state == MISR_REQ_QUEUED || kv.second->state == MISR_REQ_RUNNING) &&
             (kv.second->req.params.img_dtype != req->params.img_dtype ||
-             view_stype(kv.second->req.params) != view_stype(req->params)))
-            return set_error(MISR_E_INVAL, "requests in flight use another img_dtype or x_work");
+             view_stype(kv.second->req.params) != view_stype(req->params) ||
+             frame_stype(kv.second->req.params) != frame_stype(req->params)))
+            return set_error(MISR_E_INVAL,
+                             "requests in flight use another img_dtype, x_work or y_u16");
     r->id = s->next_id++;
     *id = r->id;
     s->queue.push_back(r.get());

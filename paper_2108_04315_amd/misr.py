@@ -51,7 +51,7 @@ class misr_params(C.Structure):
                 ("scg_sigma", C.c_double), ("scg_lambda1", C.c_double), ("n_iter", C.c_int32),
                 ("img_dtype", C.c_int32), ("tile_lr", C.c_int32), ("halo_lr", C.c_int32),
                 ("x_rounding", C.c_int32), ("x_work", C.c_int32), ("x_init", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("y_u16", C.c_int32), ("y_scale", C.c_double)]
 
 
 class misr_scg_iter(C.Structure):
