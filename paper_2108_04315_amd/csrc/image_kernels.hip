@@ -291,6 +291,9 @@ FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, 
     for (int q = 0; q < 3; ++q)
 #pragma unroll
         for (int d = 0; d < 8; ++d) hist[q][d] = 0.f;
+    float gam_sum = 0.f;
+#pragma unroll
+    for (int d = 0; d < 8; ++d) gam_sum += gam[d];
     double eacc = 0.0;
     // step t handles column cv0 + t - 2 and loads window column t + 2 (slot t % 3)
     auto step = [&](auto slot_c, auto out_c, int t) {
@@ -303,30 +306,33 @@ FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, 
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) cok[dx] = !CHECK || (V >= 0 && V + dx < W);
         const float x0 = win[0][(Q + 1) % 3];
+        // the prior's cost of the column; for interior tiles (every pair
+        // valid) the sum of gamma_d B_d, B_d = |(z_d, eps)|, less eps times
+        // the sum of the gamma_d, which shares gamma_d / B_d with the gradient
         float eb = 0.f;
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const int dx = kDX[d], dy = kDY[d];
             const float z = x0 - win[dy][(Q + 1 + dx) % 3];
-            float ps, ph;
             if (EPS0) {
-                ps = (z > 0.f) ? 1.f : ((z < 0.f) ? -1.f : 0.f);
-                ph = fabsf(z);
-            } else {
-                const float dd = fmaf(z, z, e2);
-                const float r = rsq(dd);
-                ps = z * r;
-                ph = fmaf(dd, r, -eps);
-            }
-            if (CHECK) {
+                const float ps = (z > 0.f) ? 1.f : ((z < 0.f) ? -1.f : 0.f);
                 const bool valid = rok[dy] && cok[dx];
                 hist[Q][d] = valid ? gam[d] * ps : 0.f;
-                eb = fmaf(valid ? gam[d] : 0.f, ph, eb);
+                eb = fmaf(valid ? gam[d] : 0.f, fabsf(z), eb);
+            } else if (CHECK) {
+                const bool valid = rok[dy] && cok[dx];
+                const float dd = fmaf(z, z, e2);
+                const float r = rsq(dd);
+                hist[Q][d] = valid ? gam[d] * (z * r) : 0.f;
+                eb = fmaf(valid ? gam[d] : 0.f, fmaf(dd, r, -eps), eb);
             } else {
-                hist[Q][d] = gam[d] * ps;
-                eb = fmaf(gam[d], ph, eb);
+                const float dd = fmaf(z, z, e2);
+                const float gr = gam[d] * rsq(dd);
+                hist[Q][d] = gr * z;
+                eb = fmaf(gr, dd, eb);
             }
         }
+        if (!EPS0 && !CHECK) eb = fmaf(-eps, gam_sum, eb);
         if (OUT) {
             // shares of the pairs (i - d, i): from dx steps back, dy lanes up
             float own = 0.f, back[3] = {0.f, 0.f, 0.f};
@@ -366,11 +372,13 @@ FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, 
 // sum over owned pairs of gamma q^2 Q(z, sk q), z, q the pair differences of
 // x and p.  Same sweep as btv_sweep (lanes on rows, waves on CV columns,
 // 3-slot rotating windows, unrolled by three); [ru0,ru1) x [rv0,rv1) is the
-// owned part of the tile.  With eps > 0 every pair first takes the series
-// form of psi_quot (eps^2 / B^3 times 1 - 3/2 t b + t^2 (2 b^2 - eps^2 / 2),
-// t = h / B^2); a lane that has a pair outside the series' range
-// (|h| >= 1e-3 B) recomputes those pairs with the closed form, so the common
-// case takes one branch per column instead of one per pair.
+// owned part of the tile.  With eps > 0 every pair first takes the
+// first-order series of psi_quot, Q(z, h) = eps^2 / B^3 (1 - 3/2 h z / B^2),
+// B = |(z, eps)|: in u = q / B the term is gamma eps^2 u^2 / B times
+// (1 - 3/2 sk u z / B).  The next term of the series is at most 2 (h / B)^2
+// relative, so for |h| / B = sk |u| < kCurvTau = 1e-4 the truncation stays
+// below FP32 rounding; a lane with a pair beyond that recomputes its column
+// with the closed form, so the common case takes one branch per column.
 template <int S, int L, bool CHECK, bool EPS0>
 FI void curv_sweep(const float *xs, const float *ps, const float (&gam)[8], float eps, float sk,
                    int U0, int V0, int H, int W, int ru0, int ru1, int rv0, int rv1,
@@ -399,6 +407,9 @@ FI void curv_sweep(const float *xs, const float *ps, const float (&gam)[8], floa
     float gq[8];   // gamma_d eps^2
 #pragma unroll
     for (int d = 0; d < 8; ++d) gq[d] = gam[d] * e2;
+    constexpr float kCurvTau = 1e-4f;
+    const float c15 = -1.5f * sk;
+    const float umax_ok = kCurvTau / sk;   // sk |u| < tau  <=>  |u| < tau / sk
     double acc = 0.0;
     // step t handles column cv0 + t and loads window column t + 2 (slot (t+2) % 3)
     auto step = [&](auto slot_c, int t) {
@@ -409,50 +420,58 @@ FI void curv_sweep(const float *xs, const float *ps, const float (&gam)[8], floa
             wp[dy][(Q + 2) % 3] = ps[off + dy * T::WCP + t + 2];
         }
         const int v = cv0 + t, V = V0 + v;
-        float tq[8];
+        float a = 0.f;
         if (EPS0) {
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
                 const int dx = kDX[d], dy = kDY[d];
                 const float z = wx[0][Q] - wx[dy][(Q + dx) % 3];
                 const float qd = wp[0][Q] - wp[dy][(Q + dx) % 3];
-                tq[d] = gam[d] * qd * qd * psi_quot(z, sk * qd, eps, e2);
+                const float tq = gam[d] * qd * qd * psi_quot(z, sk * qd, eps, e2);
+                if (CHECK)
+                    a += (rok[dy] && V + dx < W) ? tq : 0.f;
+                else
+                    a += tq;
             }
         } else {
-            bool slow = false;
+            float umax = 0.f;
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
                 const int dx = kDX[d], dy = kDY[d];
                 const float z = wx[0][Q] - wx[dy][(Q + dx) % 3];
                 const float qd = wp[0][Q] - wp[dy][(Q + dx) % 3];
-                const float h = sk * qd;
                 const float rB = rsq(fmaf(z, z, e2));
-                const float rB2 = rB * rB;
-                const float tt = h * rB2;
-                slow |= fabsf(h * rB) >= 1e-3f;
-                const float poly = fmaf(tt, fmaf(tt, fmaf(2.f * z, z, -0.5f * e2), -1.5f * z), 1.f);
-                tq[d] = gq[d] * (qd * qd) * (rB * rB2) * poly;
+                const float u = qd * rB;
+                const float poly = fmaf(c15, u * (z * rB), 1.f);
+                const float tq = (u * u) * rB * poly;
+                umax = fmaxf(umax, fabsf(u));
+                if (CHECK)
+                    a = fmaf((rok[dy] && V + dx < W) ? gq[d] : 0.f, tq, a);
+                else
+                    a = fmaf(gq[d], tq, a);
             }
-            if (slow) {
+            if (!(umax < umax_ok)) {
+                // some pair is beyond the series' range: the column again,
+                // each such pair with the closed form
+                a = 0.f;
 #pragma unroll
                 for (int d = 0; d < 8; ++d) {
                     const int dx = kDX[d], dy = kDY[d];
                     const float z = wx[0][Q] - wx[dy][(Q + dx) % 3];
                     const float qd = wp[0][Q] - wp[dy][(Q + dx) % 3];
-                    const float h = sk * qd;
-                    if (fabsf(h * rsq(fmaf(z, z, e2))) >= 1e-3f)
-                        tq[d] = gam[d] * qd * qd * psi_quot(z, h, eps, e2);
+                    const float rB = rsq(fmaf(z, z, e2));
+                    const float u = qd * rB;
+                    float tq;
+                    if (fabsf(u) < umax_ok)
+                        tq = gq[d] * ((u * u) * rB * fmaf(c15, u * (z * rB), 1.f));
+                    else
+                        tq = gam[d] * qd * qd * psi_quot(z, sk * qd, eps, e2);
+                    if (CHECK)
+                        a += (rok[dy] && V + dx < W) ? tq : 0.f;
+                    else
+                        a += tq;
                 }
             }
-        }
-        float a = 0.f;
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const int dx = kDX[d], dy = kDY[d];
-            if (CHECK)
-                a += (rok[dy] && V + dx < W) ? tq[d] : 0.f;
-            else
-                a += tq[d];
         }
         const bool own = own_row && (!CHECK || (v >= rv0 && v < rv1));
         acc += own ? (double)a : 0.0;
