@@ -75,7 +75,6 @@ struct Tile {
     static constexpr int RSS = NIM * NJP;
     static constexpr int GP = TW + 1;                    // row stride of the LDS gradient
     static constexpr int SMEM = lds_floats(TW);
-    static constexpr int NSTAGE = (WR * WC + kNTI - 1) / kNTI;
     static_assert(NRM <= 64 && TH + 2 <= 64 && NJM <= 64, "a wave spans a tile dimension");
     static_assert(CV % S == 0 && CU % S == 0, "phase-aligned groups");
     static constexpr int PO = XS + ((HXS + RSS > TH * GP) ? HXS + RSS : TH * GP);
@@ -492,28 +491,27 @@ FI void curv_sweep(const float *xs, const float *ps, const float (&gam)[8], floa
 }
 
 // --------------------------------------------------------------- the tiles
-// Window element s of this thread (q = tid + s * kNTI, row-major over the
-// WR x WC window whose corner is (u0 - EXT, v0 - EXT) in view coordinates):
-// its LDS slot (-1 past the window), a source index clamped into the view so
-// that every load is issued unconditionally, and whether the element is
-// inside the view (outside it reads as zero).
-struct StageAt {
-    int lds, ub, vb;
-    i64 idx;
-    bool in;
+// Window staging by rows: wave wv takes window rows wv, wv + kNWI, ... (so
+// every row quantity is wave-uniform and sits in scalar registers) and lane
+// takes columns lane + 64 c.  Loads are issued unconditionally from clamped
+// coordinates; elements outside the view are stored as zero.
+template <class T>
+struct WinMap {
+    static constexpr int NR = (T::WR + kNWI - 1) / kNWI;   // rows per wave
+    static constexpr int NC = (T::WC + 63) / 64;           // columns per lane
+};
+struct WinCol {
+    int vb, vc;   // view column, clamped into the view
+    bool in;      // inside the window and the view
 };
 template <class T>
-FI StageAt stage_at(int tid, int s, int u0, int v0, int Hb, int Wb, int ld) {
-    const int q = tid + s * kNTI;
-    const int qq = min(q, T::WR * T::WC - 1);
-    const int r = qq / T::WC, c = qq - r * T::WC;
-    StageAt a;
-    a.ub = u0 - T::EXT + r;
-    a.vb = v0 - T::EXT + c;
-    a.in = q < T::WR * T::WC && a.ub >= 0 && a.ub < Hb && a.vb >= 0 && a.vb < Wb;
-    a.idx = (i64)min(max(a.ub, 0), Hb - 1) * ld + min(max(a.vb, 0), Wb - 1);
-    a.lds = (q < T::WR * T::WC) ? r * T::WCP + c : -1;
-    return a;
+FI WinCol win_col(int lane, int c, int v0, int Wb) {
+    WinCol w;
+    const int col = lane + 64 * c;
+    w.vb = v0 - T::EXT + col;
+    w.vc = min(max(w.vb, 0), Wb - 1);
+    w.in = col < T::WC && w.vb >= 0 && w.vb < Wb;
+    return w;
 }
 
 struct TileOrigin {
@@ -566,35 +564,63 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     const i64 Wg = opg.W;
     // window of x_t into LDS: every load first (clamped, unconditional), then
     // the arithmetic, so that the loads are in flight together
-    if (mode == 1) {
-        float xr[T::NSTAGE], pr[T::NSTAGE];
+    using WM = WinMap<T>;
+    const int lane0 = tid & 63, wv0 = uni(tid >> 6);
+    WinCol wc[WM::NC];
 #pragma unroll
-        for (int s = 0; s < T::NSTAGE; ++s) {
-            const StageAt a = stage_at<T>(tid, s, o.u0, o.v0, Hb, Wb, ld);
-            xr[s] = ST::ld(xb, a.idx);
-            pr[s] = pb[a.idx];
+    for (int c = 0; c < WM::NC; ++c) wc[c] = win_col<T>(lane0, c, o.v0, Wb);
+    if (mode == 1) {
+        float xr[WM::NR][WM::NC], pr[WM::NR][WM::NC];
+#pragma unroll
+        for (int r = 0; r < WM::NR; ++r) {
+            const int ub = o.u0 - T::EXT + wv0 + kNWI * r;
+            const i64 rb = (i64)min(max(ub, 0), Hb - 1) * ld;
+#pragma unroll
+            for (int c = 0; c < WM::NC; ++c) {
+                xr[r][c] = ST::ld(xb + rb, wc[c].vc);
+                pr[r][c] = pb[rb + wc[c].vc];
+            }
         }
 #pragma unroll
-        for (int s = 0; s < T::NSTAGE; ++s) {
-            const StageAt a = stage_at<T>(tid, s, o.u0, o.v0, Hb, Wb, ld);
-            const float v = fmaf(af, pr[s], xr[s]);
-            const float vr =
-                sr ? ST::rnd_sr(v, pixel_hash((i64)(P.gy0 + a.ub) * Wg + P.gx0 + a.vb, seed))
-                   : ST::rnd(v);
-            if (a.lds >= 0) xs[a.lds] = a.in ? vr : 0.f;
-            const int ou = a.ub - o.u0, ov = a.vb - o.v0;
-            if (a.lds >= 0 && ou >= 0 && ou < T::TH && ov >= 0 && ov < T::TW)
-                po[ou * T::TW + ov] = pr[s];
+        for (int r = 0; r < WM::NR; ++r) {
+            const int row = wv0 + kNWI * r, ub = o.u0 - T::EXT + row;
+            if (row < T::WR) {
+                const bool rin = ub >= 0 && ub < Hb;
+                const int ou = row - T::EXT;
+#pragma unroll
+                for (int c = 0; c < WM::NC; ++c) {
+                    const int col = lane0 + 64 * c, ov = col - T::EXT;
+                    const float v = fmaf(af, pr[r][c], xr[r][c]);
+                    const float vr =
+                        sr ? ST::rnd_sr(v, pixel_hash((i64)(P.gy0 + ub) * Wg + P.gx0 + wc[c].vb,
+                                                      seed))
+                           : ST::rnd(v);
+                    if (col < T::WC) xs[row * T::WCP + col] = (rin && wc[c].in) ? vr : 0.f;
+                    if (ou >= 0 && ou < T::TH && ov >= 0 && ov < T::TW)
+                        po[ou * T::TW + ov] = pr[r][c];
+                }
+            }
         }
     } else {
-        float xr[T::NSTAGE];
+        float xr[WM::NR][WM::NC];
 #pragma unroll
-        for (int s = 0; s < T::NSTAGE; ++s)
-            xr[s] = ST::ld(xb, stage_at<T>(tid, s, o.u0, o.v0, Hb, Wb, ld).idx);
+        for (int r = 0; r < WM::NR; ++r) {
+            const int ub = o.u0 - T::EXT + wv0 + kNWI * r;
+            const i64 rb = (i64)min(max(ub, 0), Hb - 1) * ld;
 #pragma unroll
-        for (int s = 0; s < T::NSTAGE; ++s) {
-            const StageAt a = stage_at<T>(tid, s, o.u0, o.v0, Hb, Wb, ld);
-            if (a.lds >= 0) xs[a.lds] = a.in ? xr[s] : 0.f;
+            for (int c = 0; c < WM::NC; ++c) xr[r][c] = ST::ld(xb + rb, wc[c].vc);
+        }
+#pragma unroll
+        for (int r = 0; r < WM::NR; ++r) {
+            const int row = wv0 + kNWI * r, ub = o.u0 - T::EXT + row;
+            if (row < T::WR) {
+                const bool rin = ub >= 0 && ub < Hb;
+#pragma unroll
+                for (int c = 0; c < WM::NC; ++c) {
+                    const int col = lane0 + 64 * c;
+                    if (col < T::WC) xs[row * T::WCP + col] = (rin && wc[c].in) ? xr[r][c] : 0.f;
+                }
+            }
         }
     }
     float gacc[T::CV];
@@ -669,22 +695,24 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     AS1 float *gout = glbw(P.g[cur ^ 1]);
     const AS1 float *gk = glb(P.g[cur]);
     AS1 float *pz = glbw(P.p[xc]);
-    constexpr int NOUT = (T::TH * T::TW + kNTI - 1) / kNTI;
-    auto out_at = [&](int j, i64 &idx) {
-        const int q = tid + j * kNTI;
-        const int qq = min(q, T::TH * T::TW - 1);
-        const int uu = qq / T::TW, vv = qq - uu * T::TW;
-        idx = (i64)min(o.u0 + uu, o.u1 - 1) * ld + min(o.v0 + vv, o.v1 - 1);
-        return (q < T::TH * T::TW && o.u0 + uu < o.u1 && o.v0 + vv < o.v1) ? uu * T::GP + vv
-                                                                           : -1;
-    };
-    float gkv[NOUT];
+    // owned pixels by rows as in the staging: wave wv0 takes tile rows
+    // wv0 + kNWI r, lane takes columns lane0 + 64 c
+    constexpr int ONR = (T::TH + kNWI - 1) / kNWI, ONC = (T::TW + 63) / 64;
+    int ocol[ONC];     // clamped view column
+    bool cown[ONC];    // column owned
+#pragma unroll
+    for (int c = 0; c < ONC; ++c) {
+        const int col = lane0 + 64 * c;
+        cown[c] = col < T::TW && o.v0 + col < o.v1;
+        ocol[c] = min(o.v0 + col, o.v1 - 1);
+    }
+    float gkv[ONR][ONC];
     if (mode == 1) {
 #pragma unroll
-        for (int j = 0; j < NOUT; ++j) {
-            i64 idx;
-            (void)out_at(j, idx);
-            gkv[j] = gk[idx];
+        for (int r = 0; r < ONR; ++r) {
+            const i64 rb = (i64)min(o.u0 + wv0 + kNWI * r, o.u1 - 1) * ld;
+#pragma unroll
+            for (int c = 0; c < ONC; ++c) gkv[r][c] = gk[rb + ocol[c]];
         }
     }
     float gam[8];
@@ -706,18 +734,22 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     // owned gradient out, with its inner products
     double gg = 0.0, ggk = 0.0, gp = 0.0;
 #pragma unroll
-    for (int j = 0; j < NOUT; ++j) {
-        i64 idx;
-        const int at = out_at(j, idx);
-        if (at < 0) continue;
-        const float gv = gs[at];
-        gout[idx] = gv;
-        gg += (double)gv * (double)gv;
-        if (mode == 0) pz[idx] = 0.f;   // start direction buffer for the init pass
-        if (mode == 1) {
-            const int q = min(tid + j * kNTI, T::TH * T::TW - 1);
-            ggk += (double)gv * (double)gkv[j];
-            gp += (double)gv * (double)po[q];
+    for (int r = 0; r < ONR; ++r) {
+        const int row = wv0 + kNWI * r;
+        if (row >= T::TH || o.u0 + row >= o.u1) continue;   // wave-uniform
+        const i64 rb = (i64)(o.u0 + row) * ld;
+#pragma unroll
+        for (int c = 0; c < ONC; ++c) {
+            if (!cown[c]) continue;
+            const int col = lane0 + 64 * c;
+            const float gv = gs[row * T::GP + col];
+            gout[rb + ocol[c]] = gv;
+            gg += (double)gv * (double)gv;
+            if (mode == 0) pz[rb + ocol[c]] = 0.f;   // start direction buffer for the init pass
+            if (mode == 1) {
+                ggk += (double)gv * (double)gkv[r][c];
+                gp += (double)gv * (double)po[row * T::TW + col];
+            }
         }
     }
     double v[5] = {e_data, e_reg, gg, ggk, gp};
@@ -824,34 +856,55 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
     double pp = 0.0, pr = 0.0;
     {
         // every load first (clamped, unconditional), then the update
-        float xr[T::NSTAGE], pr0[T::NSTAGE], gr[T::NSTAGE];
+        using WM = WinMap<T>;
+        const int lane0 = tid & 63, wv0 = uni(tid >> 6);
+        WinCol wc[WM::NC];
 #pragma unroll
-        for (int s = 0; s < T::NSTAGE; ++s) {
-            const StageAt a = stage_at<T>(tid, s, o.u0, o.v0, Hb, Wb, ld);
-            xr[s] = ST::ld(xb, a.idx);
-            pr0[s] = pb[a.idx];
-            gr[s] = gt[a.idx];
+        for (int c = 0; c < WM::NC; ++c) wc[c] = win_col<T>(lane0, c, o.v0, Wb);
+        float xr[WM::NR][WM::NC], pr0[WM::NR][WM::NC], gr[WM::NR][WM::NC];
+#pragma unroll
+        for (int r = 0; r < WM::NR; ++r) {
+            const int ub = o.u0 - T::EXT + wv0 + kNWI * r;
+            const i64 rb = (i64)min(max(ub, 0), Hb - 1) * ld;
+#pragma unroll
+            for (int c = 0; c < WM::NC; ++c) {
+                xr[r][c] = ST::ld(xb + rb, wc[c].vc);
+                pr0[r][c] = pb[rb + wc[c].vc];
+                gr[r][c] = gt[rb + wc[c].vc];
+            }
         }
 #pragma unroll
-        for (int s = 0; s < T::NSTAGE; ++s) {
-            const StageAt a = stage_at<T>(tid, s, o.u0, o.v0, Hb, Wb, ld);
-            const float v = fmaf(af, pr0[s], xr[s]);
-            float xv = sr ? ST::rnd_sr(v, pixel_hash((i64)(P.gy0 + a.ub) * Wg + P.gx0 + a.vb, seed))
-                          : ST::rnd(v);
-            float pv = fmaf(bf, pr0[s], -gr[s]);
-            xv = a.in ? xv : 0.f;
-            pv = a.in ? pv : 0.f;
-            if (a.in && a.ub >= o.u0 && a.ub < o.u1 && a.vb >= o.v0 && a.vb < o.v1) {
-                ST::st(xo, a.idx, xv);
-                po[a.idx] = pv;
-                if (a.ub >= ou0 && a.ub < ou1 && a.vb >= ov0 && a.vb < ov1) {
-                    pp += (double)pv * (double)pv;
-                    pr -= (double)pv * (double)gr[s];
+        for (int r = 0; r < WM::NR; ++r) {
+            const int row = wv0 + kNWI * r, ub = o.u0 - T::EXT + row;
+            if (row < T::WR) {
+                const bool rin = ub >= 0 && ub < Hb;
+                const bool urow = rin && ub >= o.u0 && ub < o.u1;   // updated rows
+                const bool orow = ub >= ou0 && ub < ou1;            // owned rows
+                const i64 rb = (i64)ub * ld;                        // in the view when urow
+#pragma unroll
+                for (int c = 0; c < WM::NC; ++c) {
+                    const int col = lane0 + 64 * c, vb = wc[c].vb;
+                    const bool in = rin && wc[c].in;
+                    const float v = fmaf(af, pr0[r][c], xr[r][c]);
+                    float xv = sr ? ST::rnd_sr(v, pixel_hash((i64)(P.gy0 + ub) * Wg + P.gx0 + vb,
+                                                             seed))
+                                  : ST::rnd(v);
+                    float pv = fmaf(bf, pr0[r][c], -gr[r][c]);
+                    xv = in ? xv : 0.f;
+                    pv = in ? pv : 0.f;
+                    if (urow && wc[c].in && vb >= o.v0 && vb < o.v1) {
+                        ST::st(xo, rb + vb, xv);
+                        po[rb + vb] = pv;
+                        if (orow && vb >= ov0 && vb < ov1) {
+                            pp += (double)pv * (double)pv;
+                            pr -= (double)pv * (double)gr[r][c];
+                        }
+                    }
+                    if (col < T::WC) {
+                        xs[row * T::WCP + col] = xv;
+                        ps[row * T::WCP + col] = pv;
+                    }
                 }
-            }
-            if (a.lds >= 0) {
-                xs[a.lds] = xv;
-                ps[a.lds] = pv;
             }
         }
     }
