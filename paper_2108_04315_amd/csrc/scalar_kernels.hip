@@ -133,42 +133,49 @@ __device__ void scg_phase_b(ScgState &s, const double *v, IterRec *trace) {
 
 // partials: per-item sums of the trial pass (init, phase B); partials_u: of
 // the update pass (phase A).
+// The solve's state is copied into LDS by 8-byte words while its partial
+// sums are loaded (both only need the SolveRef), updated there by thread 0
+// and copied back, so the kernel waits on global memory twice per solve
+// rather than once per dependent access.
+constexpr int kStW = (int)(sizeof(ScgState) / 8);
+static_assert(sizeof(ScgState) % 8 == 0 && kStW <= kNT, "state copied by 8-byte words");
+
 __global__ void __launch_bounds__(kNT) k_scalar(const SolveRef *refs, const int *n_refs,
                                                 const double *__restrict__ partials,
                                                 const double *__restrict__ partials_u,
                                                 int phase) {
     __shared__ double red[kNV * (kNT / 64)];
     __shared__ double tot[kNV];
+    __shared__ ScgState sst;
+    unsigned long long *sw = reinterpret_cast<unsigned long long *>(&sst);
     const int ns = *n_refs;
+    // the launch grid never exceeds the SolveRef array, so the first ref is
+    // read without waiting for the count
+    SolveRef ref = refs[blockIdx.x];
     for (int sv = blockIdx.x; sv < ns; sv += gridDim.x) {
-        const SolveRef ref = refs[sv];
-        ScgState &s = *ref.st;
-        bool need;
-        if (phase == PH_INIT)
-            need = true;
-        else if (phase == PH_A)
-            need = s.active && s.success;
-        else
-            need = s.active;
-        __syncthreads();   // every thread has read the state before thread 0 writes it
-        if (need) {
-            const double *pt = (phase == PH_A) ? partials_u : partials;
-            const int i0 = (phase == PH_A) ? ref.item0u : ref.item0;
-            const int ni = (phase == PH_A) ? ref.nitemsu : ref.nitems;
-            double v[kNV] = {0, 0, 0, 0, 0, 0};
-            for (int i = i0 + threadIdx.x; i < i0 + ni; i += kNT)
+        if (sv != (int)blockIdx.x) ref = refs[sv];
+        unsigned long long *gw = reinterpret_cast<unsigned long long *>(ref.st);
+        if (threadIdx.x < kStW) sw[threadIdx.x] = gw[threadIdx.x];
+        const double *pt = (phase == PH_A) ? partials_u : partials;
+        const int i0 = (phase == PH_A) ? ref.item0u : ref.item0;
+        const int ni = (phase == PH_A) ? ref.nitemsu : ref.nitems;
+        double v[kNV] = {0, 0, 0, 0, 0, 0};
+        for (int i = i0 + threadIdx.x; i < i0 + ni; i += kNT)
 #pragma unroll
-                for (int q = 0; q < kNV; ++q) v[q] += pt[(long long)i * kNV + q];
-            block_sum_store<kNV, kNT>(v, tot, red);
-        }
+            for (int q = 0; q < kNV; ++q) v[q] += pt[(long long)i * kNV + q];
+        // the sums are used only where the phase needs them (scg_phase_a
+        // reads them after an accepted pass only)
+        block_sum_store<kNV, kNT>(v, tot, red);   // its barriers also publish sst
         if (threadIdx.x == 0) {
             if (phase == PH_INIT)
-                scg_init(s, tot);
+                scg_init(sst, tot);
             else if (phase == PH_A)
-                scg_phase_a(s, tot);
+                scg_phase_a(sst, tot);
             else
-                scg_phase_b(s, tot, ref.trace);
+                scg_phase_b(sst, tot, ref.trace);
         }
+        __syncthreads();
+        if (threadIdx.x < kStW) gw[threadIdx.x] = sw[threadIdx.x];
         __syncthreads();
     }
 }
