@@ -36,6 +36,10 @@ WORKLOAD = ("plain2048: 4 LR frames 1024x1024 f32 -> 2048x2048 HR (x2), {0,1/2}^
 
 KERNEL_SOURCES = ("image_kernels.hip", "device_common.h", "internal.h")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_trial_plain2048_hbm_traffic.md")
+SQ_SUMMARY = os.path.join(ROOT, "profiles", "k_trial_plain2048_sq_counters.md")
+# VALU issue peak: one wave64 instruction per cycle per CU (4 SIMD16 units,
+# 4 cycles each), 256 CUs at 2.4 GHz
+VALU_WAVE_INSTS_PER_S = 256 * 2.4e9
 
 
 def kernel_source_hash() -> str:
@@ -62,21 +66,27 @@ def make_inputs(misr, ctx):
     return op, shifts, psf, y, x0, y_np
 
 
+def profile_value(path: str, tag: str, key: str, src_hash: str):
+    """The value `key` of the `tag:` line of a committed counter summary, if
+    the summary was taken on the current kernel sources; else None."""
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for ln in open(path):
+        if ln.startswith(tag + ":"):
+            for kv in ln.split()[1:]:
+                k, _, v = kv.partition("=")
+                vals[k] = v
+    if vals.get("kernel_source_hash") != src_hash or key not in vals:
+        return None
+    return float(vals[key])
+
+
 def traffic_from_profile(src_hash: str):
     """HBM bytes per trial launch (FETCH_SIZE + WRITE_SIZE, scaled by the copy
     calibration) from the committed counter summary, if it was taken on the
     current kernel sources; else None."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
-        return None
-    vals = {}
-    for ln in open(TRAFFIC_SUMMARY):
-        if ln.startswith("traffic:"):
-            for kv in ln.split()[1:]:
-                k, _, v = kv.partition("=")
-                vals[k] = v
-    if vals.get("kernel_source_hash") != src_hash or "bytes_per_launch" not in vals:
-        return None
-    return float(vals["bytes_per_launch"])
+    return profile_value(TRAFFIC_SUMMARY, "traffic", "bytes_per_launch", src_hash)
 
 
 def copy_probe(mib: int, reps: int = 3):
@@ -367,6 +377,7 @@ def main():
     achieved = bytes_trial / (us_trial * 1e-6) / 1e9
     src_hash = kernel_source_hash()
     traffic = traffic_from_profile(src_hash)
+    valu_insts = profile_value(SQ_SUMMARY, "valu", "insts_per_launch", src_hash)
 
     # the paper's non-iterative baseline on the same frames: multi-image interpolation
     xi = torch.empty_like(x0)
@@ -399,7 +410,12 @@ def main():
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "avg_us": us_trial, "bytes_per_launch": bytes_trial,
-                     "kernel_source_hash": src_hash},
+                     "kernel_source_hash": src_hash,
+                     # SQ_INSTS_VALU per launch from the committed counters over
+                     # the live duration, against one wave instruction per cycle per CU
+                     "valu_wave_insts_per_launch": valu_insts,
+                     "valu_issue_frac": (None if valu_insts is None else
+                                         valu_insts / (us_trial * 1e-6 * VALU_WAVE_INSTS_PER_S))},
         "interpolation_baseline": {"hr_mpx_per_s": H * W / t_interp / 1e6,
                                    "ms": t_interp * 1e3},
         "update_pass": {"kernel": "k_upcurv (update + curvature)", "avg_us": us_update,
