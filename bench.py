@@ -233,6 +233,28 @@ def serving_leg(misr, ctx, n_req: int = 48, loads=(0.8, 1.0), seed: int = 7,
     return res
 
 
+def cpu_baseline(y_np, shifts, psf, x0_np, budget_s: float = 15.0):
+    """FP64 oracle SCG on the host cores: a few passes of the same workload,
+    extrapolated to the full pass count."""
+    import oracle
+    from oracle import scg as oscg
+    ncores = len(os.sched_getaffinity(0))
+    oracle.set_threads(ncores)
+    t0 = time.perf_counter()
+    oracle.cost_grad(x0_np, y_np, shifts, psf, S)
+    t_eval = time.perf_counter() - t0
+    n = int(max(1, min(N_ITER, budget_s / max(2.2 * t_eval, 1e-3))))
+    t0 = time.perf_counter()
+    oscg.solve(y_np, shifts, psf, S, x0_np, n)
+    t_n = time.perf_counter() - t0
+    t_pass = max(t_n - t_eval, 1e-9) / n
+    t_full = t_eval + N_ITER * t_pass
+    return dict(value=H * W / t_full / 1e6, unit="HR Mpixel/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"FP64 oracle SCG, {n} passes of the 2048^2 workload in {t_n:.1f} s "
+                       f"({t_pass:.2f} s/pass), extrapolated to {N_ITER} passes")
+
+
 # ------------------------------------------------------- other workloads
 def _base_line(metric_value, K, Wm, dt, dtype, config):
     return {"metric": "HR Mpixel/s at fixed SCG iters + p50/p99 latency, served vs plain, 1 GPU",

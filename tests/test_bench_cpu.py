@@ -1,0 +1,50 @@
+"""Host-side checks of bench.py: the helpers the default run calls exist and
+work without a GPU (the oracle baseline leg, the counter-summary parser)."""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_cpu_baseline_leg_small(monkeypatch):
+    """The oracle leg of the default run on a 64 x 64 stand-in of its workload."""
+    import oracle
+    from paper_2108_04315_amd import synth
+    monkeypatch.setattr(bench, "H", 64)
+    monkeypatch.setattr(bench, "W", 64)
+    monkeypatch.setattr(bench, "N_ITER", 4)
+    s = bench.S
+    shifts = synth.frame_shifts(s, 4, 0.05, 1)
+    psf = synth.psf_taps(0.8)
+    y = synth.add_poisson_noise(oracle.forward(synth.phantom(64, 64, 0), shifts, psf, s), 1e4, 2)
+    x0 = synth.bicubic_upsample(y[0], s)
+    out = bench.cpu_baseline(y, shifts, psf, x0, budget_s=0.5)
+    assert out["kind"] == "oracle" and out["unit"] == "HR Mpixel/s"
+    assert out["value"] > 0 and out["cores"] >= 1 and "passes" in out["sample"]
+
+
+def test_profile_values_follow_the_kernel_hash():
+    """traffic / VALU figures are reported only for the kernel sources the
+    committed summaries were taken on."""
+    h = bench.kernel_source_hash()
+    for path, tag, key in ((bench.TRAFFIC_SUMMARY, "traffic", "bytes_per_launch"),
+                           (bench.SQ_SUMMARY, "valu", "insts_per_launch")):
+        assert os.path.exists(path)
+        assert bench.profile_value(path, tag, key, "0" * 16) is None
+        v = bench.profile_value(path, tag, key, h)
+        assert v is None or (np.isfinite(v) and v > 0)
+
+
+def test_main_refuses_more_than_one_gpu(monkeypatch, capsys):
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--gpus", "2"])
+    try:
+        bench.main()
+    except SystemExit as e:
+        assert e.code not in (0, None)
+    else:
+        raise AssertionError("bench.py --gpus 2 must exit")
