@@ -6,16 +6,18 @@ links or runs anything in this package, and this package never imports the
 product.
 
 ``ops``  -- ctypes shim over ``misr_oracle.c``: the literal 2-D operators
-           (bilinear warp, P x P blur, s x s binning), J(x) and grad J(x).
+           (bilinear warp, translational or affine; P x P blur; s x s
+           binning), J(x) and grad J(x).
 ``scg``  -- Moller's scaled conjugate gradient, step by step, in numpy.
 """
 from .ops import (build, forward, adjoint, cost_grad, btv, curvature_exact, curvature_data_l1,
                   interpolate, upsample,
-                  psi_quotient, num_threads, set_threads, warp, warp_T, blur, blur_T,
-                  bin_, bin_T)
+                  psi_quotient, num_threads, set_threads, warp, warp_T, warp_affine,
+                  warp_affine_T, blur, blur_T, bin_, bin_T)
 from .scg import scg_minimize, solve, moller_scale_delta, moller_update_lambda
 
 __all__ = ["build", "forward", "adjoint", "cost_grad", "btv", "curvature_exact",
            "curvature_data_l1", "interpolate", "upsample",
-           "psi_quotient", "num_threads", "set_threads", "warp", "warp_T", "blur",
+           "psi_quotient", "num_threads", "set_threads", "warp", "warp_T", "warp_affine",
+           "warp_affine_T", "blur",
            "blur_T", "bin_", "bin_T", "scg_minimize", "solve", "moller_scale_delta", "moller_update_lambda"]

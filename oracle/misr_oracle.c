@@ -30,6 +30,11 @@
  *         h(a,b) = psf[a+R] * psf[b+R]   (P = 2R+1 taps).
  *   D   : (D w)(i,j) = s^-2 sum_{a,b<s} w(s i + a, s j + b)   (s x s binning).
  *   A_k = D B M_k, applied M first.
+ *   General warps (the "_w" functions): M_k may instead be affine,
+ *         (M_k x)(u,v) = bilinear sample of x at row m0 u + m1 v + m2,
+ *         column m3 u + m4 v + m5 (m = frame k's six coefficients, HR
+ *         pixels, zero off-grid); the translation above is
+ *         m = (1, 0, ty, 0, 1, tx).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -73,6 +78,42 @@ void orc_warp_T(int H, int W, double tx, double ty, const double *z, double *out
                            + (1 - fa) * fb * at(z, H, W, u, v - 1)
                            + fa * (1 - fb) * at(z, H, W, u - 1, v)
                            + fa * fb * at(z, H, W, u - 1, v - 1);
+        }
+}
+
+/* affine M_k (general warps): the sample of out(u,v) sits at row
+ * m[0] u + m[1] v + m[2], column m[3] u + m[4] v + m[5] */
+void orc_warp_affine(int H, int W, const double *m, const double *x, double *out) {
+#pragma omp parallel for schedule(static)
+    for (i64 u = 0; u < H; ++u)
+        for (i64 v = 0; v < W; ++v) {
+            const double r = m[0] * u + m[1] * v + m[2], c = m[3] * u + m[4] * v + m[5];
+            const double r0 = floor(r), c0 = floor(c);
+            const double fa = r - r0, fb = c - c0;
+            const i64 a0 = (i64)r0, b0 = (i64)c0;
+            out[u * W + v] = (1 - fa) * (1 - fb) * at(x, H, W, a0, b0)
+                           + (1 - fa) * fb * at(x, H, W, a0, b0 + 1)
+                           + fa * (1 - fb) * at(x, H, W, a0 + 1, b0)
+                           + fa * fb * at(x, H, W, a0 + 1, b0 + 1);
+        }
+}
+
+/* transpose of orc_warp_affine: every sample adds its value, times its four
+ * bilinear weights, to the pixels it read (serial scatter) */
+void orc_warp_affine_T(int H, int W, const double *m, const double *z, double *out) {
+    memset(out, 0, sizeof(double) * (i64)H * W);
+    for (i64 u = 0; u < H; ++u)
+        for (i64 v = 0; v < W; ++v) {
+            const double r = m[0] * u + m[1] * v + m[2], c = m[3] * u + m[4] * v + m[5];
+            const double r0 = floor(r), c0 = floor(c);
+            const double fa = r - r0, fb = c - c0;
+            const i64 a0 = (i64)r0, b0 = (i64)c0;
+            const double zv = z[u * W + v];
+            const double wgt[4] = {(1 - fa) * (1 - fb), (1 - fa) * fb, fa * (1 - fb), fa * fb};
+            const i64 ra[4] = {a0, a0, a0 + 1, a0 + 1}, cb[4] = {b0, b0 + 1, b0, b0 + 1};
+            for (int q = 0; q < 4; ++q)
+                if (ra[q] >= 0 && ra[q] < H && cb[q] >= 0 && cb[q] < W)
+                    out[ra[q] * W + cb[q]] += wgt[q] * zv;
         }
 }
 
@@ -130,13 +171,17 @@ void orc_bin_T(int H, int W, int s, const double *r, double *out) {
 /* ------------------------------------------------------ A_k and sum A_k^T */
 /* y has K frames of (H/s) x (W/s); shifts is K x 2 as (dx, dy) in LR px;
  * psf holds each frame's P x P PSF (K of them: B_k may differ per frame). */
-void orc_forward(int H, int W, int s, int K, const double *shifts, int P,
-                 const double *psf, const double *x, double *y) {
+/* warps: NULL (translations from shifts) or [K][6] affine coefficients */
+void orc_forward_w(int H, int W, int s, int K, const double *shifts, const double *warps,
+                   int P, const double *psf, const double *x, double *y) {
     const i64 n = (i64)H * W, m = (i64)(H / s) * (W / s);
     double *t1 = (double *)malloc(sizeof(double) * n);
     double *t2 = (double *)malloc(sizeof(double) * n);
     for (int k = 0; k < K; ++k) {
-        orc_warp(H, W, s * shifts[2 * k], s * shifts[2 * k + 1], x, t1);
+        if (warps)
+            orc_warp_affine(H, W, warps + 6 * k, x, t1);
+        else
+            orc_warp(H, W, s * shifts[2 * k], s * shifts[2 * k + 1], x, t1);
         orc_blur(H, W, P, psf + (i64)k * P * P, t1, t2);
         orc_bin(H, W, s, t2, y + k * m);
     }
@@ -144,8 +189,13 @@ void orc_forward(int H, int W, int s, int K, const double *shifts, int P,
     free(t2);
 }
 
-void orc_adjoint(int H, int W, int s, int K, const double *shifts, int P,
-                 const double *psf, const double *r, double *x) {
+void orc_forward(int H, int W, int s, int K, const double *shifts, int P,
+                 const double *psf, const double *x, double *y) {
+    orc_forward_w(H, W, s, K, shifts, NULL, P, psf, x, y);
+}
+
+void orc_adjoint_w(int H, int W, int s, int K, const double *shifts, const double *warps,
+                   int P, const double *psf, const double *r, double *x) {
     const i64 n = (i64)H * W, m = (i64)(H / s) * (W / s);
     double *t1 = (double *)malloc(sizeof(double) * n);
     double *t2 = (double *)malloc(sizeof(double) * n);
@@ -153,12 +203,20 @@ void orc_adjoint(int H, int W, int s, int K, const double *shifts, int P,
     for (int k = 0; k < K; ++k) {
         orc_bin_T(H, W, s, r + k * m, t1);
         orc_blur_T(H, W, P, psf + (i64)k * P * P, t1, t2);
-        orc_warp_T(H, W, s * shifts[2 * k], s * shifts[2 * k + 1], t2, t1);
+        if (warps)
+            orc_warp_affine_T(H, W, warps + 6 * k, t2, t1);
+        else
+            orc_warp_T(H, W, s * shifts[2 * k], s * shifts[2 * k + 1], t2, t1);
 #pragma omp parallel for schedule(static)
         for (i64 i = 0; i < n; ++i) x[i] += t1[i];
     }
     free(t1);
     free(t2);
+}
+
+void orc_adjoint(int H, int W, int s, int K, const double *shifts, int P,
+                 const double *psf, const double *r, double *x) {
+    orc_adjoint_w(H, W, s, K, shifts, NULL, P, psf, r, x);
 }
 
 /* ------------------------------------------------ Charbonnier phi and psi */
@@ -211,13 +269,13 @@ double orc_btv(int H, int W, double lambda, double alpha, double eps, int w,
 /* J(x) = sum_k sum phi_p(A_k x - y_k) + E_reg(x), with phi_2(r) = r^2 and
  * phi_1 = Charbonnier with eps_data.  g (nullable) receives grad J.
  * parts (nullable) receives {E_data, E_reg}.  Returns J. */
-double orc_cost_grad(int H, int W, int s, int K, const double *shifts, int P,
-                     const double *psf, double lambda, double alpha, double eps, int w,
-                     int data_p, double eps_data, const double *x, const double *y,
-                     double *g, double *parts) {
+double orc_cost_grad_w(int H, int W, int s, int K, const double *shifts,
+                       const double *warps, int P, const double *psf, double lambda,
+                       double alpha, double eps, int w, int data_p, double eps_data,
+                       const double *x, const double *y, double *g, double *parts) {
     const i64 n = (i64)H * W, m = (i64)(H / s) * (W / s) * K;
     double *r = (double *)malloc(sizeof(double) * m);
-    orc_forward(H, W, s, K, shifts, P, psf, x, r);
+    orc_forward_w(H, W, s, K, shifts, warps, P, psf, x, r);
     double Ed = 0.0;
 #pragma omp parallel for schedule(static) reduction(+ : Ed)
     for (i64 i = 0; i < m; ++i) {
@@ -230,7 +288,7 @@ double orc_cost_grad(int H, int W, int s, int K, const double *shifts, int P,
             r[i] = psi_eps(e, eps_data);
         }
     }
-    if (g) orc_adjoint(H, W, s, K, shifts, P, psf, r, g);
+    if (g) orc_adjoint_w(H, W, s, K, shifts, warps, P, psf, r, g);
     free(r);
     const double Er = orc_btv(H, W, lambda, alpha, eps, w, x, g);
     if (parts) {
@@ -239,6 +297,14 @@ double orc_cost_grad(int H, int W, int s, int K, const double *shifts, int P,
     }
     (void)n;
     return Ed + Er;
+}
+
+double orc_cost_grad(int H, int W, int s, int K, const double *shifts, int P,
+                     const double *psf, double lambda, double alpha, double eps, int w,
+                     int data_p, double eps_data, const double *x, const double *y,
+                     double *g, double *parts) {
+    return orc_cost_grad_w(H, W, s, K, shifts, NULL, P, psf, lambda, alpha, eps, w, data_p,
+                           eps_data, x, y, g, parts);
 }
 
 /* --------------------------------------- curvature in closed form (check) */

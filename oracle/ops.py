@@ -3,7 +3,9 @@
 Each function takes and returns float64 numpy arrays and forwards to the plain
 C definitions in ``misr_oracle.c``.  Shapes: HR images (H, W); LR frames
 (K, H//s, W//s); shifts (K, 2) as (dx, dy) in LR pixels; psf the 1-D taps whose
-outer product is the 2-D PSF, or per-frame PSFs (see psf_frames).
+outer product is the 2-D PSF, or per-frame PSFs (see psf_frames); warps None
+(translations from shifts) or (K, 6) affine coefficients per frame: frame k
+samples x at row m0 u + m1 v + m2, column m3 u + m4 v + m5 (HR pixels).
 """
 from __future__ import annotations
 
@@ -49,6 +51,12 @@ def _load():
         "orc_bin": [_I, _I, _I, _P, _P],
         "orc_bin_T": [_I, _I, _I, _P, _P],
         "orc_forward": [_I, _I, _I, _I, _P, _I, _P, _P, _P],
+        "orc_forward_w": [_I, _I, _I, _I, _P, _P, _I, _P, _P, _P],
+        "orc_adjoint_w": [_I, _I, _I, _I, _P, _P, _I, _P, _P, _P],
+        "orc_warp_affine": [_I, _I, _P, _P, _P],
+        "orc_warp_affine_T": [_I, _I, _P, _P, _P],
+        "orc_cost_grad_w": [_I, _I, _I, _I, _P, _P, _I, _P, _D, _D, _D, _I, _I, _D, _P, _P,
+                            _P, _P],
         "orc_adjoint": [_I, _I, _I, _I, _P, _I, _P, _P, _P],
         "orc_btv": [_I, _I, _D, _D, _D, _I, _P, _P],
         "orc_cost_grad": [_I, _I, _I, _I, _P, _I, _P, _D, _D, _D, _I, _I, _D, _P, _P,
@@ -67,6 +75,7 @@ def _load():
         fn.restype = None
     lib.orc_btv.restype = _D
     lib.orc_cost_grad.restype = _D
+    lib.orc_cost_grad_w.restype = _D
     lib.orc_psi_quotient.restype = _D
     lib.orc_curv_exact.restype = _D
     lib.orc_curv_data_l1.restype = _D
@@ -120,6 +129,28 @@ def warp_T(z, tx, ty):
     return out
 
 
+def warp_affine(x, m):
+    """Affine bilinear warp of one image: six coefficients m (general M_k)."""
+    x, m = _f64(x), _f64(m)
+    out = np.empty_like(x)
+    _load().orc_warp_affine(x.shape[0], x.shape[1], _p(m), _p(x), _p(out))
+    return out
+
+
+def warp_affine_T(z, m):
+    z, m = _f64(z), _f64(m)
+    out = np.empty_like(z)
+    _load().orc_warp_affine_T(z.shape[0], z.shape[1], _p(m), _p(z), _p(out))
+    return out
+
+
+def _warps(warps, K):
+    if warps is None:
+        return None
+    w = _f64(warps).reshape(K, 6)
+    return np.ascontiguousarray(w)
+
+
 def blur(z, psf):
     z, psf = _f64(z), psf_frames(psf, 1)[0]
     out = np.empty_like(z)
@@ -148,24 +179,26 @@ def bin_T(r, s, H, W):
     return out
 
 
-def forward(x, shifts, psf, s):
+def forward(x, shifts, psf, s, warps=None):
     """y_k = D B M_k x for every frame; returns (K, H//s, W//s)."""
     x, shifts = _f64(x), _f64(shifts)
     H, W = x.shape
     K = shifts.shape[0]
     psf = psf_frames(psf, K)
+    wp = _warps(warps, K)
     y = np.empty((K, H // s, W // s))
-    _load().orc_forward(H, W, s, K, _p(shifts), psf.shape[1], _p(psf), _p(x), _p(y))
+    _load().orc_forward_w(H, W, s, K, _p(shifts), _p(wp), psf.shape[1], _p(psf), _p(x), _p(y))
     return y
 
 
-def adjoint(r, shifts, psf, s, H, W):
+def adjoint(r, shifts, psf, s, H, W, warps=None):
     """sum_k A_k^T r_k; returns (H, W)."""
     r, shifts = _f64(r), _f64(shifts)
     K = shifts.shape[0]
     psf = psf_frames(psf, K)
+    wp = _warps(warps, K)
     x = np.empty((H, W))
-    _load().orc_adjoint(H, W, s, K, _p(shifts), psf.shape[1], _p(psf), _p(r), _p(x))
+    _load().orc_adjoint_w(H, W, s, K, _p(shifts), _p(wp), psf.shape[1], _p(psf), _p(r), _p(x))
     return x
 
 
@@ -177,17 +210,18 @@ def btv(x, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3, w=3, grad=True):
 
 
 def cost_grad(x, y, shifts, psf, s, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3, w=3,
-              data_p=2, eps_data=1e-3, grad=True):
+              data_p=2, eps_data=1e-3, grad=True, warps=None):
     """Returns (J, grad J or None, (E_data, E_reg))."""
     x, y, shifts = _f64(x), _f64(y), _f64(shifts)
     H, W = x.shape
     K = shifts.shape[0]
     psf = psf_frames(psf, K)
+    wp = _warps(warps, K)
     g = np.empty_like(x) if grad else None
     parts = np.zeros(2)
-    J = _load().orc_cost_grad(H, W, s, K, _p(shifts), psf.shape[1], _p(psf), lambda_reg,
-                              alpha_btv, eps, w, data_p, eps_data, _p(x), _p(y), _p(g),
-                              _p(parts))
+    J = _load().orc_cost_grad_w(H, W, s, K, _p(shifts), _p(wp), psf.shape[1], _p(psf),
+                                lambda_reg, alpha_btv, eps, w, data_p, eps_data, _p(x), _p(y),
+                                _p(g), _p(parts))
     return J, g, (float(parts[0]), float(parts[1]))
 
 

@@ -124,11 +124,11 @@ def scg_minimize(J_and_grad, x0: np.ndarray, n_iter: int, sigma: float = 1e-4,
 
 
 def misr_objective(y, shifts, psf, s, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3, w=3,
-                   data_p=2, eps_data=1e-3):
+                   data_p=2, eps_data=1e-3, warps=None):
     """J(x) and grad J(x) of the MISR objective through the C operators."""
     def f(x, need_grad=True):
         J, g, _ = ops.cost_grad(x, y, shifts, psf, s, lambda_reg, alpha_btv, eps, w,
-                                data_p, eps_data, grad=need_grad)
+                                data_p, eps_data, grad=need_grad, warps=warps)
         return J, g
     return f
 
@@ -140,13 +140,16 @@ def misr_curvature_exact(shifts, psf, s, lambda_reg=0.01, alpha_btv=0.4, eps=1e-
 
 
 def solve(prob_y, shifts, psf, s, x0, n_iter, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3,
-          w=3, sigma=1e-4, lam1=1e-6, exact_curvature=False, data_p=2, eps_data=1e-3):
+          w=3, sigma=1e-4, lam1=1e-6, exact_curvature=False, data_p=2, eps_data=1e-3,
+          warps=None):
     """SCG solve of the MISR objective (Eq. misr: L2 data term, or the
     Charbonnier-smoothed L1 term for data_p = 1), Moller's finite-difference
-    curvature unless exact_curvature (L2 only)."""
-    if exact_curvature and data_p != 2:
-        raise ValueError("the closed-form curvature here covers the L2 data term")
-    f = misr_objective(prob_y, shifts, psf, s, lambda_reg, alpha_btv, eps, w, data_p, eps_data)
+    curvature unless exact_curvature (L2, translational warps only); warps:
+    per-frame affine coefficients (see ops) instead of the shifts."""
+    if exact_curvature and (data_p != 2 or warps is not None):
+        raise ValueError("the closed-form curvature here covers the L2 data term and shifts")
+    f = misr_objective(prob_y, shifts, psf, s, lambda_reg, alpha_btv, eps, w, data_p, eps_data,
+                       warps)
     curv = misr_curvature_exact(shifts, psf, s, lambda_reg, alpha_btv, eps, w) \
         if exact_curvature else None
     return scg_minimize(f, x0, n_iter, sigma, lam1, curvature=curv)

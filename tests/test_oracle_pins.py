@@ -609,3 +609,92 @@ def test_per_frame_psfs_match_library_pipeline():
     same = np.stack([np.stack([taps[0, 0], taps[0, 0]])] * 4)
     assert np.array_equal(oracle.forward(x, shifts, same, s),
                           oracle.forward(x, shifts, taps[0, 0], s))
+
+
+# --------------------------------------------------------------------------
+# general operators: affine warps M_k and non-separable PSFs B_k (A_k = D B_k
+# M_k of Eq. sisr with a general M_k and B_k)
+def lib_warp_affine(x, m):
+    H, W = x.shape
+    uu, vv = np.meshgrid(np.arange(H, dtype=float), np.arange(W, dtype=float), indexing="ij")
+    return ndimage.map_coordinates(x, [m[0] * uu + m[1] * vv + m[2], m[3] * uu + m[4] * vv + m[5]],
+                                   order=1, mode="grid-constant", cval=0.0, prefilter=False)
+
+
+def rot_warp(theta, H, W, ty=0.0, tx=0.0):
+    """Rotation by theta about the image centre followed by a shift (HR px)."""
+    c, s_ = math.cos(theta), math.sin(theta)
+    cy, cx = (H - 1) / 2, (W - 1) / 2
+    return np.array([c, -s_, cy - c * cy + s_ * cx + ty, s_, c, cx - s_ * cy - c * cx + tx])
+
+
+def random_psfs(rng, K, P):
+    h = rng.uniform(0.0, 1.0, (K, P, P))
+    return h / h.sum(axis=(1, 2), keepdims=True)
+
+
+def test_affine_warp_matches_library():
+    """General M_k: bilinear samples at affine positions against scipy's
+    map_coordinates (order 1, zero outside)."""
+    rng = np.random.default_rng(61)
+    x = rng.standard_normal((11, 9))
+    for m in (rot_warp(0.3, 11, 9, 0.4, -0.7), np.array([1.1, 0.2, -0.5, -0.15, 0.9, 1.3]),
+              np.array([1.0, 0.0, 0.37, 0.0, 1.0, -1.61])):
+        assert np.allclose(oracle.warp_affine(x, m), lib_warp_affine(x, m), rtol=0, atol=1e-13)
+
+
+def test_affine_warp_special_cases():
+    """A quarter turn is an exact permutation (np.rot90), and a pure
+    translation reproduces the shift-based operator."""
+    rng = np.random.default_rng(62)
+    x = rng.standard_normal((7, 7))
+    quarter = np.array([0.0, 1.0, 0.0, -1.0, 0.0, 6.0])    # out(u, v) = x(v, 6 - u)
+    assert np.array_equal(oracle.warp_affine(x, quarter), np.rot90(x, 1))
+    H, W, s = 8, 12, 2
+    shifts = np.array([(0.0, 0.0), (-0.53, 0.21), (1.26, -0.77)])
+    psf = synth.psf_taps(0.8, 7)
+    xx = rng.standard_normal((H, W))
+    warps = np.array([[1.0, 0.0, s * dy, 0.0, 1.0, s * dx] for dx, dy in shifts])
+    assert np.allclose(oracle.forward(xx, shifts, psf, s, warps=warps),
+                       oracle.forward(xx, shifts, psf, s), rtol=0, atol=1e-13)
+
+
+def test_general_forward_matches_library_pipeline():
+    """Rotations and shears per frame with a different non-separable P x P PSF
+    per frame: the oracle against scipy (map_coordinates, convolve2d,
+    reshape-mean), and its adjoint by the dot test."""
+    rng = np.random.default_rng(63)
+    H, W, s, P = 12, 10, 2, 5
+    warps = np.stack([rot_warp(0.0, H, W), rot_warp(0.05, H, W, 0.5, 0.2),
+                      rot_warp(-0.11, H, W, -0.3, 0.9), np.array([1.02, 0.07, 0.4, -0.05, 0.97, -0.6])])
+    shifts = np.zeros((4, 2))
+    h = random_psfs(rng, 4, P)
+    x = rng.standard_normal((H, W))
+    y = oracle.forward(x, shifts, h, s, warps=warps)
+    for k in range(4):
+        z = signal.convolve2d(lib_warp_affine(x, warps[k]), h[k], mode="same", boundary="fill",
+                              fillvalue=0.0)
+        assert np.allclose(y[k], lib_bin(z, s), rtol=0, atol=1e-13)
+    r = rng.standard_normal(y.shape)
+    a = float(np.sum(y * r))
+    b = float(np.sum(x * oracle.adjoint(r, shifts, h, s, H, W, warps=warps)))
+    assert abs(a - b) <= 1e-12 * (abs(a) + abs(b))
+
+
+def test_general_gradient_central_differences():
+    """grad J with affine warps and non-separable PSFs against central
+    differences of J (Eq. objective)."""
+    rng = np.random.default_rng(64)
+    H, W, s = 8, 8, 2
+    warps = np.stack([rot_warp(0.1 * k, H, W, 0.3 * k, -0.2 * k) for k in range(4)])
+    shifts = np.zeros((4, 2))
+    h = random_psfs(rng, 4, 3)
+    x = rng.uniform(0, 1, (H, W))
+    y = oracle.forward(rng.uniform(0, 1, (H, W)), shifts, h, s, warps=warps)
+    J, g, _ = oracle.cost_grad(x, y, shifts, h, s, warps=warps)
+    for idx in [(0, 0), (3, 4), (7, 7), (5, 1)]:
+        e = np.zeros_like(x)
+        e[idx] = 1e-6
+        Jp = oracle.cost_grad(x + e, y, shifts, h, s, grad=False, warps=warps)[0]
+        Jm = oracle.cost_grad(x - e, y, shifts, h, s, grad=False, warps=warps)[0]
+        assert abs((Jp - Jm) / 2e-6 - g[idx]) <= 1e-6 * max(1.0, abs(g[idx]))
