@@ -78,12 +78,29 @@ typedef struct {
     int32_t hr_h, hr_w;       /* HR image size; both divisible by scale */
     int32_t scale;            /* s >= 1: LR frame is (hr_h/s) x (hr_w/s) */
     int32_t n_frames;         /* K >= 1 */
-    const double *shifts_lr;  /* [K][2] = (dx, dy) in LR pixels, |dx|,|dy| <= 1 */
+    const double *shifts_lr;  /* [K][2] = (dx, dy) in LR pixels, |dx|,|dy| <= 1;
+                                 may be NULL when warps is given */
     int32_t psf_size;         /* P, odd, 1 <= P <= 15 */
     const double *psf_1d;     /* [P] taps; the 2-D PSF is their outer product */
     const double *psf_frames; /* NULL, or [K][2][P]: frame k's own blur B_k (A_k =
                                  D B_k M_k), vertical taps then horizontal taps,
                                  B_k their outer product; overrides psf_1d */
+    /* General operators (A_k = D B_k M_k with a general M_k or B_k).  When
+     * either field below is set the operator is stored as a sparse matrix
+     * (ELL, A and its transpose, about 2 x 8 B x (P + s + 2)^2 per LR pixel
+     * and frame of device memory, built on the host at misr_op_create) and
+     * runs on the general kernels: FP32 images (img_dtype MISR_F32, y_u16 = 0),
+     * untiled (tile_lr = 0), x_init 0 or 1, no server; misr_interpolate is
+     * rejected. */
+    const double *warps;      /* NULL, or [K][6]: frame k's warp M_k samples x
+                                 bilinearly at row w0 u + w1 v + w2, column
+                                 w3 u + w4 v + w5 for HR pixel (u, v) (zero off
+                                 the grid); overrides shifts_lr.  The shift
+                                 (dx, dy) is (1, 0, s dy, 0, 1, s dx) */
+    const double *psf_2d;     /* NULL, or [K][P][P]: frame k's non-separable PSF,
+                                 h[a + R][b + R] weighting the sample at offset
+                                 (-a, -b), R = (P - 1) / 2 (zero padding);
+                                 overrides psf_1d and psf_frames */
 } misr_geometry;
 
 /* Objective and solver settings (Eq. objective, Eq. prior, Algorithm 1). */

@@ -1,9 +1,11 @@
 // abi.cpp -- the C ABI of libmisr.so: validation, operator construction,
 // workspace management and the device-resident SCG solve driver.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <thread>
 
 #include "runtime.h"
 
@@ -115,21 +117,33 @@ extern "C" misr_status misr_geometry_check(const misr_geometry *g) {
         return set_error(MISR_E_INVAL, "HR image too large (>= 2^31 pixels)");
     if (g->n_frames < 1 || g->n_frames > kMaxK)
         return set_error(MISR_E_INVAL, "n_frames %d outside [1, %d]", g->n_frames, kMaxK);
-    if (!g->shifts_lr) return set_error(MISR_E_INVAL, "shifts_lr is NULL");
-    for (int i = 0; i < 2 * g->n_frames; ++i)
-        if (!std::isfinite(g->shifts_lr[i]) || std::fabs(g->shifts_lr[i]) > 1.0)
-            return set_error(MISR_E_INVAL, "shift %d (%g) not finite or |shift| > 1 LR px", i,
-                             g->shifts_lr[i]);
+    if (!g->shifts_lr && !g->warps) return set_error(MISR_E_INVAL, "shifts_lr is NULL");
+    if (g->shifts_lr)
+        for (int i = 0; i < 2 * g->n_frames; ++i)
+            if (!std::isfinite(g->shifts_lr[i]) || std::fabs(g->shifts_lr[i]) > 1.0)
+                return set_error(MISR_E_INVAL, "shift %d (%g) not finite or |shift| > 1 LR px",
+                                 i, g->shifts_lr[i]);
     if (g->psf_size < 1 || g->psf_size > 15 || g->psf_size % 2 == 0)
         return set_error(MISR_E_INVAL, "psf_size %d must be odd in [1, 15]", g->psf_size);
-    if (!g->psf_1d) return set_error(MISR_E_INVAL, "psf_1d is NULL");
-    for (int i = 0; i < g->psf_size; ++i)
-        if (!std::isfinite(g->psf_1d[i]))
-            return set_error(MISR_E_INVAL, "psf tap %d not finite", i);
+    if (!g->psf_1d && !g->psf_2d) return set_error(MISR_E_INVAL, "psf_1d is NULL");
+    if (g->psf_1d)
+        for (int i = 0; i < g->psf_size; ++i)
+            if (!std::isfinite(g->psf_1d[i]))
+                return set_error(MISR_E_INVAL, "psf tap %d not finite", i);
     if (g->psf_frames)
         for (int i = 0; i < 2 * g->n_frames * g->psf_size; ++i)
             if (!std::isfinite(g->psf_frames[i]))
                 return set_error(MISR_E_INVAL, "psf_frames tap %d not finite", i);
+    if (g->psf_2d)
+        for (int i = 0; i < g->n_frames * g->psf_size * g->psf_size; ++i)
+            if (!std::isfinite(g->psf_2d[i]))
+                return set_error(MISR_E_INVAL, "psf_2d entry %d not finite", i);
+    if (g->warps) {
+        for (int i = 0; i < 6 * g->n_frames; ++i)
+            if (!std::isfinite(g->warps[i]) || std::fabs(g->warps[i]) > 1e6)
+                return set_error(MISR_E_INVAL, "warp coefficient %d not finite or > 1e6", i);
+    }
+    if (g->warps || g->psf_2d) return MISR_OK;   // general operator: no band constraints
     const int L = band_length(g);
     const int Lp = padded_band(g->scale, L);
     if (Lp < 0)
@@ -253,6 +267,176 @@ static void band_weights(int N, int s, double t, int P, const double *psf, int L
     }
 }
 
+// ---------------------------------------------------- general operators
+// Row (k, i, j) of A = [A_0; ...; A_{K-1}] for an affine warp and a P x P PSF:
+// D averages the s x s block of HR samples (U, V) = (s i + a, s j + b); B
+// takes h[pa + R][pb + R] times the warped image at (U - pa, V - pb), zero
+// off the grid; M samples x bilinearly at the affine position of that pixel,
+// zero off the grid.  Contributions to one HR pixel are merged (FP64).
+static void general_row(const misr_op *op, const double *m, const double *hk, int P, int i,
+                        int j, std::vector<std::pair<int, double>> &ent) {
+    const int H = op->H, W = op->W, s = op->s, R = (P - 1) / 2;
+    const double inv = 1.0 / ((double)s * s);
+    ent.clear();
+    for (int a = 0; a < s; ++a)
+        for (int b = 0; b < s; ++b)
+            for (int pa = -R; pa <= R; ++pa)
+                for (int pb = -R; pb <= R; ++pb) {
+                    const int u = s * i + a - pa, v = s * j + b - pb;
+                    if (u < 0 || u >= H || v < 0 || v >= W) continue;
+                    const double hw = hk[(pa + R) * P + (pb + R)] * inv;
+                    if (hw == 0.0) continue;
+                    const double r = m[0] * u + m[1] * v + m[2], c = m[3] * u + m[4] * v + m[5];
+                    const double r0 = std::floor(r), c0 = std::floor(c);
+                    const double fa = r - r0, fb = c - c0;
+                    const double wq[4] = {(1 - fa) * (1 - fb), (1 - fa) * fb, fa * (1 - fb),
+                                          fa * fb};
+                    const double rq[4] = {r0, r0, r0 + 1, r0 + 1}, cq[4] = {c0, c0 + 1, c0, c0 + 1};
+                    for (int q = 0; q < 4; ++q) {
+                        if (wq[q] == 0.0 || rq[q] < 0 || rq[q] >= H || cq[q] < 0 || cq[q] >= W)
+                            continue;
+                        ent.emplace_back((int)rq[q] * W + (int)cq[q], hw * wq[q]);
+                    }
+                }
+    std::sort(ent.begin(), ent.end(),
+              [](const std::pair<int, double> &x, const std::pair<int, double> &y) {
+                  return x.first < y.first;
+              });
+    size_t o = 0;
+    for (size_t e = 0; e < ent.size(); ++e) {
+        if (o > 0 && ent[o - 1].first == ent[e].first)
+            ent[o - 1].second += ent[e].second;
+        else
+            ent[o++] = ent[e];
+    }
+    ent.resize(o);
+}
+
+// Builds A and A^T of a general operator as ELL matrices (host, FP64 weights
+// rounded to FP32 once) and uploads them.
+static misr_status build_general(misr_op *op, const misr_geometry *g) {
+    op->general = true;
+    op->L = op->Lp = op->TH = op->TW = 0;
+    const int H = op->H, W = op->W, s = op->s, K = op->K, P = g->psf_size;
+    const int h = H / s, w = W / s;
+    const long long rows = (long long)K * h * w, n = (long long)H * W;
+    op->shifts.assign(2 * (size_t)K, 0.0);
+    if (g->shifts_lr) op->shifts.assign(g->shifts_lr, g->shifts_lr + 2 * K);
+    std::vector<double> warp(6 * (size_t)K), psf((size_t)K * P * P);
+    for (int k = 0; k < K; ++k) {
+        double *m = warp.data() + 6 * k;
+        if (g->warps) {
+            std::copy(g->warps + 6 * k, g->warps + 6 * k + 6, m);
+        } else {
+            const double mm[6] = {1.0, 0.0, s * op->shifts[2 * k + 1], 0.0, 1.0,
+                                  s * op->shifts[2 * k]};
+            std::copy(mm, mm + 6, m);
+        }
+        double *hk = psf.data() + (size_t)k * P * P;
+        if (g->psf_2d) {
+            std::copy(g->psf_2d + (size_t)k * P * P, g->psf_2d + (size_t)(k + 1) * P * P, hk);
+        } else {
+            const double *vy = g->psf_frames ? g->psf_frames + (size_t)k * 2 * P : g->psf_1d;
+            const double *vx = g->psf_frames ? vy + P : g->psf_1d;
+            for (int a = 0; a < P; ++a)
+                for (int b = 0; b < P; ++b) hk[a * P + b] = vy[a] * vx[b];
+        }
+    }
+    // rows in parallel chunks: (columns, weights) per row, then the ELL width
+    const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::vector<int>> cc(nt), len(nt);
+    std::vector<std::vector<double>> vv(nt);
+    auto work = [&](int t) {
+        std::vector<std::pair<int, double>> ent;
+        const long long r0 = rows * t / nt, r1 = rows * (t + 1) / nt;
+        for (long long r = r0; r < r1; ++r) {
+            const int k = (int)(r / ((long long)h * w));
+            const long long q = r - (long long)k * h * w;
+            general_row(op, warp.data() + 6 * k, psf.data() + (size_t)k * P * P, P,
+                        (int)(q / w), (int)(q % w), ent);
+            len[t].push_back((int)ent.size());
+            for (auto &e : ent) {
+                cc[t].push_back(e.first);
+                vv[t].push_back(e.second);
+            }
+        }
+    };
+    {
+        std::vector<std::thread> th;
+        for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
+        work(0);
+        for (auto &x : th) x.join();
+    }
+    int aw = 1;
+    for (auto &l : len)
+        for (int x : l) aw = std::max(aw, x);
+    std::vector<int> acol((size_t)aw * rows, 0), tcnt(n, 0), rlen(rows, 0);
+    std::vector<float> aval((size_t)aw * rows, 0.f);
+    {
+        long long r = 0;
+        for (int t = 0; t < nt; ++t) {
+            size_t e = 0;
+            for (int l : len[t]) {
+                rlen[r] = l;
+                for (int q = 0; q < aw; ++q) {
+                    const size_t at = (size_t)q * rows + r;
+                    if (q < l) {
+                        acol[at] = cc[t][e + q];
+                        aval[at] = (float)vv[t][e + q];
+                        tcnt[cc[t][e + q]]++;
+                    } else {
+                        acol[at] = l > 0 ? cc[t][e] : 0;   // weight 0 on one of the row's columns
+                    }
+                }
+                e += l;
+                ++r;
+            }
+            std::vector<int>().swap(cc[t]);
+            std::vector<double>().swap(vv[t]);
+        }
+    }
+    int tw = 1;
+    for (int x : tcnt) tw = std::max(tw, x);
+    std::vector<int> tcol((size_t)tw * n, -1);
+    std::vector<float> tval((size_t)tw * n, 0.f);
+    std::fill(tcnt.begin(), tcnt.end(), 0);
+    for (long long r = 0; r < rows; ++r)
+        for (int q = 0; q < rlen[r]; ++q) {
+            const size_t at = (size_t)q * rows + r;
+            const int c = acol[at];
+            const int slot = tcnt[c]++;
+            tcol[(size_t)slot * n + c] = (int)r;
+            tval[(size_t)slot * n + c] = aval[at];
+        }
+    for (long long c = 0; c < n; ++c) {
+        const int first = tcnt[c] > 0 ? tcol[c] : 0;
+        for (int q = tcnt[c]; q < tw; ++q) tcol[(size_t)q * n + c] = first;
+    }
+    MISR_HIP(op->a_col.ensure(acol.size() * 4));
+    MISR_HIP(op->a_val.ensure(aval.size() * 4));
+    MISR_HIP(op->t_col.ensure(tcol.size() * 4));
+    MISR_HIP(op->t_val.ensure(tval.size() * 4));
+    MISR_HIP(hipMemcpy(op->a_col.p, acol.data(), acol.size() * 4, hipMemcpyHostToDevice));
+    MISR_HIP(hipMemcpy(op->a_val.p, aval.data(), aval.size() * 4, hipMemcpyHostToDevice));
+    MISR_HIP(hipMemcpy(op->t_col.p, tcol.data(), tcol.size() * 4, hipMemcpyHostToDevice));
+    MISR_HIP(hipMemcpy(op->t_val.p, tval.data(), tval.size() * 4, hipMemcpyHostToDevice));
+    OpDev &hd = op->host;
+    std::memset(&hd, 0, sizeof hd);
+    hd.H = H;
+    hd.W = W;
+    hd.s = s;
+    hd.K = K;
+    hd.a_w = aw;
+    hd.t_w = tw;
+    hd.a_col = op->a_col.as<int>();
+    hd.a_val = op->a_val.as<float>();
+    hd.t_col = op->t_col.as<int>();
+    hd.t_val = op->t_val.as<float>();
+    MISR_HIP(op->opdev.ensure(sizeof(OpDev)));
+    MISR_HIP(hipMemcpy(op->opdev.p, &hd, sizeof hd, hipMemcpyHostToDevice));
+    return MISR_OK;
+}
+
 extern "C" misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, misr_op **out) {
     if (!ctx || !out) return set_error(MISR_E_INVAL, "ctx/out is NULL");
     *out = nullptr;
@@ -266,6 +450,12 @@ extern "C" misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, mis
     op->s = g->scale;
     op->K = g->n_frames;
     op->P = g->psf_size;
+    if (g->warps || g->psf_2d) {
+        if ((st = build_general(op.get(), g)) != MISR_OK) return st;
+        ctx->users++;
+        *out = op.release();
+        return MISR_OK;
+    }
     op->L = band_length(g);
     op->Lp = padded_band(op->s, op->L);
     op->TH = tile_hr(op->s, op->Lp);
@@ -323,6 +513,24 @@ extern "C" misr_status misr_op_destroy(misr_op *op) {
 }
 
 extern "C" int misr_op_band(const misr_op *op) { return op ? op->L : -1; }
+
+// General operator checks: FP32 images, untiled, no interpolation start point.
+static misr_status check_general(const misr_op *op, const misr_params &p) {
+    if (!op->general) return MISR_OK;
+    if (p.img_dtype != MISR_F32 || p.y_u16)
+        return set_error(MISR_E_INVAL, "general operators take FP32 images (img_dtype f32, "
+                         "y_u16 = 0)");
+    if (p.tile_lr > 0) return set_error(MISR_E_INVAL, "general operators run untiled");
+    if (p.x_init == 2)
+        return set_error(MISR_E_INVAL, "multi-image interpolation needs translational frames");
+    return MISR_OK;
+}
+
+// Residual buffer of a general solve (K h w floats).
+static hipError_t ensure_res(const misr_op *op, SolveBufs &b) {
+    if (!op->general) return hipSuccess;
+    return b.res.ensure((size_t)op->K * (op->H / op->s) * (op->W / op->s) * 4);
+}
 
 // ------------------------------------------------------------- plan build
 void misr::init_state(ScgState &s, const misr_params &p, long long N) {
@@ -418,6 +626,30 @@ void misr::add_views(const misr_op *op, const misr_params &prm, const void *y, v
     std::memset(&P, 0, sizeof P);
     P.y = y;
     P.op = op->opdev.as<OpDev>();
+    if (op->general) {
+        // one untiled FP32 view; items of kGenRows rows, LR rows (role 0)
+        // then HR rows (role 1), in both lists
+        P.x[0] = x;
+        P.x[1] = bufs->x1.p;
+        P.p[0] = bufs->p0.as<float>();
+        P.p[1] = bufs->p1.as<float>();
+        P.g[0] = bufs->g0.as<float>();
+        P.g[1] = bufs->g1.as<float>();
+        P.res = bufs->res.as<float>();
+        P.ld = P.Wb = op->W;
+        P.Hb = op->H;
+        P.oy1 = P.uy1 = op->H;
+        P.ox1 = P.ux1 = op->W;
+        const int pj = (int)projs.size();
+        projs.push_back(P);
+        const long long rows = (long long)op->K * (op->H / op->s) * (op->W / op->s);
+        const long long n = (long long)op->H * op->W;
+        for (auto *lst : {&items, &items_u}) {
+            for (long long b = 0; b * kGenRows < rows; ++b) lst->push_back(Item{pj, (int)b, 0, 0});
+            for (long long b = 0; b * kGenRows < n; ++b) lst->push_back(Item{pj, (int)b, 1, 0});
+        }
+        return;
+    }
     if (prm.tile_lr <= 0) {
         P.x[0] = iterate_fp32(prm) ? bufs->x0w.p : x;
         P.x[1] = bufs->x1.p;
@@ -580,10 +812,14 @@ struct Launcher {
         double *part = upd ? pd.partials_u.as<double>() : pd.partials.as<double>();
         const int off = upd ? (int)pl.classes.size() : 0;
         for (int c = 0; c < (int)cls.size(); ++c) {
-            hipError_t e = launch_image(cls[c].S, cls[c].Lp, cls[c].count, s, pd.projs.as<Proj>(),
-                                        items + cls[c].start, cnt() + off + c,
-                                        part + (size_t)cls[c].start * kNV, kind,
-                                        pl.code());
+            // band length 0: the class of general operators
+            hipError_t e =
+                cls[c].Lp == 0
+                    ? launch_general(cls[c].count, s, pd.projs.as<Proj>(), items + cls[c].start,
+                                     cnt() + off + c, part + (size_t)cls[c].start * kNV, kind)
+                    : launch_image(cls[c].S, cls[c].Lp, cls[c].count, s, pd.projs.as<Proj>(),
+                                   items + cls[c].start, cnt() + off + c,
+                                   part + (size_t)cls[c].start * kNV, kind, pl.code());
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -708,6 +944,13 @@ extern "C" misr_status misr_forward(const misr_op *cop, misr_dtype dt, const voi
         return set_error(MISR_E_INVAL, "dtype invalid");
     std::lock_guard<std::mutex> lk(op->mu);
     MISR_HIP(set_device(op->ctx->dev));
+    if (op->general) {
+        if (dt != MISR_F32) return set_error(MISR_E_INVAL, "general operators take FP32 images");
+        MISR_HIP(launch_general_forward((hipStream_t)stream, op->opdev.as<OpDev>(),
+                                        (long long)op->K * (op->H / op->s) * (op->W / op->s),
+                                        (const float *)x, (float *)y));
+        return MISR_OK;
+    }
     Plan &pl = op->plan;
     single_view(op, x, pl);
     PlanDev &pd = op->pdev;
@@ -726,6 +969,12 @@ extern "C" misr_status misr_adjoint(const misr_op *cop, misr_dtype dt, const voi
         return set_error(MISR_E_INVAL, "dtype invalid");
     std::lock_guard<std::mutex> lk(op->mu);
     MISR_HIP(set_device(op->ctx->dev));
+    if (op->general) {
+        if (dt != MISR_F32) return set_error(MISR_E_INVAL, "general operators take FP32 images");
+        MISR_HIP(launch_general_adjoint((hipStream_t)stream, op->opdev.as<OpDev>(),
+                                        (long long)op->H * op->W, (const float *)r, x));
+        return MISR_OK;
+    }
     Plan &pl = op->plan;
     single_view(op, x, pl);
     PlanDev &pd = op->pdev;
@@ -762,6 +1011,8 @@ static misr_status start_point(const misr_op *op, int kind, misr_dtype dt, const
 
 extern "C" misr_status misr_interpolate(const misr_op *op, misr_dtype dt, const void *y, void *x,
                                         void *stream) {
+    if (op && op->general)
+        return set_error(MISR_E_INVAL, "multi-image interpolation needs translational frames");
     return start_point(op, 2, dt, y, x, stream);
 }
 
@@ -776,12 +1027,14 @@ extern "C" misr_status misr_cost_grad(const misr_op *cop, const misr_params *prm
     if (!op || !x || !y || !g || !cost_dev) return set_error(MISR_E_INVAL, "NULL argument");
     misr_status st = misr_params_check(prm);
     if (st != MISR_OK) return st;
+    if ((st = check_general(op, *prm)) != MISR_OK) return st;
     if ((st = check_tiling(op, *prm)) != MISR_OK) return st;
     std::lock_guard<std::mutex> lk(op->mu);
     MISR_HIP(set_device(op->ctx->dev));
     const size_t es = dtype_size(prm->img_dtype);
     const long long n = (long long)op->H * op->W;
     MISR_HIP(op->bufs.ensure(n, es));
+    MISR_HIP(ensure_res(op, op->bufs));
     if (prm->tile_lr > 0) MISR_HIP(ensure_tiles(op, *prm, op->tiles));
     Plan &pl = op->plan;
     SolveIn si{op, *prm, y, const_cast<void *>(x), &op->bufs, &op->tiles};
@@ -812,6 +1065,7 @@ extern "C" misr_status misr_scg_solve(const misr_op *cop, const misr_params *prm
     if (!op || !y || !x) return set_error(MISR_E_INVAL, "NULL argument");
     misr_status st = misr_params_check(prm);
     if (st != MISR_OK) return st;
+    if ((st = check_general(op, *prm)) != MISR_OK) return st;
     if ((st = check_tiling(op, *prm)) != MISR_OK) return st;
     std::lock_guard<std::mutex> lk(op->mu);
     std::lock_guard<std::mutex> lc(op->ctx->mu);
@@ -821,6 +1075,7 @@ extern "C" misr_status misr_scg_solve(const misr_op *cop, const misr_params *prm
         MISR_HIP(ensure_tiles(op, *prm, op->tiles));
     else
         MISR_HIP(op->bufs.ensure_view(n, *prm));
+    MISR_HIP(ensure_res(op, op->bufs));
     Plan &pl = op->plan;
     build_plan(pl, {SolveIn{op, *prm, y, x, &op->bufs, &op->tiles}});
     hipStream_t s = (hipStream_t)stream;
@@ -851,6 +1106,7 @@ extern "C" misr_status misr_scg_solve_batch(int n, const misr_op *const *ops,
         if (!ops[i] || !y[i] || !x[i]) return set_error(MISR_E_INVAL, "NULL entry %d", i);
         misr_status st = misr_params_check(&prm[i]);
         if (st != MISR_OK) return st;
+        if ((st = check_general(ops[i], prm[i])) != MISR_OK) return st;
         if (prm[i].tile_lr > 0)
             return set_error(MISR_E_INVAL, "batch entry %d: batched solves are untiled", i);
         if (prm[i].img_dtype != prm[0].img_dtype || prm[i].x_work != prm[0].x_work ||
@@ -875,6 +1131,7 @@ extern "C" misr_status misr_scg_solve_batch(int n, const misr_op *const *ops,
     for (int i = 0; i < n; ++i) {
         if ((int)bc.bufs.size() <= i) bc.bufs.emplace_back(new SolveBufs());
         MISR_HIP(bc.bufs[i]->ensure_view((long long)ops[i]->H * ops[i]->W, prm[i]));
+        MISR_HIP(ensure_res(ops[i], *bc.bufs[i]));
         in.push_back(SolveIn{ops[i], prm[i], y[i], x[i], bc.bufs[i].get(), nullptr});
     }
     build_plan(bc.plan, in);
@@ -900,11 +1157,13 @@ extern "C" misr_status misr_time_pass(const misr_op *cop, const misr_params *prm
     misr_status st = misr_params_check(prm);
     if (st != MISR_OK) return st;
     if (prm->tile_lr > 0) return set_error(MISR_E_INVAL, "timing runs untiled");
+    if ((st = check_general(op, *prm)) != MISR_OK) return st;
     std::lock_guard<std::mutex> lk(op->mu);
     std::lock_guard<std::mutex> lc(op->ctx->mu);
     MISR_HIP(set_device(op->ctx->dev));
     const long long n = (long long)op->H * op->W;
     MISR_HIP(op->bufs.ensure(n, dtype_size(prm->img_dtype)));
+    MISR_HIP(ensure_res(op, op->bufs));
     Plan &pl = op->plan;
     misr_params p1 = *prm;
     p1.n_iter = 1;

@@ -25,13 +25,29 @@ constexpr int st_y(int code) { return code >> 4; }
 // weight wy[(k*(h + 2*kPadRows) + i)*L + l]; columns likewise with wx / offx.
 // wy/wx point at row 0 of frame 0; kPadRows zero rows sit before and after
 // every frame's rows so that kernels may index slightly outside [0, h).
+//
+// General operators (affine warps or non-separable PSFs, where A_k does not
+// factor) instead carry A = [A_0; ...; A_{K-1}] as an ELL matrix over the
+// K h w LR rows, a_w entries per row, entry q of row r at [q * rows + r]
+// (padding: weight 0 on one of the row's own columns), and its transpose the
+// same way over the H W HR rows; wy/wx are then NULL.
 struct OpDev {
     const float *wy;
     const float *wx;
     int offy[kMaxK];
     int offx[kMaxK];
     int H, W, s, K, L;
+    int a_w, t_w;
+    const int *a_col;
+    const float *a_val;
+    const int *t_col;
+    const float *t_val;
 };
+
+// Rows (LR or HR pixels) per work item of the general-operator kernels; an
+// item's tx is its role: 0 LR rows (forward, residual), 1 HR rows (adjoint,
+// prior, update).
+constexpr int kGenRows = 256;
 
 // One image (or one tile of an image held separately in HBM) in a work list.
 // Buffers are H-major with row stride ld; buffer pixel (u, v) is global
@@ -52,6 +68,7 @@ struct Proj {
     int ntx;             // tiles per row of the owned rectangle
     struct ScgState *st; // the solve this view belongs to
     const OpDev *op;
+    float *res;          // general operators: the residual term per LR row (K h w)
 };
 
 // Halo exchange: rows x cols pixels at global (gy, gx) of view src's owned

@@ -31,6 +31,14 @@ hipError_t launch_forward(int S, int Lp, int grid, hipStream_t stream, const Pro
                           const Item *items, int n, int stype, void *y);
 hipError_t launch_adjoint(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,
                           const Item *items, int n, int stype, const void *r, float *x);
+// general operators (general_kernels.hip): one pass over a class of general
+// items (kind as launch_image), and the standalone FP32 operators
+hipError_t launch_general(int grid, hipStream_t stream, const Proj *projs, const Item *items,
+                          const int *n_items, double *partials, int kind);
+hipError_t launch_general_forward(hipStream_t stream, const OpDev *op, long long rows,
+                                  const float *x, float *y);
+hipError_t launch_general_adjoint(hipStream_t stream, const OpDev *op, long long n,
+                                  const float *r, float *x);
 hipError_t launch_scalar(int grid, hipStream_t stream, const SolveRef *refs, const int *n_refs,
                          const double *partials, const double *partials_u, int phase);
 hipError_t launch_halo(hipStream_t stream, const Proj *projs, const HaloCopy *copies,
@@ -194,7 +202,10 @@ inline int frame_stype(const misr_params &p) {
 // iterate).
 struct SolveBufs {
     DevMem x1, p0, p1, g0, g1, x0w;
-    void set_pool(MemPool *pl) { x1.pool = p0.pool = p1.pool = g0.pool = g1.pool = x0w.pool = pl; }
+    DevMem res;   // general operators: the residual term per LR row
+    void set_pool(MemPool *pl) {
+        x1.pool = p0.pool = p1.pool = g0.pool = g1.pool = x0w.pool = res.pool = pl;
+    }
     hipError_t ensure(long long n, size_t es) {
         hipError_t e;
         if ((e = x1.ensure(n * es)) != hipSuccess) return e;
@@ -250,6 +261,10 @@ struct misr_op {
     std::vector<double> shifts;
     std::vector<double> psf;           // [K][2][P]: each frame's vertical, horizontal taps
     misr::DevMem wy, wx, opdev;
+    // general operator (affine warps or non-separable PSFs): A and A^T as ELL
+    // matrices (L = Lp = TH = TW = 0; the work-list class key is (s, 0))
+    bool general = false;
+    misr::DevMem a_col, a_val, t_col, t_val;
     misr::OpDev host;
     std::mutex mu;
     // cached workspace of the single-image entry points

@@ -659,6 +659,9 @@ extern "C" misr_status misr_server_submit(misr_server *s, const misr_request *re
     if (!s || !req || !id) return set_error(MISR_E_INVAL, "NULL argument");
     misr_status st = misr_geometry_check(&req->geom);
     if (st != MISR_OK) return st;
+    if (req->geom.warps || req->geom.psf_2d)
+        return set_error(MISR_E_INVAL, "the server takes translational, separable geometries "
+                         "(solve general operators with misr_scg_solve)");
     if ((st = misr_params_check(&req->params)) != MISR_OK) return st;
     if (!req->y || !req->x_out || (!req->x0 && req->params.x_init == 0))
         return set_error(MISR_E_INVAL, "NULL buffer (x0 may be NULL only with x_init > 0)");

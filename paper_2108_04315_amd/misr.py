@@ -42,7 +42,8 @@ class misr_geometry(C.Structure):
     _fields_ = [("hr_h", C.c_int32), ("hr_w", C.c_int32), ("scale", C.c_int32),
                 ("n_frames", C.c_int32), ("shifts_lr", C.POINTER(C.c_double)),
                 ("psf_size", C.c_int32), ("psf_1d", C.POINTER(C.c_double)),
-                ("psf_frames", C.POINTER(C.c_double))]
+                ("psf_frames", C.POINTER(C.c_double)), ("warps", C.POINTER(C.c_double)),
+                ("psf_2d", C.POINTER(C.c_double))]
 
 
 class misr_params(C.Structure):
@@ -170,23 +171,32 @@ def default_params(**kw) -> misr_params:
     return p
 
 
-def make_geometry(H: int, W: int, s: int, shifts, psf):
+def make_geometry(H: int, W: int, s: int, shifts, psf, warps=None):
     """Returns (misr_geometry, keepalive arrays).  psf: (P,) taps shared by
-    all frames and both axes, or (K, 2, P) per frame (vertical taps, then
-    horizontal taps)."""
+    all frames and both axes, (K, 2, P) per frame (vertical taps, then
+    horizontal taps), or (K, P, P) non-separable per frame; warps: None or
+    (K, 6) affine coefficients per frame (the general operator)."""
     sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64).reshape(-1, 2))
     pa = np.asarray(psf, dtype=np.float64)
     dp = C.POINTER(C.c_double)
+    wp = None if warps is None else np.ascontiguousarray(
+        np.asarray(warps, dtype=np.float64).reshape(sh.shape[0], 6))
+    wptr = None if wp is None else wp.ctypes.data_as(dp)
+    if pa.ndim == 3 and pa.shape[1] == pa.shape[2] and pa.shape[1] != 2:
+        p2 = np.ascontiguousarray(pa)
+        g = misr_geometry(H, W, s, sh.shape[0], sh.ctypes.data_as(dp), p2.shape[1], None, None,
+                          wptr, p2.ctypes.data_as(dp))
+        return g, (sh, p2, wp)
     if pa.ndim == 3:
         pf = np.ascontiguousarray(pa)
         ps = np.ascontiguousarray(pf[0, 0])
         g = misr_geometry(H, W, s, sh.shape[0], sh.ctypes.data_as(dp), pf.shape[2],
-                          ps.ctypes.data_as(dp), pf.ctypes.data_as(dp))
-        return g, (sh, ps, pf)
+                          ps.ctypes.data_as(dp), pf.ctypes.data_as(dp), wptr, None)
+        return g, (sh, ps, pf, wp)
     ps = np.ascontiguousarray(pa.ravel())
     g = misr_geometry(H, W, s, sh.shape[0], sh.ctypes.data_as(dp), ps.size,
-                      ps.ctypes.data_as(dp), None)
-    return g, (sh, ps)
+                      ps.ctypes.data_as(dp), None, wptr, None)
+    return g, (sh, ps, wp)
 
 
 class Context:
@@ -213,14 +223,17 @@ class Context:
 
 class Operator:
     """Observation model A_k = D B_k M_k of one geometry (built once, reused);
-    psf: (P,) taps for every frame and axis, or (K, 2, P) per frame."""
+    psf: (P,) taps for every frame and axis, (K, 2, P) per frame, or
+    (K, P, P) non-separable per frame; warps: None (the shifts) or (K, 6)
+    affine coefficients per frame.  A non-separable PSF or warps give the
+    general (sparse) operator."""
 
-    def __init__(self, ctx: Context, H: int, W: int, s: int, shifts, psf):
+    def __init__(self, ctx: Context, H: int, W: int, s: int, shifts, psf, warps=None):
         self.ctx = ctx
         self.H, self.W, self.s = H, W, s
         self.shifts = np.asarray(shifts, dtype=np.float64).reshape(-1, 2)
         self.K = self.shifts.shape[0]
-        g, keep = make_geometry(H, W, s, self.shifts, psf)
+        g, keep = make_geometry(H, W, s, self.shifts, psf, warps)
         h = C.c_void_p()
         check(lib.misr_op_create(ctx.h, C.byref(g), C.byref(h)))
         self.h = h

@@ -1,0 +1,219 @@
+"""General operators (A_k = D B_k M_k with per-frame affine warps M_k and/or
+non-separable PSFs B_k, held as sparse matrices) through the C ABI, against
+the FP64 oracle: forward and adjoint, cost and gradient (L2 and L1 data
+terms), the SCG solve, a batch mixing general and banded operators, the
+banded operator reproduced by its general form, and the parameters the
+general path rejects."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import scg as oscg
+from paper_2108_04315_amd import synth
+from gpu_common import TOL_OP, TOL_SCG, rel_l2, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def misr():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2108_04315_amd import misr as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(misr):
+    c = misr.Context(0)
+    yield c
+    c.close()
+
+
+def _f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def rot_warp(theta, H, W, ty=0.0, tx=0.0):
+    """Rotation by theta about the image centre followed by a shift (HR px)."""
+    c, s_ = math.cos(theta), math.sin(theta)
+    cy, cx = (H - 1) / 2, (W - 1) / 2
+    return np.array([c, -s_, cy - c * cy + s_ * cx + ty, s_, c, cx - s_ * cy - c * cx + tx])
+
+
+def psfs_2d(rng, K, P):
+    """Per-frame non-separable PSFs: an anisotropic rotated Gaussian plus a
+    random positive perturbation, normalised."""
+    R = (P - 1) / 2
+    a, b = np.meshgrid(np.arange(P) - R, np.arange(P) - R, indexing="ij")
+    out = []
+    for k in range(K):
+        th = 0.4 * k
+        u, v = math.cos(th) * a + math.sin(th) * b, -math.sin(th) * a + math.cos(th) * b
+        h = np.exp(-0.5 * (u / (0.7 + 0.1 * k)) ** 2 - 0.5 * (v / 1.1) ** 2)
+        h = h + 0.05 * rng.uniform(0, 1, (P, P))
+        out.append(h / h.sum())
+    return np.stack(out)
+
+
+# (H, W, s, K, P, kind): rows of ragged sizes (not multiples of 256 rows)
+CASES = [
+    (40, 52, 2, 4, 5, "affine"),
+    (42, 36, 3, 4, 7, "psf2d"),
+    (50, 46, 2, 3, 5, "both"),
+]
+
+
+def _geometry(H, W, s, K, P, kind, seed=0):
+    rng = np.random.default_rng(seed)
+    shifts = synth.frame_shifts(s, K, 0.05, seed + 1)[:K]
+    warps = None
+    psf = synth.psf_taps(0.8, P)
+    if kind in ("affine", "both"):
+        warps = np.stack([rot_warp(0.0 if k == 0 else 0.03 * k * (-1) ** k, H, W,
+                                   s * shifts[k, 1], s * shifts[k, 0]) for k in range(K)])
+    if kind in ("psf2d", "both"):
+        psf = psfs_2d(rng, K, P)
+    return shifts, psf, warps
+
+
+@pytest.mark.parametrize("H,W,s,K,P,kind", CASES)
+def test_general_operators_and_cost_grad(misr, ctx, H, W, s, K, P, kind):
+    import torch
+    shifts, psf, warps = _geometry(H, W, s, K, P, kind)
+    op = misr.Operator(ctx, H, W, s, shifts, psf, warps=warps)
+    assert op.band == 0
+    rng = np.random.default_rng(7)
+    x = _f32(rng.uniform(0, 1, (H, W)))
+    y = to_np(op.forward(to_dev(x)))
+    y_ref = oracle.forward(x, shifts, psf, s, warps=warps)
+    assert rel_l2(y, y_ref) <= TOL_OP, rel_l2(y, y_ref)
+    r = _f32(rng.standard_normal(y.shape))
+    xa = to_np(op.adjoint(to_dev(r)))
+    assert rel_l2(xa, oracle.adjoint(r, shifts, psf, s, H, W, warps=warps)) <= TOL_OP
+    yy = _f32(y_ref + 0.01 * rng.standard_normal(y_ref.shape))
+    for data_p in (2, 1):
+        prm = misr.default_params(n_iter=0)
+        prm.data_p = data_p
+        prm.eps_data = 1e-2
+        J, g_ref, _ = oracle.cost_grad(x, yy, shifts, psf, s, data_p=data_p, eps_data=1e-2,
+                                       warps=warps)
+        cost, g = op.cost_grad(to_dev(x), to_dev(yy), prm)
+        torch.cuda.synchronize()
+        assert abs(cost.cpu().numpy()[0] - J) <= TOL_OP * J
+        assert rel_l2(to_np(g), g_ref) <= TOL_OP, (data_p, rel_l2(to_np(g), g_ref))
+    op.close()
+
+
+def _solve_problem(H, W, s, K, P, kind, seed):
+    shifts, psf, warps = _geometry(H, W, s, K, P, kind, seed)
+    x_gt = synth.phantom(H, W, seed)
+    y = _f32(synth.add_poisson_noise(oracle.forward(x_gt, shifts, psf, s, warps=warps), 1e4,
+                                     seed + 2))
+    x0 = _f32(synth.bicubic_upsample(y[0], s))
+    return shifts, psf, warps, y, x0
+
+
+@pytest.mark.parametrize("kind,data_p", [("both", 2), ("affine", 1)])
+def test_general_solve_matches_oracle(misr, ctx, kind, data_p):
+    H, W, s, K, P, n = 64, 56, 2, 4, 5, 25
+    shifts, psf, warps, y, x0 = _solve_problem(H, W, s, K, P, kind, 3)
+    x_o, tr_o, _ = oscg.solve(y, shifts, psf, s, x0, n, data_p=data_p, eps_data=1e-2,
+                              warps=warps)
+    op = misr.Operator(ctx, H, W, s, shifts, psf, warps=warps)
+    prm = misr.default_params(n_iter=n)
+    prm.data_p = data_p
+    prm.eps_data = 1e-2
+    x = to_dev(x0)
+    its, info = op.scg_solve(to_dev(y), x, prm)
+    err = rel_l2(to_np(x), x_o)
+    print(f"general solve ({kind}, p={data_p}): rel-L2 vs oracle {err:.3e}, "
+          f"{info['n_success']} accepted")
+    assert err <= TOL_SCG
+    assert [t["success"] for t in its] == [t["success"] for t in tr_o]
+    op.close()
+
+
+def test_general_form_of_a_banded_operator(misr, ctx):
+    """The banded (separable, translational) operator and the same geometry
+    given as a general one (outer-product PSF as psf_2d): the same images up
+    to FP32 rounding, and their solves agree."""
+    H, W, s, K, P, n = 64, 64, 2, 4, 7, 20
+    shifts = synth.frame_shifts(s, K, 0.05, 5)
+    taps = synth.psf_taps(0.8, P)
+    x_gt = synth.phantom(H, W, 6)
+    y = _f32(synth.add_poisson_noise(oracle.forward(x_gt, shifts, taps, s), 1e4, 7))
+    x0 = _f32(synth.bicubic_upsample(y[0], s))
+    banded = misr.Operator(ctx, H, W, s, shifts, taps)
+    general = misr.Operator(ctx, H, W, s, shifts, np.stack([np.outer(taps, taps)] * K))
+    assert banded.band > 0 and general.band == 0
+    xv = to_dev(x_gt)
+    assert rel_l2(to_np(general.forward(xv)), to_np(banded.forward(xv))) <= TOL_OP
+    xb, xg = to_dev(x0), to_dev(x0)
+    tb, _ = banded.scg_solve(to_dev(y), xb, misr.default_params(n_iter=n))
+    tg, _ = general.scg_solve(to_dev(y), xg, misr.default_params(n_iter=n))
+    assert rel_l2(to_np(xg), to_np(xb)) <= TOL_SCG
+    assert [t["success"] for t in tg] == [t["success"] for t in tb]
+    banded.close()
+    general.close()
+
+
+def test_batch_mixing_general_and_banded(misr, ctx):
+    """One batch (shared launches) of a general and a banded solve equals the
+    two solved alone, bit for bit."""
+    import torch
+    n = 15
+    H, W, s, K, P = 48, 40, 2, 4, 5
+    sh, psf, warps, y1, x01 = _solve_problem(H, W, s, K, P, "both", 8)
+    g1 = misr.Operator(ctx, H, W, s, sh, psf, warps=warps)
+    shifts2 = synth.frame_shifts(2, 4, 0.05, 9)
+    taps2 = synth.psf_taps(0.8, 7)
+    x_gt2 = synth.phantom(64, 64, 9)
+    y2 = _f32(synth.add_poisson_noise(oracle.forward(x_gt2, shifts2, taps2, 2), 1e4, 10))
+    x02 = _f32(synth.bicubic_upsample(y2[0], 2))
+    b2 = misr.Operator(ctx, 64, 64, 2, shifts2, taps2)
+    prm = misr.default_params(n_iter=n)
+    xs = [to_dev(x01), to_dev(x02)]
+    misr.scg_solve_batch([g1, b2], [to_dev(y1), to_dev(y2)], xs, [prm, prm])
+    xa, xb = to_dev(x01), to_dev(x02)
+    g1.scg_solve(to_dev(y1), xa, misr.default_params(n_iter=n))
+    b2.scg_solve(to_dev(y2), xb, misr.default_params(n_iter=n))
+    torch.cuda.synchronize()
+    assert torch.equal(xs[0], xa) and torch.equal(xs[1], xb)
+    g1.close()
+    b2.close()
+
+
+def test_general_path_rejections(misr, ctx):
+    import torch
+    H, W, s, K, P = 32, 32, 2, 4, 5
+    shifts, psf, warps = _geometry(H, W, s, K, P, "both")
+    op = misr.Operator(ctx, H, W, s, shifts, psf, warps=warps)
+    y = torch.zeros((K, H // s, W // s), device="cuda")
+    x = torch.zeros((H, W), device="cuda")
+    with pytest.raises(misr.MisrError) as e:
+        op.interpolate(y, x)
+    assert e.value.status == misr.E_INVAL
+    for field, value in (("tile_lr", 8), ("x_init", 2)):
+        prm = misr.default_params(n_iter=2)
+        setattr(prm, field, value)
+        with pytest.raises(misr.MisrError) as e:
+            op.scg_solve(y, x, prm)
+        assert e.value.status == misr.E_INVAL
+    with pytest.raises(misr.MisrError) as e:
+        op.scg_solve(y.half(), x.half(), misr.default_params(n_iter=2))
+    assert e.value.status == misr.E_INVAL
+    srv = misr.Server(ctx, hbm_budget_bytes=1 << 28)
+    with pytest.raises(misr.MisrError) as e:
+        srv.submit(H, W, s, shifts, psf, y, x, torch.empty_like(x), misr.default_params(n_iter=2))
+    assert e.value.status == misr.E_INVAL
+    srv.close()
+    # bicubic start point (x_init = 1) is accepted
+    prm = misr.default_params(n_iter=2)
+    prm.x_init = 1
+    op.scg_solve(y + 0.5, x, prm)
+    torch.cuda.synchronize()
+    assert torch.isfinite(x).all()
+    op.close()
