@@ -347,6 +347,76 @@ def bench_precision(misr, ctx, K, Wm, L=2048, s=3, n_iter=100):
     return out
 
 
+def bench_general(misr, ctx, K, Wm, Hh=1024, s=2, n_iter=100, P=7):
+    """General operators (A_k = D B_k M_k with general factors): HR 1024^2
+    (4 LR frames of 512^2, x2), frame k rotated about the image centre by
+    (0, 0.5, -1.0, 1.5) degrees and shifted by its sub-pixel offset, each with
+    its own non-separable PSF (a 7 x 7 anisotropic Gaussian rotated by 0.4 k
+    rad); 100 SCG passes.  A and A^T are ELL matrices built on the host; the
+    trial and update passes stream them."""
+    import math
+    import torch
+    from paper_2108_04315_amd import synth
+    shifts = synth.frame_shifts(s, 4, 0.05, 12)
+    cy = cx = (Hh - 1) / 2
+    warps, psf = [], []
+    R = (P - 1) / 2
+    a, b = np.meshgrid(np.arange(P) - R, np.arange(P) - R, indexing="ij")
+    for k, deg in enumerate((0.0, 0.5, -1.0, 1.5)):
+        c, sn = math.cos(math.radians(deg)), math.sin(math.radians(deg))
+        ty, tx = s * shifts[k, 1], s * shifts[k, 0]
+        warps.append([c, -sn, cy - c * cy + sn * cx + ty, sn, c, cx - sn * cy - c * cx + tx])
+        th = 0.4 * k
+        u, v = math.cos(th) * a + math.sin(th) * b, -math.sin(th) * a + math.cos(th) * b
+        h = np.exp(-0.5 * (u / (0.7 + 0.1 * k)) ** 2 - 0.5 * (v / 1.1) ** 2)
+        psf.append(h / h.sum())
+    warps, psf = np.array(warps), np.stack(psf)
+    t0 = time.perf_counter()
+    op = misr.Operator(ctx, Hh, Hh, s, shifts, psf, warps=warps)
+    t_build = time.perf_counter() - t0
+    clean = op.forward(torch.from_numpy(synth.phantom(Hh, Hh, 12)).float().cuda())
+    torch.cuda.synchronize()
+    y_np = synth.add_poisson_noise(clean.double().cpu().numpy(), 1e4, 13)
+    y = torch.from_numpy(y_np).float().cuda()
+    x0 = torch.from_numpy(synth.bicubic_upsample(y_np[0], s)).float().cuda()
+    prm = misr.default_params(n_iter=n_iter)
+    xs = [x0.clone() for _ in range(K + Wm)]
+    torch.cuda.synchronize()
+    for i in range(Wm):
+        op.scg_solve(y, xs[i], prm, trace=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(Wm, Wm + K):
+        op.scg_solve(y, xs[i], prm, trace=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    us_trial = op.time_pass(y, x0.clone(), 0, reps=20, params=misr.default_params(n_iter=n_iter))
+    us_update = op.time_pass(y, x0.clone(), 1, reps=20, params=misr.default_params(n_iter=n_iter))
+    aw, tw = op.sparse_width
+    rows, n = 4 * (Hh // s) ** 2, Hh * Hh
+    # bytes each pass must move with this storage: the ELL entries (4 B column
+    # + 4 B weight) of A and A^T, and the vectors once each
+    b_trial = rows * aw * 8 + n * tw * 8 + rows * 12 + n * 20
+    b_update = rows * aw * 8 + rows * 4 + n * 24
+    out = _base_line(Hh * Hh * K / dt / 1e6, K, Wm, dt, "f32",
+                     {"workload": f"general1024: 4 LR frames {Hh // s}x{Hh // s} -> {Hh}x{Hh} "
+                                  f"HR (x2), per-frame rotation (0, 0.5, -1, 1.5 deg) + "
+                                  f"sub-pixel shift, per-frame non-separable {P}x{P} PSF, "
+                                  f"{n_iter} SCG passes", "hr": [Hh, Hh], "scale": s,
+                      "frames": 4, "scg_passes": n_iter, "parallelism": "1 GPU"})
+    out["operator"] = {"ell_width_A": aw, "ell_width_AT": tw, "build_s": t_build,
+                       "bytes_A_and_AT": rows * aw * 8 + n * tw * 8}
+    out["general_passes"] = {
+        "trial": {"kernels": "k_gen_trial_lr + k_gen_trial_hr", "avg_us": us_trial,
+                  "bytes_per_launch": b_trial,
+                  "achieved_GBs": b_trial / (us_trial * 1e-6) / 1e9,
+                  "frac_of_8TBs": b_trial / (us_trial * 1e-6) / 1e9 / PEAK_HBM_GBS},
+        "update": {"kernels": "k_gen_upd_hr + k_gen_upd_lr", "avg_us": us_update,
+                   "bytes_per_launch": b_update,
+                   "achieved_GBs": b_update / (us_update * 1e-6) / 1e9}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -355,8 +425,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--workload", default="plain2048",
-                    choices=["plain2048", "batched64", "precision6144"],
-                    help="plain2048 (default: the headline line), batched64, precision6144")
+                    choices=["plain2048", "batched64", "precision6144", "general1024"],
+                    help="plain2048 (default: the headline line), batched64, precision6144, "
+                         "general1024")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -373,7 +444,8 @@ def main():
     ctx = misr.Context(0)
     K, Wm = max(1, args.steps), max(0, args.warmup)
     if args.workload != "plain2048":
-        fn = bench_batched if args.workload == "batched64" else bench_precision
+        fn = {"batched64": bench_batched, "precision6144": bench_precision,
+              "general1024": bench_general}[args.workload]
         print(json.dumps(fn(misr, ctx, K, Wm)), flush=True)
         return
     op, shifts, psf, y, x0, y_np = make_inputs(misr, ctx)

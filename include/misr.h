@@ -189,8 +189,13 @@ misr_status misr_ctx_destroy(misr_ctx *ctx);
  * this geometry, as the paper builds A_i once per acquisition (Sec. 2.2). */
 misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, misr_op **out);
 misr_status misr_op_destroy(misr_op *op);
-/* Band length L of the per-frame 1-D factors (taps per LR pixel per axis). */
+/* Band length L of the per-frame 1-D factors (taps per LR pixel per axis);
+ * 0 for a general operator. */
 int misr_op_band(const misr_op *op);
+/* Entries per row of a general operator's sparse matrices: *a_w for A (per LR
+ * pixel and frame), *t_w for A^T (per HR pixel); both 0 for a banded
+ * operator.  MISR_E_INVAL on NULL arguments. */
+misr_status misr_op_sparse_width(const misr_op *op, int32_t *a_w, int32_t *t_w);
 
 /* --------------------------------------------------------------- operators */
 /* y[k] = A_k x for every frame (Eq. sisr without noise).

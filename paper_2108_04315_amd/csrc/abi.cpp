@@ -514,6 +514,13 @@ extern "C" misr_status misr_op_destroy(misr_op *op) {
 
 extern "C" int misr_op_band(const misr_op *op) { return op ? op->L : -1; }
 
+extern "C" misr_status misr_op_sparse_width(const misr_op *op, int32_t *a_w, int32_t *t_w) {
+    if (!op || !a_w || !t_w) return set_error(MISR_E_INVAL, "NULL argument");
+    *a_w = op->general ? op->host.a_w : 0;
+    *t_w = op->general ? op->host.t_w : 0;
+    return MISR_OK;
+}
+
 // General operator checks: FP32 images, untiled, no interpolation start point.
 static misr_status check_general(const misr_op *op, const misr_params &p) {
     if (!op->general) return MISR_OK;

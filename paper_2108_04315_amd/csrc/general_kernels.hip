@@ -24,10 +24,28 @@ __device__ constexpr int kGX[8] = {1, 2, 0, 1, 2, 0, 1, 2};
 __device__ constexpr int kGY[8] = {0, 0, 1, 1, 1, 2, 2, 2};
 
 // (A v)_r for ELL row r of `rows`, with v(c) given by f(c)
+// (entries in groups of four, every load of a group issued before its
+// arithmetic, so that a thread keeps several HBM requests in flight)
 template <class F>
 FI float ell_row(const AS1 int *col, const AS1 float *val, int width, i64 rows, i64 r, F f) {
     float acc = 0.f;
-    for (int q = 0; q < width; ++q) {
+    int q = 0;
+    for (; q + 4 <= width; q += 4) {
+        int c[4];
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const i64 at = (i64)(q + e) * rows + r;
+            c[e] = col[at];
+            v[e] = val[at];
+        }
+        float g[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) g[e] = f(c[e]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = fmaf(v[e], g[e], acc);
+    }
+    for (; q < width; ++q) {
         const i64 at = (i64)q * rows + r;
         acc = fmaf(val[at], f(col[at]), acc);
     }

@@ -98,6 +98,7 @@ _SIGS = {
     "misr_op_create": (C.c_int, [_vp, C.POINTER(misr_geometry), C.POINTER(_vp)]),
     "misr_op_destroy": (C.c_int, [_vp]),
     "misr_op_band": (C.c_int, [_vp]),
+    "misr_op_sparse_width": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "misr_forward": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "misr_interpolate": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "misr_upsample": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
@@ -241,6 +242,13 @@ class Operator:
     @property
     def band(self) -> int:
         return lib.misr_op_band(self.h)
+
+    @property
+    def sparse_width(self):
+        """(entries per row of A, of A^T) of a general operator; (0, 0) if banded."""
+        a, t = C.c_int32(), C.c_int32()
+        check(lib.misr_op_sparse_width(self.h, C.byref(a), C.byref(t)))
+        return a.value, t.value
 
     def close(self):
         if self.h:

@@ -85,12 +85,42 @@ def test_geometry_checks(misr, kw, ok):
     assert (st == misr.OK) == ok, misr.last_error()
 
 
+def test_general_geometry_checks(misr):
+    """General operators (affine warps, non-separable PSFs) are checked on the
+    host: finite coefficients, the shift bound only where shifts are used."""
+    K, H, W, s = 2, 16, 16, 2
+    warps = np.array([[1.0, 0.0, 0.3, 0.0, 1.0, -0.4], [0.99, 0.05, 0.1, -0.05, 0.99, 0.2]])
+    h2 = np.full((K, 3, 3), 1.0 / 9)
+    cases = [
+        (dict(shifts=np.zeros((K, 2)), psf=[1.0], warps=warps), True),
+        (dict(shifts=np.zeros((K, 2)), psf=h2, warps=None), True),
+        (dict(shifts=np.zeros((K, 2)), psf=h2, warps=warps), True),
+        (dict(shifts=np.zeros((K, 2)), psf=[1.0], warps=np.where(warps == 0.3, np.nan, warps)),
+         False),
+        (dict(shifts=np.zeros((K, 2)), psf=np.where(h2 == h2[0, 0, 0], np.inf, h2), warps=None),
+         False),
+        (dict(shifts=[[1.5, 0.0], [0.0, 0.0]], psf=h2, warps=None), False),
+    ]
+    for kw, ok in cases:
+        g, keep = misr.make_geometry(H, W, s, kw["shifts"], kw["psf"], kw["warps"])
+        st = misr.lib.misr_geometry_check(C.byref(g))
+        assert (st == misr.OK) == ok, (kw, misr.last_error())
+    # warps make the shifts optional
+    g, keep = misr.make_geometry(H, W, s, np.zeros((K, 2)), [1.0], warps)
+    g.shifts_lr = None
+    assert misr.lib.misr_geometry_check(C.byref(g)) == misr.OK
+    g2, keep2 = misr.make_geometry(H, W, s, np.zeros((K, 2)), [1.0])
+    g2.shifts_lr = None
+    assert misr.lib.misr_geometry_check(C.byref(g2)) == misr.E_INVAL
+
+
 def test_null_arguments_rejected_before_any_device_call(misr):
     assert misr.lib.misr_geometry_check(None) == misr.E_INVAL
     assert misr.lib.misr_op_create(None, None, None) == misr.E_INVAL
     assert misr.lib.misr_forward(None, 0, None, None, None) == misr.E_INVAL
     assert misr.lib.misr_scg_solve(None, None, None, None, None, None) == misr.E_INVAL
     assert misr.lib.misr_ctx_destroy(None) == misr.E_INVAL
+    assert misr.lib.misr_op_sparse_width(None, None, None) == misr.E_INVAL
 
 
 def test_binding_has_no_cpu_fallback():

@@ -149,6 +149,12 @@ def test_general_form_of_a_banded_operator(misr, ctx):
     banded = misr.Operator(ctx, H, W, s, shifts, taps)
     general = misr.Operator(ctx, H, W, s, shifts, np.stack([np.outer(taps, taps)] * K))
     assert banded.band > 0 and general.band == 0
+    assert banded.sparse_width == (0, 0)
+    aw, tw = general.sparse_width
+    # a row of A spans at most s + P HR pixels per axis (the block, the PSF,
+    # one more for the bilinear neighbours), so a column of A^T meets at most
+    # ceil((s + P) / s) LR pixels per axis and frame
+    assert 0 < aw <= (s + P) ** 2 and 0 < tw <= K * (-(-(s + P) // s)) ** 2
     xv = to_dev(x_gt)
     assert rel_l2(to_np(general.forward(xv)), to_np(banded.forward(xv))) <= TOL_OP
     xb, xg = to_dev(x0), to_dev(x0)
