@@ -634,7 +634,7 @@ void misr::add_views(const misr_op *op, const misr_params &prm, const void *y, v
     P.y = y;
     P.op = op->opdev.as<OpDev>();
     if (op->general) {
-        // one untiled FP32 view; items of kGenItemRows rows, LR rows (role 0)
+        // one untiled FP32 view; items of kGenRows rows, LR rows (role 0)
         // then HR rows (role 1), in both lists
         P.x[0] = x;
         P.x[1] = bufs->x1.p;
@@ -652,10 +652,8 @@ void misr::add_views(const misr_op *op, const misr_params &prm, const void *y, v
         const long long rows = (long long)op->K * (op->H / op->s) * (op->W / op->s);
         const long long n = (long long)op->H * op->W;
         for (auto *lst : {&items, &items_u}) {
-            for (long long b = 0; b * kGenItemRows < rows; ++b)
-                lst->push_back(Item{pj, (int)b, 0, 0});
-            for (long long b = 0; b * kGenItemRows < n; ++b)
-                lst->push_back(Item{pj, (int)b, 1, 0});
+            for (long long b = 0; b * kGenRows < rows; ++b) lst->push_back(Item{pj, (int)b, 0, 0});
+            for (long long b = 0; b * kGenRows < n; ++b) lst->push_back(Item{pj, (int)b, 1, 0});
         }
         return;
     }

@@ -6,10 +6,9 @@
 // A = [A_0; ...; A_{K-1}] is held as an ELL matrix over the K h w LR rows and
 // its transpose over the H W HR rows (built once per operator on the host,
 // entry q of row r at [q * rows + r], so a wave reads each entry slot of 64
-// consecutive rows in one coalesced access).  A workgroup of kGenRows
-// threads takes kGenItemRows consecutive rows, kGenPer per thread.  A pass
-// is two launches over the same item list, each taking the items of its
-// role (item.tx): the trial evaluates the LR rows
+// consecutive rows in one coalesced access).  One thread per row, kGenRows
+// rows per work item.  A pass is two launches over the same item list, each
+// taking the items of its role (item.tx): the trial evaluates the LR rows
 // (forward at x + alpha p, residual, data cost) and then the HR rows
 // (adjoint of the residual, BTV prior, gradient and inner products); the
 // update pass takes the HR rows (x, p update, prior curvature) and then the
@@ -68,14 +67,13 @@ __global__ void __launch_bounds__(kGenRows) k_gen_trial_lr(const Proj *projs, co
     if (mode == 1 && !st.active) return;
     const OpDev &op = *P.op;
     const i64 rows = (i64)op.K * (op.H / op.s) * (op.W / op.s);
+    const i64 r = (i64)itm.ty * kGenRows + threadIdx.x;
     const int xc = st.xc;
     const AS1 float *x = glb((const float *)P.x[xc]);
     const AS1 float *p = glb(P.p[xc]);
     const float af = (mode == 1) ? st.alpha_f : 0.f;
     double e = 0.0;
-    for (int rep = 0; rep < kGenPer; ++rep) {
-        const i64 r = (i64)itm.ty * kGenItemRows + rep * kGenRows + threadIdx.x;
-        if (r >= rows) break;
+    if (r < rows) {
         // mode 0 reads x alone: p is not yet initialised there
         const float ax = ell_row(glb(op.a_col), glb(op.a_val), op.a_w, rows, r, [&](int c) {
             return mode == 1 ? fmaf(af, p[c], x[c]) : x[c];
@@ -83,13 +81,13 @@ __global__ void __launch_bounds__(kGenRows) k_gen_trial_lr(const Proj *projs, co
         const float rr = ax - glb((const float *)P.y)[r] * st.wt.y_scale;
         float rv;
         if (st.wt.data_p == 2) {
-            e += (double)rr * (double)rr;
+            e = (double)rr * (double)rr;
             rv = 2.f * rr;
         } else {
             const float epsd = st.wt.eps_data;
             float ph, ps;
             phi_psi(rr, epsd, epsd * epsd, ph, ps);
-            e += (double)ph;
+            e = (double)ph;
             rv = ps;
         }
         glbw(P.res)[r] = rv;
@@ -115,14 +113,13 @@ __global__ void __launch_bounds__(kGenRows) k_gen_trial_hr(const Proj *projs, co
     const OpDev &op = *P.op;
     const int H = op.H, W = op.W;
     const i64 n = (i64)H * W;
+    const i64 u = (i64)itm.ty * kGenRows + threadIdx.x;
     const int xc = st.xc, cur = st.cur;
     const AS1 float *x = glb((const float *)P.x[xc]);
     const AS1 float *p = glb(P.p[xc]);
     const float af = (mode == 1) ? st.alpha_f : 0.f;
     double er = 0.0, gg = 0.0, ggk = 0.0, gp = 0.0;
-    for (int rep = 0; rep < kGenPer; ++rep) {
-        const i64 u = (i64)itm.ty * kGenItemRows + rep * kGenRows + threadIdx.x;
-        if (u >= n) break;
+    if (u < n) {
         const AS1 float *res = glb((const float *)P.res);
         float g = ell_row(glb(op.t_col), glb(op.t_val), op.t_w, n, u,
                           [&](int c) { return res[c]; });
@@ -145,12 +142,12 @@ __global__ void __launch_bounds__(kGenRows) k_gen_trial_hr(const Proj *projs, co
                 g = fmaf(-gam, ps, g);
             }
         }
-        er += (double)eb;
+        er = (double)eb;
         glbw(P.g[cur ^ 1])[u] = g;
-        gg += (double)g * (double)g;
+        gg = (double)g * (double)g;
         if (mode == 1) {
-            ggk += (double)g * (double)glb(P.g[cur])[u];
-            gp += (double)g * (double)p[u];
+            ggk = (double)g * (double)glb(P.g[cur])[u];
+            gp = (double)g * (double)p[u];
         } else {
             glbw(P.p[xc])[u] = 0.f;
         }
@@ -176,22 +173,21 @@ __global__ void __launch_bounds__(kGenRows) k_gen_upd_hr(const Proj *projs, cons
     const OpDev &op = *P.op;
     const int H = op.H, W = op.W;
     const i64 n = (i64)H * W;
+    const i64 u = (i64)itm.ty * kGenRows + threadIdx.x;
     const int src = st.upd_src, dst = src ^ 1;
     const AS1 float *x = glb((const float *)P.x[src]);
     const AS1 float *p = glb(P.p[src]);
     const AS1 float *gt = glb(P.g[st.cur]);
     const float af = st.alpha_f, bf = st.beta_f;
     double dreg = 0.0, pp = 0.0, pr = 0.0;
-    for (int rep = 0; rep < kGenPer; ++rep) {
-        const i64 u = (i64)itm.ty * kGenItemRows + rep * kGenRows + threadIdx.x;
-        if (u >= n) break;
+    if (u < n) {
         auto xn = [&](i64 c) { return fmaf(af, p[c], x[c]); };
         auto pn = [&](i64 c) { return fmaf(bf, p[c], -gt[c]); };
         const float x0 = xn(u), p0 = pn(u);
         glbw((float *)P.x[dst])[u] = x0;
         glbw(P.p[dst])[u] = p0;
-        pp += (double)p0 * (double)p0;
-        pr -= (double)p0 * (double)gt[u];
+        pp = (double)p0 * (double)p0;
+        pr = -(double)p0 * (double)gt[u];
         const int ui = (int)(u / W), vi = (int)(u - (i64)ui * W);
         const float eps = st.wt.eps, e2 = eps * eps, sk = st.sigk_f;
         float a = 0.f;
@@ -204,7 +200,7 @@ __global__ void __launch_bounds__(kGenRows) k_gen_upd_hr(const Proj *projs, cons
                 a += st.wt.gam[dy * 3 + dx] * q * q * psi_quot(z, sk * q, eps, e2);
             }
         }
-        dreg += (double)a;
+        dreg = (double)a;
     }
     double v[4] = {0.0, dreg, pp, pr};
     block_sum_store<4, kGenRows>(v, partials + (i64)it * kNV, red);
@@ -225,23 +221,22 @@ __global__ void __launch_bounds__(kGenRows) k_gen_upd_lr(const Proj *projs, cons
     if (!st.do_update) return;
     const OpDev &op = *P.op;
     const i64 rows = (i64)op.K * (op.H / op.s) * (op.W / op.s);
+    const i64 r = (i64)itm.ty * kGenRows + threadIdx.x;
     const int dst = st.upd_src ^ 1;
     const AS1 float *xn = glb((const float *)P.x[dst]);
     const AS1 float *pn = glb(P.p[dst]);
     double dd = 0.0;
-    for (int rep = 0; rep < kGenPer; ++rep) {
-        const i64 r = (i64)itm.ty * kGenItemRows + rep * kGenRows + threadIdx.x;
-        if (r >= rows) break;
+    if (r < rows) {
         const float ap = ell_row(glb(op.a_col), glb(op.a_val), op.a_w, rows, r,
                                  [&](int c) { return pn[c]; });
         if (st.wt.data_p == 2) {
-            dd += 2.0 * (double)ap * (double)ap;
+            dd = 2.0 * (double)ap * (double)ap;
         } else {
             const float ax = ell_row(glb(op.a_col), glb(op.a_val), op.a_w, rows, r,
                                      [&](int c) { return xn[c]; });
             const float rr = ax - glb((const float *)P.y)[r] * st.wt.y_scale;
             const float epsd = st.wt.eps_data;
-            dd += (double)(ap * ap * psi_quot(rr, st.sigk_f * ap, epsd, epsd * epsd));
+            dd = (double)(ap * ap * psi_quot(rr, st.sigk_f * ap, epsd, epsd * epsd));
         }
     }
     double v[4] = {dd, 0.0, 0.0, 0.0};

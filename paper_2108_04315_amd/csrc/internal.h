@@ -44,13 +44,10 @@ struct OpDev {
     const float *t_val;
 };
 
-// General-operator kernels: kGenRows threads per workgroup, each taking
-// kGenPer rows (LR or HR pixels) of its work item, kGenRows * kGenPer rows per
-// item; an item's tx is its role: 0 LR rows (forward, residual), 1 HR rows
-// (adjoint, prior, update).
+// Rows (LR or HR pixels) per work item of the general-operator kernels; an
+// item's tx is its role: 0 LR rows (forward, residual), 1 HR rows (adjoint,
+// prior, update).
 constexpr int kGenRows = 256;
-constexpr int kGenPer = 1;
-constexpr int kGenItemRows = kGenRows * kGenPer;
 
 // One image (or one tile of an image held separately in HBM) in a work list.
 // Buffers are H-major with row stride ld; buffer pixel (u, v) is global
