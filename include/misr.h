@@ -90,8 +90,8 @@ typedef struct {
      * (ELL, A and its transpose, about 2 x 8 B x (P + s + 2)^2 per LR pixel
      * and frame of device memory, built on the host at misr_op_create) and
      * runs on the general kernels: FP32 images (img_dtype MISR_F32, y_u16 = 0),
-     * untiled (tile_lr = 0), x_init 0 or 1, no server; misr_interpolate is
-     * rejected. */
+     * untiled (tile_lr = 0), x_init 0 or 1 (solves, batches and served
+     * requests alike); misr_interpolate is rejected. */
     const double *warps;      /* NULL, or [K][6]: frame k's warp M_k samples x
                                  bilinearly at row w0 u + w1 v + w2, column
                                  w3 u + w4 v + w5 for HR pixel (u, v) (zero off

@@ -33,17 +33,18 @@ double now_us() {
 
 struct OpKey {
     int H, W, s, K, P;
-    std::vector<double> shifts, psf, psf_frames;
+    std::vector<double> shifts, psf, psf_frames, warps, psf_2d;
     bool operator<(const OpKey &o) const {
-        return std::tie(H, W, s, K, P, shifts, psf, psf_frames) <
-               std::tie(o.H, o.W, o.s, o.K, o.P, o.shifts, o.psf, o.psf_frames);
+        return std::tie(H, W, s, K, P, shifts, psf, psf_frames, warps, psf_2d) <
+               std::tie(o.H, o.W, o.s, o.K, o.P, o.shifts, o.psf, o.psf_frames, o.warps,
+                        o.psf_2d);
     }
 };
 
 struct SReq {
     uint64_t id = 0;
     misr_request req{};
-    std::vector<double> shifts, psf, psf_frames;
+    std::vector<double> shifts, psf, psf_frames, warps, psf_2d;   // geometry copies
     misr_req_state state = MISR_REQ_QUEUED;
     misr_req_stats stats{};
     bool cancel = false;
@@ -200,10 +201,13 @@ bool misr_server::setup(SReq *r) {
     const misr_request &q = r->req;
     if (cfg.fail_alloc_n > 0 && ++alloc_count == cfg.fail_alloc_n) return false;
     misr_geometry g = q.geom;
-    g.shifts_lr = r->shifts.data();
-    g.psf_1d = r->psf.data();
+    g.shifts_lr = r->shifts.empty() ? nullptr : r->shifts.data();
+    g.psf_1d = r->psf.empty() ? nullptr : r->psf.data();
     g.psf_frames = r->psf_frames.empty() ? nullptr : r->psf_frames.data();
-    OpKey key{g.hr_h, g.hr_w, g.scale, g.n_frames, g.psf_size, r->shifts, r->psf, r->psf_frames};
+    g.warps = r->warps.empty() ? nullptr : r->warps.data();
+    g.psf_2d = r->psf_2d.empty() ? nullptr : r->psf_2d.data();
+    OpKey key{g.hr_h, g.hr_w, g.scale, g.n_frames, g.psf_size, r->shifts, r->psf, r->psf_frames,
+              r->warps, r->psf_2d};
     auto it = ops.find(key);
     if (it == ops.end()) {
         misr_op *op = nullptr;
@@ -216,6 +220,7 @@ bool misr_server::setup(SReq *r) {
         return false;
     const long long m = (long long)(g.hr_h / g.scale) * (g.hr_w / g.scale) * g.n_frames;
     if (!r->tiled && r->bufs.ensure_view(r->n, q.params) != hipSuccess) return false;
+    if (r->op->general && r->bufs.res.ensure((size_t)m * 4) != hipSuccess) return false;
     const size_t per = (size_t)std::max(1, q.params.n_iter);
     if (r->dstate.ensure(sizeof(ScgState) + per * sizeof(IterRec)) != hipSuccess) return false;
     r->st_dev = r->dstate.as<ScgState>();
@@ -381,9 +386,13 @@ hipError_t misr_server::enqueue_image(List &L, int kind, bool fresh) {
         const int n = cls[c].start + cls[c].count - first;
         if (n <= 0) continue;
         const int cidx = (fresh ? 2 * nc + 2 : 0) + (upd ? nc : 0) + c;
-        hipError_t e = launch_image(cls[c].S, cls[c].Lp, n, stream, L.projs.as<Proj>(),
-                                    items + first, L.cnt(cidx), part + (size_t)first * kNV, kind,
-                                    code);
+        // band length 0: the class of general operators
+        hipError_t e =
+            cls[c].Lp == 0
+                ? launch_general(n, stream, L.projs.as<Proj>(), items + first, L.cnt(cidx),
+                                 part + (size_t)first * kNV, kind)
+                : launch_image(cls[c].S, cls[c].Lp, n, stream, L.projs.as<Proj>(), items + first,
+                               L.cnt(cidx), part + (size_t)first * kNV, kind, code);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -659,16 +668,21 @@ extern "C" misr_status misr_server_submit(misr_server *s, const misr_request *re
     if (!s || !req || !id) return set_error(MISR_E_INVAL, "NULL argument");
     misr_status st = misr_geometry_check(&req->geom);
     if (st != MISR_OK) return st;
-    if (req->geom.warps || req->geom.psf_2d)
-        return set_error(MISR_E_INVAL, "the server takes translational, separable geometries "
-                         "(solve general operators with misr_scg_solve)");
     if ((st = misr_params_check(&req->params)) != MISR_OK) return st;
+    const bool general = req->geom.warps || req->geom.psf_2d;
+    if (general && (req->params.img_dtype != MISR_F32 || req->params.y_u16 ||
+                    req->params.tile_lr > 0 || req->params.x_init == 2))
+        return set_error(MISR_E_INVAL, "general geometries (warps, psf_2d) are served with FP32 "
+                         "images, untiled, x_init 0 or 1");
     if (!req->y || !req->x_out || (!req->x0 && req->params.x_init == 0))
         return set_error(MISR_E_INVAL, "NULL buffer (x0 may be NULL only with x_init > 0)");
     auto r = std::make_unique<SReq>();
     r->req = *req;
-    r->shifts.assign(req->geom.shifts_lr, req->geom.shifts_lr + 2 * req->geom.n_frames);
-    r->psf.assign(req->geom.psf_1d, req->geom.psf_1d + req->geom.psf_size);
+    const int K = req->geom.n_frames, P = req->geom.psf_size;
+    if (req->geom.shifts_lr) r->shifts.assign(req->geom.shifts_lr, req->geom.shifts_lr + 2 * K);
+    if (req->geom.psf_1d) r->psf.assign(req->geom.psf_1d, req->geom.psf_1d + P);
+    if (req->geom.warps) r->warps.assign(req->geom.warps, req->geom.warps + 6 * K);
+    if (req->geom.psf_2d) r->psf_2d.assign(req->geom.psf_2d, req->geom.psf_2d + (size_t)K * P * P);
     if (req->geom.psf_frames)
         r->psf_frames.assign(req->geom.psf_frames,
                              req->geom.psf_frames + 2 * (size_t)req->geom.n_frames *
@@ -680,6 +694,7 @@ extern "C" misr_status misr_server_submit(misr_server *s, const misr_request *re
     const long long m = (long long)(req->geom.hr_h / req->geom.scale) *
                         (req->geom.hr_w / req->geom.scale);
     r->bytes = request_bytes(*req, r->n, r->es, req->geom.n_frames, m);
+    if (general) r->bytes += (size_t)m * K * 4;   // the residual buffer
     r->stats.t_submit_us = now_us();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->closing) return set_error(MISR_E_INVAL, "server is shutting down");

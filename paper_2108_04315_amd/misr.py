@@ -385,12 +385,12 @@ class Server:
         self._keep = {}
 
     def submit(self, H, W, s, shifts, psf, y, x0, x_out, params: misr_params | None = None,
-               on_device: bool = True) -> int:
+               on_device: bool = True, warps=None) -> int:
         """Queues one solve; y, x0, x_out are device tensors (or host numpy
         arrays with on_device=False) that must stay alive until it finishes;
         x0 may be None with params.x_init > 0 (start point computed on the
-        device)."""
-        g, keep = make_geometry(H, W, s, shifts, psf)
+        device); psf and warps as for Operator."""
+        g, keep = make_geometry(H, W, s, shifts, psf, warps)
         p = params or default_params()
         if on_device:
             p.img_dtype = dtype_code(x_out)

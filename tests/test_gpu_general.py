@@ -1,9 +1,9 @@
 """General operators (A_k = D B_k M_k with per-frame affine warps M_k and/or
 non-separable PSFs B_k, held as sparse matrices) through the C ABI, against
 the FP64 oracle: forward and adjoint, cost and gradient (L2 and L1 data
-terms), the SCG solve, a batch mixing general and banded operators, the
-banded operator reproduced by its general form, and the parameters the
-general path rejects."""
+terms), the SCG solve, a batch and a served stream mixing general and banded
+operators, the banded operator reproduced by its general form, and the
+parameters the general path rejects."""
 import math
 
 import numpy as np
@@ -212,8 +212,15 @@ def test_general_path_rejections(misr, ctx):
         op.scg_solve(y.half(), x.half(), misr.default_params(n_iter=2))
     assert e.value.status == misr.E_INVAL
     srv = misr.Server(ctx, hbm_budget_bytes=1 << 28)
+    for field, value in (("tile_lr", 8), ("x_init", 2)):
+        prm = misr.default_params(n_iter=2)
+        setattr(prm, field, value)
+        with pytest.raises(misr.MisrError) as e:
+            srv.submit(H, W, s, shifts, psf, y, x, torch.empty_like(x), prm, warps=warps)
+        assert e.value.status == misr.E_INVAL
     with pytest.raises(misr.MisrError) as e:
-        srv.submit(H, W, s, shifts, psf, y, x, torch.empty_like(x), misr.default_params(n_iter=2))
+        srv.submit(H, W, s, shifts, psf, y.half(), x.half(), x.half(),
+                   misr.default_params(n_iter=2), warps=warps)
     assert e.value.status == misr.E_INVAL
     srv.close()
     # bicubic start point (x_init = 1) is accepted
@@ -223,3 +230,41 @@ def test_general_path_rejections(misr, ctx):
     torch.cuda.synchronize()
     assert torch.isfinite(x).all()
     op.close()
+
+
+def test_served_general_and_banded_requests(misr, ctx):
+    """A served stream mixing general requests (warps + non-separable PSFs,
+    x0 given and x_init = 1) with a banded one: every result equals the plain
+    solve of the same request bit for bit."""
+    import torch
+    n = 12
+    H, W, s, K, P = 48, 40, 2, 4, 5
+    sh, psf, warps, y1, x01 = _solve_problem(H, W, s, K, P, "both", 21)
+    sh2, psf2, warps2, y2, x02 = _solve_problem(56, 48, 2, 4, 5, "affine", 22)
+    shifts3 = synth.frame_shifts(2, 4, 0.05, 23)
+    taps3 = synth.psf_taps(0.8, 7)
+    y3 = _f32(synth.add_poisson_noise(oracle.forward(synth.phantom(64, 64, 23), shifts3, taps3,
+                                                     2), 1e4, 24))
+    x03 = _f32(synth.bicubic_upsample(y3[0], 2))
+    reqs = [(H, W, sh, psf, warps, y1, x01, 0), (56, 48, sh2, psf2, warps2, y2, x02, 0),
+            (H, W, sh, psf, warps, y1, None, 1), (64, 64, shifts3, taps3, None, y3, x03, 0)]
+    srv = misr.Server(ctx, hbm_budget_bytes=1 << 30)
+    outs, ids, keep = [], [], []
+    for (h, w, shf, pp, wp, yy, x0, init) in reqs:
+        prm = misr.default_params(n_iter=n, x_init=init)
+        yd = to_dev(yy)
+        x0d = to_dev(x0) if x0 is not None else None
+        out = torch.empty((h, w), device="cuda")
+        keep.append((yd, x0d))
+        ids.append(srv.submit(h, w, 2, shf, pp, yd, x0d, out, prm, warps=wp))
+        outs.append(out)
+    for rid in ids:
+        assert srv.wait(rid, 120_000_000) == misr.OK and srv.poll(rid)[0] == misr.REQ_DONE
+    srv.close()
+    for (h, w, shf, pp, wp, yy, x0, init), out in zip(reqs, outs):
+        op = misr.Operator(ctx, h, w, 2, shf, pp, warps=wp)
+        x = to_dev(x0) if x0 is not None else torch.zeros((h, w), device="cuda")
+        op.scg_solve(to_dev(yy), x, misr.default_params(n_iter=n, x_init=init), trace=False)
+        torch.cuda.synchronize()
+        assert torch.equal(out, x)
+        op.close()
