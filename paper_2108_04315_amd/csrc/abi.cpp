@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <new>
 #include <thread>
 
 #include "runtime.h"
@@ -451,7 +452,12 @@ extern "C" misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, mis
     op->K = g->n_frames;
     op->P = g->psf_size;
     if (g->warps || g->psf_2d) {
-        if ((st = build_general(op.get(), g)) != MISR_OK) return st;
+        try {
+            st = build_general(op.get(), g);
+        } catch (const std::bad_alloc &) {
+            st = set_error(MISR_E_NOMEM, "host memory for the general operator's matrices");
+        }
+        if (st != MISR_OK) return st;
         ctx->users++;
         *out = op.release();
         return MISR_OK;
