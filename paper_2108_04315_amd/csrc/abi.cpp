@@ -1,6 +1,7 @@
 // abi.cpp -- the C ABI of libmisr.so: validation, operator construction,
 // workspace management and the device-resident SCG solve driver.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -347,19 +348,24 @@ static misr_status build_general(misr_op *op, const misr_geometry *g) {
     const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<std::vector<int>> cc(nt), len(nt);
     std::vector<std::vector<double>> vv(nt);
+    std::atomic<bool> oom{false};
     auto work = [&](int t) {
-        std::vector<std::pair<int, double>> ent;
-        const long long r0 = rows * t / nt, r1 = rows * (t + 1) / nt;
-        for (long long r = r0; r < r1; ++r) {
-            const int k = (int)(r / ((long long)h * w));
-            const long long q = r - (long long)k * h * w;
-            general_row(op, warp.data() + 6 * k, psf.data() + (size_t)k * P * P, P,
-                        (int)(q / w), (int)(q % w), ent);
-            len[t].push_back((int)ent.size());
-            for (auto &e : ent) {
-                cc[t].push_back(e.first);
-                vv[t].push_back(e.second);
+        try {
+            std::vector<std::pair<int, double>> ent;
+            const long long r0 = rows * t / nt, r1 = rows * (t + 1) / nt;
+            for (long long r = r0; r < r1 && !oom; ++r) {
+                const int k = (int)(r / ((long long)h * w));
+                const long long q = r - (long long)k * h * w;
+                general_row(op, warp.data() + 6 * k, psf.data() + (size_t)k * P * P, P,
+                            (int)(q / w), (int)(q % w), ent);
+                len[t].push_back((int)ent.size());
+                for (auto &e : ent) {
+                    cc[t].push_back(e.first);
+                    vv[t].push_back(e.second);
+                }
             }
+        } catch (const std::bad_alloc &) {
+            oom = true;
         }
     };
     {
@@ -368,6 +374,7 @@ static misr_status build_general(misr_op *op, const misr_geometry *g) {
         work(0);
         for (auto &x : th) x.join();
     }
+    if (oom) throw std::bad_alloc();
     int aw = 1;
     for (auto &l : len)
         for (int x : l) aw = std::max(aw, x);
