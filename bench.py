@@ -131,6 +131,32 @@ def _serve_problem(misr, ctx, L, s, seed):
 SERVE_FILL_MPX = 8   # about two waves of 48 x 96 tiles over the 256 CUs
 
 
+def host_buffer_leg(misr, ctx, shifts, psf, y_np, x0_np, x_ref, n_req: int = 4):
+    """The headline workload served from host memory (misr_request.on_device =
+    0): frames and start point are read from host arrays and the result is
+    written back to one, so the rate includes the PCIe transfers.  Each result
+    must equal the device-resident solve (x_ref) bit for bit."""
+    y32 = np.ascontiguousarray(y_np, dtype=np.float32)
+    x032 = np.ascontiguousarray(x0_np, dtype=np.float32)
+    outs = [np.zeros((H, W), np.float32) for _ in range(n_req)]
+    srv = misr.Server(ctx, hbm_budget_bytes=16 << 30)
+    prm = misr.default_params(n_iter=N_ITER)
+    # one warm-up request (operator construction, graph capture)
+    rid = srv.submit(H, W, S, shifts, psf, y32, x032, outs[0], prm, on_device=False)
+    srv.wait(rid, 120_000_000)
+    t0 = time.perf_counter()
+    ids = [srv.submit(H, W, S, shifts, psf, y32, x032, outs[i], misr.default_params(n_iter=N_ITER),
+                      on_device=False) for i in range(n_req)]
+    for rid in ids:
+        srv.wait(rid, 120_000_000)
+    dt = time.perf_counter() - t0
+    srv.close()
+    return {"requests": n_req, "hr_mpx_per_s": H * W * n_req / dt / 1e6,
+            "ms_per_request": dt / n_req * 1e3,
+            "bytes_over_pcie_per_request": int(y32.nbytes + 2 * x032.nbytes),
+            "equals_device_solve_bitwise": all(np.array_equal(o, x_ref) for o in outs)}
+
+
 def serving_leg(misr, ctx, n_req: int = 48, loads=(0.8, 1.0), seed: int = 7,
                 fill_mpx: int = SERVE_FILL_MPX, sizes=SERVE_SIZES):
     """A stream of SR requests (LR 512^2..2048^2, scale 2 or 3, 80 SCG passes
@@ -518,6 +544,9 @@ def main():
     if not args.no_serve:
         out["serving"] = serving_leg(misr, ctx)
         out["serving_small"] = serving_leg(misr, ctx, sizes=(512,), seed=8)
+        out["host_buffers"] = host_buffer_leg(misr, ctx, shifts, psf, y_np,
+                                              x0.double().cpu().numpy(),
+                                              xs[-1].cpu().numpy())
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(y_np, shifts, psf, x0.double().cpu().numpy())
     print(json.dumps(out), flush=True)
