@@ -197,6 +197,23 @@ int misr_op_band(const misr_op *op);
  * operator.  MISR_E_INVAL on NULL arguments. */
 misr_status misr_op_sparse_width(const misr_op *op, int32_t *a_w, int32_t *t_w);
 
+/* Tile autotuner: times the trial and update passes of every compiled tile
+ * shape of this banded operator (the widest tile that fits, and one about
+ * half as wide, which gives small images more workgroups) on the caller's
+ * frames y and image x (device buffers, img_dtype storage; x is read only),
+ * `reps` launches each with HIP events, and keeps the fastest for every
+ * later call on this operator (solves, batches, operators).  *tile_h x
+ * *tile_w: the chosen tile in HR pixels.  A general operator has no tiles
+ * (both 0).  Synchronises with `stream`.  Results do not depend on the tile
+ * shape except for the summation order of the cost and inner products. */
+misr_status misr_op_tune(misr_op *op, const misr_params *params, const void *y, void *x,
+                         int reps, int32_t *tile_h, int32_t *tile_w, void *stream);
+/* The operator's current tile shape (HR pixels; 0 x 0 for a general operator). */
+misr_status misr_op_tile(const misr_op *op, int32_t *tile_h, int32_t *tile_w);
+/* Selects a compiled tile shape directly: variant 0 the widest (the default),
+ * 1 about half as wide.  MISR_E_INVAL for other values or a general operator. */
+misr_status misr_op_set_tile(misr_op *op, int variant);
+
 /* --------------------------------------------------------------- operators */
 /* y[k] = A_k x for every frame (Eq. sisr without noise).
  * x: device, H*W elements of dtype dt.  y: device, K*(H/s)*(W/s) of dtype dt. */

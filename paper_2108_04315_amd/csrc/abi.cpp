@@ -764,7 +764,7 @@ static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
     std::map<std::pair<int, int>, std::vector<int>> groups;
     std::vector<std::pair<int, int>> order;
     for (int i = 0; i < (int)ns; ++i) {
-        auto key = std::make_pair(in[i].op->s, in[i].op->Lp);
+        auto key = std::make_pair(in[i].op->s, in[i].op->kernel_key());
         if (!groups.count(key)) order.push_back(key);
         groups[key].push_back(i);
     }
@@ -976,7 +976,7 @@ extern "C" misr_status misr_forward(const misr_op *cop, misr_dtype dt, const voi
     PlanDev &pd = op->pdev;
     hipStream_t s = (hipStream_t)stream;
     MISR_HIP(pd.upload(pl, 0, s));
-    MISR_HIP(launch_forward(op->s, op->Lp, (int)pl.items.size(), s, pd.projs.as<Proj>(),
+    MISR_HIP(launch_forward(op->s, op->kernel_key(), (int)pl.items.size(), s, pd.projs.as<Proj>(),
                             pd.items.as<Item>(), (int)pl.items.size(), (int)dt, y));
     return MISR_OK;
 }
@@ -1000,7 +1000,7 @@ extern "C" misr_status misr_adjoint(const misr_op *cop, misr_dtype dt, const voi
     PlanDev &pd = op->pdev;
     hipStream_t s = (hipStream_t)stream;
     MISR_HIP(pd.upload(pl, 0, s));
-    MISR_HIP(launch_adjoint(op->s, op->Lp, (int)pl.items.size(), s, pd.projs.as<Proj>(),
+    MISR_HIP(launch_adjoint(op->s, op->kernel_key(), (int)pl.items.size(), s, pd.projs.as<Proj>(),
                             pd.items.as<Item>(), (int)pl.items.size(), (int)dt, r, x));
     return MISR_OK;
 }
@@ -1168,19 +1168,9 @@ extern "C" misr_status misr_scg_solve_batch(int n, const misr_op *const *ops,
 }
 
 // ------------------------------------------------------------- measurement
-extern "C" misr_status misr_time_pass(const misr_op *cop, const misr_params *prm, const void *y,
-                                      void *x, int which, int reps, double *avg_us,
-                                      void *stream) {
-    misr_op *op = const_cast<misr_op *>(cop);
-    if (!op || !y || !x || !avg_us || reps < 1 || (which != 0 && which != 1))
-        return set_error(MISR_E_INVAL, "bad arguments");
-    misr_status st = misr_params_check(prm);
-    if (st != MISR_OK) return st;
-    if (prm->tile_lr > 0) return set_error(MISR_E_INVAL, "timing runs untiled");
-    if ((st = check_general(op, *prm)) != MISR_OK) return st;
-    std::lock_guard<std::mutex> lk(op->mu);
-    std::lock_guard<std::mutex> lc(op->ctx->mu);
-    MISR_HIP(set_device(op->ctx->dev));
+// One image pass timed with HIP events (caller holds op->mu and the ctx lock).
+static misr_status time_pass_impl(misr_op *op, const misr_params *prm, const void *y, void *x,
+                                  int which, int reps, double *avg_us, void *stream) {
     const long long n = (long long)op->H * op->W;
     MISR_HIP(op->bufs.ensure(n, dtype_size(prm->img_dtype)));
     MISR_HIP(ensure_res(op, op->bufs));
@@ -1215,5 +1205,80 @@ extern "C" misr_status misr_time_pass(const misr_op *cop, const misr_params *prm
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "misr_time_pass");
     *avg_us = 1e3 * ms / reps;
+    return MISR_OK;
+}
+
+extern "C" misr_status misr_time_pass(const misr_op *cop, const misr_params *prm, const void *y,
+                                      void *x, int which, int reps, double *avg_us,
+                                      void *stream) {
+    misr_op *op = const_cast<misr_op *>(cop);
+    if (!op || !y || !x || !avg_us || reps < 1 || (which != 0 && which != 1))
+        return set_error(MISR_E_INVAL, "bad arguments");
+    misr_status st = misr_params_check(prm);
+    if (st != MISR_OK) return st;
+    if (prm->tile_lr > 0) return set_error(MISR_E_INVAL, "timing runs untiled");
+    if ((st = check_general(op, *prm)) != MISR_OK) return st;
+    std::lock_guard<std::mutex> lk(op->mu);
+    std::lock_guard<std::mutex> lc(op->ctx->mu);
+    MISR_HIP(set_device(op->ctx->dev));
+    return time_pass_impl(op, prm, y, x, which, reps, avg_us, stream);
+}
+
+// ------------------------------------------------------------ tile autotuner
+static void set_tile_variant(misr_op *op, int tv) {
+    op->tv = tv;
+    op->TH = tile_hr(op->s, op->kernel_key());
+    op->TW = tile_wr(op->s, op->kernel_key());
+}
+
+extern "C" misr_status misr_op_tune(misr_op *op, const misr_params *prm, const void *y, void *x,
+                                    int reps, int32_t *tile_h, int32_t *tile_w, void *stream) {
+    if (!op || !y || !x || !tile_h || !tile_w || reps < 1)
+        return set_error(MISR_E_INVAL, "bad arguments");
+    misr_status st = misr_params_check(prm);
+    if (st != MISR_OK) return st;
+    if (prm->tile_lr > 0) return set_error(MISR_E_INVAL, "tuning runs untiled");
+    if ((st = check_general(op, *prm)) != MISR_OK) return st;
+    std::lock_guard<std::mutex> lk(op->mu);
+    std::lock_guard<std::mutex> lc(op->ctx->mu);
+    MISR_HIP(set_device(op->ctx->dev));
+    if (!op->general) {
+        double best = 0.0;
+        int best_tv = 0;
+        for (int tv = 0; tv < 2; ++tv) {
+            if (tile_hr(op->s, op->Lp | (tv << 8)) <= 0) continue;
+            set_tile_variant(op, tv);
+            double t_trial = 0.0, t_upd = 0.0;
+            if ((st = time_pass_impl(op, prm, y, x, 0, reps, &t_trial, stream)) != MISR_OK ||
+                (st = time_pass_impl(op, prm, y, x, 1, reps, &t_upd, stream)) != MISR_OK) {
+                set_tile_variant(op, 0);
+                return st;
+            }
+            if (tv == 0 || t_trial + t_upd < best) {
+                best = t_trial + t_upd;
+                best_tv = tv;
+            }
+        }
+        set_tile_variant(op, best_tv);
+    }
+    *tile_h = op->TH;
+    *tile_w = op->TW;
+    return MISR_OK;
+}
+
+extern "C" misr_status misr_op_set_tile(misr_op *op, int variant) {
+    if (!op) return set_error(MISR_E_INVAL, "op is NULL");
+    if (op->general) return set_error(MISR_E_INVAL, "a general operator has no tiles");
+    if (variant < 0 || variant > 1 || tile_hr(op->s, op->Lp | (variant << 8)) <= 0)
+        return set_error(MISR_E_INVAL, "tile variant %d not compiled", variant);
+    std::lock_guard<std::mutex> lk(op->mu);
+    set_tile_variant(op, variant);
+    return MISR_OK;
+}
+
+extern "C" misr_status misr_op_tile(const misr_op *op, int32_t *tile_h, int32_t *tile_w) {
+    if (!op || !tile_h || !tile_w) return set_error(MISR_E_INVAL, "NULL argument");
+    *tile_h = op->TH;
+    *tile_w = op->TW;
     return MISR_OK;
 }

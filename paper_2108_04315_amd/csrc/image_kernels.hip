@@ -31,7 +31,7 @@ namespace misr {
 constexpr int kNTI = 512;          // threads per workgroup of the image kernels
 constexpr int kNWI = kNTI / 64;    // waves per workgroup
 
-template <int S, int L>
+template <int S, int L, int TV>
 struct Tile {
     static constexpr int EXT = (L - 1 > 2) ? L - 1 : 2;   // window margin (HR px)
     static constexpr int NTAP = (L + S - 1) / S;         // adjoint taps per output
@@ -63,6 +63,11 @@ struct Tile {
         int best = kNWI * S;
         for (int tw = kNWI * S; tw <= 1024; tw += kNWI * S)
             if ((tw + L - 2) / S + 1 <= 64 && lds_floats(tw) * 4 <= 79 * 1024) best = tw;
+        // variant 1: about half as wide (more workgroups for small images)
+        if (TV == 1) {
+            const int half = best / 2 / (kNWI * S) * (kNWI * S);
+            best = half > kNWI * S ? half : kNWI * S;
+        }
         return best;
     }
     static constexpr int TW = calc_tw();
@@ -86,10 +91,10 @@ struct Tile {
 // Waves take groups of CJ LR columns (their weights are scalar loads), lanes
 // take rows; each lane keeps the S(CJ-1)+L window samples it needs in
 // registers.
-template <int S, int L>
+template <int S, int L, int TV>
 FI void pass1(const float *win, int wr0, int wc0, int NR, int NJ, const AS4 float *wxk, int jA,
               int jlast, float *hx) {
-    using T = Tile<S, L>;
+    using T = Tile<S, L, TV>;
     constexpr int CJ = T::CJ, NX = S * (CJ - 1) + L;
     const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
     for (int jg = wv; jg * CJ < NJ; jg += kNWI) {
@@ -119,9 +124,9 @@ FI void pass1(const float *win, int wr0, int wc0, int NR, int NJ, const AS4 floa
 
 // pass 2: a = sum_l wy[iA+i][l] hx[S i + l][j]; waves take groups of CI LR
 // rows, lanes take LR columns; out(i, j, a) consumes each result.
-template <int S, int L, class F>
+template <int S, int L, int TV, class F>
 FI void pass2(const float *hx, int NI, int NJ, const AS4 float *wyk, int iA, int ilast, F out) {
-    using T = Tile<S, L>;
+    using T = Tile<S, L, TV>;
     constexpr int CI = T::CI, NH = S * (CI - 1) + L;
     const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
     for (int ig = wv; ig * CI < NI; ig += kNWI) {
@@ -151,10 +156,10 @@ FI void pass2(const float *hx, int NI, int NJ, const AS4 float *wyk, int iA, int
 
 // pass 3: tt[u][j] = sum_i wy[i][U - S i - offy] rs[i][j] for the TH rows.
 // PH = (U0 - offy) mod S fixes every tap offset at compile time.
-template <int S, int L, int PH>
+template <int S, int L, int TV, int PH>
 FI void pass3_ph(const float *rs, float *tt, int U0, int offy, int iA, int iB, int NJ,
                  const AS4 float *wyk) {
-    using T = Tile<S, L>;
+    using T = Tile<S, L, TV>;
     constexpr int CU = T::CU, NTAP = T::NTAP;
     constexpr int NIG = (PH + CU - 1) / S + NTAP;
     const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
@@ -196,10 +201,10 @@ FI void pass3_ph(const float *rs, float *tt, int U0, int offy, int iA, int iB, i
 
 // pass 4: g[u][v] += sum_j wx[j][V - S j - offx] tt[u][j] for the wave's CV
 // columns; lanes take rows (u = lane - 2).
-template <int S, int L, int PH>
-FI void pass4_ph(const float *tt, float (&gacc)[Tile<S, L>::CV], int V0, int offx, int jA,
+template <int S, int L, int TV, int PH>
+FI void pass4_ph(const float *tt, float (&gacc)[Tile<S, L, TV>::CV], int V0, int offx, int jA,
                  int jB, const AS4 float *wxk) {
-    using T = Tile<S, L>;
+    using T = Tile<S, L, TV>;
     constexpr int CV = T::CV, NTAP = T::NTAP;
     constexpr int NJG = (PH + CV - 1) / S + NTAP;
     const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
@@ -229,22 +234,22 @@ FI void pass4_ph(const float *tt, float (&gacc)[Tile<S, L>::CV], int V0, int off
     }
 }
 
-template <int S, int L>
+template <int S, int L, int TV>
 FI void pass3(int ph, const float *rs, float *tt, int U0, int offy, int iA, int iB, int NJ,
               const AS4 float *wyk) {
-    if (ph == 0) pass3_ph<S, L, 0>(rs, tt, U0, offy, iA, iB, NJ, wyk);
-    if constexpr (S > 1) if (ph == 1) pass3_ph<S, L, 1>(rs, tt, U0, offy, iA, iB, NJ, wyk);
-    if constexpr (S > 2) if (ph == 2) pass3_ph<S, L, 2>(rs, tt, U0, offy, iA, iB, NJ, wyk);
-    if constexpr (S > 3) if (ph == 3) pass3_ph<S, L, 3>(rs, tt, U0, offy, iA, iB, NJ, wyk);
+    if (ph == 0) pass3_ph<S, L, TV, 0>(rs, tt, U0, offy, iA, iB, NJ, wyk);
+    if constexpr (S > 1) if (ph == 1) pass3_ph<S, L, TV, 1>(rs, tt, U0, offy, iA, iB, NJ, wyk);
+    if constexpr (S > 2) if (ph == 2) pass3_ph<S, L, TV, 2>(rs, tt, U0, offy, iA, iB, NJ, wyk);
+    if constexpr (S > 3) if (ph == 3) pass3_ph<S, L, TV, 3>(rs, tt, U0, offy, iA, iB, NJ, wyk);
 }
 
-template <int S, int L>
-FI void pass4(int ph, const float *tt, float (&gacc)[Tile<S, L>::CV], int V0, int offx, int jA,
+template <int S, int L, int TV>
+FI void pass4(int ph, const float *tt, float (&gacc)[Tile<S, L, TV>::CV], int V0, int offx, int jA,
               int jB, const AS4 float *wxk) {
-    if (ph == 0) pass4_ph<S, L, 0>(tt, gacc, V0, offx, jA, jB, wxk);
-    if constexpr (S > 1) if (ph == 1) pass4_ph<S, L, 1>(tt, gacc, V0, offx, jA, jB, wxk);
-    if constexpr (S > 2) if (ph == 2) pass4_ph<S, L, 2>(tt, gacc, V0, offx, jA, jB, wxk);
-    if constexpr (S > 3) if (ph == 3) pass4_ph<S, L, 3>(tt, gacc, V0, offx, jA, jB, wxk);
+    if (ph == 0) pass4_ph<S, L, TV, 0>(tt, gacc, V0, offx, jA, jB, wxk);
+    if constexpr (S > 1) if (ph == 1) pass4_ph<S, L, TV, 1>(tt, gacc, V0, offx, jA, jB, wxk);
+    if constexpr (S > 2) if (ph == 2) pass4_ph<S, L, TV, 2>(tt, gacc, V0, offx, jA, jB, wxk);
+    if constexpr (S > 3) if (ph == 3) pass4_ph<S, L, TV, 3>(tt, gacc, V0, offx, jA, jB, wxk);
 }
 
 // The 8 BTV offsets d = (dx, dy) in [0, 2]^2 minus the origin (Eq. prior, w = 3).
@@ -260,10 +265,10 @@ __device__ constexpr int kDY[8] = {0, 0, 1, 1, 1, 2, 2, 2};
 // slots, so the loop is unrolled by three and nothing is moved.  Steps 0
 // and 1 (columns cv0-2, cv0-1) only fill the history.  The gradient
 // accumulates into gs (LDS, row stride GP).
-template <int S, int L, bool EPS0, bool CHECK>
+template <int S, int L, int TV, bool EPS0, bool CHECK>
 FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, int U0, int V0,
                   int H, int W, int th_own, int tw_own, double &e_reg) {
-    using T = Tile<S, L>;
+    using T = Tile<S, L, TV>;
     constexpr int NSTEP = T::CV + 2;
     const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
     const int u = lane - 2;
@@ -378,11 +383,11 @@ FI void btv_sweep(const float *xs, float *gs, const float (&gam)[8], float eps, 
 // relative, so for |h| / B = sk |u| < kCurvTau = 1e-4 the truncation stays
 // below FP32 rounding; a lane with a pair beyond that recomputes its column
 // with the closed form, so the common case takes one branch per column.
-template <int S, int L, bool CHECK, bool EPS0>
+template <int S, int L, int TV, bool CHECK, bool EPS0>
 FI void curv_sweep(const float *xs, const float *ps, const float (&gam)[8], float eps, float sk,
                    int U0, int V0, int H, int W, int ru0, int ru1, int rv0, int rv1,
                    double &dreg) {
-    using T = Tile<S, L>;
+    using T = Tile<S, L, TV>;
     constexpr int NSTEP = T::CV;
     const int lane = threadIdx.x & 63, wv = uni(threadIdx.x >> 6);
     const int u = lane;
@@ -518,9 +523,9 @@ struct TileOrigin {
     int u0, v0, u1, v1, U0, V0;
 };
 
-template <int S, int L>
+template <int S, int L, int TV>
 FI TileOrigin tile_origin(const AS4 Proj &P, int ty, int tx) {
-    using T = Tile<S, L>;
+    using T = Tile<S, L, TV>;
     TileOrigin o;
     o.u0 = P.oy0 + ty * T::TH;
     o.v0 = P.ox0 + tx * T::TW;
@@ -535,10 +540,10 @@ FI TileOrigin tile_origin(const AS4 Proj &P, int ty, int tx) {
 // every frame's forward, residual, data cost and adjoint, then the BTV cost
 // and gradient; writes g_t = grad J(x_t) to g[cur^1] for the owned pixels and
 // the partial sums {E_data, E_reg, |g_t|^2, g_t.g_k, g_t.p}.
-template <int S, int L, class ST, class SY>
+template <int S, int L, int TV, class ST, class SY>
 FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, int mode,
                    float *sm, double *red, double *part) {
-    using T = Tile<S, L>;
+    using T = Tile<S, L, TV>;
     using raw = typename ST::raw;
     using rawy = typename SY::raw;
     const AS4 OpDev &op = *cst(P.op);
@@ -546,7 +551,7 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     // per-tile index arithmetic is recomputed rather than kept live across the
     // work-list loop (where it would be spilled)
     asm volatile("" : "+v"(tid));
-    const TileOrigin o = tile_origin<S, L>(P, ty, tx);
+    const TileOrigin o = tile_origin<S, L, TV>(P, ty, tx);
     const int H = op.H, W = op.W, h = H / S, w = W / S, K = op.K;
     float *xs = sm;
     float *hx = xs + T::XS;
@@ -643,11 +648,11 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
         if (NI <= 0 || NJ <= 0) continue;
         const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
         const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
-        pass1<S, L>(xs, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
+        pass1<S, L, TV>(xs, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
                     S * (NI - 1) + L, NJ, wxk, jA, w - 1, hx);
         __syncthreads();
         const AS1 rawy *yk = yb + (i64)k * h * w;
-        pass2<S, L>(hx, NI, NJ, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
+        pass2<S, L, TV>(hx, NI, NJ, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
             const int gj = jA + j;
             float yv[T::CI];
 #pragma unroll
@@ -674,9 +679,9 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
             }
         });
         __syncthreads();
-        pass3<S, L>(pmod(o.U0 - offy, S), rs, hx, o.U0, offy, iA, iB, NJ, wyk);
+        pass3<S, L, TV>(pmod(o.U0 - offy, S), rs, hx, o.U0, offy, iA, iB, NJ, wyk);
         __syncthreads();
-        pass4<S, L>(pmod(o.V0 - offx, S), hx, gacc, o.V0, offx, jA, jB, wxk);
+        pass4<S, L, TV>(pmod(o.V0 - offx, S), hx, gacc, o.V0, offx, jA, jB, wxk);
         __syncthreads();
     }
 
@@ -725,11 +730,11 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
                        o.V0 + T::TW + 2 <= W && o.u1 - o.u0 == T::TH && o.v1 - o.v0 == T::TW;
     const int tho = o.u1 - o.u0, two = o.v1 - o.v0;
     if (eps == 0.f)
-        btv_sweep<S, L, true, true>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
+        btv_sweep<S, L, TV, true, true>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
     else if (inner)
-        btv_sweep<S, L, false, false>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
+        btv_sweep<S, L, TV, false, false>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
     else
-        btv_sweep<S, L, false, true>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
+        btv_sweep<S, L, TV, false, true>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
     __syncthreads();
     // owned gradient out, with its inner products
     double gg = 0.0, ggk = 0.0, gp = 0.0;
@@ -760,11 +765,11 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
 // multiples of S): L2 (DP = 2), 2 |A_k p|^2, exact since the term is
 // quadratic; L1 (DP = 1, Charbonnier), the sum of (A_k p)^2 Q(r, sk A_k p) with
 // r = A_k x - y_k and Q the quotient the prior's pairs use.
-template <int S, int L, class SY, int DP>
+template <int S, int L, int TV, class SY, int DP>
 FI double upd_data_part(const AS4 Proj &P, const AS4 ScgState &st, const TileOrigin &o,
                         const float *xs, const float *ps, float *hx, float *ax, int NIo,
                         int NJo, int iA, int jA) {
-    using T = Tile<S, L>;
+    using T = Tile<S, L, TV>;
     using rawy = typename SY::raw;
     const AS4 OpDev &op = *cst(P.op);
     const int h = op.H / S, w = op.W / S, K = op.K;
@@ -776,21 +781,21 @@ FI double upd_data_part(const AS4 Proj &P, const AS4 ScgState &st, const TileOri
         const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
         const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
         if (DP == 1) {
-            pass1<S, L>(xs, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
+            pass1<S, L, TV>(xs, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
                         S * (NIo - 1) + L, NJo, wxk, jA, w - 1, hx);
             __syncthreads();
-            pass2<S, L>(hx, NIo, NJo, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
+            pass2<S, L, TV>(hx, NIo, NJo, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
 #pragma unroll
                 for (int c = 0; c < T::CI; ++c)
                     if (i0 + c < NIo) ax[(i0 + c) * T::NJP + j] = av[c];
             });
             __syncthreads();
         }
-        pass1<S, L>(ps, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
+        pass1<S, L, TV>(ps, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
                     S * (NIo - 1) + L, NJo, wxk, jA, w - 1, hx);
         __syncthreads();
         const AS1 rawy *yk = yb + (i64)k * h * w;
-        pass2<S, L>(hx, NIo, NJo, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
+        pass2<S, L, TV>(hx, NIo, NJo, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
 #pragma unroll
             for (int c = 0; c < T::CI; ++c) {
                 if (i0 + c >= NIo) break;
@@ -815,10 +820,10 @@ FI double upd_data_part(const AS4 Proj &P, const AS4 ScgState &st, const TileOri
 // quadratic) or sum_k (A_k p)^2 Q(A_k x - y_k, sigma_k A_k p) for the L1
 // (Charbonnier) term, prior part lambda sum gamma q^2 Q(z, sigma_k q).
 // Partial sums {data part, prior part, |p|^2, p.r}.
-template <int S, int L, class ST, class SY>
+template <int S, int L, int TV, class ST, class SY>
 FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, float *sm,
                     double *red, double *part) {
-    using T = Tile<S, L>;
+    using T = Tile<S, L, TV>;
     using raw = typename ST::raw;
     const AS4 OpDev &op = *cst(P.op);
     int tid = threadIdx.x;
@@ -919,9 +924,9 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
     const int data_p = st.wt.data_p;
     if (NIo > 0 && NJo > 0) {
         if (data_p == 2)
-            ap2 = upd_data_part<S, L, SY, 2>(P, st, o, xs, ps, hx, ax, NIo, NJo, iA, jA);
+            ap2 = upd_data_part<S, L, TV, SY, 2>(P, st, o, xs, ps, hx, ax, NIo, NJo, iA, jA);
         else
-            ap2 = upd_data_part<S, L, SY, 1>(P, st, o, xs, ps, hx, ax, NIo, NJo, iA, jA);
+            ap2 = upd_data_part<S, L, TV, SY, 1>(P, st, o, xs, ps, hx, ax, NIo, NJo, iA, jA);
     }
     // prior part over the owned pairs (i, i+d)
     const float eps = st.wt.eps, sk = st.sigk_f;
@@ -933,29 +938,29 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
     const bool inner = o.U0 + T::TH + 2 <= H && o.V0 + T::TW + 2 <= W && ru0 == 0 &&
                        ru1 == T::TH && rv0 == 0 && rv1 == T::TW;
     if (eps == 0.f)
-        curv_sweep<S, L, true, true>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0, rv1,
+        curv_sweep<S, L, TV, true, true>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0, rv1,
                                      dreg);
     else if (inner)
-        curv_sweep<S, L, false, false>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0,
+        curv_sweep<S, L, TV, false, false>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0,
                                        rv1, dreg);
     else
-        curv_sweep<S, L, true, false>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0,
+        curv_sweep<S, L, TV, true, false>(xs, ps, gam, eps, sk, o.U0, o.V0, H, W, ru0, ru1, rv0,
                                       rv1, dreg);
     double v[4] = {ap2, dreg, pp, pr};
     block_sum_store<4, kNTI>(v, part, red);
 }
 
 // y[k] = A_k x on the owned LR pixels of one tile.
-template <int S, int L, class ST>
+template <int S, int L, int TV, class ST>
 FI void tile_forward(const AS4 Proj &P, int ty, int tx, void *yout, float *sm) {
-    using T = Tile<S, L>;
+    using T = Tile<S, L, TV>;
     using raw = typename ST::raw;
     const AS4 OpDev &op = *cst(P.op);
     int tid = threadIdx.x;
     // per-tile index arithmetic is recomputed rather than kept live across the
     // work-list loop (where it would be spilled)
     asm volatile("" : "+v"(tid));
-    const TileOrigin o = tile_origin<S, L>(P, ty, tx);
+    const TileOrigin o = tile_origin<S, L, TV>(P, ty, tx);
     const int h = op.H / S, w = op.W / S, K = op.K;
     float *xs = sm;
     float *hx = xs + T::XS;
@@ -977,10 +982,10 @@ FI void tile_forward(const AS4 Proj &P, int ty, int tx, void *yout, float *sm) {
         const int offy = op.offy[k], offx = op.offx[k];
         const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
         const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
-        pass1<S, L>(xs, offy + T::EXT, offx + T::EXT, S * (NIo - 1) + L, NJo, wxk, jA, w - 1, hx);
+        pass1<S, L, TV>(xs, offy + T::EXT, offx + T::EXT, S * (NIo - 1) + L, NJo, wxk, jA, w - 1, hx);
         __syncthreads();
         const i64 yb = (i64)k * h * w;
-        pass2<S, L>(hx, NIo, NJo, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
+        pass2<S, L, TV>(hx, NIo, NJo, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
 #pragma unroll
             for (int c = 0; c < T::CI; ++c)
                 if (i0 + c < NIo) ST::st(yo, yb + (i64)(iA + i0 + c) * w + jA + j, av[c]);
@@ -990,16 +995,16 @@ FI void tile_forward(const AS4 Proj &P, int ty, int tx, void *yout, float *sm) {
 }
 
 // x = sum_k A_k^T r_k on the owned HR pixels of one tile.
-template <int S, int L, class ST>
+template <int S, int L, int TV, class ST>
 FI void tile_adjoint(const AS4 Proj &P, int ty, int tx, const void *r, float *xout, float *sm) {
-    using T = Tile<S, L>;
+    using T = Tile<S, L, TV>;
     using raw = typename ST::raw;
     const AS4 OpDev &op = *cst(P.op);
     int tid = threadIdx.x;
     // per-tile index arithmetic is recomputed rather than kept live across the
     // work-list loop (where it would be spilled)
     asm volatile("" : "+v"(tid));
-    const TileOrigin o = tile_origin<S, L>(P, ty, tx);
+    const TileOrigin o = tile_origin<S, L, TV>(P, ty, tx);
     const int h = op.H / S, w = op.W / S, K = op.K;
     float *gs = sm;
     float *tt = gs + T::XS;
@@ -1023,9 +1028,9 @@ FI void tile_adjoint(const AS4 Proj &P, int ty, int tx, const void *r, float *xo
             if (jj < NJ) rs[q] = ST::ld(rb, (i64)k * h * w + (i64)(iA + ii) * w + jA + jj);
         }
         __syncthreads();
-        pass3<S, L>(pmod(o.U0 - offy, S), rs, tt, o.U0, offy, iA, iB, NJ, wyk);
+        pass3<S, L, TV>(pmod(o.U0 - offy, S), rs, tt, o.U0, offy, iA, iB, NJ, wyk);
         __syncthreads();
-        pass4<S, L>(pmod(o.V0 - offx, S), tt, gacc, o.V0, offx, jA, jB, wxk);
+        pass4<S, L, TV>(pmod(o.V0 - offx, S), tt, gacc, o.V0, offx, jA, jB, wxk);
         __syncthreads();
     }
     {
@@ -1060,11 +1065,11 @@ FI int xcd_item(int b, int n) {
     const int q = n >> 3, r = n & 7, x = b & 7, j = b >> 3;
     return x * q + min(x, r) + j;
 }
-template <int S, int L, class ST, class SY>
+template <int S, int L, int TV, class ST, class SY>
 __global__ void __launch_bounds__(kNTI, 4) k_trial(const Proj *projs, const Item *items,
                                                 const int *n_items, double *partials,
                                                 int mode) {
-    __shared__ float sm[Tile<S, L>::SMEM];
+    __shared__ float sm[Tile<S, L, TV>::SMEM];
     __shared__ double red[kNV * kNWI];
     // one workgroup per item (the launch grid is the item count): no loop, so
     // nothing is hoisted out of one and kept live through the tile
@@ -1076,13 +1081,13 @@ __global__ void __launch_bounds__(kNTI, 4) k_trial(const Proj *projs, const Item
     const AS4 Proj &P = cst(projs)[itm.proj];
     const AS4 ScgState &st = *cst(P.st);
     if (mode == 1 && !st.active) return;
-    tile_trial<S, L, ST, SY>(P, st, itm.ty, itm.tx, mode, sm, red, partials + (i64)it * kNV);
+    tile_trial<S, L, TV, ST, SY>(P, st, itm.ty, itm.tx, mode, sm, red, partials + (i64)it * kNV);
 }
 
-template <int S, int L, class ST, class SY>
+template <int S, int L, int TV, class ST, class SY>
 __global__ void __launch_bounds__(kNTI, 4) k_upcurv(const Proj *projs, const Item *items,
                                                  const int *n_items, double *partials) {
-    __shared__ float sm[Tile<S, L>::SMEM];
+    __shared__ float sm[Tile<S, L, TV>::SMEM];
     __shared__ double red[kNV * kNWI];
     const int n = *cst(n_items);
     const int b = blockIdx.x;
@@ -1092,27 +1097,27 @@ __global__ void __launch_bounds__(kNTI, 4) k_upcurv(const Proj *projs, const Ite
     const AS4 Proj &P = cst(projs)[itm.proj];
     const AS4 ScgState &st = *cst(P.st);
     if (!st.do_update) return;
-    tile_upcurv<S, L, ST, SY>(P, st, itm.ty, itm.tx, sm, red, partials + (i64)it * kNV);
+    tile_upcurv<S, L, TV, ST, SY>(P, st, itm.ty, itm.tx, sm, red, partials + (i64)it * kNV);
 }
 
-template <int S, int L, class ST>
+template <int S, int L, int TV, class ST>
 __global__ void __launch_bounds__(kNTI) k_forward(const Proj *projs, const Item *items, int n,
                                                   void *yout) {
-    __shared__ float sm[Tile<S, L>::SMEM];
+    __shared__ float sm[Tile<S, L, TV>::SMEM];
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const AS4 Item &itm = cst(items)[it];
-        tile_forward<S, L, ST>(cst(projs)[itm.proj], itm.ty, itm.tx, yout, sm);
+        tile_forward<S, L, TV, ST>(cst(projs)[itm.proj], itm.ty, itm.tx, yout, sm);
         __syncthreads();
     }
 }
 
-template <int S, int L, class ST>
+template <int S, int L, int TV, class ST>
 __global__ void __launch_bounds__(kNTI) k_adjoint(const Proj *projs, const Item *items, int n,
                                                   const void *r, float *xout) {
-    __shared__ float sm[Tile<S, L>::SMEM];
+    __shared__ float sm[Tile<S, L, TV>::SMEM];
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const AS4 Item &itm = cst(items)[it];
-        tile_adjoint<S, L, ST>(cst(projs)[itm.proj], itm.ty, itm.tx, r, xout, sm);
+        tile_adjoint<S, L, TV, ST>(cst(projs)[itm.proj], itm.ty, itm.tx, r, xout, sm);
         __syncthreads();
     }
 }
@@ -1133,13 +1138,32 @@ __global__ void __launch_bounds__(kNTI) k_adjoint(const Proj *projs, const Item 
 #define MISR_CAT(a, b) MISR_CAT2(a, b)
 #define MISR_FN(name) MISR_CAT(name, MISR_SCALE)
 
-// Tile shape of band length Lp at this scale (0 if not instantiated).
-int MISR_FN(tile_dims_s)(int Lp, int *th, int *tw) {
-#define X(l)                       \
-    if (Lp == l) {                 \
-        *th = Tile<MISR_SCALE, l>::TH; \
-        *tw = Tile<MISR_SCALE, l>::TW; \
-        return 1;                  \
+// Kernel keys: key = Lp | (tile variant << 8); variant 0 is the widest tile
+// that fits, variant 1 about half as wide (chosen per operator by the tile
+// autotuner).
+#define MISR_VARIANT(key, BODY) \
+    if (((key) >> 8) == 0) {    \
+        constexpr int tv = 0;   \
+        BODY                    \
+    } else {                    \
+        constexpr int tv = 1;   \
+        BODY                    \
+    }
+
+// Tile shape of kernel key `key` at this scale (0 if not instantiated).
+int MISR_FN(tile_dims_s)(int key, int *th, int *tw) {
+    if ((key >> 8) > 1) return 0;
+    const int Lp = key & 255;
+#define X(l)                                       \
+    if (Lp == l) {                                 \
+        if ((key >> 8) == 0) {                     \
+            *th = Tile<MISR_SCALE, l, 0>::TH;      \
+            *tw = Tile<MISR_SCALE, l, 0>::TW;      \
+        } else {                                   \
+            *th = Tile<MISR_SCALE, l, 1>::TH;      \
+            *tw = Tile<MISR_SCALE, l, 1>::TW;      \
+        }                                          \
+        return 1;                                  \
     }
     MISR_LIST(X)
 #undef X
@@ -1148,29 +1172,34 @@ int MISR_FN(tile_dims_s)(int Lp, int *th, int *tw) {
 
 // code = st_code(x storage, y storage): the frames share the iterate's
 // storage, or the iterate is FP32 over 16-bit frames.
-hipError_t MISR_FN(launch_trial_s)(int Lp, int code, int grid, hipStream_t s, const Proj *projs,
+#define MISR_CODES(LAUNCH, l)                         \
+    if (code == st_code(ST_F32, ST_F32))              \
+        LAUNCH(l, StF32, StF32);                      \
+    else if (code == st_code(ST_F16, ST_F16))         \
+        LAUNCH(l, StF16, StF16);                      \
+    else if (code == st_code(ST_BF16, ST_BF16))       \
+        LAUNCH(l, StBF16, StBF16);                    \
+    else if (code == st_code(ST_F32, ST_F16))         \
+        LAUNCH(l, StF32, StF16);                      \
+    else if (code == st_code(ST_F32, ST_BF16))        \
+        LAUNCH(l, StF32, StBF16);                     \
+    else if (code == st_code(ST_F32, ST_U16))         \
+        LAUNCH(l, StF32, StU16);                      \
+    else                                              \
+        return hipErrorInvalidValue;
+
+hipError_t MISR_FN(launch_trial_s)(int key, int code, int grid, hipStream_t s, const Proj *projs,
                                    const Item *items, const int *n_items, double *partials,
                                    int mode) {
-#define LAUNCH(l, SX, SY)                                                                     \
-    hipLaunchKernelGGL((k_trial<MISR_SCALE, l, SX, SY>), dim3(grid), dim3(kNTI), 0, s, projs, \
-                       items, n_items, partials, mode)
-#define X(l)                                                                                  \
-    if (Lp == l) {                                                                            \
-        if (code == st_code(ST_F32, ST_F32))                                                  \
-            LAUNCH(l, StF32, StF32);                                                          \
-        else if (code == st_code(ST_F16, ST_F16))                                             \
-            LAUNCH(l, StF16, StF16);                                                          \
-        else if (code == st_code(ST_BF16, ST_BF16))                                           \
-            LAUNCH(l, StBF16, StBF16);                                                        \
-        else if (code == st_code(ST_F32, ST_F16))                                             \
-            LAUNCH(l, StF32, StF16);                                                          \
-        else if (code == st_code(ST_F32, ST_BF16))                                            \
-            LAUNCH(l, StF32, StBF16);                                                         \
-        else if (code == st_code(ST_F32, ST_U16))                                             \
-            LAUNCH(l, StF32, StU16);                                                          \
-        else                                                                                  \
-            return hipErrorInvalidValue;                                                      \
-        return hipGetLastError();                                                             \
+    if ((key >> 8) > 1) return hipErrorInvalidValue;
+    const int Lp = key & 255;
+#define LAUNCH(l, SX, SY)                                                                    \
+    hipLaunchKernelGGL((k_trial<MISR_SCALE, l, tv, SX, SY>), dim3(grid), dim3(kNTI), 0, s, \
+                       projs, items, n_items, partials, mode)
+#define X(l)                                        \
+    if (Lp == l) {                                  \
+        MISR_VARIANT(key, MISR_CODES(LAUNCH, l))    \
+        return hipGetLastError();                   \
     }
     MISR_LIST(X)
 #undef X
@@ -1178,29 +1207,18 @@ hipError_t MISR_FN(launch_trial_s)(int Lp, int code, int grid, hipStream_t s, co
     return hipErrorInvalidValue;
 }
 
-hipError_t MISR_FN(launch_upcurv_s)(int Lp, int code, int grid, hipStream_t s, const Proj *projs,
+hipError_t MISR_FN(launch_upcurv_s)(int key, int code, int grid, hipStream_t s, const Proj *projs,
                                     const Item *items, const int *n_items,
                                     double *partials) {
-#define LAUNCH(l, SX, SY)                                                                      \
-    hipLaunchKernelGGL((k_upcurv<MISR_SCALE, l, SX, SY>), dim3(grid), dim3(kNTI), 0, s, projs, \
-                       items, n_items, partials)
-#define X(l)                                                                                   \
-    if (Lp == l) {                                                                             \
-        if (code == st_code(ST_F32, ST_F32))                                                   \
-            LAUNCH(l, StF32, StF32);                                                           \
-        else if (code == st_code(ST_F16, ST_F16))                                              \
-            LAUNCH(l, StF16, StF16);                                                           \
-        else if (code == st_code(ST_BF16, ST_BF16))                                            \
-            LAUNCH(l, StBF16, StBF16);                                                         \
-        else if (code == st_code(ST_F32, ST_F16))                                              \
-            LAUNCH(l, StF32, StF16);                                                           \
-        else if (code == st_code(ST_F32, ST_BF16))                                             \
-            LAUNCH(l, StF32, StBF16);                                                          \
-        else if (code == st_code(ST_F32, ST_U16))                                              \
-            LAUNCH(l, StF32, StU16);                                                           \
-        else                                                                                   \
-            return hipErrorInvalidValue;                                                       \
-        return hipGetLastError();                                                              \
+    if ((key >> 8) > 1) return hipErrorInvalidValue;
+    const int Lp = key & 255;
+#define LAUNCH(l, SX, SY)                                                                     \
+    hipLaunchKernelGGL((k_upcurv<MISR_SCALE, l, tv, SX, SY>), dim3(grid), dim3(kNTI), 0, s, \
+                       projs, items, n_items, partials)
+#define X(l)                                        \
+    if (Lp == l) {                                  \
+        MISR_VARIANT(key, MISR_CODES(LAUNCH, l))    \
+        return hipGetLastError();                   \
     }
     MISR_LIST(X)
 #undef X
@@ -1208,43 +1226,47 @@ hipError_t MISR_FN(launch_upcurv_s)(int Lp, int code, int grid, hipStream_t s, c
     return hipErrorInvalidValue;
 }
 
-hipError_t MISR_FN(launch_forward_s)(int Lp, int stype, int grid, hipStream_t s, const Proj *projs,
+#define MISR_STYPES(LAUNCH, l)          \
+    if (stype == ST_F32)                \
+        LAUNCH(l, StF32);               \
+    else if (stype == ST_F16)           \
+        LAUNCH(l, StF16);               \
+    else                                \
+        LAUNCH(l, StBF16);
+
+hipError_t MISR_FN(launch_forward_s)(int key, int stype, int grid, hipStream_t s, const Proj *projs,
                                      const Item *items, int n, void *y) {
-#define X(l)                                                                                      \
-    if (Lp == l) {                                                                                \
-        if (stype == ST_F32)                                                                      \
-            hipLaunchKernelGGL((k_forward<MISR_SCALE, l, StF32>), dim3(grid), dim3(kNTI), 0, s,     \
-                               projs, items, n, y);                                               \
-        else if (stype == ST_F16)                                                                 \
-            hipLaunchKernelGGL((k_forward<MISR_SCALE, l, StF16>), dim3(grid), dim3(kNTI), 0, s,     \
-                               projs, items, n, y);                                               \
-        else                                                                                      \
-            hipLaunchKernelGGL((k_forward<MISR_SCALE, l, StBF16>), dim3(grid), dim3(kNTI), 0, s,    \
-                               projs, items, n, y);                                               \
-        return hipGetLastError();                                                                 \
+    if ((key >> 8) > 1) return hipErrorInvalidValue;
+    const int Lp = key & 255;
+#define LAUNCH(l, ST)                                                                            \
+    hipLaunchKernelGGL((k_forward<MISR_SCALE, l, tv, ST>), dim3(grid), dim3(kNTI), 0, s, projs, \
+                       items, n, y)
+#define X(l)                                         \
+    if (Lp == l) {                                   \
+        MISR_VARIANT(key, MISR_STYPES(LAUNCH, l))    \
+        return hipGetLastError();                    \
     }
     MISR_LIST(X)
 #undef X
+#undef LAUNCH
     return hipErrorInvalidValue;
 }
 
-hipError_t MISR_FN(launch_adjoint_s)(int Lp, int stype, int grid, hipStream_t s, const Proj *projs,
+hipError_t MISR_FN(launch_adjoint_s)(int key, int stype, int grid, hipStream_t s, const Proj *projs,
                                      const Item *items, int n, const void *r, float *x) {
-#define X(l)                                                                                      \
-    if (Lp == l) {                                                                                \
-        if (stype == ST_F32)                                                                      \
-            hipLaunchKernelGGL((k_adjoint<MISR_SCALE, l, StF32>), dim3(grid), dim3(kNTI), 0, s,     \
-                               projs, items, n, r, x);                                            \
-        else if (stype == ST_F16)                                                                 \
-            hipLaunchKernelGGL((k_adjoint<MISR_SCALE, l, StF16>), dim3(grid), dim3(kNTI), 0, s,     \
-                               projs, items, n, r, x);                                            \
-        else                                                                                      \
-            hipLaunchKernelGGL((k_adjoint<MISR_SCALE, l, StBF16>), dim3(grid), dim3(kNTI), 0, s,    \
-                               projs, items, n, r, x);                                            \
-        return hipGetLastError();                                                                 \
+    if ((key >> 8) > 1) return hipErrorInvalidValue;
+    const int Lp = key & 255;
+#define LAUNCH(l, ST)                                                                            \
+    hipLaunchKernelGGL((k_adjoint<MISR_SCALE, l, tv, ST>), dim3(grid), dim3(kNTI), 0, s, projs, \
+                       items, n, r, x)
+#define X(l)                                         \
+    if (Lp == l) {                                   \
+        MISR_VARIANT(key, MISR_STYPES(LAUNCH, l))    \
+        return hipGetLastError();                    \
     }
     MISR_LIST(X)
 #undef X
+#undef LAUNCH
     return hipErrorInvalidValue;
 }
 

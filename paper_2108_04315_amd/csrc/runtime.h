@@ -19,8 +19,9 @@ namespace misr {
 
 // launchers (kernels.hip)
 int padded_band(int S, int L);
-int tile_hr(int S, int Lp);
-int tile_wr(int S, int Lp);
+// tile shape of a kernel key (band length | variant << 8), -1 if none
+int tile_hr(int S, int key);
+int tile_wr(int S, int key);
 // code = st_code(storage of the views' x, storage of y).  grid must equal the
 // item count (*n_items): the trial and update kernels run one workgroup per
 // item.
@@ -258,6 +259,9 @@ struct misr_ctx {
 struct misr_op {
     misr_ctx *ctx;
     int H, W, s, K, P, L, Lp, TH, TW;  // TH x TW: HR tile of the image kernels
+    int tv = 0;                        // tile variant (set by misr_op_tune)
+    // key of the image kernels: band length and tile variant
+    int kernel_key() const { return Lp | (tv << 8); }
     std::vector<double> shifts;
     std::vector<double> psf;           // [K][2][P]: each frame's vertical, horizontal taps
     misr::DevMem wy, wx, opdev;

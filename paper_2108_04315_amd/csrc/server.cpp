@@ -294,7 +294,7 @@ void misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
     for (int pass = 0; pass < 2; ++pass)       // running solves first, then new ones
         for (SReq *r : rs) {
             if (r->fresh != (pass == 1)) continue;
-            auto key = std::make_pair(r->op->s, r->op->Lp);
+            auto key = std::make_pair(r->op->s, r->op->kernel_key());
             if (!groups.count(key)) order.push_back(key);
             groups[key].push_back(r);
         }

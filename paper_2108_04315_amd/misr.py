@@ -99,6 +99,10 @@ _SIGS = {
     "misr_op_destroy": (C.c_int, [_vp]),
     "misr_op_band": (C.c_int, [_vp]),
     "misr_op_sparse_width": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "misr_op_tune": (C.c_int, [_vp, C.POINTER(misr_params), _vp, _vp, C.c_int,
+                               C.POINTER(C.c_int32), C.POINTER(C.c_int32), _vp]),
+    "misr_op_tile": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "misr_op_set_tile": (C.c_int, [_vp, C.c_int]),
     "misr_forward": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "misr_interpolate": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "misr_upsample": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
@@ -242,6 +246,27 @@ class Operator:
     @property
     def band(self) -> int:
         return lib.misr_op_band(self.h)
+
+    @property
+    def tile(self):
+        """(rows, columns) of the image kernels' HR tile; (0, 0) if general."""
+        a, t = C.c_int32(), C.c_int32()
+        check(lib.misr_op_tile(self.h, C.byref(a), C.byref(t)))
+        return a.value, t.value
+
+    def set_tile(self, variant: int) -> None:
+        """Selects a compiled tile shape: 0 widest (default), 1 about half as wide."""
+        check(lib.misr_op_set_tile(self.h, variant))
+
+    def tune(self, y, x, params: misr_params | None = None, reps: int = 10, stream=None):
+        """Tile autotuner: times every compiled tile shape on (y, x) and keeps
+        the fastest for this operator; returns the chosen (rows, columns)."""
+        p = params or default_params()
+        p.img_dtype = dtype_code(x)
+        a, t = C.c_int32(), C.c_int32()
+        check(lib.misr_op_tune(self.h, C.byref(p), _ptr(y), _ptr(x), reps, C.byref(a),
+                               C.byref(t), stream_handle(stream)))
+        return a.value, t.value
 
     @property
     def sparse_width(self):

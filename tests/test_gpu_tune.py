@@ -1,0 +1,95 @@
+"""Tile shapes and the tile autotuner through the C ABI: both compiled tile
+shapes match the FP64 oracle and each other to FP32 rounding; the
+solve on the narrow tile matches the oracle's literal SCG; the autotuner
+keeps one of the compiled shapes and later calls use it."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import scg as oscg
+from gpu_common import TOL_OP, TOL_SCG, problem, rel_l2, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def misr():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2108_04315_amd import misr as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(misr):
+    c = misr.Context(0)
+    yield c
+    c.close()
+
+
+def _f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("L,s,sig", [(60, 2, 0.8), (44, 3, 1.0)])
+def test_tile_variants_same_gradient_and_oracle(misr, ctx, L, s, sig):
+    import torch
+    prob = problem(L, s, sig, None, jitter=0.05, n_iter=10, seeds=(3, 4, 5), Lw=L + 6)
+    op = misr.Operator(ctx, prob.H, prob.W, s, prob.shifts, prob.psf)
+    th0, tw0 = op.tile
+    op.set_tile(1)
+    th1, tw1 = op.tile
+    assert th1 == th0 and 0 < tw1 < tw0
+    x = _f32(np.random.default_rng(8).uniform(0, 1, (prob.H, prob.W)))
+    y = _f32(prob.y)
+    J, g_ref, _ = oracle.cost_grad(x, y, prob.shifts, prob.psf, s)
+    out = {}
+    for v in (0, 1):
+        op.set_tile(v)
+        cost, g = op.cost_grad(to_dev(x), to_dev(y))
+        torch.cuda.synchronize()
+        assert abs(cost.cpu().numpy()[0] - J) <= TOL_OP * J
+        assert rel_l2(to_np(g), g_ref) <= TOL_OP
+        yf = to_np(op.forward(to_dev(x)))
+        assert rel_l2(yf, oracle.forward(x, prob.shifts, prob.psf, s)) <= TOL_OP
+        out[v] = (g.clone(), cost.clone())
+    # the same per-pixel sums; the two instantiations may contract a product
+    # and a sum into one fused multiply-add differently, so FP32 rounding only
+    assert rel_l2(to_np(out[1][0]), to_np(out[0][0])) <= 1e-6
+    assert abs(float(out[0][1][0] - out[1][1][0])) <= 1e-9 * abs(float(out[0][1][0]))
+    op.close()
+
+
+def test_narrow_tile_solve_matches_oracle(misr, ctx):
+    prob = problem(64, 2, 0.8, None, jitter=0.05, n_iter=25, seeds=(6, 7, 8))
+    x_o, tr_o, _ = oscg.solve(_f32(prob.y), prob.shifts, prob.psf, 2, _f32(prob.x0), 25)
+    op = misr.Operator(ctx, prob.H, prob.W, 2, prob.shifts, prob.psf)
+    op.set_tile(1)
+    x = to_dev(_f32(prob.x0))
+    its, _ = op.scg_solve(to_dev(_f32(prob.y)), x, misr.default_params(n_iter=25))
+    assert rel_l2(to_np(x), x_o) <= TOL_SCG
+    assert [t["success"] for t in its] == [t["success"] for t in tr_o]
+    op.close()
+
+
+def test_autotuner_keeps_a_compiled_shape(misr, ctx):
+    import torch
+    prob = problem(128, 2, 0.8, None, jitter=0.05, n_iter=10, seeds=(9, 9, 9))
+    op = misr.Operator(ctx, prob.H, prob.W, 2, prob.shifts, prob.psf)
+    shapes = []
+    for v in (0, 1):
+        op.set_tile(v)
+        shapes.append(op.tile)
+    y, x0 = to_dev(_f32(prob.y)), to_dev(_f32(prob.x0))
+    before = x0.clone()
+    th, tw = op.tune(y, x0, reps=5)
+    torch.cuda.synchronize()
+    assert (th, tw) in shapes and op.tile == (th, tw)
+    assert torch.equal(x0, before)   # the tuner reads x only
+    x = x0.clone()
+    op.scg_solve(y, x, misr.default_params(n_iter=10), trace=False)
+    torch.cuda.synchronize()
+    assert torch.isfinite(x).all()
+    with pytest.raises(misr.MisrError):
+        op.set_tile(2)
+    op.close()
