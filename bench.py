@@ -299,6 +299,10 @@ def bench_batched(misr, ctx, K, Wm, n_proj=64, n_iter=60, seed=11):
     geoms = [(int(rng.choice(SERVE_SIZES)), int(rng.choice([2, 3]))) for _ in range(n_proj)]
     probs = {g: _serve_problem(misr, ctx, g[0], g[1], 200 + i)
              for i, g in enumerate(sorted(set(geoms)))}
+    # the tile autotuner, once per geometry on that geometry's data
+    tiles = {f"{g[0]}x{g[1]}": probs[g]["op"].tune(probs[g]["y"], probs[g]["x0"].clone(),
+                                                   misr.default_params(n_iter=n_iter), reps=5)
+             for g in sorted(probs)}
     ops = [probs[g]["op"] for g in geoms]
     ys = [probs[g]["y"].clone() for g in geoms]     # every projection its own frames
     prms = [misr.default_params(n_iter=n_iter) for _ in geoms]
@@ -319,6 +323,7 @@ def bench_batched(misr, ctx, K, Wm, n_proj=64, n_iter=60, seed=11):
                                   f"one shared work list", "hr_pixels": hr_px,
                       "scg_passes": n_iter, "parallelism": "1 GPU"})
     out["scg_passes_per_s"] = n_iter * K / dt
+    out["tiles"] = {"by_lr_size_x_scale": tiles, "by": "misr_op_tune"}
     return out
 
 
@@ -340,6 +345,7 @@ def bench_precision(misr, ctx, K, Wm, L=2048, s=3, n_iter=100):
     y_np = synth.add_poisson_noise(clean.double().cpu().numpy(), 1e4, 6)
     y32 = torch.from_numpy(y_np).float().cuda()
     x032 = torch.from_numpy(synth.bicubic_upsample(y_np[0], s)).float().cuda()
+    tile = op.tune(y32, x032.clone(), misr.default_params(n_iter=n_iter), reps=5)
     modes = [("f32", torch.float32, 0), ("f16", torch.float16, 0), ("bf16", torch.bfloat16, 0),
              ("f16-iterate16", torch.float16, 1), ("bf16-iterate16", torch.bfloat16, 1)]
     res, x_ref, dt_f32 = {}, None, None
@@ -370,6 +376,7 @@ def bench_precision(misr, ctx, K, Wm, L=2048, s=3, n_iter=100):
                       "hr": [Hh, Hh], "scale": s, "frames": s * s, "scg_passes": n_iter,
                       "parallelism": "1 GPU"})
     out["modes"] = res
+    out["tile"] = {"chosen": list(tile), "by": "misr_op_tune"}
     return out
 
 
@@ -476,6 +483,7 @@ def main():
         return
     op, shifts, psf, y, x0, y_np = make_inputs(misr, ctx)
     prm = misr.default_params(n_iter=N_ITER)
+    tile = op.tune(y, x0.clone(), prm, reps=10)   # the tile autotuner (outside the timed region)
     xs = [x0.clone() for _ in range(K + Wm)]
     torch.cuda.synchronize()
     for i in range(Wm):
@@ -522,6 +530,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
+        "tile": {"chosen": list(tile), "by": "misr_op_tune"},
         "config": {"workload": WORKLOAD, "hr": [H, W], "scale": S, "frames": 4,
                    "scg_passes": N_ITER, "parallelism": "1 GPU"},
         "scg_passes_per_s": N_ITER * K / dt,
