@@ -711,15 +711,20 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
         cown[c] = col < T::TW && o.v0 + col < o.v1;
         ocol[c] = min(o.v0 + col, o.v1 - 1);
     }
+    // g_k at the owned pixels; the wide tile issues these loads before the
+    // prior's sweep so that they are in flight during it, the narrow tile
+    // (whose sweep leaves no registers to carry them) after it
+    constexpr bool PRE = TV == 0;
     float gkv[ONR][ONC];
-    if (mode == 1) {
+    auto load_gk = [&]() {
 #pragma unroll
         for (int r = 0; r < ONR; ++r) {
             const i64 rb = (i64)min(o.u0 + wv0 + kNWI * r, o.u1 - 1) * ld;
 #pragma unroll
             for (int c = 0; c < ONC; ++c) gkv[r][c] = gk[rb + ocol[c]];
         }
-    }
+    };
+    if (PRE && mode == 1) load_gk();
     float gam[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) gam[d] = st.wt.gam[kDY[d] * 3 + kDX[d]];
@@ -736,8 +741,16 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     else
         btv_sweep<S, L, TV, false, true>(xs, gs, gam, eps, o.U0, o.V0, H, W, tho, two, e_reg);
     __syncthreads();
-    // owned gradient out, with its inner products
+    // owned gradient out, with its inner products (g_k is widened to double
+    // only here: widened at its load, it would be carried across the sweep
+    // in twice the registers)
     double gg = 0.0, ggk = 0.0, gp = 0.0;
+    if (!PRE && mode == 1) load_gk();
+    if (mode == 1)
+#pragma unroll
+        for (int r = 0; r < ONR; ++r)
+#pragma unroll
+            for (int c = 0; c < ONC; ++c) asm volatile("" : "+v"(gkv[r][c]));
 #pragma unroll
     for (int r = 0; r < ONR; ++r) {
         const int row = wv0 + kNWI * r;
