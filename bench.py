@@ -66,6 +66,13 @@ def make_inputs(misr, ctx):
     return op, shifts, psf, y, x0, y_np
 
 
+def tile_choice(op) -> dict:
+    """The operator's tile variant and its trial- and update-pass tiles (HR px)."""
+    th, tw = op.tile
+    v, twt = op.tile_variant
+    return {"variant": v, "trial": [th, twt], "update": [th, tw]}
+
+
 def profile_value(path: str, tag: str, key: str, src_hash: str):
     """The value `key` of the `tag:` line of a committed counter summary, if
     the summary was taken on the current kernel sources; else None."""
@@ -300,9 +307,11 @@ def bench_batched(misr, ctx, K, Wm, n_proj=64, n_iter=60, seed=11):
     probs = {g: _serve_problem(misr, ctx, g[0], g[1], 200 + i)
              for i, g in enumerate(sorted(set(geoms)))}
     # the tile autotuner, once per geometry on that geometry's data
-    tiles = {f"{g[0]}x{g[1]}": probs[g]["op"].tune(probs[g]["y"], probs[g]["x0"].clone(),
-                                                   misr.default_params(n_iter=n_iter), reps=5)
-             for g in sorted(probs)}
+    tiles = {}
+    for g in sorted(probs):
+        probs[g]["op"].tune(probs[g]["y"], probs[g]["x0"].clone(),
+                            misr.default_params(n_iter=n_iter), reps=5)
+        tiles[f"{g[0]}x{g[1]}"] = tile_choice(probs[g]["op"])
     ops = [probs[g]["op"] for g in geoms]
     ys = [probs[g]["y"].clone() for g in geoms]     # every projection its own frames
     prms = [misr.default_params(n_iter=n_iter) for _ in geoms]
@@ -345,7 +354,8 @@ def bench_precision(misr, ctx, K, Wm, L=2048, s=3, n_iter=100):
     y_np = synth.add_poisson_noise(clean.double().cpu().numpy(), 1e4, 6)
     y32 = torch.from_numpy(y_np).float().cuda()
     x032 = torch.from_numpy(synth.bicubic_upsample(y_np[0], s)).float().cuda()
-    tile = op.tune(y32, x032.clone(), misr.default_params(n_iter=n_iter), reps=5)
+    op.tune(y32, x032.clone(), misr.default_params(n_iter=n_iter), reps=5)
+    tile = tile_choice(op)
     modes = [("f32", torch.float32, 0), ("f16", torch.float16, 0), ("bf16", torch.bfloat16, 0),
              ("f16-iterate16", torch.float16, 1), ("bf16-iterate16", torch.bfloat16, 1)]
     res, x_ref, dt_f32 = {}, None, None
@@ -376,7 +386,7 @@ def bench_precision(misr, ctx, K, Wm, L=2048, s=3, n_iter=100):
                       "hr": [Hh, Hh], "scale": s, "frames": s * s, "scg_passes": n_iter,
                       "parallelism": "1 GPU"})
     out["modes"] = res
-    out["tile"] = {"chosen": list(tile), "by": "misr_op_tune"}
+    out["tile"] = dict(tile, by="misr_op_tune")
     return out
 
 
@@ -483,7 +493,8 @@ def main():
         return
     op, shifts, psf, y, x0, y_np = make_inputs(misr, ctx)
     prm = misr.default_params(n_iter=N_ITER)
-    tile = op.tune(y, x0.clone(), prm, reps=10)   # the tile autotuner (outside the timed region)
+    op.tune(y, x0.clone(), prm, reps=10)   # the tile autotuner (outside the timed region)
+    tile = tile_choice(op)
     xs = [x0.clone() for _ in range(K + Wm)]
     torch.cuda.synchronize()
     for i in range(Wm):
@@ -530,7 +541,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "tile": {"chosen": list(tile), "by": "misr_op_tune"},
+        "tile": dict(tile, by="misr_op_tune"),
         "config": {"workload": WORKLOAD, "hr": [H, W], "scale": S, "frames": 4,
                    "scg_passes": N_ITER, "parallelism": "1 GPU"},
         "scg_passes_per_s": N_ITER * K / dt,

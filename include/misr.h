@@ -198,8 +198,10 @@ int misr_op_band(const misr_op *op);
 misr_status misr_op_sparse_width(const misr_op *op, int32_t *a_w, int32_t *t_w);
 
 /* Tile autotuner: times the trial and update passes of every compiled tile
- * shape of this banded operator (the widest tile that fits, and one about
- * half as wide, which gives small images more workgroups) on the caller's
+ * variant of this banded operator (0: the widest tile that fits both passes;
+ * 1: one about half as wide, which gives small images more workgroups; 2,
+ * where it exists: variant 0 with a wider trial-pass tile, the widest the
+ * trial pass's LDS alone allows) on the caller's
  * frames y and image x (device buffers, img_dtype storage; x is read only),
  * `reps` launches each with HIP events, and keeps the fastest for every
  * later call on this operator (solves, batches, operators).  *tile_h x
@@ -208,10 +210,16 @@ misr_status misr_op_sparse_width(const misr_op *op, int32_t *a_w, int32_t *t_w);
  * shape except for the summation order of the cost and inner products. */
 misr_status misr_op_tune(misr_op *op, const misr_params *params, const void *y, void *x,
                          int reps, int32_t *tile_h, int32_t *tile_w, void *stream);
-/* The operator's current tile shape (HR pixels; 0 x 0 for a general operator). */
+/* The operator's current tile shape of the update pass and the operators
+ * (HR pixels; 0 x 0 for a general operator); the trial pass's tile has the
+ * same height. */
 misr_status misr_op_tile(const misr_op *op, int32_t *tile_h, int32_t *tile_w);
-/* Selects a compiled tile shape directly: variant 0 the widest (the default),
- * 1 about half as wide.  MISR_E_INVAL for other values or a general operator. */
+/* The operator's current tile variant (-1 for a general operator) and the
+ * width of its trial-pass tile in HR pixels. */
+misr_status misr_op_tile_variant(const misr_op *op, int32_t *variant, int32_t *trial_w);
+/* Selects a compiled tile variant directly (as listed for misr_op_tune; 0 is
+ * the default).  MISR_E_INVAL for a variant not compiled for this operator's
+ * scale and band length, or for a general operator. */
 misr_status misr_op_set_tile(misr_op *op, int variant);
 
 /* --------------------------------------------------------------- operators */

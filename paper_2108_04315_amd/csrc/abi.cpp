@@ -318,7 +318,7 @@ static void general_row(const misr_op *op, const double *m, const double *hk, in
 // rounded to FP32 once) and uploads them.
 static misr_status build_general(misr_op *op, const misr_geometry *g) {
     op->general = true;
-    op->L = op->Lp = op->TH = op->TW = 0;
+    op->L = op->Lp = op->TH = op->TW = op->TWt = 0;
     const int H = op->H, W = op->W, s = op->s, K = op->K, P = g->psf_size;
     const int h = H / s, w = W / s;
     const long long rows = (long long)K * h * w, n = (long long)H * W;
@@ -473,6 +473,7 @@ extern "C" misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, mis
     op->Lp = padded_band(op->s, op->L);
     op->TH = tile_hr(op->s, op->Lp);
     op->TW = tile_wr(op->s, op->Lp);
+    op->TWt = tile_wt(op->s, op->Lp);
     op->shifts.assign(g->shifts_lr, g->shifts_lr + 2 * g->n_frames);
     // taps per frame and axis: [K][2][P], vertical then horizontal
     if (g->psf_frames) {
@@ -684,7 +685,7 @@ void misr::add_views(const misr_op *op, const misr_params &prm, const void *y, v
         P.ntx = (op->W + op->TW - 1) / op->TW;
         const int pj = (int)projs.size();
         projs.push_back(P);
-        add_items(items, pj, op->H, op->W, op->TH, op->TW);
+        add_items(items, pj, op->H, op->W, op->TH, op->TWt);
         add_items(items_u, pj, op->H, op->W, op->TH, op->TW);
         return;
     }
@@ -720,7 +721,7 @@ void misr::add_views(const misr_op *op, const misr_params &prm, const void *y, v
             Q.ntx = (C1 - C0 + op->TW - 1) / op->TW;
             const int pj = (int)projs.size();
             projs.push_back(Q);
-            add_items(items, pj, R1 - R0, C1 - C0, op->TH, op->TW);
+            add_items(items, pj, R1 - R0, C1 - C0, op->TH, op->TWt);
             add_items(items_u, pj, Q.Hb, Q.Wb, op->TH, op->TW);
         }
     // halo exchanges: every view's halo from the views that own it
@@ -976,8 +977,10 @@ extern "C" misr_status misr_forward(const misr_op *cop, misr_dtype dt, const voi
     PlanDev &pd = op->pdev;
     hipStream_t s = (hipStream_t)stream;
     MISR_HIP(pd.upload(pl, 0, s));
-    MISR_HIP(launch_forward(op->s, op->kernel_key(), (int)pl.items.size(), s, pd.projs.as<Proj>(),
-                            pd.items.as<Item>(), (int)pl.items.size(), (int)dt, y));
+    // the update list: tiles of the operator's (update-pass) shape
+    MISR_HIP(launch_forward(op->s, op->kernel_key(), (int)pl.items_u.size(), s,
+                            pd.projs.as<Proj>(), pd.items_u.as<Item>(), (int)pl.items_u.size(),
+                            (int)dt, y));
     return MISR_OK;
 }
 
@@ -1000,8 +1003,9 @@ extern "C" misr_status misr_adjoint(const misr_op *cop, misr_dtype dt, const voi
     PlanDev &pd = op->pdev;
     hipStream_t s = (hipStream_t)stream;
     MISR_HIP(pd.upload(pl, 0, s));
-    MISR_HIP(launch_adjoint(op->s, op->kernel_key(), (int)pl.items.size(), s, pd.projs.as<Proj>(),
-                            pd.items.as<Item>(), (int)pl.items.size(), (int)dt, r, x));
+    MISR_HIP(launch_adjoint(op->s, op->kernel_key(), (int)pl.items_u.size(), s,
+                            pd.projs.as<Proj>(), pd.items_u.as<Item>(), (int)pl.items_u.size(),
+                            (int)dt, r, x));
     return MISR_OK;
 }
 
@@ -1229,6 +1233,7 @@ static void set_tile_variant(misr_op *op, int tv) {
     op->tv = tv;
     op->TH = tile_hr(op->s, op->kernel_key());
     op->TW = tile_wr(op->s, op->kernel_key());
+    op->TWt = tile_wt(op->s, op->kernel_key());
 }
 
 extern "C" misr_status misr_op_tune(misr_op *op, const misr_params *prm, const void *y, void *x,
@@ -1245,7 +1250,7 @@ extern "C" misr_status misr_op_tune(misr_op *op, const misr_params *prm, const v
     if (!op->general) {
         double best = 0.0;
         int best_tv = 0;
-        for (int tv = 0; tv < 2; ++tv) {
+        for (int tv = 0; tv < 3; ++tv) {
             if (tile_hr(op->s, op->Lp | (tv << 8)) <= 0) continue;
             set_tile_variant(op, tv);
             double t_trial = 0.0, t_upd = 0.0;
@@ -1269,7 +1274,7 @@ extern "C" misr_status misr_op_tune(misr_op *op, const misr_params *prm, const v
 extern "C" misr_status misr_op_set_tile(misr_op *op, int variant) {
     if (!op) return set_error(MISR_E_INVAL, "op is NULL");
     if (op->general) return set_error(MISR_E_INVAL, "a general operator has no tiles");
-    if (variant < 0 || variant > 1 || tile_hr(op->s, op->Lp | (variant << 8)) <= 0)
+    if (variant < 0 || variant > 2 || tile_hr(op->s, op->Lp | (variant << 8)) <= 0)
         return set_error(MISR_E_INVAL, "tile variant %d not compiled", variant);
     std::lock_guard<std::mutex> lk(op->mu);
     set_tile_variant(op, variant);
@@ -1280,5 +1285,13 @@ extern "C" misr_status misr_op_tile(const misr_op *op, int32_t *tile_h, int32_t 
     if (!op || !tile_h || !tile_w) return set_error(MISR_E_INVAL, "NULL argument");
     *tile_h = op->TH;
     *tile_w = op->TW;
+    return MISR_OK;
+}
+
+extern "C" misr_status misr_op_tile_variant(const misr_op *op, int32_t *variant,
+                                            int32_t *trial_w) {
+    if (!op || !variant || !trial_w) return set_error(MISR_E_INVAL, "NULL argument");
+    *variant = op->general ? -1 : op->tv;
+    *trial_w = op->TWt;
     return MISR_OK;
 }

@@ -31,6 +31,12 @@ namespace misr {
 constexpr int kNTI = 512;          // threads per workgroup of the image kernels
 constexpr int kNWI = kNTI / 64;    // waves per workgroup
 
+// Tile shapes: variant 0 is the widest tile for which one 64-lane wave spans
+// every tile dimension a pass maps to lanes and two workgroups fit a CU's LDS
+// in both the trial and the update pass; variant 1 is about half as wide;
+// variant 2 is a trial-kernel shape as wide as the trial pass's LDS alone
+// allows (the update pass stages two windows), paired with variant 0's
+// update shape.
 template <int S, int L, int TV>
 struct Tile {
     static constexpr int EXT = (L - 1 > 2) ? L - 1 : 2;   // window margin (HR px)
@@ -48,6 +54,8 @@ struct Tile {
     static constexpr int NIM = (TH + L - 2) / S + 1;     // LR rows touching the tile
     static constexpr int NRM = S * (NIM - 1) + L;        // HR rows those read
     static constexpr int odd(int v) { return (v % 2) ? v : v + 1; }
+    // LDS floats of a tile tw wide: the trial pass's, and the update pass's
+    // unless the shape is the trial kernel's own (variant 2)
     static constexpr int lds_floats(int tw) {
         const int wcp = odd(tw + 2 * EXT);
         const int njp = odd((tw + L - 2) / S + 1);
@@ -57,7 +65,7 @@ struct Tile {
         const int gs = TH * (tw + 1);
         const int trial = xs + (hr > gs ? hr : gs) + TH * tw;   // + the owned p
         const int upd = 2 * xs + hx + NIM * njp;                // + A_k x for p = 1
-        return trial > upd ? trial : upd;
+        return (TV == 2 || trial > upd) ? trial : upd;
     }
     static constexpr int calc_tw() {
         int best = kNWI * S;
@@ -836,6 +844,7 @@ FI double upd_data_part(const AS4 Proj &P, const AS4 ScgState &st, const TileOri
 template <int S, int L, int TV, class ST, class SY>
 FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, float *sm,
                     double *red, double *part) {
+    static_assert(TV != 2, "the trial kernel's own tile shape");
     using T = Tile<S, L, TV>;
     using raw = typename ST::raw;
     const AS4 OpDev &op = *cst(P.op);
@@ -1154,33 +1163,69 @@ __global__ void __launch_bounds__(kNTI) k_adjoint(const Proj *projs, const Item 
 // Kernel keys: key = Lp | (tile variant << 8); variant 0 is the widest tile
 // that fits, variant 1 about half as wide (chosen per operator by the tile
 // autotuner).
+// the update pass and the operators: variant 2 runs variant 0's shape
 #define MISR_VARIANT(key, BODY) \
-    if (((key) >> 8) == 0) {    \
-        constexpr int tv = 0;   \
-        BODY                    \
-    } else {                    \
+    if (((key) >> 8) == 1) {    \
         constexpr int tv = 1;   \
         BODY                    \
+    } else {                    \
+        constexpr int tv = 0;   \
+        BODY                    \
+    }
+// the trial pass: every variant is its own shape
+#define MISR_VARIANT_TRIAL(key, BODY) \
+    if (((key) >> 8) == 0) {          \
+        constexpr int tv = 0;         \
+        BODY                          \
+    } else if (((key) >> 8) == 1) {   \
+        constexpr int tv = 1;         \
+        BODY                          \
+    } else {                          \
+        constexpr int tv = 2;         \
+        BODY                          \
     }
 
-// Tile shape of kernel key `key` at this scale (0 if not instantiated).
+// Tile shapes of a kernel key (band length | variant << 8): the update
+// pass's (and the operators'), then the trial pass's.  Variant 2 pairs the
+// trial kernel's own wider shape with variant 0's update shape; it exists
+// only where that shape is wider.
+template <int L>
+constexpr bool wide_trial() {
+    return Tile<MISR_SCALE, L, 2>::TW > Tile<MISR_SCALE, L, 0>::TW;
+}
+
 int MISR_FN(tile_dims_s)(int key, int *th, int *tw) {
-    if ((key >> 8) > 1) return 0;
-    const int Lp = key & 255;
-#define X(l)                                       \
-    if (Lp == l) {                                 \
-        if ((key >> 8) == 0) {                     \
-            *th = Tile<MISR_SCALE, l, 0>::TH;      \
-            *tw = Tile<MISR_SCALE, l, 0>::TW;      \
-        } else {                                   \
-            *th = Tile<MISR_SCALE, l, 1>::TH;      \
-            *tw = Tile<MISR_SCALE, l, 1>::TW;      \
-        }                                          \
-        return 1;                                  \
+    const int v = key >> 8, Lp = key & 255;
+#define X(l)                                                        \
+    if (Lp == l) {                                                  \
+        if (v == 1) {                                               \
+            *th = Tile<MISR_SCALE, l, 1>::TH;                       \
+            *tw = Tile<MISR_SCALE, l, 1>::TW;                       \
+            return 1;                                               \
+        }                                                           \
+        if (v == 0 || (v == 2 && wide_trial<l>())) {                \
+            *th = Tile<MISR_SCALE, l, 0>::TH;                       \
+            *tw = Tile<MISR_SCALE, l, 0>::TW;                       \
+            return 1;                                               \
+        }                                                           \
+        return 0;                                                   \
     }
     MISR_LIST(X)
 #undef X
     return 0;
+}
+
+int MISR_FN(tile_dims_trial_s)(int key, int *th, int *tw) {
+    if (!MISR_FN(tile_dims_s)(key, th, tw)) return 0;
+    const int Lp = key & 255;
+#define X(l)                                         \
+    if (Lp == l && (key >> 8) == 2) {                \
+        *th = Tile<MISR_SCALE, l, 2>::TH;            \
+        *tw = Tile<MISR_SCALE, l, 2>::TW;            \
+    }
+    MISR_LIST(X)
+#undef X
+    return 1;
 }
 
 // code = st_code(x storage, y storage): the frames share the iterate's
@@ -1204,14 +1249,14 @@ int MISR_FN(tile_dims_s)(int key, int *th, int *tw) {
 hipError_t MISR_FN(launch_trial_s)(int key, int code, int grid, hipStream_t s, const Proj *projs,
                                    const Item *items, const int *n_items, double *partials,
                                    int mode) {
-    if ((key >> 8) > 1) return hipErrorInvalidValue;
+    if ((key >> 8) > 2) return hipErrorInvalidValue;
     const int Lp = key & 255;
 #define LAUNCH(l, SX, SY)                                                                    \
     hipLaunchKernelGGL((k_trial<MISR_SCALE, l, tv, SX, SY>), dim3(grid), dim3(kNTI), 0, s, \
                        projs, items, n_items, partials, mode)
 #define X(l)                                        \
     if (Lp == l) {                                  \
-        MISR_VARIANT(key, MISR_CODES(LAUNCH, l))    \
+        MISR_VARIANT_TRIAL(key, MISR_CODES(LAUNCH, l))    \
         return hipGetLastError();                   \
     }
     MISR_LIST(X)
@@ -1223,7 +1268,7 @@ hipError_t MISR_FN(launch_trial_s)(int key, int code, int grid, hipStream_t s, c
 hipError_t MISR_FN(launch_upcurv_s)(int key, int code, int grid, hipStream_t s, const Proj *projs,
                                     const Item *items, const int *n_items,
                                     double *partials) {
-    if ((key >> 8) > 1) return hipErrorInvalidValue;
+    if ((key >> 8) > 2) return hipErrorInvalidValue;
     const int Lp = key & 255;
 #define LAUNCH(l, SX, SY)                                                                     \
     hipLaunchKernelGGL((k_upcurv<MISR_SCALE, l, tv, SX, SY>), dim3(grid), dim3(kNTI), 0, s, \
@@ -1249,7 +1294,7 @@ hipError_t MISR_FN(launch_upcurv_s)(int key, int code, int grid, hipStream_t s, 
 
 hipError_t MISR_FN(launch_forward_s)(int key, int stype, int grid, hipStream_t s, const Proj *projs,
                                      const Item *items, int n, void *y) {
-    if ((key >> 8) > 1) return hipErrorInvalidValue;
+    if ((key >> 8) > 2) return hipErrorInvalidValue;
     const int Lp = key & 255;
 #define LAUNCH(l, ST)                                                                            \
     hipLaunchKernelGGL((k_forward<MISR_SCALE, l, tv, ST>), dim3(grid), dim3(kNTI), 0, s, projs, \
@@ -1267,7 +1312,7 @@ hipError_t MISR_FN(launch_forward_s)(int key, int stype, int grid, hipStream_t s
 
 hipError_t MISR_FN(launch_adjoint_s)(int key, int stype, int grid, hipStream_t s, const Proj *projs,
                                      const Item *items, int n, const void *r, float *x) {
-    if ((key >> 8) > 1) return hipErrorInvalidValue;
+    if ((key >> 8) > 2) return hipErrorInvalidValue;
     const int Lp = key & 255;
 #define LAUNCH(l, ST)                                                                            \
     hipLaunchKernelGGL((k_adjoint<MISR_SCALE, l, tv, ST>), dim3(grid), dim3(kNTI), 0, s, projs, \

@@ -22,6 +22,9 @@ int padded_band(int S, int L);
 // tile shape of a kernel key (band length | variant << 8), -1 if none
 int tile_hr(int S, int key);
 int tile_wr(int S, int key);
+// width of the trial kernel's tile (its own, wider shape for variant 0; the
+// height is the same)
+int tile_wt(int S, int key);
 // code = st_code(storage of the views' x, storage of y).  grid must equal the
 // item count (*n_items): the trial and update kernels run one workgroup per
 // item.
@@ -259,6 +262,7 @@ struct misr_ctx {
 struct misr_op {
     misr_ctx *ctx;
     int H, W, s, K, P, L, Lp, TH, TW;  // TH x TW: HR tile of the image kernels
+    int TWt = 0;                       // TH x TWt: the trial kernel's tile
     int tv = 0;                        // tile variant (set by misr_op_tune)
     // key of the image kernels: band length and tile variant
     int kernel_key() const { return Lp | (tv << 8); }

@@ -397,6 +397,7 @@ __global__ void k_upsample(InitArgs a, const void *y, void *x, int st) {
 #define MISR_SCALES(X) X(1) X(2) X(3) X(4)
 #define X(s)                                                                                   \
     int tile_dims_s##s(int Lp, int *th, int *tw);                                              \
+    int tile_dims_trial_s##s(int Lp, int *th, int *tw);                                        \
     hipError_t launch_trial_s##s(int Lp, int stype, int grid, hipStream_t st, const Proj *projs, \
                                  const Item *items, const int *n_items, double *partials,      \
                                  int mode);                                                    \
@@ -440,6 +441,17 @@ int tile_hr(int S, int Lp) {
 int tile_wr(int S, int Lp) {
     int th = -1, tw = -1;
     return tile_dims(S, Lp, &th, &tw) ? tw : -1;
+}
+
+int tile_wt(int S, int key) {
+    int th = -1, tw = -1, ok = 0;
+    switch (S) {
+    case 1: ok = tile_dims_trial_s1(key, &th, &tw); break;
+    case 2: ok = tile_dims_trial_s2(key, &th, &tw); break;
+    case 3: ok = tile_dims_trial_s3(key, &th, &tw); break;
+    case 4: ok = tile_dims_trial_s4(key, &th, &tw); break;
+    }
+    return ok ? tw : -1;
 }
 
 hipError_t launch_image(int S, int Lp, int grid, hipStream_t stream, const Proj *projs,

@@ -102,6 +102,7 @@ _SIGS = {
     "misr_op_tune": (C.c_int, [_vp, C.POINTER(misr_params), _vp, _vp, C.c_int,
                                C.POINTER(C.c_int32), C.POINTER(C.c_int32), _vp]),
     "misr_op_tile": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "misr_op_tile_variant": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "misr_op_set_tile": (C.c_int, [_vp, C.c_int]),
     "misr_forward": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "misr_interpolate": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
@@ -254,8 +255,16 @@ class Operator:
         check(lib.misr_op_tile(self.h, C.byref(a), C.byref(t)))
         return a.value, t.value
 
+    @property
+    def tile_variant(self):
+        """(variant, trial-pass tile width); variant -1 if general."""
+        v, t = C.c_int32(), C.c_int32()
+        check(lib.misr_op_tile_variant(self.h, C.byref(v), C.byref(t)))
+        return v.value, t.value
+
     def set_tile(self, variant: int) -> None:
-        """Selects a compiled tile shape: 0 widest (default), 1 about half as wide."""
+        """Selects a compiled tile variant: 0 widest (default), 1 about half as
+        wide, 2 (where compiled) variant 0 with a wider trial-pass tile."""
         check(lib.misr_op_set_tile(self.h, variant))
 
     def tune(self, y, x, params: misr_params | None = None, reps: int = 10, stream=None):

@@ -44,8 +44,12 @@ def test_tile_variants_same_gradient_and_oracle(misr, ctx, L, s, sig):
     y = _f32(prob.y)
     J, g_ref, _ = oracle.cost_grad(x, y, prob.shifts, prob.psf, s)
     out = {}
-    for v in (0, 1):
-        op.set_tile(v)
+    for v in (0, 1, 2):
+        try:
+            op.set_tile(v)
+        except misr.MisrError:
+            assert v == 2   # variant 2 exists only where its trial tile is wider
+            continue
         cost, g = op.cost_grad(to_dev(x), to_dev(y))
         torch.cuda.synchronize()
         assert abs(cost.cpu().numpy()[0] - J) <= TOL_OP * J
@@ -53,10 +57,35 @@ def test_tile_variants_same_gradient_and_oracle(misr, ctx, L, s, sig):
         yf = to_np(op.forward(to_dev(x)))
         assert rel_l2(yf, oracle.forward(x, prob.shifts, prob.psf, s)) <= TOL_OP
         out[v] = (g.clone(), cost.clone())
-    # the same per-pixel sums; the two instantiations may contract a product
-    # and a sum into one fused multiply-add differently, so FP32 rounding only
-    assert rel_l2(to_np(out[1][0]), to_np(out[0][0])) <= 1e-6
-    assert abs(float(out[0][1][0] - out[1][1][0])) <= 1e-9 * abs(float(out[0][1][0]))
+    # the same per-pixel sums; the instantiations may contract a product and
+    # a sum into one fused multiply-add differently, so FP32 rounding only
+    for v in out:
+        assert rel_l2(to_np(out[v][0]), to_np(out[0][0])) <= 1e-6
+        assert abs(float(out[0][1][0] - out[v][1][0])) <= 1e-9 * abs(float(out[0][1][0]))
+    op.close()
+
+
+def test_wide_trial_tile_solve_matches_oracle(misr, ctx):
+    """Variant 2: the trial pass on its own wider tiles (112 HR columns at
+    s = 2, L = 9, here with a ragged last column) and the update pass on
+    variant 0's; the solve follows the oracle's and variant 0's."""
+    prob = problem(80, 2, 0.8, None, jitter=0.05, n_iter=25, seeds=(6, 7, 8))
+    x_o, tr_o, _ = oscg.solve(_f32(prob.y), prob.shifts, prob.psf, 2, _f32(prob.x0), 25)
+    op = misr.Operator(ctx, prob.H, prob.W, 2, prob.shifts, prob.psf)
+    _, tw0 = op.tile
+    assert op.tile_variant == (0, tw0)
+    op.set_tile(2)
+    v, twt = op.tile_variant
+    assert v == 2 and op.tile == (op.tile[0], tw0) and twt > tw0
+    assert prob.W % twt != 0
+    x = to_dev(_f32(prob.x0))
+    its, _ = op.scg_solve(to_dev(_f32(prob.y)), x, misr.default_params(n_iter=25))
+    assert rel_l2(to_np(x), x_o) <= TOL_SCG
+    assert [t["success"] for t in its] == [t["success"] for t in tr_o]
+    op.set_tile(0)
+    x0v = to_dev(_f32(prob.x0))
+    op.scg_solve(to_dev(_f32(prob.y)), x0v, misr.default_params(n_iter=25), trace=False)
+    assert rel_l2(to_np(x), to_np(x0v)) <= 1e-5
     op.close()
 
 
@@ -76,20 +105,21 @@ def test_autotuner_keeps_a_compiled_shape(misr, ctx):
     import torch
     prob = problem(128, 2, 0.8, None, jitter=0.05, n_iter=10, seeds=(9, 9, 9))
     op = misr.Operator(ctx, prob.H, prob.W, 2, prob.shifts, prob.psf)
-    shapes = []
-    for v in (0, 1):
+    shapes = {}
+    for v in (0, 1, 2):
         op.set_tile(v)
-        shapes.append(op.tile)
+        shapes[v] = (op.tile, op.tile_variant)
     y, x0 = to_dev(_f32(prob.y)), to_dev(_f32(prob.x0))
     before = x0.clone()
     th, tw = op.tune(y, x0, reps=5)
     torch.cuda.synchronize()
-    assert (th, tw) in shapes and op.tile == (th, tw)
+    v, twt = op.tile_variant
+    assert shapes[v] == ((th, tw), (v, twt)) and op.tile == (th, tw)
     assert torch.equal(x0, before)   # the tuner reads x only
     x = x0.clone()
     op.scg_solve(y, x, misr.default_params(n_iter=10), trace=False)
     torch.cuda.synchronize()
     assert torch.isfinite(x).all()
     with pytest.raises(misr.MisrError):
-        op.set_tile(2)
+        op.set_tile(3)
     op.close()
