@@ -73,27 +73,27 @@ def tile_choice(op) -> dict:
     return {"variant": v, "trial": [th, twt], "update": [th, tw]}
 
 
-def profile_value(path: str, tag: str, key: str, src_hash: str):
-    """The value `key` of the `tag:` line of a committed counter summary, if
-    the summary was taken on the current kernel sources; else None."""
+def profile_value(path: str, tag: str, key: str, src_hash: str, variant: int):
+    """The value `key` of the `tag:` line of a committed counter summary taken
+    on the current kernel sources for the trial kernel of tile variant
+    `variant`; else None."""
     if not os.path.exists(path):
         return None
-    vals = {}
     for ln in open(path):
-        if ln.startswith(tag + ":"):
-            for kv in ln.split()[1:]:
-                k, _, v = kv.partition("=")
-                vals[k] = v
-    if vals.get("kernel_source_hash") != src_hash or key not in vals:
-        return None
-    return float(vals[key])
+        if not ln.startswith(tag + ":"):
+            continue
+        vals = dict(kv.partition("=")[::2] for kv in ln.split()[1:])
+        if (vals.get("kernel_source_hash") == src_hash and key in vals
+                and vals.get("variant") == str(variant)):
+            return float(vals[key])
+    return None
 
 
-def traffic_from_profile(src_hash: str):
+def traffic_from_profile(src_hash: str, variant: int):
     """HBM bytes per trial launch (FETCH_SIZE + WRITE_SIZE, scaled by the copy
     calibration) from the committed counter summary, if it was taken on the
-    current kernel sources; else None."""
-    return profile_value(TRAFFIC_SUMMARY, "traffic", "bytes_per_launch", src_hash)
+    current kernel sources and tile variant; else None."""
+    return profile_value(TRAFFIC_SUMMARY, "traffic", "bytes_per_launch", src_hash, variant)
 
 
 def copy_probe(mib: int, reps: int = 3):
@@ -515,8 +515,8 @@ def main():
     bytes_trial = BYTES_TRIAL * H * W
     achieved = bytes_trial / (us_trial * 1e-6) / 1e9
     src_hash = kernel_source_hash()
-    traffic = traffic_from_profile(src_hash)
-    valu_insts = profile_value(SQ_SUMMARY, "valu", "insts_per_launch", src_hash)
+    traffic = traffic_from_profile(src_hash, tile["variant"])
+    valu_insts = profile_value(SQ_SUMMARY, "valu", "insts_per_launch", src_hash, tile["variant"])
 
     # the paper's non-iterative baseline on the same frames: multi-image interpolation
     xi = torch.empty_like(x0)

@@ -35,9 +35,24 @@ def test_profile_values_follow_the_kernel_hash():
     for path, tag, key in ((bench.TRAFFIC_SUMMARY, "traffic", "bytes_per_launch"),
                            (bench.SQ_SUMMARY, "valu", "insts_per_launch")):
         assert os.path.exists(path)
-        assert bench.profile_value(path, tag, key, "0" * 16) is None
-        v = bench.profile_value(path, tag, key, h)
-        assert v is None or (np.isfinite(v) and v > 0)
+        for variant in (0, 1, 2):
+            assert bench.profile_value(path, tag, key, "0" * 16, variant) is None
+            v = bench.profile_value(path, tag, key, h, variant)
+            assert v is None or (np.isfinite(v) and v > 0)
+        assert bench.profile_value(path, tag, key, h, 7) is None
+
+
+def test_profile_value_selects_the_variant(tmp_path):
+    p = tmp_path / "summary.md"
+    p.write_text("text\ntraffic: kernel_source_hash=abc variant=0 bytes_per_launch=10\n"
+                 "traffic: kernel_source_hash=abc variant=2 bytes_per_launch=12\n"
+                 "traffic: kernel_source_hash=old variant=1 bytes_per_launch=99\n")
+    f = bench.profile_value
+    assert f(str(p), "traffic", "bytes_per_launch", "abc", 0) == 10
+    assert f(str(p), "traffic", "bytes_per_launch", "abc", 2) == 12
+    assert f(str(p), "traffic", "bytes_per_launch", "abc", 1) is None
+    assert f(str(p), "traffic", "bytes_per_launch", "old", 1) == 99
+    assert f(str(p), "valu", "bytes_per_launch", "abc", 0) is None
 
 
 def test_main_refuses_more_than_one_gpu(monkeypatch, capsys):
