@@ -159,24 +159,26 @@ __global__ void __launch_bounds__(kNT) k_scalar(const SolveRef *refs, const int 
         const double *pt = (phase == PH_A) ? partials_u : partials;
         const int i0 = (phase == PH_A) ? ref.item0u : ref.item0;
         const int ni = (phase == PH_A) ? ref.nitemsu : ref.nitems;
-        // four items per step, their loads issued before the additions (a
-        // solve may hold thousands of items)
+        // four items per step, all their loads issued before the additions
+        // (a solve may hold thousands of items); past the end an item is
+        // loaded from a valid address and counted as zero, so each thread
+        // adds its items in the same order whatever the count, and in one
+        // memory round trip per 4 x kNT items
         double v[kNV] = {0, 0, 0, 0, 0, 0};
-        int i = i0 + threadIdx.x;
-        for (; i + 3 * kNT < i0 + ni; i += 4 * kNT) {
+        const int end = i0 + ni;
+        for (int i = i0 + threadIdx.x; i < end; i += 4 * kNT) {
             double t[4][kNV];
 #pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int j = (i + a * kNT < end) ? i + a * kNT : i;
+#pragma unroll
+                for (int q = 0; q < kNV; ++q) t[a][q] = pt[(long long)j * kNV + q];
+            }
+#pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int q = 0; q < kNV; ++q) t[a][q] = pt[(long long)(i + a * kNT) * kNV + q];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int q = 0; q < kNV; ++q) v[q] += t[a][q];
+                for (int q = 0; q < kNV; ++q) v[q] += (i + a * kNT < end) ? t[a][q] : 0.0;
         }
-        for (; i < i0 + ni; i += kNT)
-#pragma unroll
-            for (int q = 0; q < kNV; ++q) v[q] += pt[(long long)i * kNV + q];
         // the sums are used only where the phase needs them (scg_phase_a
         // reads them after an accepted pass only)
         block_sum_store<kNV, kNT>(v, tot, red);   // its barriers also publish sst
