@@ -177,6 +177,30 @@ def test_batch_equals_solo_and_oracle(misr, ctx):
         assert rel_l2(to_np(xs[i]), x_o) <= TOL_SCG
 
 
+def test_batch_mixing_tile_variants(misr, ctx):
+    """Operators on different tile variants (0, the narrow 1, and 2 with its
+    wider trial tiles) in one batch: one launch per (scale, band, variant)
+    class, and every projection equals its solo solve bit for bit."""
+    import torch
+    specs = [(56, 2, 0.8, 20, 2), (40, 2, 0.8, 15, 1), (48, 2, 0.8, 20, 0), (30, 3, 1.0, 15, 1)]
+    probs = [problem(L, s, sig, None, jitter=0.05, n_iter=n, seeds=(i + 3, i + 5, i + 8))
+             for i, (L, s, sig, n, _) in enumerate(specs)]
+    ops = [misr.Operator(ctx, p.H, p.W, p.s, p.shifts, p.psf) for p in probs]
+    for op, sp in zip(ops, specs):
+        op.set_tile(sp[4])
+    ys = [to_dev(_f32(p.y)) for p in probs]
+    xs = [to_dev(_f32(p.x0)) for p in probs]
+    prms = [misr.default_params(n_iter=sp[3]) for sp in specs]
+    misr.scg_solve_batch(ops, ys, xs, prms, trace=False)
+    for i, p in enumerate(probs):
+        xsolo = to_dev(_f32(p.x0))
+        ops[i].scg_solve(ys[i], xsolo, misr.default_params(n_iter=specs[i][3]), trace=False)
+        torch.cuda.synchronize()
+        assert torch.equal(xsolo, xs[i]), f"projection {i} (variant {specs[i][4]}) differs"
+    for op in ops:
+        op.close()
+
+
 def test_repeat_solves_deterministic(misr, ctx):
     import torch
     prob = problem(64, 2, 0.8, None, jitter=0.05, n_iter=20, seeds=(9, 9, 9))

@@ -79,3 +79,29 @@ def test_halo_below_reach_rejected(misr, ctx):
     with pytest.raises(misr.MisrError) as ei:
         op.scg_solve(y, x, misr.default_params(n_iter=2, tile_lr=16, halo_lr=3))   # 6 HR px < 8
     assert ei.value.status == misr.E_INVAL
+
+
+@pytest.mark.parametrize("L,Lw,s,tile,halo", [c for c in CASES if c[2] == 2])
+def test_tiled_equals_untiled_on_wide_trial_tiles(misr, ctx, L, Lw, s, tile, halo):
+    """Tile variant 2 (the trial pass on its own wider tiles, the update pass
+    on variant 0's): the tiled layout builds its trial work list with the
+    trial width, and still equals the untiled solve."""
+    import torch
+    prob = problem(L, s, 0.8, None, jitter=0.05, n_iter=20, seeds=(7, 8, 9), Lw=Lw)
+    op = misr.Operator(ctx, prob.H, prob.W, s, prob.shifts, prob.psf)
+    op.set_tile(2)
+    assert op.tile_variant[1] > op.tile[1]
+    x, y = to_dev(_f32(prob.x0)), to_dev(_f32(prob.y))
+    c0, g0 = op.cost_grad(x, y, misr.default_params())
+    c1, g1 = op.cost_grad(x, y, misr.default_params(tile_lr=tile, halo_lr=halo))
+    torch.cuda.synchronize()
+    assert torch.equal(g0, g1)
+    assert abs(c1.cpu().numpy()[0] - c0.cpu().numpy()[0]) <= 1e-12 * abs(c0.cpu().numpy()[0])
+    xa, xb = to_dev(_f32(prob.x0)), to_dev(_f32(prob.x0))
+    ta, _ = op.scg_solve(y, xa, misr.default_params(n_iter=20))
+    tb, _ = op.scg_solve(y, xb, misr.default_params(n_iter=20, tile_lr=tile, halo_lr=halo))
+    assert [t["success"] for t in ta] == [t["success"] for t in tb]
+    assert rel_l2(to_np(xb), to_np(xa)) <= 1e-5
+    J, g_ref, _ = oracle.cost_grad(_f32(prob.x0), _f32(prob.y), prob.shifts, prob.psf, s)
+    assert rel_l2(to_np(g1), g_ref) <= TOL_OP
+    op.close()
