@@ -206,8 +206,9 @@ misr_status misr_op_sparse_width(const misr_op *op, int32_t *a_w, int32_t *t_w);
  * `reps` launches each with HIP events, and keeps the fastest for every
  * later call on this operator (solves, batches, operators).  *tile_h x
  * *tile_w: the chosen tile in HR pixels.  A general operator has no tiles
- * (both 0).  Synchronises with `stream`.  Results do not depend on the tile
- * shape except for the summation order of the cost and inner products. */
+ * (both 0).  Synchronises with `stream`.  On an error the operator keeps the
+ * variant it had.  Results do not depend on the tile shape except for the
+ * summation order of the cost and inner products. */
 misr_status misr_op_tune(misr_op *op, const misr_params *params, const void *y, void *x,
                          int reps, int32_t *tile_h, int32_t *tile_w, void *stream);
 /* The operator's current tile shape of the update pass and the operators

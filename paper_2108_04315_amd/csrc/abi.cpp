@@ -1248,6 +1248,7 @@ extern "C" misr_status misr_op_tune(misr_op *op, const misr_params *prm, const v
     std::lock_guard<std::mutex> lc(op->ctx->mu);
     MISR_HIP(set_device(op->ctx->dev));
     if (!op->general) {
+        const int prev = op->tv;   // kept if a timing run fails
         double best = 0.0;
         int best_tv = 0;
         for (int tv = 0; tv < 3; ++tv) {
@@ -1256,7 +1257,7 @@ extern "C" misr_status misr_op_tune(misr_op *op, const misr_params *prm, const v
             double t_trial = 0.0, t_upd = 0.0;
             if ((st = time_pass_impl(op, prm, y, x, 0, reps, &t_trial, stream)) != MISR_OK ||
                 (st = time_pass_impl(op, prm, y, x, 1, reps, &t_upd, stream)) != MISR_OK) {
-                set_tile_variant(op, 0);
+                set_tile_variant(op, prev);
                 return st;
             }
             if (tv == 0 || t_trial + t_upd < best) {
