@@ -197,7 +197,8 @@ int misr_op_band(const misr_op *op);
  * operator.  MISR_E_INVAL on NULL arguments. */
 misr_status misr_op_sparse_width(const misr_op *op, int32_t *a_w, int32_t *t_w);
 
-/* Tile autotuner: times the trial and update passes of every compiled tile
+/* Tile autotuner: times the trial and update passes (alternating, as in a
+ * solve) of every compiled tile
  * variant of this banded operator (0: the widest tile that fits both passes;
  * 1: one about half as wide, which gives small images more workgroups; 2,
  * where it exists: variant 0 with a wider trial-pass tile, the widest the
@@ -278,8 +279,9 @@ misr_status misr_scg_solve_batch(int n, const misr_op *const *ops,
 /* Measurement aid: times one image pass of the solve in isolation.  Prepares
  * the state of misr_scg_solve(op, params, y, x) up to the first trial point,
  * then launches pass `which` (0: fused cost+gradient at x + alpha p,
- * 1: update + curvature) `reps` times on the library stream between two HIP
- * events and returns the mean duration in microseconds in *avg_us (host).
+ * 1: update + curvature, 2: the two in turn, as in a solve) `reps` times on
+ * the library stream between two HIP events and returns the mean duration
+ * in microseconds in *avg_us (host; for 2, of one trial + update pair).
  * Both passes are idempotent at a fixed state, so repeated launches do the
  * work of one pass each.  x is left unchanged.  Synchronises the stream. */
 misr_status misr_time_pass(const misr_op *op, const misr_params *params, const void *y,

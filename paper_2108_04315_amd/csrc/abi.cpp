@@ -1197,10 +1197,16 @@ static misr_status time_pass_impl(misr_op *op, const misr_params *prm, const voi
     hipEvent_t e0, e1;
     MISR_HIP(hipEventCreate(&e0));
     MISR_HIP(hipEventCreate(&e1));
-    const int kind = which == 0 ? KIND_TRIAL : KIND_UPCURV;
-    hipError_t e = Lr.image(kind);   // warm-up launch
+    // which 2: a trial pass and then an update pass, as they follow each
+    // other in a solve (the update writes the x and p the trial reads)
+    auto pass = [&]() {
+        hipError_t e1 = Lr.image(which == 1 ? KIND_UPCURV : KIND_TRIAL);
+        if (e1 == hipSuccess && which == 2) e1 = Lr.image(KIND_UPCURV);
+        return e1;
+    };
+    hipError_t e = pass();   // warm-up launch
     if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = Lr.image(kind);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = pass();
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -1216,7 +1222,7 @@ extern "C" misr_status misr_time_pass(const misr_op *cop, const misr_params *prm
                                       void *x, int which, int reps, double *avg_us,
                                       void *stream) {
     misr_op *op = const_cast<misr_op *>(cop);
-    if (!op || !y || !x || !avg_us || reps < 1 || (which != 0 && which != 1))
+    if (!op || !y || !x || !avg_us || reps < 1 || which < 0 || which > 2)
         return set_error(MISR_E_INVAL, "bad arguments");
     misr_status st = misr_params_check(prm);
     if (st != MISR_OK) return st;
@@ -1254,14 +1260,16 @@ extern "C" misr_status misr_op_tune(misr_op *op, const misr_params *prm, const v
         for (int tv = 0; tv < 3; ++tv) {
             if (tile_hr(op->s, op->Lp | (tv << 8)) <= 0) continue;
             set_tile_variant(op, tv);
-            double t_trial = 0.0, t_upd = 0.0;
-            if ((st = time_pass_impl(op, prm, y, x, 0, reps, &t_trial, stream)) != MISR_OK ||
-                (st = time_pass_impl(op, prm, y, x, 1, reps, &t_upd, stream)) != MISR_OK) {
+            // the two passes alternating, as in a solve: a trial tile that
+            // lines up with the update tiles finds the update's output in its
+            // XCD's L2, which timing each pass alone would not show
+            double t_pair = 0.0;
+            if ((st = time_pass_impl(op, prm, y, x, 2, reps, &t_pair, stream)) != MISR_OK) {
                 set_tile_variant(op, prev);
                 return st;
             }
-            if (tv == 0 || t_trial + t_upd < best) {
-                best = t_trial + t_upd;
+            if (tv == 0 || t_pair < best) {
+                best = t_pair;
                 best_tv = tv;
             }
         }

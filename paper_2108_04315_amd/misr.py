@@ -359,8 +359,9 @@ class Operator:
 
     def time_pass(self, y, x, which: int, reps: int = 20, params: misr_params | None = None,
                   stream=None) -> float:
-        """Mean duration (us) of one image pass (0: trial, 1: update) at the
-        solve's first trial point, timed with HIP events."""
+        """Mean duration (us) of one image pass (0: trial, 1: update; 2: one
+        trial + update pair, as in a solve) at the solve's first trial point,
+        timed with HIP events."""
         p = params or default_params()
         p.img_dtype = dtype_code(x)
         out = C.c_double()
