@@ -2,7 +2,7 @@
  * misr.h -- C ABI of libmisr.so: the SCG cost/gradient hot path of multi-image
  * super-resolution (FL-MISR, arXiv 2108.04315) on one AMD MI355X (gfx950).
  *
- * Problem statement (Sec. 2.1): K low-resolution frames y_k, each the image of
+ * Problem statement (Sec. 3.1): K low-resolution frames y_k, each the image of
  * the unknown high-resolution image x under a known system matrix
  * A_k = D B M_k (Eq. sisr: M_k motion, B blur, D decimation), plus noise.
  * x minimises (Eq. objective, split as in Eq. reformulated)
@@ -11,7 +11,7 @@
  *
  * with the bilateral total variation prior of Eq. prior, gamma(d) = alpha^(dx+dy),
  * d in [0, w-1]^2 minus the origin.  The minimiser is found with the scaled
- * conjugate gradient method the paper uses (Sec. 2.1, Algorithm 1; Moller 1993)
+ * conjugate gradient method the paper uses (Sec. 3.1, Algorithm 1; Moller 1993)
  * for a fixed number of passes (Algorithm 1's loop bound).
  *
  * Readings fixed by this library where the paper is silent:
@@ -71,7 +71,7 @@ typedef struct misr_ctx misr_ctx;
 typedef struct misr_op misr_op;
 typedef struct misr_server misr_server;
 
-/* Acquisition geometry (Sec. 2.1 Eq. sisr; Sec. 2.2: frames shifted by a
+/* Acquisition geometry (Sec. 3.1 Eq. sisr; Sec. 3.2: frames shifted by a
  * fraction of a detector pixel).  All pointers are host memory, read during
  * misr_op_create only. */
 typedef struct {
@@ -138,7 +138,7 @@ typedef struct {
     int32_t y_u16;       /* 0: y stored in img_dtype (default); 1: y holds the
                             detector's uint16 counts and frame values are
                             y_scale * count (the paper's 16-bit input images,
-                            Sec. 3); cost/gradient, solves and served requests */
+                            Sec. 4); cost/gradient, solves and served requests */
     double y_scale;      /* > 0 with y_u16 = 1 */
 } misr_params;
 
@@ -186,7 +186,7 @@ misr_status misr_ctx_destroy(misr_ctx *ctx);
 /* Precomputes the operator: per frame, the 1-D band weights of A_k's row and
  * column factors (A_k = C_y,k (x) C_x,k is exact because M, B and D are all
  * separable, zero padding included).  Built once and reused by every call on
- * this geometry, as the paper builds A_i once per acquisition (Sec. 2.2). */
+ * this geometry, as the paper builds A_i once per acquisition (Sec. 3.2). */
 misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, misr_op **out);
 misr_status misr_op_destroy(misr_op *op);
 /* Band length L of the per-frame 1-D factors (taps per LR pixel per axis);
@@ -236,7 +236,7 @@ misr_status misr_adjoint(const misr_op *op, misr_dtype dt, const void *r, float 
                          void *stream);
 
 /* Multi-image interpolation, the paper's non-iterative fusion baseline
- * (Sec. 3: LR pixel values inserted at their integer HR positions).  Frame
+ * (Sec. 4: LR pixel values inserted at their integer HR positions).  Frame
  * k's pixel (i, j) is written to HR (s i + ty_k, s j + tx_k) with
  * t_k = round(s d_k) (halves away from zero); an HR pixel that receives
  * several samples takes their mean (frame order), one that receives none
@@ -288,7 +288,7 @@ misr_status misr_time_pass(const misr_op *op, const misr_params *params, const v
                            void *x, int which, int reps, double *avg_us, void *stream);
 
 /* ------------------------------------------------------------------ serving */
-/* On-the-fly acquisition (Sec. 2.2): each rotation angle's frames arrive as a
+/* On-the-fly acquisition (Sec. 3.2): each rotation angle's frames arrive as a
  * request; requests are admitted while device memory allows and solved
  * together, each pass of every admitted solve in the same launches. */
 typedef enum {

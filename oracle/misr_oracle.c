@@ -8,7 +8,7 @@
  *
  * Every operator is the plain 2-D definition written out, in double precision,
  * on an H x W high-resolution grid with zero outside the grid:
- *   - observation model y_k = D B M_k x                   (Sec. 2.1, Eq. sisr)
+ *   - observation model y_k = D B M_k x                   (Sec. 3.1, Eq. sisr)
  *   - data term sum_k ||A_k x - y_k||_p^p, p in {1, 2}    (Eq. l2misr, Eq. misr)
  *   - BTV prior sum_d alpha^(dx+dy) ||x - S_d x||_1       (Eq. prior)
  *   - objective J = data + lambda * prior                 (Eq. objective)
@@ -384,7 +384,7 @@ double orc_curv_data_l1(int H, int W, int s, int K, const double *shifts, int P,
 }
 
 /* Multi-image interpolation, the paper's non-iterative fusion baseline
- * (Sec. 3: LR pixel values inserted at their integer HR positions).  Frame
+ * (Sec. 4: LR pixel values inserted at their integer HR positions).  Frame
  * k's pixel (i, j) lands on HR (s i + ty_k, s j + tx_k), t_k = round(s d_k)
  * (halves away from zero); an HR pixel takes the mean of the samples landing
  * on it, in frame order; one that receives none takes frame 0's pixel

@@ -12,7 +12,7 @@
 //                     pass 4 along rows    (LR cols -> HR cols)
 //
 // A_k = C_y,k (x) C_x,k holds exactly because the warp, the PSF and the
-// binning of the observation model (Sec. 2.1, Eq. sisr) are all separable,
+// binning of the observation model (Sec. 3.1, Eq. sisr) are all separable,
 // zero padding included, so each 2-D operator becomes two 1-D banded ones.
 // Band weights are read per LR row/column from the operator's tables with
 // wave-uniform (scalar) loads: every pass maps one weight row to one wave.

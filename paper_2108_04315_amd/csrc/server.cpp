@@ -1,7 +1,7 @@
 // server.cpp -- continuous-batching serving of SR solves (misr_server_*).
 //
 // The paper super-resolves each rotation angle's frames as soon as they are
-// captured, reusing the system matrices built once per acquisition (Sec. 2.2).
+// captured, reusing the system matrices built once per acquisition (Sec. 3.2).
 // Here every request is one such solve.  A scheduler thread admits queued
 // requests while device memory (a byte budget) and slots allow, keeps each
 // admitted solve's SCG state resident on the device, and advances all admitted

@@ -6,9 +6,9 @@ taps, additive noise and the bicubic initial guess.  It holds none of the
 observation model or the SCG arithmetic: clean low-resolution frames are made
 by a forward operator that the caller passes in (``forward_fn``).
 
-Workload shapes follow the paper's experiments (Sec. 3 and Table "runtime"):
+Workload shapes follow the paper's experiments (Sec. 4 and Table "runtime"):
 x2 upscaling from 4 frames shifted by half a detector pixel (the detector moves
-right, down, left, up; Sec. 2.2 "Real-Time MISR for CT"), x3 with 9 frames on a
+right, down, left, up; Sec. 3.2 "Real-Time MISR for CT"), x3 with 9 frames on a
 1/3-pixel grid (Table "natural"), piecewise-constant disks and bar patterns
 standing in for the aluminium cylinder and QRM bar phantoms, which are not
 available here.

@@ -1,5 +1,5 @@
 """Start points on the device (through the C ABI) against the oracle: the
-paper's multi-image interpolation (Sec. 3 fusion baseline) and the bicubic
+paper's multi-image interpolation (Sec. 4 fusion baseline) and the bicubic
 upsampling of frame 0; solves and served requests that compute their start
 point on the device."""
 import numpy as np

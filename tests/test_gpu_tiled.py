@@ -1,5 +1,5 @@
 """Tiles held separately in HBM with a halo exchanged on the device every pass:
-the one-GPU form of the paper's inner-outer border exchange (Sec. 2.1), whose
+the one-GPU form of the paper's inner-outer border exchange (Sec. 3.1), whose
 invariants are that the tile objectives sum to the global one and that the
 tiled result equals the untiled one (no seams)."""
 import numpy as np

@@ -23,7 +23,7 @@ def _built():
 
 
 # --------------------------------------------------------------------------
-# independent library pipeline for A_k = D B M_k (Sec. 2.1, Eq. sisr)
+# independent library pipeline for A_k = D B M_k (Sec. 3.1, Eq. sisr)
 def lib_warp(x, tx, ty):
     H, W = x.shape
     uu, vv = np.meshgrid(np.arange(H, dtype=float), np.arange(W, dtype=float), indexing="ij")
@@ -67,7 +67,7 @@ CASES = [
 
 @pytest.mark.parametrize("H,W,s,shifts,sig,P", CASES)
 def test_forward_matches_library_pipeline(H, W, s, shifts, sig, P):
-    """Sec. 2.1 Eq. sisr: A_k = D B M_k with bilinear M, P x P Gaussian B, s x s mean D."""
+    """Sec. 3.1 Eq. sisr: A_k = D B M_k with bilinear M, P x P Gaussian B, s x s mean D."""
     rng = np.random.default_rng(0)
     shifts = np.array(shifts)
     psf = synth.psf_taps(sig, P)
@@ -167,7 +167,7 @@ def test_zero_data_cost_at_ground_truth_noiseless():
 # BTV prior (Eq. prior) with the paper's gamma(d) = alpha^(dx+dy)
 def test_gamma_table_golden():
     """tests/golden/btv_gamma.txt: gamma(d) = alpha^(dx+dy), alpha = 0.4, w = 3 (Eq. prior;
-    alpha = 0.4 is the paper's setting in Sec. 3)."""
+    alpha = 0.4 is the paper's setting in Sec. 4)."""
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "btv_gamma.txt")
     rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
@@ -336,7 +336,7 @@ def test_psi_quotient_stable_form():
 
 
 # --------------------------------------------------------------------------
-# SCG (Moller 1993, cited for the solver in Sec. 2.1; loop of Algorithm 1)
+# SCG (Moller 1993, cited for the solver in Sec. 3.1; loop of Algorithm 1)
 def test_moller_scale_delta_rules():
     # positive delta: only the lam shift
     d, l, lb = oscg.moller_scale_delta(2.0, 0.5, 0.0, 4.0)
@@ -537,7 +537,7 @@ def test_l1_data_curvature_closed_form():
 
 @pytest.mark.parametrize("s,jitter", [(2, 0.0), (2, 0.05), (3, 0.04)])
 def test_interpolation_inverts_grid_sampling(s, jitter):
-    """Multi-image interpolation (Sec. 3): frames that sample an HR image at
+    """Multi-image interpolation (Sec. 4): frames that sample an HR image at
     every integer offset of the s x s grid are put back together exactly,
     whatever jitter below half an HR pixel does to the shifts."""
     rng = np.random.default_rng(20 + s)
