@@ -261,10 +261,23 @@ misr_status misr_cost_grad(const misr_op *op, const misr_params *params, const v
 /* SCG solve (Algorithm 1 on one GPU): params->n_iter passes from x_inout,
  * result written back to x_inout (device, params->img_dtype).  y: device.
  * trace (host, nullable): when given, the call synchronises the stream and
- * fills it.  Returns MISR_E_NUMERIC (only when trace is given) if the solve
- * stopped on a non-finite value; x_inout then holds the last finite iterate. */
+ * fills it.  Returns MISR_E_NUMERIC (only when trace is given; without a trace,
+ * misr_scg_status reports it) if the solve stopped on a non-finite value;
+ * x_inout then holds the last finite iterate. */
 misr_status misr_scg_solve(const misr_op *op, const misr_params *params, const void *y,
                            void *x_inout, misr_scg_trace *trace, void *stream);
+
+/* Outcome of the last misr_scg_solve on this operator, for callers that pass
+ * no trace: Algorithm 1's output is the last iterate, and this library stops a
+ * solve whose cost or curvature turns non-finite (keeping the last finite
+ * iterate).  Waits for that solve: synchronises `stream`, which must be the
+ * solve's stream or a stream ordered after it.  Fills summary's counters
+ * (n_passes, n_success, stop, E0, E_final; summary->iters is not touched) when
+ * summary is not NULL.  Returns MISR_E_NUMERIC if that solve stopped on a
+ * non-finite value (stop = 2), MISR_OK otherwise; MISR_E_INVAL if no solve has
+ * run on the operator.  misr_cost_grad, misr_forward and the other calls on
+ * the operator do not change what it reports. */
+misr_status misr_scg_status(const misr_op *op, misr_scg_trace *summary, void *stream);
 
 /* n independent solves advanced together: every SCG pass of every projection
  * runs in the same kernel launches (one work list over all projections' tiles).
@@ -324,7 +337,25 @@ typedef struct {
                                  pixels (a request is always admitted when none
                                  runs), so small requests are batched to fill the
                                  device and large ones keep first-come order */
+    int32_t fail_list_n;      /* fault hook: the n-th work-list allocation fails
+                                 (0 off); every request of that cycle then fails
+                                 with MISR_E_NOMEM and none of its kernels runs */
+    int32_t max_idle_ops;     /* operators kept cached after their last request
+                                 finished, least recently used evicted first
+                                 (0: 8); idle operators are also evicted when
+                                 admission needs their memory */
 } misr_server_config;
+
+/* Occupancy of a server (misr_server_query). */
+typedef struct {
+    int32_t queued;           /* requests waiting for admission */
+    int32_t running;          /* requests admitted and not yet retired */
+    int32_t n_ops;            /* cached operators (one per distinct geometry) */
+    int32_t n_idle_ops;       /* of those, operators no admitted request uses */
+    size_t used_bytes;        /* device bytes charged against hbm_budget_bytes:
+                                 the admitted requests' buffers and work-list
+                                 share, and the cached operators' tables */
+} misr_server_info;
 
 typedef struct {
     double t_submit_us, t_admit_us, t_done_us;  /* host steady clock */
@@ -343,6 +374,8 @@ misr_status misr_server_poll(misr_server *s, uint64_t id, misr_req_state *state,
 /* Blocks until the request leaves QUEUED/RUNNING or timeout_us passes (<0: forever). */
 misr_status misr_server_wait(misr_server *s, uint64_t id, int64_t timeout_us);
 misr_status misr_server_cancel(misr_server *s, uint64_t id);
+/* Current occupancy (host-side counters; no device call). */
+misr_status misr_server_query(misr_server *s, misr_server_info *out);
 /* Drains every submitted request, then frees the server. */
 misr_status misr_server_destroy(misr_server *s);
 

@@ -98,7 +98,7 @@ extern "C" void misr_params_default(misr_params *p) {
     p->halo_lr = 8;
 }
 
-static int band_length(const misr_geometry *g) {
+int misr::band_length(const misr_geometry *g) {
     bool frac = false;
     for (int k = 0; k < g->n_frames; ++k)
         for (int a = 0; a < 2; ++a) {
@@ -802,12 +802,20 @@ static void build_plan(Plan &pl, const std::vector<SolveIn> &in) {
     pl.finish_counts();
 }
 
+// Everything a captured solve bakes in as launch arguments: pass count,
+// storage codes, start-point kernels (kind, buffers, storage and grid with
+// the frames' integer offsets), counts and class ranges.
 static std::string plan_key(const Plan &pl, int n_iter) {
-    std::string k = std::to_string(n_iter) + "/" + std::to_string(pl.code()) + "/i";
+    std::string k = std::to_string(n_iter) + "/" + std::to_string(pl.code()) + "," +
+                    std::to_string(pl.gt) + "/i";
     for (auto &it : pl.inits) {
-        char b[64];
-        snprintf(b, sizeof b, "%d,%p,%p;", it.kind, it.y, it.x);
+        char b[96];
+        snprintf(b, sizeof b, "%d,%p,%p,%d,%d,%d,%d,%d", it.kind, it.y, it.x, it.st, it.a.H,
+                 it.a.W, it.a.s, it.a.K);
         k += b;
+        for (int f = 0; f < it.a.K; ++f)
+            k += "," + std::to_string(it.a.ty[f]) + "," + std::to_string(it.a.tx[f]);
+        k += ";";
     }
     k += "/" +
                      std::to_string(pl.states.size()) + "/" + std::to_string(pl.projs.size()) +
@@ -1105,8 +1113,37 @@ extern "C" misr_status misr_scg_solve(const misr_op *cop, const misr_params *prm
     hipStream_t s = (hipStream_t)stream;
     st = run_plan(op->ctx, pl, op->pdev, prm->n_iter, s);
     if (st != MISR_OK) return st;
+    // the final state, kept for misr_scg_status (later calls on the op reuse
+    // the plan's state buffer)
+    MISR_HIP(op->last_state.ensure(sizeof(ScgState)));
+    MISR_HIP(hipMemcpyAsync(op->last_state.p, op->pdev.states.p, sizeof(ScgState),
+                            hipMemcpyDeviceToDevice, s));
+    op->have_last = true;
     if (trace) return fetch_trace(op->pdev, 0, trace, s);
     return MISR_OK;
+}
+
+extern "C" misr_status misr_scg_status(const misr_op *cop, misr_scg_trace *summary,
+                                       void *stream) {
+    misr_op *op = const_cast<misr_op *>(cop);
+    if (!op) return set_error(MISR_E_INVAL, "op is NULL");
+    std::lock_guard<std::mutex> lk(op->mu);
+    if (!op->have_last) return set_error(MISR_E_INVAL, "no solve has run on this operator");
+    MISR_HIP(set_device(op->ctx->dev));
+    hipStream_t s = (hipStream_t)stream;
+    ScgState st;
+    MISR_HIP(hipMemcpyAsync(&st, op->last_state.p, sizeof st, hipMemcpyDeviceToHost, s));
+    MISR_HIP(hipStreamSynchronize(s));
+    if (summary) {
+        summary->n_passes = st.it;
+        summary->n_success = st.n_success;
+        summary->stop = st.stop;
+        summary->E0 = st.E0;
+        summary->E_final = st.E;
+    }
+    return st.stop == 2 ? set_error(MISR_E_NUMERIC, "non-finite cost or curvature at pass %d",
+                                    st.it)
+                        : MISR_OK;
 }
 
 namespace {

@@ -275,6 +275,9 @@ struct misr_op {
     misr::DevMem a_col, a_val, t_col, t_val;
     misr::OpDev host;
     std::mutex mu;
+    // final SCG state of the last misr_scg_solve (read by misr_scg_status)
+    misr::DevMem last_state;
+    bool have_last = false;
     // cached workspace of the single-image entry points
     misr::SolveBufs bufs;
     misr::TileSet tiles;
@@ -286,6 +289,9 @@ namespace misr {
 
 // SCG state of a new solve from its parameters (N = HR pixels).
 void init_state(ScgState &s, const misr_params &p, long long N);
+// Band length L of a translational geometry's 1-D factors (before rounding
+// up to a compiled length).
+int band_length(const misr_geometry *g);
 
 
 // Tile grid of a tiled solve: tile t = (a, b) owns HR rows [a T, (a+1) T) and

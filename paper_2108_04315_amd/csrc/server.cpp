@@ -41,10 +41,22 @@ struct OpKey {
     }
 };
 
+// A cached operator: the requests admitted on it hold references; with none
+// it is idle and may be evicted (least recently used first).
+struct OpEnt {
+    misr_op *op = nullptr;
+    int refs = 0;
+    size_t bytes = 0;        // device bytes of its tables, charged to admission
+    uint64_t last_use = 0;
+};
+
 struct SReq {
     uint64_t id = 0;
     misr_request req{};
     std::vector<double> shifts, psf, psf_frames, warps, psf_2d;   // geometry copies
+    OpKey key;            // its operator's cache key
+    OpEnt *ope = nullptr; // the cache entry it holds a reference on (admitted only)
+    size_t op_bytes = 0;  // estimate of its operator's tables, if not cached
     misr_req_state state = MISR_REQ_QUEUED;
     misr_req_stats stats{};
     bool cancel = false;
@@ -110,7 +122,10 @@ struct misr_server {
     std::vector<SReq *> active;   // scheduler thread only
     size_t used = 0;
     int alloc_count = 0;
-    std::map<OpKey, misr_op *> ops;
+    int list_count = 0;           // work-list builds (fault hook fail_list_n)
+    std::map<OpKey, OpEnt> ops;   // guarded by mu
+    uint64_t use_clock = 0;
+    int n_idle = 0;
     // work list of all active solves; per class, the running solves' items
     // come first and the newly admitted ones' after, so that the init passes
     // of the new solves run over a sub-range of each class.
@@ -158,7 +173,11 @@ struct misr_server {
     void retire(Cycle &C);
     bool setup(SReq *r);
     void release(SReq *r);
-    void build_list(List &L, const std::vector<SReq *> &rs);
+    hipError_t build_list(List &L, const std::vector<SReq *> &rs);
+    // idle operators evicted (caller holds mu) until at most keep remain idle
+    // and, if need > 0, until used + need fits the budget
+    void evict_idle(int keep, size_t need);
+    int max_idle() const { return cfg.max_idle_ops > 0 ? cfg.max_idle_ops : 8; }
     hipError_t enqueue_init(List &L);
     hipError_t enqueue_image(List &L, int kind, bool fresh);
     hipError_t enqueue_scalar(List &L, int phase, bool fresh);
@@ -197,6 +216,84 @@ static size_t request_bytes(const misr_request &q, long long n, size_t es, int K
     return b;
 }
 
+// Device bytes of a request's share of the work lists: its trial and update
+// items (an Item and kNV FP64 partial sums each), views and halo copies, in
+// each of the two alternating cycles' lists.  Server operators keep tile
+// variant 0.
+static size_t list_bytes(const misr_request &q, bool general) {
+    const int H = q.geom.hr_h, W = q.geom.hr_w, s = q.geom.scale, K = q.geom.n_frames;
+    long long ni = 0, nu = 0, nviews = 1, nhalo = 0;
+    auto cd = [](long long a, long long b) { return (a + b - 1) / b; };
+    if (general) {
+        ni = nu = cd((long long)K * (H / s) * (W / s), kGenRows) + cd((long long)H * W, kGenRows);
+    } else {
+        const int Lp = padded_band(s, band_length(&q.geom));
+        const int TH = tile_hr(s, Lp), TW = tile_wr(s, Lp), TWt = tile_wt(s, Lp);
+        if (TH <= 0 || TW <= 0 || TWt <= 0) return 0;   // rejected at op creation
+        if (q.params.tile_lr <= 0) {
+            ni = cd(H, TH) * cd(W, TWt);
+            nu = cd(H, TH) * cd(W, TW);
+        } else {
+            const int T = q.params.tile_lr * s, Hh = q.params.halo_lr * s;
+            nviews = 0;
+            for (int a = 0; a * T < H; ++a)
+                for (int c = 0; c * T < W; ++c) {
+                    const int R0 = a * T, R1 = std::min(H, R0 + T), C0 = c * T,
+                              C1 = std::min(W, C0 + T);
+                    const int hb = std::min(H, R1 + Hh) - std::max(0, R0 - Hh);
+                    const int wb = std::min(W, C1 + Hh) - std::max(0, C0 - Hh);
+                    ni += cd(R1 - R0, TH) * cd(C1 - C0, TWt);
+                    nu += cd(hb, TH) * cd(wb, TW);
+                    ++nviews;
+                }
+            nhalo = 8 * nviews;
+        }
+    }
+    const size_t per = (size_t)(ni + nu) * (sizeof(Item) + kNV * sizeof(double)) +
+                       (size_t)nviews * sizeof(Proj) + (size_t)nhalo * 2 * sizeof(HaloCopy) +
+                       2 * sizeof(SolveRef);
+    return 2 * per;
+}
+
+// Device bytes of an operator's tables before it is built: the banded
+// factors' weight rows, or the sparse A and A^T of a general geometry (at most
+// (P + s + 2)^2 entries of 8 B per LR pixel and frame, each way).
+static size_t op_bytes_estimate(const misr_geometry &g, bool general) {
+    const long long h = g.hr_h / g.scale, w = g.hr_w / g.scale;
+    if (general) {
+        const long long e = (long long)(g.psf_size + g.scale + 2) * (g.psf_size + g.scale + 2);
+        return (size_t)(2 * 8 * e * g.n_frames * h * w) + sizeof(OpDev);
+    }
+    const int Lp = padded_band(g.scale, band_length(&g));
+    return (size_t)g.n_frames * (size_t)(h + w + 4 * kPadRows) * (size_t)std::max(Lp, 1) * 4 +
+           sizeof(OpDev);
+}
+
+// Device bytes an operator holds.
+static size_t op_bytes(const misr_op *op) {
+    return op->wy.n + op->wx.n + op->opdev.n + op->a_col.n + op->a_val.n + op->t_col.n +
+           op->t_val.n;
+}
+
+void misr_server::evict_idle(int keep, size_t need) {
+    for (;;) {
+        if (n_idle == 0) return;
+        const bool over = n_idle > keep;
+        const bool short_mem = need > 0 && used + need > cfg.hbm_budget_bytes;
+        if (!over && !short_mem) return;
+        auto lru = ops.end();
+        for (auto it = ops.begin(); it != ops.end(); ++it)
+            if (it->second.refs == 0 && (lru == ops.end() || it->second.last_use <
+                                                                lru->second.last_use))
+                lru = it;
+        if (lru == ops.end()) return;
+        used -= std::min(used, lru->second.bytes);
+        (void)misr_op_destroy(lru->second.op);
+        ops.erase(lru);
+        --n_idle;
+    }
+}
+
 bool misr_server::setup(SReq *r) {
     const misr_request &q = r->req;
     if (cfg.fail_alloc_n > 0 && ++alloc_count == cfg.fail_alloc_n) return false;
@@ -206,15 +303,27 @@ bool misr_server::setup(SReq *r) {
     g.psf_frames = r->psf_frames.empty() ? nullptr : r->psf_frames.data();
     g.warps = r->warps.empty() ? nullptr : r->warps.data();
     g.psf_2d = r->psf_2d.empty() ? nullptr : r->psf_2d.data();
-    OpKey key{g.hr_h, g.hr_w, g.scale, g.n_frames, g.psf_size, r->shifts, r->psf, r->psf_frames,
-              r->warps, r->psf_2d};
-    auto it = ops.find(key);
-    if (it == ops.end()) {
-        misr_op *op = nullptr;
-        if (misr_op_create(ctx, &g, &op) != MISR_OK) return false;
-        it = ops.emplace(key, op).first;
+    {
+        std::unique_lock<std::mutex> lk(mu);
+        auto it = ops.find(r->key);
+        if (it == ops.end()) {
+            lk.unlock();   // building a general operator takes a while
+            misr_op *op = nullptr;
+            if (misr_op_create(ctx, &g, &op) != MISR_OK) return false;
+            lk.lock();
+            OpEnt ent;
+            ent.op = op;
+            ent.bytes = op_bytes(op);
+            used += ent.bytes;
+            it = ops.emplace(r->key, ent).first;
+        } else if (it->second.refs == 0) {
+            --n_idle;
+        }
+        it->second.refs++;
+        it->second.last_use = ++use_clock;
+        r->ope = &it->second;
+        r->op = it->second.op;
     }
-    r->op = it->second;
     if (r->tiled && (check_tiling(r->op, q.params) != MISR_OK ||
                      ensure_tiles(r->op, q.params, r->tiles) != hipSuccess))
         return false;
@@ -274,9 +383,17 @@ void misr_server::release(SReq *r) {
     r->tiles.x0.clear();
     std::lock_guard<std::mutex> lk(mu);
     used -= std::min(used, r->bytes);
+    if (r->ope) {
+        if (--r->ope->refs == 0) {
+            r->ope->last_use = ++use_clock;
+            ++n_idle;
+        }
+        r->ope = nullptr;
+        evict_idle(max_idle(), 0);
+    }
 }
 
-void misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
+hipError_t misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
     Plan &pl = L.pl;
     pl.projs.clear();
     pl.items.clear();
@@ -357,7 +474,15 @@ void misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
     size_t total = 0;
     for (auto &u : ups) total += (u.n + 255) & ~(size_t)255;
     total = std::max<size_t>(total, 256);
-    if (!L.stage.ensure(total) || L.blob.ensure(total) != hipSuccess) return;
+    if (cfg.fail_list_n > 0 && ++list_count == cfg.fail_list_n) return hipErrorOutOfMemory;
+    if (!L.stage.ensure(total)) return hipErrorOutOfMemory;
+    hipError_t e = L.blob.ensure(total);
+    if (e == hipSuccess) e = L.partials.ensure(std::max<size_t>(ni, 1) * kNV * sizeof(double));
+    if (e == hipSuccess) e = L.partials_u.ensure(std::max<size_t>(nu, 1) * kNV * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e;
+    }
     char *hp = (char *)L.stage.h, *dp = L.blob.as<char>();
     for (auto &u : ups) {
         if (u.n) std::memcpy(hp, u.h, u.n);
@@ -366,10 +491,8 @@ void misr_server::build_list(List &L, const std::vector<SReq *> &rs) {
         hp += step;
         dp += step;
     }
-    (void)hipMemcpyAsync(L.blob.p, L.stage.h, (size_t)(hp - (char *)L.stage.h),
-                         hipMemcpyHostToDevice, stream);
-    (void)L.partials.ensure(std::max<size_t>(ni, 1) * kNV * sizeof(double));
-    (void)L.partials_u.ensure(std::max<size_t>(nu, 1) * kNV * sizeof(double));
+    return hipMemcpyAsync(L.blob.p, L.stage.h, (size_t)(hp - (char *)L.stage.h),
+                          hipMemcpyHostToDevice, stream);
 }
 
 // Image pass over the whole list (fresh = false) or over the new solves' tail
@@ -511,7 +634,10 @@ void misr_server::run() {
                 if (cfg.fill_mpx > 0 && !(active.empty() && admitted.empty()) &&
                     held_mpx + r->n * 1e-6 > cfg.fill_mpx)
                     break;
-                if (used + r->bytes > cfg.hbm_budget_bytes) {
+                // its buffers, and its operator's tables unless cached
+                const size_t need = r->bytes + (ops.count(r->key) ? 0 : r->op_bytes);
+                if (used + need > cfg.hbm_budget_bytes) evict_idle(0, need);
+                if (used + need > cfg.hbm_budget_bytes) {
                     if (active.empty() && admitted.empty() && !P.pending) {
                         queue.pop_front();
                         r->state = MISR_REQ_FAILED;
@@ -557,8 +683,17 @@ void misr_server::run() {
             n_ep = std::max(1, std::min(64, n_ep));
             for (SReq *r : active) n_ep = std::min(n_ep, r->req.params.n_iter - r->passes);
             n_ep = std::max(n_ep, 0);
-            build_list(C.list, active);
-            e = hipEventRecord(C.ev0, stream);
+            if (build_list(C.list, active) != hipSuccess) {
+                // no work list for this cycle: its requests fail before any launch
+                for (SReq *r : active) {
+                    r->drop_state = MISR_REQ_FAILED;
+                    r->drop_code = MISR_E_NOMEM;
+                    C.dropped.push_back(r);
+                }
+                active.clear();
+                n_ep = 0;
+            }
+            if (!active.empty()) e = hipEventRecord(C.ev0, stream);
             bool any_fresh = false;
             for (SReq *r : active) any_fresh |= r->fresh;
             if (e == hipSuccess && any_fresh) e = enqueue_init(C.list);
@@ -695,6 +830,10 @@ extern "C" misr_status misr_server_submit(misr_server *s, const misr_request *re
                         (req->geom.hr_w / req->geom.scale);
     r->bytes = request_bytes(*req, r->n, r->es, req->geom.n_frames, m);
     if (general) r->bytes += (size_t)m * K * 4;   // the residual buffer
+    r->bytes += list_bytes(*req, general);
+    r->op_bytes = op_bytes_estimate(req->geom, general);
+    r->key = OpKey{req->geom.hr_h, req->geom.hr_w, req->geom.scale, K, P, r->shifts, r->psf,
+                   r->psf_frames, r->warps, r->psf_2d};
     r->stats.t_submit_us = now_us();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->closing) return set_error(MISR_E_INVAL, "server is shutting down");
@@ -772,6 +911,19 @@ extern "C" misr_status misr_server_cancel(misr_server *s, uint64_t id) {
     return MISR_OK;
 }
 
+extern "C" misr_status misr_server_query(misr_server *s, misr_server_info *out) {
+    if (!s || !out) return set_error(MISR_E_INVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    out->queued = (int32_t)s->queue.size();
+    int running = 0;
+    for (auto &kv : s->reqs) running += kv.second->state == MISR_REQ_RUNNING;
+    out->running = running;
+    out->n_ops = (int32_t)s->ops.size();
+    out->n_idle_ops = s->n_idle;
+    out->used_bytes = s->used;
+    return MISR_OK;
+}
+
 extern "C" misr_status misr_server_destroy(misr_server *s) {
     if (!s) return set_error(MISR_E_INVAL, "NULL server");
     {
@@ -782,7 +934,7 @@ extern "C" misr_status misr_server_destroy(misr_server *s) {
     if (s->th.joinable()) s->th.join();
     (void)hipStreamSynchronize(s->stream);
     s->reqs.clear();   // their buffers went back to the pool when they retired
-    for (auto &kv : s->ops) misr_op_destroy(kv.second);
+    for (auto &kv : s->ops) misr_op_destroy(kv.second.op);
     for (auto &c : s->cyc) {
         if (c.ev0) (void)hipEventDestroy(c.ev0);
         if (c.ev1) (void)hipEventDestroy(c.ev1);

@@ -78,7 +78,13 @@ class misr_request(C.Structure):
 
 class misr_server_config(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32),
-                ("max_queue", C.c_int32), ("fail_alloc_n", C.c_int32), ("fill_mpx", C.c_int32)]
+                ("max_queue", C.c_int32), ("fail_alloc_n", C.c_int32), ("fill_mpx", C.c_int32),
+                ("fail_list_n", C.c_int32), ("max_idle_ops", C.c_int32)]
+
+
+class misr_server_info(C.Structure):
+    _fields_ = [("queued", C.c_int32), ("running", C.c_int32), ("n_ops", C.c_int32),
+                ("n_idle_ops", C.c_int32), ("used_bytes", C.c_size_t)]
 
 
 class misr_req_stats(C.Structure):
@@ -111,6 +117,7 @@ _SIGS = {
     "misr_cost_grad": (C.c_int, [_vp, C.POINTER(misr_params), _vp, _vp, _vp, _vp, _vp]),
     "misr_scg_solve": (C.c_int, [_vp, C.POINTER(misr_params), _vp, _vp,
                                  C.POINTER(misr_scg_trace), _vp]),
+    "misr_scg_status": (C.c_int, [_vp, C.POINTER(misr_scg_trace), _vp]),
     "misr_scg_solve_batch": (C.c_int, [C.c_int, C.POINTER(_vp), C.POINTER(misr_params),
                                        C.POINTER(_vp), C.POINTER(_vp),
                                        C.POINTER(misr_scg_trace), _vp]),
@@ -122,6 +129,7 @@ _SIGS = {
                                    C.POINTER(misr_req_stats)]),
     "misr_server_wait": (C.c_int, [_vp, C.c_uint64, C.c_int64]),
     "misr_server_cancel": (C.c_int, [_vp, C.c_uint64]),
+    "misr_server_query": (C.c_int, [_vp, C.POINTER(misr_server_info)]),
     "misr_server_destroy": (C.c_int, [_vp]),
 }
 EXPORTS = []
@@ -356,6 +364,14 @@ class Operator:
             return None
         return _trace_out(tr, recs, st)
 
+    def scg_status(self, stream=None) -> dict:
+        """Outcome of the last scg_solve on this operator (waits for it): the
+        summary dict of scg_solve(trace=True) without the per-pass records."""
+        tr = misr_scg_trace()
+        st = lib.misr_scg_status(self.h, C.byref(tr), stream_handle(stream))
+        if st not in (OK, E_NUMERIC):
+            check(st)
+        return _trace_out(tr, [], st)[1]
 
     def time_pass(self, y, x, which: int, reps: int = 20, params: misr_params | None = None,
                   stream=None) -> float:
@@ -412,8 +428,10 @@ class Server:
     """Continuous-batching server of SR solves (misr_server_*)."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 64,
-                 max_queue: int = 0, fail_alloc_n: int = 0, fill_mpx: int = 0):
-        cfg = misr_server_config(hbm_budget_bytes, max_slots, max_queue, fail_alloc_n, fill_mpx)
+                 max_queue: int = 0, fail_alloc_n: int = 0, fill_mpx: int = 0,
+                 fail_list_n: int = 0, max_idle_ops: int = 0):
+        cfg = misr_server_config(hbm_budget_bytes, max_slots, max_queue, fail_alloc_n, fill_mpx,
+                                 fail_list_n, max_idle_ops)
         h = C.c_void_p()
         check(lib.misr_server_create(ctx.h, C.byref(cfg), C.byref(h)))
         self.h = h
@@ -444,6 +462,13 @@ class Server:
         stats = misr_req_stats()
         check(lib.misr_server_poll(self.h, rid, C.byref(st), C.byref(stats)))
         return st.value, stats
+
+    def info(self) -> dict:
+        """Occupancy: queued and running requests, cached and idle operators,
+        device bytes charged against the budget."""
+        inf = misr_server_info()
+        check(lib.misr_server_query(self.h, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in misr_server_info._fields_}
 
     def wait(self, rid: int, timeout_us: int = -1) -> int:
         return lib.misr_server_wait(self.h, rid, timeout_us)

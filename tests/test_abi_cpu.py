@@ -35,7 +35,7 @@ def test_struct_layouts_match_header(misr, tmp_path):
     structs = {"misr_geometry": misr.misr_geometry, "misr_params": misr.misr_params,
                "misr_scg_iter": misr.misr_scg_iter, "misr_scg_trace": misr.misr_scg_trace,
                "misr_request": misr.misr_request, "misr_server_config": misr.misr_server_config,
-               "misr_req_stats": misr.misr_req_stats}
+               "misr_req_stats": misr.misr_req_stats, "misr_server_info": misr.misr_server_info}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "misr.h"', "int main(void){"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
@@ -121,6 +121,8 @@ def test_null_arguments_rejected_before_any_device_call(misr):
     assert misr.lib.misr_scg_solve(None, None, None, None, None, None) == misr.E_INVAL
     assert misr.lib.misr_ctx_destroy(None) == misr.E_INVAL
     assert misr.lib.misr_op_sparse_width(None, None, None) == misr.E_INVAL
+    assert misr.lib.misr_scg_status(None, None, None) == misr.E_INVAL
+    assert misr.lib.misr_server_query(None, None) == misr.E_INVAL
 
 
 def test_binding_has_no_cpu_fallback():

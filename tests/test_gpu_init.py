@@ -101,3 +101,27 @@ def test_served_request_without_x0(misr, ctx, x_init):
     assert srv.poll(rid)[0] == misr.REQ_DONE
     assert torch.equal(out, ref)
     srv.close()
+
+
+def test_batch_graph_rebuilt_for_new_frame_offsets(misr, ctx):
+    """Two batches on the same device buffers whose operators differ only in
+    their shifts, with the start point computed on the device (x_init = 2,
+    multi-image interpolation, whose integer frame offsets are launch
+    arguments of the captured solve): each batch equals its solo solves."""
+    import torch
+    n = 8
+    pa = problem(32, 2, 0.8, None, jitter=0.0, n_iter=n, seeds=(21, 22, 23))
+    ys = [to_dev(_f32(pa.y)), to_dev(_f32(pa.y[::-1].copy()))]
+    xs = [torch.empty((pa.H, pa.W), device="cuda") for _ in range(2)]
+    for shifts in (pa.shifts, pa.shifts[::-1].copy()):
+        ops = [misr.Operator(ctx, pa.H, pa.W, pa.s, shifts, pa.psf) for _ in range(2)]
+        prm = [misr.default_params(n_iter=n, x_init=2) for _ in range(2)]
+        misr.scg_solve_batch(ops, ys, xs, prm, trace=False)
+        torch.cuda.synchronize()
+        for i in range(2):
+            ref = torch.empty_like(xs[i])
+            ops[i].scg_solve(ys[i], ref, misr.default_params(n_iter=n, x_init=2))
+            torch.cuda.synchronize()
+            assert torch.equal(xs[i], ref)
+        for o in ops:
+            o.close()

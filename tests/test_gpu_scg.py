@@ -226,6 +226,30 @@ def test_nonfinite_input_stops_with_numeric(misr, ctx):
     assert np.all(np.isfinite(to_np(x)))
 
 
+def test_nonfinite_stop_reported_without_trace(misr, ctx):
+    """A solve run without a trace returns at once (asynchronous); its
+    non-finite stop is reported by misr_scg_status (E_NUMERIC, stop 2), and a
+    later finite solve on the same operator reports OK."""
+    import torch
+    prob = problem(32, 2, 0.6, 5, noise=("gauss", 0.01), jitter=0.0, seeds=(2, 2, 3))
+    y_bad = _f32(prob.y)
+    y_bad[2, 5, 1] = np.nan
+    op = misr.Operator(ctx, prob.H, prob.W, 2, prob.shifts, prob.psf)
+    with pytest.raises(misr.MisrError):
+        op.scg_status()   # no solve yet
+    x = to_dev(_f32(prob.x0))
+    assert op.scg_solve(to_dev(y_bad), x, misr.default_params(n_iter=10), trace=False) is None
+    # a cost/gradient call in between does not change the report
+    op.cost_grad(x, to_dev(_f32(prob.y)))
+    st = op.scg_status()
+    assert st["status"] == "E_NUMERIC" and st["stop"] == 2
+    assert np.all(np.isfinite(to_np(x)))
+    x = to_dev(_f32(prob.x0))
+    op.scg_solve(to_dev(_f32(prob.y)), x, misr.default_params(n_iter=10), trace=False)
+    st = op.scg_status(torch.cuda.current_stream())
+    assert st["status"] == "OK" and st["stop"] == 0 and st["n_passes"] == 10
+
+
 @pytest.mark.parametrize("eps_data", [1e-2, 1e-3])
 def test_l1_data_solve_matches_oracle(misr, ctx, eps_data):
     """Eq. misr with p = 1 (Charbonnier-smoothed L1 data term): the device

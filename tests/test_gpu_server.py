@@ -260,3 +260,57 @@ def test_l1_requests_match_plain(misr, ctx, probs):
         assert srv.poll(rid)[0] == misr.REQ_DONE
         assert torch.equal(out, ref)
     srv.close()
+
+
+def test_work_list_allocation_failure_fails_cleanly(misr, ctx, probs):
+    """Fault hook on the cycle's work-list allocation: the requests of that
+    cycle fail with E_NOMEM before any of their kernels runs (the output
+    still holds x0, copied at admission), and the next request is served
+    normally (equal to its solo solve)."""
+    import torch
+    p, n = probs[0], SPECS[0][3]
+    srv = misr.Server(ctx, hbm_budget_bytes=1 << 30, max_slots=1, fail_list_n=1)
+    x0 = to_dev(_f32(p.x0))
+    out = torch.full_like(x0, 7.0)
+    rid = srv.submit(p.H, p.W, p.s, p.shifts, p.psf, to_dev(_f32(p.y)), x0, out,
+                     misr.default_params(n_iter=n))
+    assert srv.wait(rid, 60_000_000) == misr.OK
+    st, stats = srv.poll(rid)
+    assert st == misr.REQ_FAILED and stats.status == misr.E_NOMEM
+    torch.cuda.synchronize()
+    assert torch.equal(out, x0)
+    out2 = torch.empty_like(x0)
+    rid2 = srv.submit(p.H, p.W, p.s, p.shifts, p.psf, to_dev(_f32(p.y)), x0, out2,
+                      misr.default_params(n_iter=n))
+    assert srv.wait(rid2, 60_000_000) == misr.OK
+    assert srv.poll(rid2)[0] == misr.REQ_DONE
+    assert torch.equal(out2, _solo(misr, ctx, p, n))
+    info = srv.info()
+    assert info["running"] == 0 and info["queued"] == 0
+    srv.close()
+
+
+def test_operator_cache_stays_bounded(misr, ctx):
+    """A stream of requests whose frames all have different (jittered)
+    shifts: each needs its own operator, and the server keeps at most
+    max_idle_ops of them once their requests finish (least recently used
+    evicted), so device memory does not grow with the stream.  Each result
+    equals its solo solve."""
+    import torch
+    srv = misr.Server(ctx, hbm_budget_bytes=1 << 30, max_idle_ops=2)
+    n = 6
+    for i in range(7):
+        p = problem(24, 2, 0.8, None, jitter=0.05, n_iter=n, seeds=(40 + i, 60 + i, 80 + i))
+        x0 = to_dev(_f32(p.x0))
+        out = torch.empty_like(x0)
+        rid = srv.submit(p.H, p.W, p.s, p.shifts, p.psf, to_dev(_f32(p.y)), x0, out,
+                         misr.default_params(n_iter=n))
+        assert srv.wait(rid, 60_000_000) == misr.OK
+        assert srv.poll(rid)[0] == misr.REQ_DONE
+        assert torch.equal(out, _solo(misr, ctx, p, n))
+        info = srv.info()
+        assert info["n_ops"] <= 2 and info["n_idle_ops"] == info["n_ops"]
+    # only the idle operators' tables remain charged against the budget
+    assert 0 < srv.info()["used_bytes"] < 1 << 20
+    assert srv.info()["n_ops"] == 2
+    srv.close()
