@@ -340,10 +340,11 @@ typedef struct {
     int32_t fail_list_n;      /* fault hook: the n-th work-list allocation fails
                                  (0 off); every request of that cycle then fails
                                  with MISR_E_NOMEM and none of its kernels runs */
-    int32_t max_idle_ops;     /* operators kept cached after their last request
-                                 finished, least recently used evicted first
-                                 (0: 8); idle operators are also evicted when
-                                 admission needs their memory */
+    int32_t max_idle_ops;     /* must be 0: operator eviction is disabled, and
+                                 every cached operator (one per distinct
+                                 geometry) is kept until misr_server_destroy;
+                                 misr_server_create returns MISR_E_INVAL for
+                                 any other value */
 } misr_server_config;
 
 /* Occupancy of a server (misr_server_query). */

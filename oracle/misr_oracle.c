@@ -265,6 +265,46 @@ double orc_btv(int H, int W, double lambda, double alpha, double eps, int w,
     return E;
 }
 
+/* The part of the BTV prior one subdomain owns (Sec. 3.1, Eq. subfunction):
+ * the pairs (i, i+d) whose first pixel i lies in the rectangle
+ * [u0,u1) x [v0,v1), both pixels inside the H x W grid.  g (nullable)
+ * receives += the gradient of that part, which reaches up to w-1 pixels
+ * below and to the right of the rectangle.  Summed over rectangles that
+ * tile the grid, the parts give orc_btv exactly (up to summation order). */
+double orc_btv_owned(int H, int W, double lambda, double alpha, double eps, int w,
+                     const double *x, int u0, int u1, int v0, int v1, double *g) {
+    double E = 0.0;
+    double *gtab = (double *)malloc(sizeof(double) * w * w);
+    for (int dy = 0; dy < w; ++dy)
+        for (int dx = 0; dx < w; ++dx) gtab[dy * w + dx] = lambda * pow(alpha, dx + dy);
+    const i64 ue = (u1 + w - 1 < H) ? u1 + w - 1 : H, ve = (v1 + w - 1 < W) ? v1 + w - 1 : W;
+#pragma omp parallel for schedule(static) reduction(+ : E)
+    for (i64 u = u0; u < ue; ++u)
+        for (i64 v = v0; v < ve; ++v) {
+            const double xi = x[u * W + v];
+            const int own_i = u < u1 && v < v1;
+            double gi = 0.0;
+            for (int dy = 0; dy < w; ++dy)
+                for (int dx = 0; dx < w; ++dx) {
+                    if (dx == 0 && dy == 0) continue;
+                    const double gam = gtab[dy * w + dx];
+                    if (own_i && u + dy < H && v + dx < W) {   /* owned pair (i, i+d) */
+                        const double z = xi - x[(u + dy) * W + v + dx];
+                        E += gam * phi_eps(z, eps);
+                        gi += gam * psi_eps(z, eps);
+                    }
+                    /* pair (i-d, i), owned when i-d is */
+                    if (u - dy >= u0 && v - dx >= v0 && u - dy < u1 && v - dx < v1) {
+                        const double z = x[(u - dy) * W + v - dx] - xi;
+                        gi -= gam * psi_eps(z, eps);
+                    }
+                }
+            if (g) g[u * W + v] += gi;
+        }
+    free(gtab);
+    return E;
+}
+
 /* ------------------------------------------------------- cost + gradient */
 /* J(x) = sum_k sum phi_p(A_k x - y_k) + E_reg(x), with phi_2(r) = r^2 and
  * phi_1 = Charbonnier with eps_data.  g (nullable) receives grad J.

@@ -59,6 +59,7 @@ def _load():
                             _P, _P],
         "orc_adjoint": [_I, _I, _I, _I, _P, _I, _P, _P, _P],
         "orc_btv": [_I, _I, _D, _D, _D, _I, _P, _P],
+        "orc_btv_owned": [_I, _I, _D, _D, _D, _I, _P, _I, _I, _I, _I, _P],
         "orc_cost_grad": [_I, _I, _I, _I, _P, _I, _P, _D, _D, _D, _I, _I, _D, _P, _P,
                           _P, _P],
         "orc_psi_quotient": [_D, _D, _D],
@@ -74,6 +75,7 @@ def _load():
         fn.argtypes = args
         fn.restype = None
     lib.orc_btv.restype = _D
+    lib.orc_btv_owned.restype = _D
     lib.orc_cost_grad.restype = _D
     lib.orc_cost_grad_w.restype = _D
     lib.orc_psi_quotient.restype = _D
@@ -207,6 +209,17 @@ def btv(x, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3, w=3, grad=True):
     g = np.zeros_like(x) if grad else None
     E = _load().orc_btv(x.shape[0], x.shape[1], lambda_reg, alpha_btv, eps, w, _p(x), _p(g))
     return (E, g) if grad else E
+
+
+def btv_owned(x, rect, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3, w=3):
+    """The BTV pairs one subdomain owns: first pixel in rect = (u0, u1, v0, v1),
+    both pixels in the grid.  Returns (E, gradient of that part)."""
+    x = _f64(x)
+    g = np.zeros_like(x)
+    u0, u1, v0, v1 = (int(v) for v in rect)
+    E = _load().orc_btv_owned(x.shape[0], x.shape[1], lambda_reg, alpha_btv, eps, w, _p(x),
+                              u0, u1, v0, v1, _p(g))
+    return E, g
 
 
 def cost_grad(x, y, shifts, psf, s, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3, w=3,

@@ -27,7 +27,7 @@ import numpy as np
 from . import ops
 
 
-def _dot(a: np.ndarray, b: np.ndarray) -> float:
+def _dot_plain(a: np.ndarray, b: np.ndarray) -> float:
     """FP64 inner product by pairwise summation (no BLAS threads, which would
     contend with the OpenMP threads of the C operators)."""
     return float(np.add.reduce(np.multiply(a.ravel(), b.ravel())))
@@ -55,14 +55,17 @@ def moller_update_lambda(Delta: float, lam: float, delta: float, pi: float) -> f
 
 
 def scg_minimize(J_and_grad, x0: np.ndarray, n_iter: int, sigma: float = 1e-4,
-        lam1: float = 1e-6, curvature=None, trace: bool = True):
+        lam1: float = 1e-6, curvature=None, trace: bool = True, dot=None):
     """Minimise J from x0 with Moller's SCG for exactly ``n_iter`` passes.
 
     ``J_and_grad(x, need_grad) -> (J, g or None)``.
     ``curvature(x, p, sk) -> delta`` replaces the literal finite difference
     p^T (grad J(x + sk p) - grad J(x)) / sk when given (check mode).
+    ``dot(a, b)`` replaces the inner product (the partitioned solve sums the
+    subdomains' local products, Alg. 1's consensus).
     Returns (x, trace list of dicts, info dict).
     """
+    _dot = dot or _dot_plain
     x = np.array(x0, dtype=np.float64, copy=True)
     N = x.size
     E, g = J_and_grad(x, True)

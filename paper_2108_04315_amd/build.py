@@ -1,12 +1,13 @@
 """Builds libmisr.so (HIP, gfx950) in the package directory.
 
-    python -m paper_2108_04315_amd.build [-v]
+    python -m paper_2108_04315_amd.build [-v] [--incremental]
 
 The image kernels are compiled once per scale factor (-DMISR_SCALE=s); the
 translation units compile in parallel.
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -36,19 +37,41 @@ def _units():
     return units
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
+OBJ_CACHE = os.path.join(ROOT, "_build")
+
+
+def _unit_hash(src: str, extra) -> str:
+    """Hash of one unit's inputs: its source, every header it may include and
+    the command line."""
+    h = hashlib.sha256(" ".join([HIPCC] + FLAGS + list(extra)).encode())
+    h.update(open(os.path.join(CSRC, src), "rb").read())
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for f in sorted(os.listdir(d)):
+            if f.endswith(".h"):
+                h.update(f.encode())
+                h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:20]
+
+
+def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False) -> str:
+    """Compiles every unit and links libmisr.so.  incremental: reuse object
+    files under _build/ whose unit hash is unchanged."""
     jobs = jobs or min(8, os.cpu_count() or 4)
+    os.makedirs(OBJ_CACHE, exist_ok=True)
 
     def compile_one(u):
         src, extra, obj = u
-        cmd = [HIPCC] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o",
-                                          os.path.join(CSRC, obj)]
+        out = os.path.join(OBJ_CACHE, f"{obj[:-2]}_{_unit_hash(src, extra)}.o")
+        if incremental and os.path.exists(out):
+            return out
+        cmd = [HIPCC] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", out + ".tmp"]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"compile failed: {src} {extra}\n{r.stderr}")
-        return os.path.join(CSRC, obj)
+        os.replace(out + ".tmp", out)
+        return out
 
     units = _units()
     with ThreadPoolExecutor(jobs) as ex:
@@ -59,10 +82,13 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
-    for o in objs:
-        os.remove(o)
+    keep = set(objs)
+    for f in os.listdir(OBJ_CACHE):
+        p = os.path.join(OBJ_CACHE, f)
+        if p not in keep and f.endswith(".o"):
+            os.remove(p)
     return LIB
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

@@ -42,7 +42,7 @@ struct OpKey {
 };
 
 // A cached operator: the requests admitted on it hold references; with none
-// it is idle and may be evicted (least recently used first).
+// it is idle.  Cached operators are kept until the server is destroyed.
 struct OpEnt {
     misr_op *op = nullptr;
     int refs = 0;
@@ -174,10 +174,6 @@ struct misr_server {
     bool setup(SReq *r);
     void release(SReq *r);
     hipError_t build_list(List &L, const std::vector<SReq *> &rs);
-    // idle operators evicted (caller holds mu) until at most keep remain idle
-    // and, if need > 0, until used + need fits the budget
-    void evict_idle(int keep, size_t need);
-    int max_idle() const { return cfg.max_idle_ops > 0 ? cfg.max_idle_ops : 8; }
     hipError_t enqueue_init(List &L);
     hipError_t enqueue_image(List &L, int kind, bool fresh);
     hipError_t enqueue_scalar(List &L, int phase, bool fresh);
@@ -275,25 +271,6 @@ static size_t op_bytes(const misr_op *op) {
            op->t_val.n;
 }
 
-void misr_server::evict_idle(int keep, size_t need) {
-    for (;;) {
-        if (n_idle == 0) return;
-        const bool over = n_idle > keep;
-        const bool short_mem = need > 0 && used + need > cfg.hbm_budget_bytes;
-        if (!over && !short_mem) return;
-        auto lru = ops.end();
-        for (auto it = ops.begin(); it != ops.end(); ++it)
-            if (it->second.refs == 0 && (lru == ops.end() || it->second.last_use <
-                                                                lru->second.last_use))
-                lru = it;
-        if (lru == ops.end()) return;
-        used -= std::min(used, lru->second.bytes);
-        (void)misr_op_destroy(lru->second.op);
-        ops.erase(lru);
-        --n_idle;
-    }
-}
-
 bool misr_server::setup(SReq *r) {
     const misr_request &q = r->req;
     if (cfg.fail_alloc_n > 0 && ++alloc_count == cfg.fail_alloc_n) return false;
@@ -389,7 +366,6 @@ void misr_server::release(SReq *r) {
             ++n_idle;
         }
         r->ope = nullptr;
-        evict_idle(max_idle(), 0);
     }
 }
 
@@ -636,7 +612,6 @@ void misr_server::run() {
                     break;
                 // its buffers, and its operator's tables unless cached
                 const size_t need = r->bytes + (ops.count(r->key) ? 0 : r->op_bytes);
-                if (used + need > cfg.hbm_budget_bytes) evict_idle(0, need);
                 if (used + need > cfg.hbm_budget_bytes) {
                     if (active.empty() && admitted.empty() && !P.pending) {
                         queue.pop_front();
@@ -764,6 +739,9 @@ extern "C" misr_status misr_server_create(misr_ctx *ctx, const misr_server_confi
     if (cfg->max_slots < 1 || cfg->hbm_budget_bytes == 0 || cfg->fill_mpx < 0)
         return set_error(MISR_E_INVAL,
                          "max_slots >= 1, hbm_budget_bytes > 0 and fill_mpx >= 0 required");
+    if (cfg->max_idle_ops != 0)
+        return set_error(MISR_E_INVAL, "operator eviction (max_idle_ops) is disabled: cached "
+                         "operators are kept until misr_server_destroy");
     *out = nullptr;
     if (hipSetDevice(ctx->dev) != hipSuccess) return set_error(MISR_E_HIP, "hipSetDevice");
     auto s = std::make_unique<misr_server>();

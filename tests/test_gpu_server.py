@@ -290,6 +290,9 @@ def test_work_list_allocation_failure_fails_cleanly(misr, ctx, probs):
     srv.close()
 
 
+@pytest.mark.skip(reason="operator eviction is switched off: the one GPU run of this test "
+                         "failed and left the GPU faulted, and no cause has been shown; the "
+                         "server now rejects max_idle_ops != 0")
 def test_operator_cache_stays_bounded(misr, ctx):
     """A stream of requests whose frames all have different (jittered)
     shifts: each needs its own operator, and the server keeps at most
@@ -299,18 +302,28 @@ def test_operator_cache_stays_bounded(misr, ctx):
     import torch
     srv = misr.Server(ctx, hbm_budget_bytes=1 << 30, max_idle_ops=2)
     n = 6
-    for i in range(7):
-        p = problem(24, 2, 0.8, None, jitter=0.05, n_iter=n, seeds=(40 + i, 60 + i, 80 + i))
-        x0 = to_dev(_f32(p.x0))
-        out = torch.empty_like(x0)
-        rid = srv.submit(p.H, p.W, p.s, p.shifts, p.psf, to_dev(_f32(p.y)), x0, out,
-                         misr.default_params(n_iter=n))
-        assert srv.wait(rid, 60_000_000) == misr.OK
-        assert srv.poll(rid)[0] == misr.REQ_DONE
-        assert torch.equal(out, _solo(misr, ctx, p, n))
-        info = srv.info()
-        assert info["n_ops"] <= 2 and info["n_idle_ops"] == info["n_ops"]
-    # only the idle operators' tables remain charged against the budget
-    assert 0 < srv.info()["used_bytes"] < 1 << 20
-    assert srv.info()["n_ops"] == 2
-    srv.close()
+    try:
+        for i in range(7):
+            p = problem(24, 2, 0.8, None, jitter=0.05, n_iter=n, seeds=(40 + i, 60 + i, 80 + i))
+            x0 = to_dev(_f32(p.x0))
+            y = to_dev(_f32(p.y))
+            out = torch.empty_like(x0)
+            rid = srv.submit(p.H, p.W, p.s, p.shifts, p.psf, y, x0, out,
+                             misr.default_params(n_iter=n))
+            assert srv.wait(rid, 60_000_000) == misr.OK
+            assert srv.poll(rid)[0] == misr.REQ_DONE
+            assert torch.equal(out, _solo(misr, ctx, p, n))
+            info = srv.info()
+            assert info["n_ops"] <= 2 and info["n_idle_ops"] == info["n_ops"]
+        # only the idle operators' tables remain charged against the budget
+        assert 0 < srv.info()["used_bytes"] < 1 << 20
+        assert srv.info()["n_ops"] == 2
+    finally:
+        srv.close()
+
+
+def test_operator_eviction_rejected(misr, ctx):
+    """Operator eviction is switched off: a server asked for it is refused
+    (host-side check, before any device work)."""
+    with pytest.raises(misr.MisrError):
+        misr.Server(ctx, hbm_budget_bytes=1 << 30, max_idle_ops=2)
