@@ -258,6 +258,26 @@ misr_status misr_upsample(const misr_op *op, misr_dtype dt, const void *y, void 
 misr_status misr_cost_grad(const misr_op *op, const misr_params *params, const void *x,
                            const void *y, float *g, double *cost_dev, void *stream);
 
+/* misr_cost_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same J(x), grad J(x) and cost_dev {J, data term, lambda * prior}, bit
+ * for bit, with no device allocation, free or host-to-device copy.  Its work
+ * list, solver state and partial sums live in a fixed workspace of
+ * misr_cost_grad_noalloc_max_bytes() bytes (2 MiB) in device memory of every
+ * GPU the library runs on (located when a context is created on that device,
+ * held until the process ends).  Banded operators (translational frames,
+ * separable PSFs), untiled (params->tile_lr == 0); x and y stored as
+ * params->img_dtype (x evaluated as stored).  The workspace holds 32 752
+ * tiles (8192 x 8192 HR at the 48 x 96 tiles of x2 operators fits); larger
+ * images return MISR_E_INVAL with the limit in misr_last_error(), before any
+ * launch.  Every call on a device shares that device's workspace, and only the
+ * values a call writes are read back: calls that overlap on one device (other
+ * streams or threads) race; calls ordered on one stream do not. */
+misr_status misr_cost_grad_noalloc(const misr_op *op, const misr_params *params, const void *x,
+                                   const void *y, float *g, double *cost_dev, void *stream);
+/* Bytes of the workspace of misr_cost_grad_noalloc on each device. */
+size_t misr_cost_grad_noalloc_max_bytes(void);
+
 /* SCG solve (Algorithm 1 on one GPU): params->n_iter passes from x_inout,
  * result written back to x_inout (device, params->img_dtype).  y: device.
  * trace (host, nullable): when given, the call synchronises the stream and

@@ -31,6 +31,7 @@ def _units():
     units = [("image_kernels.hip", [f"-DMISR_SCALE={s}"], f"_image_s{s}.o") for s in (1, 2, 3, 4)]
     units.append(("scalar_kernels.hip", [], "_scalar.o"))
     units.append(("general_kernels.hip", [], "_general.o"))
+    units.append(("noalloc.hip", [], "_noalloc.o"))
     for src in ("abi.cpp", "server.cpp"):
         if os.path.exists(os.path.join(CSRC, src)):
             units.append((src, ["-x", "hip"], "_" + src.replace(".cpp", ".o")))

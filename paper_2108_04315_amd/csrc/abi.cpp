@@ -216,6 +216,14 @@ extern "C" misr_status misr_ctx_create(int dev, misr_ctx **out) {
         delete c;
         return set_error(MISR_E_HIP, "stream/event creation failed");
     }
+    // the workspace of misr_cost_grad_noalloc on this device
+    if ((e = scratch_init(dev)) != hipSuccess) {
+        (void)hipEventDestroy(c->ev_in);
+        (void)hipEventDestroy(c->ev_out);
+        (void)hipStreamDestroy(c->stream);
+        delete c;
+        return hip_fail(e, "hipGetSymbolAddress (no-allocation workspace)");
+    }
     *out = c;
     return MISR_OK;
 }

@@ -771,7 +771,9 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
             const float gv = gs[row * T::GP + col];
             gout[rb + ocol[c]] = gv;
             gg += (double)gv * (double)gv;
-            if (mode == 0) pz[rb + ocol[c]] = 0.f;   // start direction buffer for the init pass
+            // start direction buffer for the init pass (none when the caller
+            // evaluates the cost and gradient alone without one)
+            if (mode == 0 && pz) pz[rb + ocol[c]] = 0.f;
             if (mode == 1) {
                 ggk += (double)gv * (double)gkv[r][c];
                 gp += (double)gv * (double)po[row * T::TW + col];

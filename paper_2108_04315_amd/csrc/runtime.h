@@ -289,6 +289,9 @@ namespace misr {
 
 // SCG state of a new solve from its parameters (N = HR pixels).
 void init_state(ScgState &s, const misr_params &p, long long N);
+// Looks up, on device dev (current), the address of the workspace of
+// misr_cost_grad_noalloc; once per device (noalloc.hip).
+hipError_t scratch_init(int dev);
 // Band length L of a translational geometry's 1-D factors (before rounding
 // up to a compiled length).
 int band_length(const misr_geometry *g);

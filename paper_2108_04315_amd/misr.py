@@ -115,6 +115,9 @@ _SIGS = {
     "misr_upsample": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "misr_adjoint": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "misr_cost_grad": (C.c_int, [_vp, C.POINTER(misr_params), _vp, _vp, _vp, _vp, _vp]),
+    "misr_cost_grad_noalloc": (C.c_int, [_vp, C.POINTER(misr_params), _vp, _vp, _vp, _vp,
+                                         _vp]),
+    "misr_cost_grad_noalloc_max_bytes": (C.c_size_t, []),
     "misr_scg_solve": (C.c_int, [_vp, C.POINTER(misr_params), _vp, _vp,
                                  C.POINTER(misr_scg_trace), _vp]),
     "misr_scg_status": (C.c_int, [_vp, C.POINTER(misr_scg_trace), _vp]),
@@ -348,6 +351,16 @@ class Operator:
         check(lib.misr_cost_grad(self.h, C.byref(p), _ptr(x), _ptr(y), _ptr(g), _ptr(cost),
                                  stream_handle(stream)))
         return cost, g
+
+    def cost_grad_noalloc(self, x, y, g, cost, params: misr_params | None = None,
+                          stream=None) -> int:
+        """misr_cost_grad_noalloc: the caller passes the outputs g (H x W
+        float32) and cost (3 float64), both on the device; returns the status
+        code (no exception, so that callers can test the rejections)."""
+        p = params or default_params()
+        p.img_dtype = dtype_code(x)
+        return lib.misr_cost_grad_noalloc(self.h, C.byref(p), _ptr(x), _ptr(y), _ptr(g),
+                                          _ptr(cost), stream_handle(stream))
 
     def scg_solve(self, y, x_inout, params: misr_params | None = None, trace: bool = True,
                   stream=None):
