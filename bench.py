@@ -7,7 +7,10 @@ Workload (one step = one whole solve): 4 synthetic LR frames of 1024x1024
 with +-0.05 px jitter, 7x7 Gaussian PSF (sigma 0.8 HR px), Poisson noise at
 1e4 mean counts, BTV lambda 0.01 / alpha 0.4, 100 SCG passes from the bicubic
 upsample of frame 0, all FP32.  Inputs are resident in HBM before the timed
-region.  Prints one JSON line.
+region.  Prints one JSON line, which also carries: the serving stream (LR
+512^2..4096^2, served against plain at 0.5, 0.8 and 1.0 of the plain
+capacity), the batched and precision workloads, and the FP64 oracle's timing
+on the host cores with the GPU results' errors against it.
 """
 from __future__ import annotations
 
@@ -112,14 +115,19 @@ def copy_probe(mib: int, reps: int = 3):
 
 
 # ------------------------------------------------------------------ serving
-SERVE_SIZES = (512, 768, 1024, 1536, 2048)
+SERVE_SIZES = (512, 768, 1024, 1536, 2048, 3072, 4096)   # LR side of the serving stream
+BATCH_SIZES = (512, 768, 1024, 1536, 2048)               # LR side of the batched workload
 SERVE_ITERS = 80
+SERVE_TILED_LR = 4096   # requests this large are split into tiles ...
+SERVE_TILE_LR = 1024    # ... of 1024^2 LR px ...
+SERVE_HALO_LR = 8       # ... with an 8-LR-px halo exchanged on the device every pass
 
 
-def _serve_problem(misr, ctx, L, s, seed):
+def _serve_problem(misr, ctx, L, s, seed, x0=True):
     """One synthetic projection: LR L x L, scale s (4 frames on the {0,1/2}^2
     grid at s=2, 9 frames on the 3x3 grid at s=3), jittered shifts, 7x7 PSF
-    sigma 0.8, Poisson 1e4 counts; y and x0 (bicubic of frame 0) on the device."""
+    sigma 0.8, Poisson 1e4 counts; y (and x0, the bicubic of frame 0, unless
+    x0 is False) on the device."""
     import torch
     from paper_2108_04315_amd import synth
     Hh = L * s
@@ -130,9 +138,11 @@ def _serve_problem(misr, ctx, L, s, seed):
     clean = op.forward(torch.from_numpy(synth.phantom(Hh, Hh, seed)).float().cuda())
     torch.cuda.synchronize()
     y_np = synth.add_poisson_noise(clean.double().cpu().numpy(), 1e4, seed + 1)
+    del clean
     y = torch.from_numpy(y_np).float().cuda()
-    x0 = torch.from_numpy(synth.bicubic_upsample(y_np[0], s)).float().cuda()
-    return dict(op=op, y=y, x0=x0, shifts=shifts, psf=psf, H=Hh, s=s)
+    xs = (torch.from_numpy(synth.bicubic_upsample(y_np[0], s)).float().cuda() if x0 else
+          torch.empty((Hh, Hh), dtype=torch.float32, device="cuda"))
+    return dict(op=op, y=y, x0=xs, shifts=shifts, psf=psf, H=Hh, s=s, L=L)
 
 
 SERVE_FILL_MPX = 8   # about two waves of 48 x 96 tiles over the 256 CUs
@@ -164,45 +174,55 @@ def host_buffer_leg(misr, ctx, shifts, psf, y_np, x0_np, x_ref, n_req: int = 4):
             "equals_device_solve_bitwise": all(np.array_equal(o, x_ref) for o in outs)}
 
 
-def serving_leg(misr, ctx, n_req: int = 48, loads=(0.8, 1.0), seed: int = 7,
+def serving_leg(misr, ctx, n_req: int = 200, loads=(0.5, 0.8, 1.0), seed: int = 7,
                 fill_mpx: int = SERVE_FILL_MPX, sizes=SERVE_SIZES):
-    """A stream of SR requests (LR 512^2..2048^2, scale 2 or 3, 80 SCG passes
-    each) solved (a) plain: one solve at a time in arrival order, each solve
-    one captured graph, synchronised; (b) served: misr_server continuous
-    batching.  Capacity: every request submitted at t = 0.  Latency
-    (completion - arrival): Poisson arrivals at `load` x the plain capacity
-    (in requests/s).  Both paths compute each request's start point (bicubic
-    of frame 0) on the device.  The server admits in arrival order while the admitted
-    solves hold fewer than fill_mpx million HR pixels (0: no cap), so small
-    requests share the device and large ones keep first-come order.  Served
-    results must equal plain ones bit for bit."""
+    """The serving workload: a seeded stream of n_req SR requests, LR side
+    uniform in `sizes` (512^2 ... 4096^2), scale 2 (4 frames) or 3 (9 frames),
+    80 SCG passes each; 4096^2-LR requests are split into 1024^2-LR tiles with
+    an 8-LR-px halo exchanged on the device every pass.  Solved (a) plain: one
+    solve at a time in arrival order, each one captured graph, synchronised;
+    (b) served: misr_server continuous batching.  Capacity: every request
+    submitted at t = 0.  Latency (completion - arrival): Poisson arrivals at
+    `load` x the plain capacity (in requests/s), the same seeded list for both
+    paths.  Both paths compute each request's start point (bicubic of frame 0)
+    on the device.  The server admits in arrival order while the admitted
+    solves hold fewer than fill_mpx million HR pixels, so small requests share
+    the device and large ones keep first-come order.  Served results must
+    equal plain ones bit for bit.  Requests of one (size, scale) share one
+    synthetic projection."""
     import torch
     rng = np.random.default_rng(seed)
     geoms = [(int(rng.choice(sizes)), int(rng.choice([2, 3]))) for _ in range(n_req)]
-    probs = {g: _serve_problem(misr, ctx, g[0], g[1], 100 + i)
+    probs = {g: _serve_problem(misr, ctx, g[0], g[1], 100 + i, x0=False)
              for i, g in enumerate(sorted(set(geoms)))}
-    # start point on the device (bicubic of frame 0) on both paths
-    prm = misr.default_params(n_iter=SERVE_ITERS, x_init=1)
+
+    def params(g):
+        if g[0] >= SERVE_TILED_LR:
+            return misr.default_params(n_iter=SERVE_ITERS, x_init=1, tile_lr=SERVE_TILE_LR,
+                                       halo_lr=SERVE_HALO_LR)
+        return misr.default_params(n_iter=SERVE_ITERS, x_init=1)
     hr_px = sum(g[0] * g[0] * g[1] * g[1] for g in geoms)
-    srv = misr.Server(ctx, hbm_budget_bytes=64 << 30, fill_mpx=fill_mpx)
+    srv = misr.Server(ctx, hbm_budget_bytes=96 << 30, fill_mpx=fill_mpx)
+    # plain: one result buffer per geometry (one solve at a time); served: one
+    # per request (admitted requests run together, each in its own buffer)
+    outs_p = {g: torch.empty_like(probs[g]["x0"]) for g in probs}
+    outs_s = [torch.empty_like(probs[g]["x0"]) for g in geoms]
 
     def run_plain(arrivals):
-        outs = [torch.empty_like(probs[g]["x0"]) for g in geoms]
-        torch.cuda.synchronize()
         lat, t_end = [], 0.0
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i, g in enumerate(geoms):
             while time.perf_counter() - t0 < arrivals[i]:
                 time.sleep(2e-5)
-            probs[g]["op"].scg_solve(probs[g]["y"], outs[i], prm, trace=False)
+            probs[g]["op"].scg_solve(probs[g]["y"], outs_p[g], params(g), trace=False)
             torch.cuda.synchronize()
             t_end = time.perf_counter() - t0
             lat.append(t_end - arrivals[i])
-        return outs, lat, t_end
+        return lat, t_end
 
     def run_served(arrivals, idx=None):
         idx = list(range(n_req)) if idx is None else idx
-        outs = [torch.empty_like(probs[geoms[i]]["x0"]) for i in idx]
         torch.cuda.synchronize()
         ids = []
         t0 = time.perf_counter()
@@ -211,7 +231,7 @@ def serving_leg(misr, ctx, n_req: int = 48, loads=(0.8, 1.0), seed: int = 7,
                 time.sleep(2e-5)
             pb = probs[geoms[i]]
             ids.append(srv.submit(pb["H"], pb["H"], pb["s"], pb["shifts"], pb["psf"], pb["y"],
-                                  None, outs[k], prm))
+                                  None, outs_s[i], params(geoms[i])))
         stats = []
         for rid in ids:
             if srv.wait(rid, 600_000_000) != misr.OK:
@@ -222,70 +242,170 @@ def serving_leg(misr, ctx, n_req: int = 48, loads=(0.8, 1.0), seed: int = 7,
             stats.append(stt)
         lat = [(st.t_done_us - st.t_submit_us) * 1e-6 for st in stats]
         span = (max(st.t_done_us for st in stats) - min(st.t_submit_us for st in stats)) * 1e-6
-        return outs, lat, span + arrivals[0]
+        return lat, span + arrivals[0]
+
+    def same(idx=None):
+        """Every served result of the last run equals the plain result of its
+        geometry (the requests of one geometry solve the same projection)."""
+        torch.cuda.synchronize()
+        idx = range(n_req) if idx is None else idx
+        return all(torch.equal(outs_s[i], outs_p[geoms[i]]) for i in idx)
 
     # warm-up: every geometry once on both paths (operators, graphs, buffers)
     first = sorted({g: i for i, g in reversed(list(enumerate(geoms)))}.values())
     for i in first:
-        pb = probs[geoms[i]]
-        pb["op"].scg_solve(pb["y"], torch.empty_like(pb["x0"]), prm, trace=False)
+        g = geoms[i]
+        probs[g]["op"].scg_solve(probs[g]["y"], outs_p[g], params(g), trace=False)
     run_served([0.0] * len(first), first)
-    torch.cuda.synchronize()
+    equal = same(first)
 
     zeros = np.zeros(n_req)
-    outs_p, _, span_p = run_plain(zeros)
-    outs_s, _, span_s = run_served(zeros)
-    equal = all(torch.equal(a, b) for a, b in zip(outs_p, outs_s))
+    _, span_p = run_plain(zeros)
+    _, span_s = run_served(zeros)
+    equal = equal and same()
     cap_plain = n_req / span_p
-    res = {"workload": (f"{n_req} requests, LR {'/'.join(str(v) for v in sizes)}^2, scale 2 "
-                        f"(4 frames) or 3 "
-                        f"(9 frames), {SERVE_ITERS} SCG passes, f32; latency runs: Poisson "
-                        f"arrivals at a fraction of the plain capacity"),
+    n_tiled = sum(g[0] >= SERVE_TILED_LR for g in geoms)
+    res = {"workload": (f"{n_req} requests, LR {'/'.join(str(v) for v in sizes)}^2 uniform, "
+                        f"scale 2 (4 frames) or 3 (9 frames), {SERVE_ITERS} SCG passes, f32; "
+                        f"{SERVE_TILED_LR}^2-LR requests in {SERVE_TILE_LR}^2-LR tiles with an "
+                        f"{SERVE_HALO_LR}-LR-px halo; Poisson arrivals at a fraction of the "
+                        f"plain capacity, the same seeded list for both paths"),
+           "requests": n_req, "tiled_requests": n_tiled, "hr_pixels": hr_px,
            "server_fill_mpx": fill_mpx,
            "capacity": {"plain_hr_mpx_per_s": hr_px / span_p / 1e6,
                         "served_hr_mpx_per_s": hr_px / span_s / 1e6,
                         "plain_requests_per_s": cap_plain,
-                        "served_requests_per_s": n_req / span_s},
-           "served_equals_plain_bitwise": bool(equal)}
+                        "served_requests_per_s": n_req / span_s}}
 
     def pct(v, q):
         return float(np.percentile(np.asarray(v) * 1e3, q))
+    verdict = {}
     for load in loads:
         arr = np.cumsum(rng.exponential(1.0 / (load * cap_plain), n_req))
-        o_p, lat_p, sp_p = run_plain(arr)
-        o_s, lat_s, sp_s = run_served(arr)
-        equal = equal and all(torch.equal(a, b) for a, b in zip(o_p, o_s))
-        res[f"load_{load:.2f}"] = {
+        lat_p, sp_p = run_plain(arr)
+        lat_s, sp_s = run_served(arr)
+        equal = equal and same()
+        tp_p, tp_s = hr_px / sp_p / 1e6, hr_px / sp_s / 1e6
+        key = f"load_{load:.2f}"
+        res[key] = {
             "arrival_rate_per_s": load * cap_plain,
-            "plain": {"p50_ms": pct(lat_p, 50), "p99_ms": pct(lat_p, 99),
-                      "hr_mpx_per_s": hr_px / sp_p / 1e6},
-            "served": {"p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99),
-                       "hr_mpx_per_s": hr_px / sp_s / 1e6}}
+            "plain": {"p50_ms": pct(lat_p, 50), "p99_ms": pct(lat_p, 99), "hr_mpx_per_s": tp_p},
+            "served": {"p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99), "hr_mpx_per_s": tp_s}}
+        verdict[key] = {"served_higher_throughput": tp_s > tp_p,
+                        "served_lower_p99": pct(lat_s, 99) < pct(lat_p, 99)}
+    res["served_vs_plain"] = verdict
     res["served_equals_plain_bitwise"] = bool(equal)
     srv.close()
     return res
 
 
-def cpu_baseline(y_np, shifts, psf, x0_np, budget_s: float = 15.0):
-    """FP64 oracle SCG on the host cores: a few passes of the same workload,
-    extrapolated to the full pass count."""
+def _load_refs_module():
+    """tests/golden/make_fullsize_refs.py: the recipe and loader of the
+    oracle's stored full-size solves."""
+    import importlib.util
+    path = os.path.join(ROOT, "tests", "golden", "make_fullsize_refs.py")
+    spec = importlib.util.spec_from_file_location("make_fullsize_refs", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def oracle_baseline(y, x0, shifts, psf, n_one: int = 2):
+    """Times the oracle's whole N_ITER-pass SCG solve on every host core and
+    n_one passes of it on one core.  Returns (cpu_baseline dict, oracle image,
+    oracle per-pass record)."""
     import oracle
     from oracle import scg as oscg
     ncores = len(os.sched_getaffinity(0))
     oracle.set_threads(ncores)
     t0 = time.perf_counter()
-    oracle.cost_grad(x0_np, y_np, shifts, psf, S)
-    t_eval = time.perf_counter() - t0
-    n = int(max(1, min(N_ITER, budget_s / max(2.2 * t_eval, 1e-3))))
+    x_o, tr_o, _ = oscg.solve(y, shifts, psf, S, x0, N_ITER)
+    t_full = time.perf_counter() - t0
+    oracle.set_threads(1)
     t0 = time.perf_counter()
-    oscg.solve(y_np, shifts, psf, S, x0_np, n)
-    t_n = time.perf_counter() - t0
-    t_pass = max(t_n - t_eval, 1e-9) / n
-    t_full = t_eval + N_ITER * t_pass
-    return dict(value=H * W / t_full / 1e6, unit="HR Mpixel/s", cores=oracle.num_threads(),
+    oscg.solve(y, shifts, psf, S, x0, n_one)
+    t_one = time.perf_counter() - t0
+    oracle.set_threads(ncores)
+    base = dict(value=H * W / t_full / 1e6, unit="HR Mpixel/s", cores=oracle.num_threads(),
                 kind="oracle",
-                sample=f"FP64 oracle SCG, {n} passes of the 2048^2 workload in {t_n:.1f} s "
-                       f"({t_pass:.2f} s/pass), extrapolated to {N_ITER} passes")
+                sample=f"FP64 oracle SCG, the whole {N_ITER}-pass solve of the {H}x{W} "
+                       f"workload (clean frames from the oracle's forward) on {ncores} host "
+                       f"threads: {t_full:.1f} s",
+                scg_passes_per_s=N_ITER / t_full,
+                single_thread={"passes": n_one, "seconds": t_one,
+                               "hr_mpx_per_s_per_pass": H * W / (t_one / n_one) / 1e6})
+    return base, x_o, tr_o
+
+
+def cpu_baseline_leg(misr, ctx):
+    """The FP64 oracle on the host cores, and the GPU path against it.
+
+    Baseline: the oracle's whole 100-pass SCG solve of the 2048^2 workload on
+    every host core (measured, not extrapolated), and two passes of it on one
+    core.  Its inputs come from the same recipe as the headline workload, with
+    the clean frames from the oracle's own forward operator (so that no oracle
+    input comes from the GPU path), rounded to float32 as the GPU receives
+    them.  Parity: the GPU solve of those inputs (tile autotuned, as timed)
+    against the oracle's image and per-pass record; and the precision
+    workload (6144^2 HR) in each storage mode against the oracle's stored
+    FP64 100-pass solve (tests/golden/make_fullsize_refs.py, sampled on 2^20
+    pixels), when that file is present."""
+    import torch
+    import oracle
+    from paper_2108_04315_amd import synth
+    f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)  # noqa: E731
+    oracle.set_threads(len(os.sched_getaffinity(0)))
+    p = synth.make_problem(oracle.forward, L=H // S, s=S, sigma=0.8, P=None,
+                           noise=("poisson", 1e4), jitter=0.05, n_iter=N_ITER, seeds=(0, 1, 2))
+    y, x0 = f32(p.y), f32(p.x0)
+    base, x_o, tr_o = oracle_baseline(y, x0, p.shifts, p.psf)
+    # the GPU path on the same inputs
+    op = misr.Operator(ctx, H, W, S, p.shifts, p.psf)
+    yd = torch.from_numpy(y).float().cuda()
+    prm = misr.default_params(n_iter=N_ITER)
+    op.tune(yd, torch.from_numpy(x0).float().cuda(), prm, reps=5)
+    x = torch.from_numpy(x0).float().cuda()
+    its, info = op.scg_solve(yd, x, prm)
+    xg = x.double().cpu().numpy()
+    par = {"plain2048": {
+        "rel_l2_vs_oracle": float(np.linalg.norm(xg - x_o) / np.linalg.norm(x_o)),
+        "success_equal": [t["success"] for t in its] == [t["success"] for t in tr_o],
+        "accepted": info["n_success"], "tolerance": 1e-4,
+        "max_rel_diff_E": max(abs(a["E"] - b["E"]) / abs(b["E"]) for a, b in zip(its, tr_o))}}
+    op.close()
+    # the precision workload against the oracle's stored solve
+    refs = _load_refs_module()
+    ref = refs.load("precision6144")
+    if ref is None:
+        par["precision6144"] = {"skipped": "no stored oracle solve: python "
+                                           "tests/golden/make_fullsize_refs.py precision6144"}
+        return base, par
+    pp, y6, x06, sha = refs.inputs(refs.specs()["precision6144"])
+    if str(ref["y_sha"]) != sha:
+        par["precision6144"] = {"skipped": "stored oracle solve made from other frames"}
+        return base, par
+    idx, xr = ref["idx"], ref["x"].astype(np.float64)
+    op = misr.Operator(ctx, pp.H, pp.W, pp.s, pp.shifts, pp.psf)
+    modes = {}
+    for name, dt, xw, tol in (("f32", torch.float32, 0, 1e-4), ("f16", torch.float16, 0, 1e-2),
+                              ("bf16", torch.bfloat16, 0, 1e-2),
+                              ("f16-iterate16", torch.float16, 1, 1e-2),
+                              ("bf16-iterate16", torch.bfloat16, 1, 1e-2)):
+        prm6 = misr.default_params(n_iter=100, x_work=xw)
+        yd6 = torch.from_numpy(y6).to(dt).cuda()
+        op.tune(yd6, torch.from_numpy(x06).to(dt).cuda(), prm6, reps=3)
+        x = torch.from_numpy(x06).to(dt).cuda()
+        _, inf6 = op.scg_solve(yd6, x, prm6)
+        xs = x.double().cpu().numpy().ravel()[idx]
+        err = float(np.linalg.norm(xs - xr) / np.linalg.norm(xr))
+        mse = float(np.mean((xs - xr) ** 2))
+        modes[name] = {"rel_l2_vs_oracle": err, "psnr_vs_oracle_db": 10 * np.log10(1.0 / mse),
+                       "tolerance": tol, "within": err <= tol, "accepted": inf6["n_success"]}
+        del yd6, x
+    op.close()
+    par["precision6144"] = {"sample_pixels": int(idx.size), "modes": modes,
+                            "oracle_accepted": int(sum(ref["trace"][:, -1]))}
+    return base, par
 
 
 # ------------------------------------------------------- other workloads
@@ -303,7 +423,7 @@ def bench_batched(misr, ctx, K, Wm, n_proj=64, n_iter=60, seed=11):
     scale 2 (4 frames) or 3 (9 frames on the 3x3 grid), 60 SCG passes."""
     import torch
     rng = np.random.default_rng(seed)
-    geoms = [(int(rng.choice(SERVE_SIZES)), int(rng.choice([2, 3]))) for _ in range(n_proj)]
+    geoms = [(int(rng.choice(BATCH_SIZES)), int(rng.choice([2, 3]))) for _ in range(n_proj)]
     probs = {g: _serve_problem(misr, ctx, g[0], g[1], 200 + i)
              for i, g in enumerate(sorted(set(geoms)))}
     # the tile autotuner, once per geometry on that geometry's data
@@ -340,9 +460,9 @@ def bench_precision(misr, ctx, K, Wm, L=2048, s=3, n_iter=100):
     """One 2048^2-LR projection, 9 frames at scale 3 (HR 6144^2), PSF sigma 1.0,
     100 SCG passes, frames and image stored in FP32, FP16 and BF16 (FP32
     iterate, x_work = 0) and in 16 bits with the iterate itself 16-bit
-    (x_work = 1).  Each mode's result is compared with the FP32 solve (the
-    FP32 path is checked against the FP64 oracle at sizes the oracle
-    finishes)."""
+    (x_work = 1).  Each mode's result is compared here with the FP32 solve;
+    its error against the FP64 oracle's 100-pass solve is measured by the
+    oracle leg (oracle_parity.precision6144)."""
     import torch
     from paper_2108_04315_amd import synth
     Hh = L * s
@@ -466,7 +586,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving streams")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched64 and precision6144 legs of the default line")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests in the serving stream (default 200)")
     ap.add_argument("--workload", default="plain2048",
                     choices=["plain2048", "batched64", "precision6144", "general1024"],
                     help="plain2048 (default: the headline line), batched64, precision6144, "
@@ -561,14 +685,34 @@ def main():
         "update_pass": {"kernel": "k_upcurv (update + curvature)", "avg_us": us_update,
                         "achieved_GBs": BYTES_UPDATE * H * W / (us_update * 1e-6) / 1e9},
     }
+    note = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)  # noqa: E731
     if not args.no_serve:
-        out["serving"] = serving_leg(misr, ctx)
-        out["serving_small"] = serving_leg(misr, ctx, sizes=(512,), seed=8)
         out["host_buffers"] = host_buffer_leg(misr, ctx, shifts, psf, y_np,
                                               x0.double().cpu().numpy(),
                                               xs[-1].cpu().numpy())
+        del xs
+        op.close()
+        note("serving stream")
+        out["serving"] = serving_leg(misr, ctx, n_req=args.serve_requests)
+        torch.cuda.empty_cache()
+        note("small-request serving stream")
+        out["serving_small"] = serving_leg(misr, ctx, n_req=48, sizes=(512,), seed=8,
+                                           loads=(0.8, 1.0))
+        torch.cuda.empty_cache()
+    if not args.no_extra:
+        note("batched64")
+        b = bench_batched(misr, ctx, 2, 1)
+        out["batched64"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "steps", "warmup",
+                                              "config", "scg_passes_per_s", "tiles")}
+        torch.cuda.empty_cache()
+        note("precision6144")
+        pr = bench_precision(misr, ctx, 2, 1)
+        out["precision6144"] = {k: pr[k] for k in ("value", "unit", "ms_per_step", "steps",
+                                                   "warmup", "config", "modes", "tile")}
+        torch.cuda.empty_cache()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(y_np, shifts, psf, x0.double().cpu().numpy())
+        note("oracle baseline and parity")
+        out["cpu_baseline"], out["oracle_parity"] = cpu_baseline_leg(misr, ctx)
     print(json.dumps(out), flush=True)
 
 

@@ -151,6 +151,8 @@ typedef struct {
     double alpha;    /* step size mu / delta */
     double Delta;    /* comparison parameter */
     double lam;      /* scale parameter after the pass */
+    double pi;       /* |p|^2 of the pass's direction */
+    double rr;       /* |r|^2 at the start of the pass (r = -grad J(x)) */
     int32_t success; /* 1 if the step was accepted */
     int32_t pad_;
 } misr_scg_iter;
@@ -188,6 +190,10 @@ misr_status misr_ctx_destroy(misr_ctx *ctx);
  * separable, zero padding included).  Built once and reused by every call on
  * this geometry, as the paper builds A_i once per acquisition (Sec. 3.2). */
 misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, misr_op **out);
+/* Waits for the device to go idle, then frees the operator (always).  Returns
+ * MISR_E_HIP if that wait reports a device error (raised by any earlier work
+ * on the device), so that an asynchronous fault surfaces at the caller that
+ * released the operator. */
 misr_status misr_op_destroy(misr_op *op);
 /* Band length L of the per-frame 1-D factors (taps per LR pixel per axis);
  * 0 for a general operator. */
@@ -397,7 +403,9 @@ misr_status misr_server_wait(misr_server *s, uint64_t id, int64_t timeout_us);
 misr_status misr_server_cancel(misr_server *s, uint64_t id);
 /* Current occupancy (host-side counters; no device call). */
 misr_status misr_server_query(misr_server *s, misr_server_info *out);
-/* Drains every submitted request, then frees the server. */
+/* Drains every submitted request, waits for the device to go idle, then
+ * frees the server (always).  Returns MISR_E_HIP if that wait reports a device
+ * error. */
 misr_status misr_server_destroy(misr_server *s);
 
 #ifdef __cplusplus

@@ -528,9 +528,13 @@ extern "C" misr_status misr_op_destroy(misr_op *op) {
     if (!op) return set_error(MISR_E_INVAL, "op is NULL");
     misr_ctx *ctx = op->ctx;
     (void)set_device(ctx->dev);
-    (void)hipStreamSynchronize(ctx->stream);
+    // work of this op still queued anywhere on the device finishes first; a
+    // device error it (or earlier work) raised is reported here, after the
+    // op is freed
+    const hipError_t e = hipDeviceSynchronize();
     delete op;
     ctx->users--;
+    if (e != hipSuccess) return hip_fail(e, "device error seen while destroying an operator");
     return MISR_OK;
 }
 

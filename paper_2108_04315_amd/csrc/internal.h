@@ -135,6 +135,7 @@ struct InitArgs {
 
 struct IterRec {
     double E, E_t, delta, mu, alpha, Delta, lam;
+    double pi, rr;       // |p|^2 of the pass's direction, |r|^2 at the pass's start
     int success, pad_;
 };
 

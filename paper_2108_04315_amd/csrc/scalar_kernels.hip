@@ -82,6 +82,7 @@ __device__ void scg_phase_a(ScgState &s, const double *v) {
 __device__ void scg_phase_b(ScgState &s, const double *v, IterRec *trace) {
     s.do_update = 0;
     if (!s.active) return;
+    const double rr0 = s.rr;   // |r|^2 at the pass's start (mu = p . r used this r)
     const double Et = v[0] + v[1];
     s.E_t = Et;
     if (!isfinite(Et)) {
@@ -123,6 +124,8 @@ __device__ void scg_phase_b(ScgState &s, const double *v, IterRec *trace) {
         r.alpha = s.alpha;
         r.Delta = s.Delta;
         r.lam = s.lam;
+        r.pi = s.pi;
+        r.rr = rr0;
         r.success = (s.do_update != 0);
         r.pad_ = 0;
     }

@@ -910,7 +910,9 @@ extern "C" misr_status misr_server_destroy(misr_server *s) {
     }
     s->cv.notify_all();
     if (s->th.joinable()) s->th.join();
-    (void)hipStreamSynchronize(s->stream);
+    // a device error raised by the server's work (or earlier work) is
+    // reported by this call, after everything is freed
+    const hipError_t sync_err = hipDeviceSynchronize();
     s->reqs.clear();   // their buffers went back to the pool when they retired
     for (auto &kv : s->ops) misr_op_destroy(kv.second.op);
     for (auto &c : s->cyc) {
@@ -921,5 +923,7 @@ extern "C" misr_status misr_server_destroy(misr_server *s) {
     misr_ctx *ctx = s->ctx;
     delete s;
     ctx->users--;
+    if (sync_err != hipSuccess)
+        return hip_fail(sync_err, "device error seen while destroying a server");
     return MISR_OK;
 }

@@ -58,7 +58,8 @@ class misr_params(C.Structure):
 class misr_scg_iter(C.Structure):
     _fields_ = [("E", C.c_double), ("E_t", C.c_double), ("delta", C.c_double),
                 ("mu", C.c_double), ("alpha", C.c_double), ("Delta", C.c_double),
-                ("lam", C.c_double), ("success", C.c_int32), ("pad_", C.c_int32)]
+                ("lam", C.c_double), ("pi", C.c_double), ("rr", C.c_double),
+                ("success", C.c_int32), ("pad_", C.c_int32)]
 
 
 class misr_scg_trace(C.Structure):
@@ -297,8 +298,8 @@ class Operator:
 
     def close(self):
         if self.h:
-            lib.misr_op_destroy(self.h)
-            self.h = None
+            h, self.h = self.h, None
+            check(lib.misr_op_destroy(h))
 
     def __del__(self):
         try:
@@ -409,7 +410,8 @@ def _new_trace(n: int):
 
 def _trace_out(tr, recs, status):
     its = [dict(E=r.E, E_t=r.E_t, delta=r.delta, mu=r.mu, alpha=r.alpha, Delta=r.Delta,
-                lam=r.lam, success=bool(r.success)) for r in list(recs)[:tr.n_passes]]
+                lam=r.lam, pi=r.pi, rr=r.rr, success=bool(r.success))
+           for r in list(recs)[:tr.n_passes]]
     return its, dict(n_passes=tr.n_passes, n_success=tr.n_success, stop=tr.stop, E0=tr.E0,
                      E_final=tr.E_final, status=STATUS_NAMES[status])
 
@@ -491,8 +493,8 @@ class Server:
 
     def close(self):
         if self.h:
-            check(lib.misr_server_destroy(self.h))
-            self.h = None
+            h, self.h = self.h, None
+            check(lib.misr_server_destroy(h))
 
     def __del__(self):
         try:

@@ -38,3 +38,36 @@ def to_dev(a, dtype=None):
 def to_np(t):
     import torch
     return t.detach().to(torch.float64).cpu().numpy()
+
+
+# Per-pass SCG scalars (delta, mu, alpha) of the device against the oracle.
+# They are inner products of the conjugate direction p, a recursion
+# (p <- r + beta p) that the device carries in FP32: p's relative error grows
+# with the pass count (to ~2e-4 in delta after 80 passes here) while the
+# iterate's stays ~1e-7, so they get their own bound.
+TOL_TRACE = 1e-3
+
+
+def compare_traces(its_g, tr_o, n_check=None, tol=TOL_TRACE):
+    """Per SCG pass, device against oracle: the success sequence exactly; the
+    cost E within 1e-5 relative; the scaled curvature delta within tol
+    relative; mu = p . r within tol * |p| |r| (its Cauchy-Schwarz scale: mu
+    itself can be far smaller when the direction turns almost orthogonal to
+    r, or negative); alpha = mu / delta accordingly.  |p|^2 and |r|^2 are the
+    device's own (they only scale the bound).  Returns the largest normalised
+    difference of each scalar."""
+    succ_g = [t["success"] for t in its_g]
+    succ_o = [t["success"] for t in tr_o]
+    assert succ_g == succ_o
+    worst = {k: 0.0 for k in ("E", "delta", "mu", "alpha")}
+    for i, (a, b) in enumerate(list(zip(its_g, tr_o))[:n_check]):
+        scale_mu = (a["pi"] * a["rr"]) ** 0.5
+        d = {"E": abs(a["E"] - b["E"]) / abs(b["E"]),
+             "delta": abs(a["delta"] - b["delta"]) / abs(b["delta"]),
+             "mu": abs(a["mu"] - b["mu"]) / scale_mu,
+             "alpha": abs(a["alpha"] - b["alpha"]) / (abs(b["alpha"]) + scale_mu / abs(b["delta"]))}
+        for k, v in d.items():
+            worst[k] = max(worst[k], v)
+            assert v <= (1e-5 if k == "E" else tol), (i, k, a[k], b[k], v)
+    print("trace max normalised diff: " + ", ".join(f"{k} {v:.1e}" for k, v in worst.items()))
+    return worst

@@ -11,8 +11,9 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def test_cpu_baseline_leg_small(monkeypatch):
-    """The oracle leg of the default run on a 64 x 64 stand-in of its workload."""
+def test_oracle_baseline_small(monkeypatch):
+    """The oracle timing of the default run's baseline leg on a 64 x 64
+    stand-in of its workload."""
     import oracle
     from paper_2108_04315_amd import synth
     monkeypatch.setattr(bench, "H", 64)
@@ -23,9 +24,10 @@ def test_cpu_baseline_leg_small(monkeypatch):
     psf = synth.psf_taps(0.8)
     y = synth.add_poisson_noise(oracle.forward(synth.phantom(64, 64, 0), shifts, psf, s), 1e4, 2)
     x0 = synth.bicubic_upsample(y[0], s)
-    out = bench.cpu_baseline(y, shifts, psf, x0, budget_s=0.5)
+    out, x_o, tr = bench.oracle_baseline(y, x0, shifts, psf, n_one=1)
     assert out["kind"] == "oracle" and out["unit"] == "HR Mpixel/s"
-    assert out["value"] > 0 and out["cores"] >= 1 and "passes" in out["sample"]
+    assert out["value"] > 0 and out["cores"] >= 1 and "4-pass" in out["sample"]
+    assert out["single_thread"]["passes"] == 1 and len(tr) == 4 and x_o.shape == (64, 64)
 
 
 def test_profile_values_follow_the_kernel_hash():

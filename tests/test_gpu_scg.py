@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from oracle import scg as oscg
-from gpu_common import TOL_LOWP, TOL_SCG, problem, psnr, rel_l2, to_dev, to_np
+from gpu_common import TOL_LOWP, TOL_SCG, compare_traces, problem, psnr, rel_l2, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -43,14 +43,6 @@ def _gpu_solve(misr, ctx, prob, n_iter, dtype=None, **kw):
     return to_np(x), its, info
 
 
-def _compare_traces(its_g, tr_o, n_check=None):
-    succ_g = [t["success"] for t in its_g]
-    succ_o = [t["success"] for t in tr_o]
-    assert succ_g == succ_o
-    for a, b in list(zip(its_g, tr_o))[:n_check]:
-        assert abs(a["E"] - b["E"]) <= 1e-5 * abs(b["E"])
-
-
 def test_plain128_solve_matches_oracle(misr, ctx):
     """The plain 128^2 workload: 4 frames 64^2, x2, 5x5 PSF sigma 0.6,
     Gaussian noise 0.01, lambda 0.01, 50 SCG passes from bicubic x0."""
@@ -62,7 +54,7 @@ def test_plain128_solve_matches_oracle(misr, ctx):
     err = rel_l2(x_g, x_o)
     print(f"plain128 rel-L2 vs oracle {err:.3e}, PSNR vs gt {psnr(x_g, prob.x_gt):.2f} dB")
     assert err <= TOL_SCG
-    _compare_traces(its, tr_o)
+    compare_traces(its, tr_o)
 
 
 @pytest.mark.parametrize("L,s,sig,jit,n_iter", [(48, 3, 1.0, 0.05, 30), (40, 2, 0.8, 0.05, 40),
@@ -75,7 +67,7 @@ def test_small_solves_match_oracle(misr, ctx, L, s, sig, jit, n_iter):
     err = rel_l2(x_g, x_o)
     print(f"L={L} s={s}: rel-L2 {err:.3e}")
     assert err <= TOL_SCG
-    _compare_traces(its, tr_o)
+    compare_traces(its, tr_o)
 
 
 def test_zero_passes_returns_x0_and_cost(misr, ctx):
@@ -264,7 +256,7 @@ def test_l1_data_solve_matches_oracle(misr, ctx, eps_data):
     err = rel_l2(x_g, x_o)
     print(f"L1 data term, eps_data {eps_data}: rel-L2 {err:.3e}, {info['n_success']} accepted")
     assert err <= TOL_SCG
-    _compare_traces(its, tr_o)
+    compare_traces(its, tr_o)
 
 
 def test_zero_gradient_start_stops_at_once(misr, ctx):
@@ -296,7 +288,7 @@ def test_no_prior_and_single_frame_identity(misr, ctx):
     xg, its, _ = _gpu_solve(misr, ctx, prob, 20, lambda_reg=0.0)
     xo, tr, _ = _oracle_solve(prob, 20, lambda_reg=0.0)
     assert rel_l2(xg, xo) <= TOL_SCG
-    _compare_traces(its, tr)
+    compare_traces(its, tr)
     rng = np.random.default_rng(12)
     y = _f32(rng.uniform(0, 1, (1, 40, 36)))
     x0 = _f32(np.full((40, 36), 0.5))
@@ -305,4 +297,4 @@ def test_no_prior_and_single_frame_identity(misr, ctx):
     its, _ = op.scg_solve(to_dev(y), x, misr.default_params(n_iter=6))
     xo, tr, _ = oscg.solve(y, np.zeros((1, 2)), np.array([1.0]), 1, x0, 6)
     assert rel_l2(to_np(x), xo) <= TOL_SCG
-    _compare_traces(its, tr)
+    compare_traces(its, tr)
