@@ -123,6 +123,22 @@ SERVE_TILE_LR = 1024    # ... of 1024^2 LR px ...
 SERVE_HALO_LR = 8       # ... with an 8-LR-px halo exchanged on the device every pass
 
 
+def _json_default(o):
+    """numpy scalars in the result line as plain JSON numbers and booleans."""
+    if isinstance(o, np.bool_):
+        return bool(o)
+    if isinstance(o, np.integer):
+        return int(o)
+    if isinstance(o, np.floating):
+        return float(o)
+    raise TypeError(f"not JSON serialisable: {type(o).__name__}")
+
+
+def _note(msg: str) -> None:
+    """Progress line on stderr (the benchmark's stdout is its one JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def _serve_problem(misr, ctx, L, s, seed, x0=True):
     """One synthetic projection: LR L x L, scale s (4 frames on the {0,1/2}^2
     grid at s=2, 9 frames on the 3x3 grid at s=3), jittered shifts, 7x7 PSF
@@ -193,8 +209,10 @@ def serving_leg(misr, ctx, n_req: int = 200, loads=(0.5, 0.8, 1.0), seed: int = 
     import torch
     rng = np.random.default_rng(seed)
     geoms = [(int(rng.choice(sizes)), int(rng.choice([2, 3]))) for _ in range(n_req)]
-    probs = {g: _serve_problem(misr, ctx, g[0], g[1], 100 + i, x0=False)
-             for i, g in enumerate(sorted(set(geoms)))}
+    probs = {}
+    for i, g in enumerate(sorted(set(geoms))):
+        probs[g] = _serve_problem(misr, ctx, g[0], g[1], 100 + i, x0=False)
+        _note(f"serving: projection LR {g[0]}^2 x{g[1]} ready")
 
     def params(g):
         if g[0] >= SERVE_TILED_LR:
@@ -209,10 +227,13 @@ def serving_leg(misr, ctx, n_req: int = 200, loads=(0.5, 0.8, 1.0), seed: int = 
     outs_s = [torch.empty_like(probs[g]["x0"]) for g in geoms]
 
     def run_plain(arrivals):
+        _note(f"serving: plain run of {n_req} requests")
         lat, t_end = [], 0.0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i, g in enumerate(geoms):
+            if i % 50 == 49:
+                _note(f"serving: plain request {i + 1}")
             while time.perf_counter() - t0 < arrivals[i]:
                 time.sleep(2e-5)
             probs[g]["op"].scg_solve(probs[g]["y"], outs_p[g], params(g), trace=False)
@@ -223,6 +244,7 @@ def serving_leg(misr, ctx, n_req: int = 200, loads=(0.5, 0.8, 1.0), seed: int = 
 
     def run_served(arrivals, idx=None):
         idx = list(range(n_req)) if idx is None else idx
+        _note(f"serving: served run of {len(idx)} requests")
         torch.cuda.synchronize()
         ids = []
         t0 = time.perf_counter()
@@ -233,7 +255,9 @@ def serving_leg(misr, ctx, n_req: int = 200, loads=(0.5, 0.8, 1.0), seed: int = 
             ids.append(srv.submit(pb["H"], pb["H"], pb["s"], pb["shifts"], pb["psf"], pb["y"],
                                   None, outs_s[i], params(geoms[i])))
         stats = []
-        for rid in ids:
+        for k, rid in enumerate(ids):
+            if k % 50 == 49:
+                _note(f"serving: served request {k + 1} done")
             if srv.wait(rid, 600_000_000) != misr.OK:
                 raise RuntimeError("served request did not finish")
             st, stt = srv.poll(rid)
@@ -358,7 +382,9 @@ def cpu_baseline_leg(misr, ctx):
     p = synth.make_problem(oracle.forward, L=H // S, s=S, sigma=0.8, P=None,
                            noise=("poisson", 1e4), jitter=0.05, n_iter=N_ITER, seeds=(0, 1, 2))
     y, x0 = f32(p.y), f32(p.x0)
+    _note(f"oracle: {N_ITER}-pass FP64 solve of the {H}x{W} workload on the host cores")
     base, x_o, tr_o = oracle_baseline(y, x0, p.shifts, p.psf)
+    _note(f"oracle: done ({base['sample']})")
     # the GPU path on the same inputs
     op = misr.Operator(ctx, H, W, S, p.shifts, p.psf)
     yd = torch.from_numpy(y).float().cuda()
@@ -380,6 +406,7 @@ def cpu_baseline_leg(misr, ctx):
         par["precision6144"] = {"skipped": "no stored oracle solve: python "
                                            "tests/golden/make_fullsize_refs.py precision6144"}
         return base, par
+    _note("oracle: precision workload inputs (oracle forward)")
     pp, y6, x06, sha = refs.inputs(refs.specs()["precision6144"])
     if str(ref["y_sha"]) != sha:
         par["precision6144"] = {"skipped": "stored oracle solve made from other frames"}
@@ -400,7 +427,8 @@ def cpu_baseline_leg(misr, ctx):
         err = float(np.linalg.norm(xs - xr) / np.linalg.norm(xr))
         mse = float(np.mean((xs - xr) ** 2))
         modes[name] = {"rel_l2_vs_oracle": err, "psnr_vs_oracle_db": 10 * np.log10(1.0 / mse),
-                       "tolerance": tol, "within": err <= tol, "accepted": inf6["n_success"]}
+                       "tolerance": tol, "within": bool(err <= tol),
+                       "accepted": int(inf6["n_success"])}
         del yd6, x
     op.close()
     par["precision6144"] = {"sample_pixels": int(idx.size), "modes": modes,
@@ -427,6 +455,7 @@ def bench_batched(misr, ctx, K, Wm, n_proj=64, n_iter=60, seed=11):
     probs = {g: _serve_problem(misr, ctx, g[0], g[1], 200 + i)
              for i, g in enumerate(sorted(set(geoms)))}
     # the tile autotuner, once per geometry on that geometry's data
+    _note(f"batched64: {len(probs)} geometries ready")
     tiles = {}
     for g in sorted(probs):
         probs[g]["op"].tune(probs[g]["y"], probs[g]["x0"].clone(),
@@ -480,6 +509,7 @@ def bench_precision(misr, ctx, K, Wm, L=2048, s=3, n_iter=100):
              ("f16-iterate16", torch.float16, 1), ("bf16-iterate16", torch.bfloat16, 1)]
     res, x_ref, dt_f32 = {}, None, None
     for name, dt, xw in modes:
+        _note(f"precision6144: mode {name}")
         y = y32.to(dt)
         prm = misr.default_params(n_iter=n_iter, x_work=xw)
         xs = [x032.to(dt) for _ in range(K + Wm)]
@@ -613,7 +643,7 @@ def main():
     if args.workload != "plain2048":
         fn = {"batched64": bench_batched, "precision6144": bench_precision,
               "general1024": bench_general}[args.workload]
-        print(json.dumps(fn(misr, ctx, K, Wm)), flush=True)
+        print(json.dumps(fn(misr, ctx, K, Wm), default=_json_default), flush=True)
         return
     op, shifts, psf, y, x0, y_np = make_inputs(misr, ctx)
     prm = misr.default_params(n_iter=N_ITER)
@@ -685,7 +715,7 @@ def main():
         "update_pass": {"kernel": "k_upcurv (update + curvature)", "avg_us": us_update,
                         "achieved_GBs": BYTES_UPDATE * H * W / (us_update * 1e-6) / 1e9},
     }
-    note = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)  # noqa: E731
+    note = _note
     if not args.no_serve:
         out["host_buffers"] = host_buffer_leg(misr, ctx, shifts, psf, y_np,
                                               x0.double().cpu().numpy(),
@@ -713,7 +743,7 @@ def main():
     if not args.no_cpu:
         note("oracle baseline and parity")
         out["cpu_baseline"], out["oracle_parity"] = cpu_baseline_leg(misr, ctx)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, default=_json_default), flush=True)
 
 
 if __name__ == "__main__":
