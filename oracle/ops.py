@@ -17,7 +17,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "misr_oracle.c")
-_LIB = os.path.join(_HERE, "libmisr_oracle.so")
+# MISR_ORACLE_SANITIZE=1 loads a build instrumented with AddressSanitizer and
+# UndefinedBehaviorSanitizer (run under LD_PRELOAD of libasan; see build())
+_SAN = os.environ.get("MISR_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "libmisr_oracle_san.so" if _SAN else "libmisr_oracle.so")
 _lib = None
 
 _D = ctypes.c_double
@@ -25,15 +28,21 @@ _I = ctypes.c_int
 _P = ctypes.POINTER(ctypes.c_double)
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (OpenMP, -O2, no fast-math)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
-                               "-fno-fast-math", "-ffp-contract=off",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = True, sanitize: bool = _SAN) -> str:
+    """Compile the oracle with gcc (OpenMP, -O2, no fast-math).  sanitize:
+    the AddressSanitizer + UndefinedBehaviorSanitizer build
+    (libmisr_oracle_san.so), which a process loads with
+    MISR_ORACLE_SANITIZE=1 and LD_PRELOAD=$(gcc -print-file-name=libasan.so)."""
+    lib = os.path.join(_HERE, "libmisr_oracle_san.so" if sanitize else "libmisr_oracle.so")
+    if force or not os.path.exists(lib):
+        tmp = lib + ".tmp"
+        flags = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                 "-fno-omit-frame-pointer"] if sanitize else ["-O2"]
+        subprocess.check_call(["gcc"] + flags + ["-fopenmp", "-fPIC", "-shared",
+                                                 "-fno-fast-math", "-ffp-contract=off",
+                                                 "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 def _load():

@@ -1,6 +1,6 @@
 """Builds libmisr.so (HIP, gfx950) in the package directory.
 
-    python -m paper_2108_04315_amd.build [-v] [--incremental]
+    python -m paper_2108_04315_amd.build [-v] [--incremental] [--sanitize]
 
 The image kernels are compiled once per scale factor (-DMISR_SCALE=s); the
 translation units compile in parallel.
@@ -54,14 +54,24 @@ def _unit_hash(src: str, extra) -> str:
     return h.hexdigest()[:20]
 
 
-def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False) -> str:
+# host code only: the device code is never built with a sanitizer
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False,
+          sanitize: bool = False) -> str:
     """Compiles every unit and links libmisr.so.  incremental: reuse object
-    files under _build/ whose unit hash is unchanged."""
+    files under _build/ whose unit hash is unchanged.  sanitize: link
+    libmisr_san.so instead, its host code instrumented with AddressSanitizer
+    and UndefinedBehaviorSanitizer (loaded when MISR_SANITIZE=1)."""
     jobs = jobs or min(8, os.cpu_count() or 4)
     os.makedirs(OBJ_CACHE, exist_ok=True)
+    san = SAN_FLAGS if sanitize else []
 
     def compile_one(u):
         src, extra, obj = u
+        extra = list(extra) + san
         out = os.path.join(OBJ_CACHE, f"{obj[:-2]}_{_unit_hash(src, extra)}.o")
         if incremental and os.path.exists(out):
             return out
@@ -77,12 +87,17 @@ def build(verbose: bool = False, jobs: int | None = None, incremental: bool = Fa
     units = _units()
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(compile_one, units))
-    tmp = LIB + ".tmp"
+    lib = os.path.join(HERE, "libmisr_san.so") if sanitize else LIB
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    if sanitize:
+        cmd += ["-Xarch_host", "-fsanitize=address,undefined", "-shared-libsan"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+    if sanitize:
+        return lib
     keep = set(objs)
     for f in os.listdir(OBJ_CACHE):
         p = os.path.join(OBJ_CACHE, f)
@@ -92,4 +107,5 @@ def build(verbose: bool = False, jobs: int | None = None, incremental: bool = Fa
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv,
+                sanitize="--sanitize" in sys.argv))

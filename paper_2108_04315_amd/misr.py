@@ -18,7 +18,11 @@ import numpy as np
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmisr.so")
+# MISR_SANITIZE=1 loads the build whose host code carries AddressSanitizer
+# and UndefinedBehaviorSanitizer (python -m paper_2108_04315_amd.build
+# --sanitize; run under LD_PRELOAD of libasan)
+LIB_PATH = os.path.join(_HERE, "libmisr_san.so" if os.environ.get("MISR_SANITIZE") == "1"
+                        else "libmisr.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} not built: run `python -m paper_2108_04315_amd.build`")
 lib = C.CDLL(LIB_PATH)
