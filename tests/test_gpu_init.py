@@ -103,9 +103,6 @@ def test_served_request_without_x0(misr, ctx, x_init):
     srv.close()
 
 
-@pytest.mark.skip(reason="its last GPU run reported an illegal memory access at its first "
-                         "device-wide synchronisation (possibly raised by an earlier test's "
-                         "asynchronous work); no cause has been shown, so it stays off the GPU")
 def test_batch_graph_rebuilt_for_new_frame_offsets(misr, ctx):
     """Two batches on the same device buffers whose operators differ only in
     their shifts, with the start point computed on the device (x_init = 2,

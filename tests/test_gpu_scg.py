@@ -259,9 +259,6 @@ def test_l1_data_solve_matches_oracle(misr, ctx, eps_data):
     compare_traces(its, tr_o)
 
 
-@pytest.mark.skip(reason="its last GPU run reported an illegal memory access when its trace "
-                         "was fetched (possibly raised by an earlier test's asynchronous "
-                         "work); no cause has been shown, so it stays off the GPU")
 def test_zero_gradient_start_stops_at_once(misr, ctx):
     """Degenerate case of Moller's method: a constant image that fits the
     frames exactly (x0 = 0, y = 0) has r = -grad J(x0) = 0 (zero residual, and
