@@ -366,11 +366,13 @@ typedef struct {
     int32_t fail_list_n;      /* fault hook: the n-th work-list allocation fails
                                  (0 off); every request of that cycle then fails
                                  with MISR_E_NOMEM and none of its kernels runs */
-    int32_t max_idle_ops;     /* must be 0: operator eviction is disabled, and
-                                 every cached operator (one per distinct
-                                 geometry) is kept until misr_server_destroy;
-                                 misr_server_create returns MISR_E_INVAL for
-                                 any other value */
+    int32_t max_idle_ops;     /* cached operators (one per distinct geometry)
+                                 that no admitted request uses are kept up to
+                                 this many (0: 8), least recently used evicted
+                                 first; idle ones are also evicted when a
+                                 request would not fit the budget.  Evicting
+                                 waits for the device (misr_op_destroy).
+                                 Negative: MISR_E_INVAL */
 } misr_server_config;
 
 /* Occupancy of a server (misr_server_query). */
@@ -390,6 +392,11 @@ typedef struct {
     misr_status status;
     int32_t pad_;
     double E_final;
+    size_t bytes;             /* device bytes charged to the request while it
+                                 is admitted: its buffers and work-list share */
+    size_t op_bytes;          /* estimate of its operator's tables, charged at
+                                 admission unless the operator is cached (the
+                                 cache then charges the tables' exact size) */
 } misr_req_stats;
 
 misr_status misr_server_create(misr_ctx *ctx, const misr_server_config *cfg,

@@ -453,6 +453,24 @@ static misr_status build_general(misr_op *op, const misr_geometry *g) {
     return MISR_OK;
 }
 
+// The adjoint band passes compute every row (column) of a tile, so a last
+// tile that reaches past the image edge reads weight rows beyond the last LR
+// row: with shifts of at most one LR pixel, up to (extent + L + group + 2 S) / S
+// rows, extent the tile height (width) and group the HR rows (columns) one
+// wave step covers.  The zero padding after each frame covers the largest
+// tile of every compiled variant, so that no load leaves the table.
+void misr::band_pad_after(int S, int Lp, int &pad_y, int &pad_x) {
+    int th = 0, tw = 0;
+    for (int tv = 0; tv < 3; ++tv) {
+        const int key = Lp | (tv << 8);
+        th = std::max(th, tile_hr(S, key));
+        tw = std::max({tw, tile_wr(S, key), tile_wt(S, key)});
+    }
+    const int cu = 8;   // at most 8 HR rows per wave step (pass 3)
+    pad_y = std::max(kPadRows, (th + Lp + cu + 2 * S) / S + 2);
+    pad_x = std::max(kPadRows, (tw + tw / 8 + Lp + 2 * S) / S + 2);
+}
+
 extern "C" misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, misr_op **out) {
     if (!ctx || !out) return set_error(MISR_E_INVAL, "ctx/out is NULL");
     *out = nullptr;
@@ -492,7 +510,10 @@ extern "C" misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, mis
             op->psf.insert(op->psf.end(), g->psf_1d, g->psf_1d + g->psf_size);
     }
     const int h = op->H / op->s, w = op->W / op->s, R = (op->P - 1) / 2;
-    const size_t fy = (size_t)(h + 2 * kPadRows) * op->Lp, fx = (size_t)(w + 2 * kPadRows) * op->Lp;
+    int pad_y = 0, pad_x = 0;
+    band_pad_after(op->s, op->Lp, pad_y, pad_x);
+    const int fsy = h + kPadRows + pad_y, fsx = w + kPadRows + pad_x;
+    const size_t fy = (size_t)fsy * op->Lp, fx = (size_t)fsx * op->Lp;
     std::vector<float> wy((size_t)op->K * fy, 0.f), wx((size_t)op->K * fx, 0.f);
     OpDev &hd = op->host;
     std::memset(&hd, 0, sizeof hd);
@@ -518,6 +539,8 @@ extern "C" misr_status misr_op_create(misr_ctx *ctx, const misr_geometry *g, mis
     hd.s = op->s;
     hd.K = op->K;
     hd.L = op->Lp;
+    hd.fsy = fsy;
+    hd.fsx = fsx;
     MISR_HIP(hipMemcpy(op->opdev.p, &hd, sizeof hd, hipMemcpyHostToDevice));
     ctx->users++;
     *out = op.release();

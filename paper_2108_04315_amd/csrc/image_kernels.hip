@@ -162,20 +162,11 @@ FI void pass2(const float *hx, int NI, int NJ, const AS4 float *wyk, int iA, int
     }
 }
 
-// Weight row of a band table: rows [-kPadRows, n + kPadRows) exist (the
-// padding is zero).  The adjoint passes compute every row and column of a
-// tile, also those past the image edge (their outputs are discarded) and, for
-// large shifts, rows far outside the image: a wave whose rows would leave the
-// table reads clamped rows instead.  Every row outside [0, n) is only ever
-// multiplied by a zero residual, so the clamp changes no result; it keeps
-// the loads inside the table.
-FI int wrow(int r, int n) { return min(max(r, -kPadRows), n + kPadRows - 1); }
-
 // pass 3: tt[u][j] = sum_i wy[i][U - S i - offy] rs[i][j] for the TH rows.
 // PH = (U0 - offy) mod S fixes every tap offset at compile time.
 template <int S, int L, int TV, int PH>
 FI void pass3_ph(const float *rs, float *tt, int U0, int offy, int iA, int iB, int NJ,
-                 const AS4 float *wyk, int h) {
+                 const AS4 float *wyk) {
     using T = Tile<S, L, TV>;
     constexpr int CU = T::CU, NTAP = T::NTAP;
     constexpr int NIG = (PH + CU - 1) / S + NTAP;
@@ -184,30 +175,18 @@ FI void pass3_ph(const float *rs, float *tt, int U0, int offy, int iA, int iB, i
         const int u0 = ug * CU;
         const int q0 = fdiv(U0 + u0 - offy, S);
         const int ib = q0 - (NTAP - 1);
-        // the wave reads table rows ib .. ib + NIG - 1; LR rows outside
-        // [0, h) read the zero padding, rows beyond it are clamped
-        const bool in_table = ib >= -kPadRows && ib + NIG - 1 <= h + kPadRows - 1;
+        // LR rows outside [0, h) read the zero padding of the table (the
+        // rows of a last tile past the image edge included: the padding
+        // after each frame covers the widest compiled tile)
         const AS4 float *wb = wyk + ib * L;
         float wg[CU][NTAP];
-        if (in_table) {
 #pragma unroll
-            for (int c = 0; c < CU; ++c) {
-                const int dq = (PH + c) / S, ph = (PH + c) % S;
+        for (int c = 0; c < CU; ++c) {
+            const int dq = (PH + c) / S, ph = (PH + c) % S;
 #pragma unroll
-                for (int m = 0; m < NTAP; ++m) {
-                    const int l = ph + S * m;
-                    wg[c][m] = (l < L) ? wb[(dq - m + NTAP - 1) * L + l] : 0.f;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < CU; ++c) {
-                const int dq = (PH + c) / S, ph = (PH + c) % S;
-#pragma unroll
-                for (int m = 0; m < NTAP; ++m) {
-                    const int l = ph + S * m;
-                    wg[c][m] = (l < L) ? wyk[wrow(ib + dq - m + NTAP - 1, h) * L + l] : 0.f;
-                }
+            for (int m = 0; m < NTAP; ++m) {
+                const int l = ph + S * m;
+                wg[c][m] = (l < L) ? wb[(dq - m + NTAP - 1) * L + l] : 0.f;
             }
         }
         if (lane < NJ) {
@@ -234,7 +213,7 @@ FI void pass3_ph(const float *rs, float *tt, int U0, int offy, int iA, int iB, i
 // columns; lanes take rows (u = lane - 2).
 template <int S, int L, int TV, int PH>
 FI void pass4_ph(const float *tt, float (&gacc)[Tile<S, L, TV>::CV], int V0, int offx, int jA,
-                 int jB, const AS4 float *wxk, int w) {
+                 int jB, const AS4 float *wxk) {
     using T = Tile<S, L, TV>;
     constexpr int CV = T::CV, NTAP = T::NTAP;
     constexpr int NJG = (PH + CV - 1) / S + NTAP;
@@ -252,53 +231,35 @@ FI void pass4_ph(const float *tt, float (&gacc)[Tile<S, L, TV>::CV], int V0, int
         const float v = tt[ur * T::NJP + (min(max(j, jA), jB) - jA)];
         tv[t] = (j >= jA && j <= jB) ? v : 0.f;
     }
-    // the wave reads table rows jb .. jb + NJG - 1 (clamped where they would
-    // leave the table: the last tile's columns past the image edge)
-    if (jb >= -kPadRows && jb + NJG - 1 <= w + kPadRows - 1) {
 #pragma unroll
-        for (int c = 0; c < CV; ++c) {
-            const int dq = (PH + c) / S, ph = (PH + c) % S;
-            float a = 0.f;
+    for (int c = 0; c < CV; ++c) {
+        const int dq = (PH + c) / S, ph = (PH + c) % S;
+        float a = 0.f;
 #pragma unroll
-            for (int m = 0; m < NTAP; ++m) {
-                const int l = ph + S * m;
-                if (l < L) a = fmaf(wb[(dq - m + NTAP - 1) * L + l], tv[dq - m + NTAP - 1], a);
-            }
-            gacc[c] += a;
+        for (int m = 0; m < NTAP; ++m) {
+            const int l = ph + S * m;
+            if (l < L) a = fmaf(wb[(dq - m + NTAP - 1) * L + l], tv[dq - m + NTAP - 1], a);
         }
-    } else {
-#pragma unroll
-        for (int c = 0; c < CV; ++c) {
-            const int dq = (PH + c) / S, ph = (PH + c) % S;
-            float a = 0.f;
-#pragma unroll
-            for (int m = 0; m < NTAP; ++m) {
-                const int l = ph + S * m;
-                if (l < L)
-                    a = fmaf(wxk[wrow(jb + dq - m + NTAP - 1, w) * L + l],
-                             tv[dq - m + NTAP - 1], a);
-            }
-            gacc[c] += a;
-        }
+        gacc[c] += a;
     }
 }
 
 template <int S, int L, int TV>
 FI void pass3(int ph, const float *rs, float *tt, int U0, int offy, int iA, int iB, int NJ,
-              const AS4 float *wyk, int h) {
-    if (ph == 0) pass3_ph<S, L, TV, 0>(rs, tt, U0, offy, iA, iB, NJ, wyk, h);
-    if constexpr (S > 1) if (ph == 1) pass3_ph<S, L, TV, 1>(rs, tt, U0, offy, iA, iB, NJ, wyk, h);
-    if constexpr (S > 2) if (ph == 2) pass3_ph<S, L, TV, 2>(rs, tt, U0, offy, iA, iB, NJ, wyk, h);
-    if constexpr (S > 3) if (ph == 3) pass3_ph<S, L, TV, 3>(rs, tt, U0, offy, iA, iB, NJ, wyk, h);
+              const AS4 float *wyk) {
+    if (ph == 0) pass3_ph<S, L, TV, 0>(rs, tt, U0, offy, iA, iB, NJ, wyk);
+    if constexpr (S > 1) if (ph == 1) pass3_ph<S, L, TV, 1>(rs, tt, U0, offy, iA, iB, NJ, wyk);
+    if constexpr (S > 2) if (ph == 2) pass3_ph<S, L, TV, 2>(rs, tt, U0, offy, iA, iB, NJ, wyk);
+    if constexpr (S > 3) if (ph == 3) pass3_ph<S, L, TV, 3>(rs, tt, U0, offy, iA, iB, NJ, wyk);
 }
 
 template <int S, int L, int TV>
 FI void pass4(int ph, const float *tt, float (&gacc)[Tile<S, L, TV>::CV], int V0, int offx, int jA,
-              int jB, const AS4 float *wxk, int w) {
-    if (ph == 0) pass4_ph<S, L, TV, 0>(tt, gacc, V0, offx, jA, jB, wxk, w);
-    if constexpr (S > 1) if (ph == 1) pass4_ph<S, L, TV, 1>(tt, gacc, V0, offx, jA, jB, wxk, w);
-    if constexpr (S > 2) if (ph == 2) pass4_ph<S, L, TV, 2>(tt, gacc, V0, offx, jA, jB, wxk, w);
-    if constexpr (S > 3) if (ph == 3) pass4_ph<S, L, TV, 3>(tt, gacc, V0, offx, jA, jB, wxk, w);
+              int jB, const AS4 float *wxk) {
+    if (ph == 0) pass4_ph<S, L, TV, 0>(tt, gacc, V0, offx, jA, jB, wxk);
+    if constexpr (S > 1) if (ph == 1) pass4_ph<S, L, TV, 1>(tt, gacc, V0, offx, jA, jB, wxk);
+    if constexpr (S > 2) if (ph == 2) pass4_ph<S, L, TV, 2>(tt, gacc, V0, offx, jA, jB, wxk);
+    if constexpr (S > 3) if (ph == 3) pass4_ph<S, L, TV, 3>(tt, gacc, V0, offx, jA, jB, wxk);
 }
 
 // The 8 BTV offsets d = (dx, dy) in [0, 2]^2 minus the origin (Eq. prior, w = 3).
@@ -695,8 +656,8 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
         const int jB = min(w - 1, fdiv(o.V0 + T::TW - 1 - offx, S));
         const int NI = iB - iA + 1, NJ = jB - jA + 1;
         if (NI <= 0 || NJ <= 0) continue;
-        const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
-        const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
+        const AS4 float *wyk = cst(op.wy) + (i64)k * op.fsy * L;
+        const AS4 float *wxk = cst(op.wx) + (i64)k * op.fsx * L;
         pass1<S, L, TV>(xs, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
                     S * (NI - 1) + L, NJ, wxk, jA, w - 1, hx);
         __syncthreads();
@@ -728,9 +689,9 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
             }
         });
         __syncthreads();
-        pass3<S, L, TV>(pmod(o.U0 - offy, S), rs, hx, o.U0, offy, iA, iB, NJ, wyk, h);
+        pass3<S, L, TV>(pmod(o.U0 - offy, S), rs, hx, o.U0, offy, iA, iB, NJ, wyk);
         __syncthreads();
-        pass4<S, L, TV>(pmod(o.V0 - offx, S), hx, gacc, o.V0, offx, jA, jB, wxk, w);
+        pass4<S, L, TV>(pmod(o.V0 - offx, S), hx, gacc, o.V0, offx, jA, jB, wxk);
         __syncthreads();
     }
 
@@ -842,8 +803,8 @@ FI double upd_data_part(const AS4 Proj &P, const AS4 ScgState &st, const TileOri
     double ap2 = 0.0;
     for (int k = 0; k < K; ++k) {
         const int offy = op.offy[k], offx = op.offx[k];
-        const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
-        const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
+        const AS4 float *wyk = cst(op.wy) + (i64)k * op.fsy * L;
+        const AS4 float *wxk = cst(op.wx) + (i64)k * op.fsx * L;
         if (DP == 1) {
             pass1<S, L, TV>(xs, S * iA + offy - o.U0 + T::EXT, S * jA + offx - o.V0 + T::EXT,
                         S * (NIo - 1) + L, NJo, wxk, jA, w - 1, hx);
@@ -1045,8 +1006,8 @@ FI void tile_forward(const AS4 Proj &P, int ty, int tx, void *yout, float *sm) {
     AS1 raw *yo = glbw((raw *)yout);
     for (int k = 0; k < K; ++k) {
         const int offy = op.offy[k], offx = op.offx[k];
-        const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
-        const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
+        const AS4 float *wyk = cst(op.wy) + (i64)k * op.fsy * L;
+        const AS4 float *wxk = cst(op.wx) + (i64)k * op.fsx * L;
         pass1<S, L, TV>(xs, offy + T::EXT, offx + T::EXT, S * (NIo - 1) + L, NJo, wxk, jA, w - 1, hx);
         __syncthreads();
         const i64 yb = (i64)k * h * w;
@@ -1086,16 +1047,16 @@ FI void tile_adjoint(const AS4 Proj &P, int ty, int tx, const void *r, float *xo
         const int jB = min(w - 1, fdiv(o.V0 + T::TW - 1 - offx, S));
         const int NI = iB - iA + 1, NJ = jB - jA + 1;
         if (NI <= 0 || NJ <= 0) continue;
-        const AS4 float *wyk = cst(op.wy) + (i64)k * (h + 2 * kPadRows) * L;
-        const AS4 float *wxk = cst(op.wx) + (i64)k * (w + 2 * kPadRows) * L;
+        const AS4 float *wyk = cst(op.wy) + (i64)k * op.fsy * L;
+        const AS4 float *wxk = cst(op.wx) + (i64)k * op.fsx * L;
         for (int q = tid; q < NI * T::NJP; q += kNTI) {
             const int ii = q / T::NJP, jj = q - ii * T::NJP;
             if (jj < NJ) rs[q] = ST::ld(rb, (i64)k * h * w + (i64)(iA + ii) * w + jA + jj);
         }
         __syncthreads();
-        pass3<S, L, TV>(pmod(o.U0 - offy, S), rs, tt, o.U0, offy, iA, iB, NJ, wyk, h);
+        pass3<S, L, TV>(pmod(o.U0 - offy, S), rs, tt, o.U0, offy, iA, iB, NJ, wyk);
         __syncthreads();
-        pass4<S, L, TV>(pmod(o.V0 - offx, S), tt, gacc, o.V0, offx, jA, jB, wxk, w);
+        pass4<S, L, TV>(pmod(o.V0 - offx, S), tt, gacc, o.V0, offx, jA, jB, wxk);
         __syncthreads();
     }
     {

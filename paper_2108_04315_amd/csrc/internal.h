@@ -11,7 +11,7 @@ constexpr int kNT = 256;     // threads per workgroup of the image kernels
 constexpr int kNV = 6;       // FP64 partial sums per work item
 constexpr int kMaxK = 16;    // frames per projection
 constexpr int kMaxL = 16;    // band length
-constexpr int kPadRows = 16; // zero weight rows before and after each frame's table
+constexpr int kPadRows = 16; // zero weight rows before each frame's table
 
 enum StorageType : int { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2, ST_U16 = 3 };
 // Launch code of the image kernels: storage of the views' iterate x (low
@@ -22,9 +22,12 @@ constexpr int st_y(int code) { return code >> 4; }
 
 // Operator of one geometry: per frame the two 1-D factors of A_k.
 // Row factor: LR row i reads HR rows s*i + offy[k] + l, l in [0, L), with
-// weight wy[(k*(h + 2*kPadRows) + i)*L + l]; columns likewise with wx / offx.
-// wy/wx point at row 0 of frame 0; kPadRows zero rows sit before and after
-// every frame's rows so that kernels may index slightly outside [0, h).
+// weight wy[(k*fsy + i)*L + l]; columns likewise with wx / offx / fsx.
+// wy/wx point at row 0 of frame 0; kPadRows zero rows sit before every
+// frame's rows and fsy - h - kPadRows (fsx - w - kPadRows) after them, so
+// that kernels may index outside [0, h): the adjoint passes compute whole
+// tiles, and a last tile past the image edge reads rows up to about a tile
+// extent / s beyond it (band_pad_after).
 //
 // General operators (affine warps or non-separable PSFs, where A_k does not
 // factor) instead carry A = [A_0; ...; A_{K-1}] as an ELL matrix over the
@@ -37,6 +40,7 @@ struct OpDev {
     int offy[kMaxK];
     int offx[kMaxK];
     int H, W, s, K, L;
+    int fsy, fsx;        // frame stride of wy / wx in rows (padding included)
     int a_w, t_w;
     const int *a_col;
     const float *a_val;

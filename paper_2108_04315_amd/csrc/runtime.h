@@ -295,6 +295,9 @@ hipError_t scratch_init(int dev);
 // Band length L of a translational geometry's 1-D factors (before rounding
 // up to a compiled length).
 int band_length(const misr_geometry *g);
+// Zero weight rows after each frame's row (pad_y) and column (pad_x) tables
+// of a banded operator of scale S and compiled band Lp.
+void band_pad_after(int S, int Lp, int &pad_y, int &pad_x);
 
 
 // Tile grid of a tiled solve: tile t = (a, b) owns HR rows [a T, (a+1) T) and

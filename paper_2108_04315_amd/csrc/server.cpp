@@ -42,7 +42,9 @@ struct OpKey {
 };
 
 // A cached operator: the requests admitted on it hold references; with none
-// it is idle.  Cached operators are kept until the server is destroyed.
+// it is idle and may be evicted (least recently used first).  Every request
+// that used it has retired, so none of the work still in flight reads its
+// tables; its destruction waits for the device all the same.
 struct OpEnt {
     misr_op *op = nullptr;
     int refs = 0;
@@ -174,6 +176,11 @@ struct misr_server {
     bool setup(SReq *r);
     void release(SReq *r);
     hipError_t build_list(List &L, const std::vector<SReq *> &rs);
+    // idle operators evicted (caller holds mu) until at most keep remain idle
+    // and, if need > 0, until used + need fits the budget; the operators of
+    // the requests being admitted (spare) are kept
+    void evict_idle(int keep, size_t need, const std::vector<SReq *> *spare = nullptr);
+    int max_idle() const { return cfg.max_idle_ops > 0 ? cfg.max_idle_ops : 8; }
     hipError_t enqueue_init(List &L);
     hipError_t enqueue_image(List &L, int kind, bool fresh);
     hipError_t enqueue_scalar(List &L, int phase, bool fresh);
@@ -261,14 +268,41 @@ static size_t op_bytes_estimate(const misr_geometry &g, bool general) {
         return (size_t)(2 * 8 * e * g.n_frames * h * w) + sizeof(OpDev);
     }
     const int Lp = padded_band(g.scale, band_length(&g));
-    return (size_t)g.n_frames * (size_t)(h + w + 4 * kPadRows) * (size_t)std::max(Lp, 1) * 4 +
-           sizeof(OpDev);
+    int pad_y = 0, pad_x = 0;
+    band_pad_after(g.scale, Lp, pad_y, pad_x);
+    return (size_t)g.n_frames * (size_t)(h + w + 2 * kPadRows + pad_y + pad_x) *
+               (size_t)std::max(Lp, 1) * 4 + sizeof(OpDev);
 }
 
 // Device bytes an operator holds.
 static size_t op_bytes(const misr_op *op) {
     return op->wy.n + op->wx.n + op->opdev.n + op->a_col.n + op->a_val.n + op->t_col.n +
            op->t_val.n;
+}
+
+void misr_server::evict_idle(int keep, size_t need, const std::vector<SReq *> *spare) {
+    auto kept = [&](const OpKey &k) {
+        if (spare)
+            for (const SReq *r : *spare)
+                if (!(r->key < k) && !(k < r->key)) return true;
+        return false;
+    };
+    while (n_idle > 0) {
+        const bool over = n_idle > keep;
+        const bool short_mem = need > 0 && used + need > cfg.hbm_budget_bytes;
+        if (!over && !short_mem) return;
+        auto lru = ops.end();
+        for (auto it = ops.begin(); it != ops.end(); ++it) {
+            if (it->second.refs != 0 || kept(it->first)) continue;
+            if (lru == ops.end() || it->second.last_use < lru->second.last_use) lru = it;
+        }
+        if (lru == ops.end()) return;
+        used -= std::min(used, lru->second.bytes);
+        // a device error seen here also fails the next cycle's launches
+        (void)misr_op_destroy(lru->second.op);
+        ops.erase(lru);
+        --n_idle;
+    }
 }
 
 bool misr_server::setup(SReq *r) {
@@ -366,6 +400,7 @@ void misr_server::release(SReq *r) {
             ++n_idle;
         }
         r->ope = nullptr;
+        evict_idle(max_idle(), 0);
     }
 }
 
@@ -613,6 +648,11 @@ void misr_server::run() {
                 // its buffers, and its operator's tables unless cached
                 const size_t need = r->bytes + (ops.count(r->key) ? 0 : r->op_bytes);
                 if (used + need > cfg.hbm_budget_bytes) {
+                    admitted.push_back(r);   // its operator, and those admitted before it, stay
+                    evict_idle(0, need, &admitted);
+                    admitted.pop_back();
+                }
+                if (used + need > cfg.hbm_budget_bytes) {
                     if (active.empty() && admitted.empty() && !P.pending) {
                         queue.pop_front();
                         r->state = MISR_REQ_FAILED;
@@ -739,9 +779,7 @@ extern "C" misr_status misr_server_create(misr_ctx *ctx, const misr_server_confi
     if (cfg->max_slots < 1 || cfg->hbm_budget_bytes == 0 || cfg->fill_mpx < 0)
         return set_error(MISR_E_INVAL,
                          "max_slots >= 1, hbm_budget_bytes > 0 and fill_mpx >= 0 required");
-    if (cfg->max_idle_ops != 0)
-        return set_error(MISR_E_INVAL, "operator eviction (max_idle_ops) is disabled: cached "
-                         "operators are kept until misr_server_destroy");
+    if (cfg->max_idle_ops < 0) return set_error(MISR_E_INVAL, "max_idle_ops >= 0 required");
     *out = nullptr;
     if (hipSetDevice(ctx->dev) != hipSuccess) return set_error(MISR_E_HIP, "hipSetDevice");
     auto s = std::make_unique<misr_server>();
@@ -841,7 +879,11 @@ extern "C" misr_status misr_server_poll(misr_server *s, uint64_t id, misr_req_st
     if (it == s->reqs.end()) return set_error(MISR_E_NOTFOUND, "unknown request %llu",
                                               (unsigned long long)id);
     if (state) *state = it->second->state;
-    if (stats) *stats = it->second->stats;
+    if (stats) {
+        *stats = it->second->stats;
+        stats->bytes = it->second->bytes;
+        stats->op_bytes = it->second->op_bytes;
+    }
     return MISR_OK;
 }
 

@@ -95,7 +95,8 @@ class misr_server_info(C.Structure):
 class misr_req_stats(C.Structure):
     _fields_ = [("t_submit_us", C.c_double), ("t_admit_us", C.c_double),
                 ("t_done_us", C.c_double), ("n_passes", C.c_int32), ("n_success", C.c_int32),
-                ("status", C.c_int), ("pad_", C.c_int32), ("E_final", C.c_double)]
+                ("status", C.c_int), ("pad_", C.c_int32), ("E_final", C.c_double),
+                ("bytes", C.c_size_t), ("op_bytes", C.c_size_t)]
 
 
 _vp = C.c_void_p

@@ -290,9 +290,6 @@ def test_work_list_allocation_failure_fails_cleanly(misr, ctx, probs):
     srv.close()
 
 
-@pytest.mark.skip(reason="operator eviction is switched off: the one GPU run of this test "
-                         "failed and left the GPU faulted, and no cause has been shown; the "
-                         "server now rejects max_idle_ops != 0")
 def test_operator_cache_stays_bounded(misr, ctx):
     """A stream of requests whose frames all have different (jittered)
     shifts: each needs its own operator, and the server keeps at most
@@ -322,8 +319,50 @@ def test_operator_cache_stays_bounded(misr, ctx):
         srv.close()
 
 
-def test_operator_eviction_rejected(misr, ctx):
-    """Operator eviction is switched off: a server asked for it is refused
-    (host-side check, before any device work)."""
+def _distinct_stream(misr, ctx, srv, n, count, seed0):
+    """count requests, one after another, whose frames all have different
+    (jittered) shifts, so each needs its own operator; each result must equal
+    its solo solve.  Yields the server's occupancy after each."""
+    import torch
+    for i in range(count):
+        p = problem(24, 2, 0.8, None, jitter=0.05, n_iter=n,
+                    seeds=(seed0 + i, seed0 + 20 + i, seed0 + 40 + i))
+        x0 = to_dev(_f32(p.x0))
+        y = to_dev(_f32(p.y))
+        out = torch.empty_like(x0)
+        rid = srv.submit(p.H, p.W, p.s, p.shifts, p.psf, y, x0, out,
+                         misr.default_params(n_iter=n))
+        assert srv.wait(rid, 60_000_000) == misr.OK
+        state, stats = srv.poll(rid)
+        assert state == misr.REQ_DONE
+        assert torch.equal(out, _solo(misr, ctx, p, n))
+        yield stats, srv.info()
+
+
+def test_operator_eviction_by_budget(misr, ctx):
+    """A budget that holds one request and one operator but not a second
+    operator: with count-based eviction out of reach (max_idle_ops large),
+    each new geometry is admitted only by evicting the idle operator of the
+    previous one.  Without eviction the second request would fail with
+    MISR_E_NOMEM (nothing runs, and it does not fit)."""
+    probe = misr.Server(ctx, hbm_budget_bytes=1 << 30, max_idle_ops=100)
+    try:
+        stats, info = next(_distinct_stream(misr, ctx, probe, 4, 1, 300))
+    finally:
+        probe.close()
+    op_exact = info["used_bytes"]           # only the idle operator's tables remain
+    assert info["n_ops"] == 1 and op_exact > 0
+    budget = stats.bytes + stats.op_bytes + op_exact // 2
+    assert budget < stats.bytes + stats.op_bytes + op_exact
+    srv = misr.Server(ctx, hbm_budget_bytes=budget, max_idle_ops=100)
+    try:
+        for _, info in _distinct_stream(misr, ctx, srv, 4, 4, 400):
+            assert info["n_ops"] == 1 and info["n_idle_ops"] == 1
+    finally:
+        srv.close()
+
+
+def test_operator_eviction_negative_rejected(misr, ctx):
+    """max_idle_ops < 0 is refused (host-side check, before any device work)."""
     with pytest.raises(misr.MisrError):
-        misr.Server(ctx, hbm_budget_bytes=1 << 30, max_idle_ops=2)
+        misr.Server(ctx, hbm_budget_bytes=1 << 30, max_idle_ops=-1)
