@@ -545,8 +545,10 @@ def bench_general(misr, ctx, K, Wm, Hh=1024, s=2, n_iter=100, P=7):
     (4 LR frames of 512^2, x2), frame k rotated about the image centre by
     (0, 0.5, -1.0, 1.5) degrees and shifted by its sub-pixel offset, each with
     its own non-separable PSF (a 7 x 7 anisotropic Gaussian rotated by 0.4 k
-    rad); 100 SCG passes.  A and A^T are ELL matrices built on the host; the
-    trial and update passes stream them."""
+    rad); 100 SCG passes.  The value is the matrix-free operator's (A_k
+    applied from its factors); the same solves on the stored form (A and A^T
+    as ELL matrices built on the host, streamed each pass) are timed beside
+    it, with the two results' difference."""
     import math
     import torch
     from paper_2108_04315_amd import synth
@@ -564,49 +566,72 @@ def bench_general(misr, ctx, K, Wm, Hh=1024, s=2, n_iter=100, P=7):
         h = np.exp(-0.5 * (u / (0.7 + 0.1 * k)) ** 2 - 0.5 * (v / 1.1) ** 2)
         psf.append(h / h.sum())
     warps, psf = np.array(warps), np.stack(psf)
-    t0 = time.perf_counter()
-    op = misr.Operator(ctx, Hh, Hh, s, shifts, psf, warps=warps)
-    t_build = time.perf_counter() - t0
+    forms = {}
+    for ell in (False, True):
+        t0 = time.perf_counter()
+        op = misr.Operator(ctx, Hh, Hh, s, shifts, psf, warps=warps, general_ell=ell)
+        forms[ell] = (op, time.perf_counter() - t0)
+        _note(f"general1024: {'stored' if ell else 'matrix-free'} operator built")
+    op, t_build = forms[False]
+    assert op.sparse_width == (0, 0), "the matrix-free kernels did not take the workload"
     clean = op.forward(torch.from_numpy(synth.phantom(Hh, Hh, 12)).float().cuda())
     torch.cuda.synchronize()
     y_np = synth.add_poisson_noise(clean.double().cpu().numpy(), 1e4, 13)
     y = torch.from_numpy(y_np).float().cuda()
     x0 = torch.from_numpy(synth.bicubic_upsample(y_np[0], s)).float().cuda()
     prm = misr.default_params(n_iter=n_iter)
-    xs = [x0.clone() for _ in range(K + Wm)]
-    torch.cuda.synchronize()
-    for i in range(Wm):
-        op.scg_solve(y, xs[i], prm, trace=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(Wm, Wm + K):
-        op.scg_solve(y, xs[i], prm, trace=False)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    us_trial = op.time_pass(y, x0.clone(), 0, reps=20, params=misr.default_params(n_iter=n_iter))
-    us_update = op.time_pass(y, x0.clone(), 1, reps=20, params=misr.default_params(n_iter=n_iter))
-    aw, tw = op.sparse_width
     rows, n = 4 * (Hh // s) ** 2, Hh * Hh
-    # bytes each pass must move with this storage: the ELL entries (4 B column
-    # + 4 B weight) of A and A^T, and the vectors once each
-    b_trial = rows * aw * 8 + n * tw * 8 + rows * 12 + n * 20
-    b_update = rows * aw * 8 + rows * 4 + n * 24
-    out = _base_line(Hh * Hh * K / dt / 1e6, K, Wm, dt, "f32",
+    res = {}
+    for ell, (o, tb) in forms.items():
+        xs = [x0.clone() for _ in range(K + Wm)]
+        torch.cuda.synchronize()
+        for i in range(Wm):
+            o.scg_solve(y, xs[i], prm, trace=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(Wm, Wm + K):
+            o.scg_solve(y, xs[i], prm, trace=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        us_trial = o.time_pass(y, x0.clone(), 0, reps=20, params=misr.default_params(n_iter=n_iter))
+        us_update = o.time_pass(y, x0.clone(), 1, reps=20,
+                                params=misr.default_params(n_iter=n_iter))
+        aw, tw = o.sparse_width
+        # bytes each pass must move: the vectors once each (the trial: x, p
+        # and y read, the residual written and read back, g_k read, g_t
+        # written; the update: x, p, g_t read, x, p written, the new p read
+        # by the forward), plus the ELL entries (4 B column + 4 B weight) of
+        # A and A^T for the stored form
+        b_trial = rows * aw * 8 + n * tw * 8 + rows * 12 + n * 20
+        b_update = rows * aw * 8 + rows * 4 + n * 24
+        res[ell] = dict(dt=dt, x=xs[-1], us_trial=us_trial, us_update=us_update, aw=aw, tw=tw,
+                        b_trial=b_trial, b_update=b_update, build_s=tb)
+        _note(f"general1024: {'stored' if ell else 'matrix-free'} {dt / K * 1e3:.2f} ms per solve")
+    m, e = res[False], res[True]
+    out = _base_line(Hh * Hh * K / m["dt"] / 1e6, K, Wm, m["dt"], "f32",
                      {"workload": f"general1024: 4 LR frames {Hh // s}x{Hh // s} -> {Hh}x{Hh} "
                                   f"HR (x2), per-frame rotation (0, 0.5, -1, 1.5 deg) + "
                                   f"sub-pixel shift, per-frame non-separable {P}x{P} PSF, "
                                   f"{n_iter} SCG passes", "hr": [Hh, Hh], "scale": s,
                       "frames": 4, "scg_passes": n_iter, "parallelism": "1 GPU"})
-    out["operator"] = {"ell_width_A": aw, "ell_width_AT": tw, "build_s": t_build,
-                       "bytes_A_and_AT": rows * aw * 8 + n * tw * 8}
+    out["operator"] = {"form": "matrix-free (warp coefficients + blur-and-bin kernel per frame)",
+                       "build_s": m["build_s"]}
     out["general_passes"] = {
-        "trial": {"kernels": "k_gen_trial_lr + k_gen_trial_hr", "avg_us": us_trial,
-                  "bytes_per_launch": b_trial,
-                  "achieved_GBs": b_trial / (us_trial * 1e-6) / 1e9,
-                  "frac_of_8TBs": b_trial / (us_trial * 1e-6) / 1e9 / PEAK_HBM_GBS},
-        "update": {"kernels": "k_gen_upd_hr + k_gen_upd_lr", "avg_us": us_update,
-                   "bytes_per_launch": b_update,
-                   "achieved_GBs": b_update / (us_update * 1e-6) / 1e9}}
+        "trial": {"kernels": "k_gen_trial_lr + k_gen_trial_hr", "avg_us": m["us_trial"],
+                  "bytes_per_launch": m["b_trial"],
+                  "achieved_GBs": m["b_trial"] / (m["us_trial"] * 1e-6) / 1e9,
+                  "frac_of_8TBs": m["b_trial"] / (m["us_trial"] * 1e-6) / 1e9 / PEAK_HBM_GBS},
+        "update": {"kernels": "k_gen_upd_hr + k_gen_upd_lr", "avg_us": m["us_update"],
+                   "bytes_per_launch": m["b_update"],
+                   "achieved_GBs": m["b_update"] / (m["us_update"] * 1e-6) / 1e9}}
+    xm, xe = m["x"].double(), e["x"].double()
+    out["stored_form"] = {
+        "hr_mpx_per_s": Hh * Hh * K / e["dt"] / 1e6, "ms_per_solve": e["dt"] / K * 1e3,
+        "ell_width_A": e["aw"], "ell_width_AT": e["tw"], "build_s": e["build_s"],
+        "bytes_A_and_AT": rows * e["aw"] * 8 + n * e["tw"] * 8,
+        "trial_us": e["us_trial"], "update_us": e["us_update"],
+        "matrix_free_speedup": e["dt"] / m["dt"],
+        "rel_l2_matrix_free_vs_stored": float(torch.linalg.norm(xm - xe) / torch.linalg.norm(xe))}
     return out
 
 

@@ -86,12 +86,17 @@ typedef struct {
                                  D B_k M_k), vertical taps then horizontal taps,
                                  B_k their outer product; overrides psf_1d */
     /* General operators (A_k = D B_k M_k with a general M_k or B_k).  When
-     * either field below is set the operator is stored as a sparse matrix
-     * (ELL, A and its transpose, about 2 x 8 B x (P + s + 2)^2 per LR pixel
-     * and frame of device memory, built on the host at misr_op_create) and
-     * runs on the general kernels: FP32 images (img_dtype MISR_F32, y_u16 = 0),
-     * untiled (tile_lr = 0), x_init 0 or 1 (solves, batches and served
-     * requests alike); misr_interpolate is rejected. */
+     * either field below is set the operator runs on the general kernels:
+     * FP32 images (img_dtype MISR_F32, y_u16 = 0), untiled (tile_lr = 0),
+     * x_init 0 or 1 (solves, batches and served requests alike);
+     * misr_interpolate is rejected.  A_k is evaluated from its factors
+     * (matrix-free: the warp's six coefficients and a Q x Q blur-and-bin
+     * kernel per frame, Q = s + P - 1) when every frame's warp is invertible
+     * and the windows its adjoint gathers from fit the kernels' local memory
+     * (warps that shrink the image by less than about 3x); otherwise, or with
+     * general_ell = 1, A and its transpose are stored as sparse matrices
+     * (ELL, about 2 x 8 B x (P + s + 2)^2 per LR pixel and frame of device
+     * memory, built on the host at misr_op_create). */
     const double *warps;      /* NULL, or [K][6]: frame k's warp M_k samples x
                                  bilinearly at row w0 u + w1 v + w2, column
                                  w3 u + w4 v + w5 for HR pixel (u, v) (zero off
@@ -101,6 +106,9 @@ typedef struct {
                                  h[a + R][b + R] weighting the sample at offset
                                  (-a, -b), R = (P - 1) / 2 (zero padding);
                                  overrides psf_1d and psf_frames */
+    int32_t general_ell;      /* 1: a general operator is stored as sparse
+                                 matrices even where the matrix-free kernels
+                                 apply (0: matrix-free where they apply) */
 } misr_geometry;
 
 /* Objective and solver settings (Eq. objective, Eq. prior, Algorithm 1). */
@@ -199,8 +207,9 @@ misr_status misr_op_destroy(misr_op *op);
  * 0 for a general operator. */
 int misr_op_band(const misr_op *op);
 /* Entries per row of a general operator's sparse matrices: *a_w for A (per LR
- * pixel and frame), *t_w for A^T (per HR pixel); both 0 for a banded
- * operator.  MISR_E_INVAL on NULL arguments. */
+ * pixel and frame), *t_w for A^T (per HR pixel); both 0 for a banded or a
+ * matrix-free general operator (no stored matrices).  MISR_E_INVAL on NULL
+ * arguments. */
 misr_status misr_op_sparse_width(const misr_op *op, int32_t *a_w, int32_t *t_w);
 
 /* Tile autotuner: times the trial and update passes (alternating, as in a

@@ -322,8 +322,116 @@ static void general_row(const misr_op *op, const double *m, const double *hk, in
     ent.resize(o);
 }
 
-// Builds A and A^T of a general operator as ELL matrices (host, FP64 weights
-// rounded to FP32 once) and uploads them.
+// Frame k's warp of a general geometry (its shift as a translation when no
+// warps are given) and its P x P PSF.
+static void general_warp(const misr_geometry *g, int k, double m[6]) {
+    if (g->warps) {
+        std::copy(g->warps + 6 * k, g->warps + 6 * k + 6, m);
+        return;
+    }
+    const double s = g->scale;
+    const double ty = g->shifts_lr ? s * g->shifts_lr[2 * k + 1] : 0.0;
+    const double tx = g->shifts_lr ? s * g->shifts_lr[2 * k] : 0.0;
+    const double mm[6] = {1.0, 0.0, ty, 0.0, 1.0, tx};
+    std::copy(mm, mm + 6, m);
+}
+
+static void general_psf(const misr_geometry *g, int k, double *hk) {
+    const int P = g->psf_size;
+    if (g->psf_2d) {
+        std::copy(g->psf_2d + (size_t)k * P * P, g->psf_2d + (size_t)(k + 1) * P * P, hk);
+        return;
+    }
+    const double *vy = g->psf_frames ? g->psf_frames + (size_t)k * 2 * P : g->psf_1d;
+    const double *vx = g->psf_frames ? vy + P : g->psf_1d;
+    for (int a = 0; a < P; ++a)
+        for (int b = 0; b < P; ++b) hk[a * P + b] = vy[a] * vx[b];
+}
+
+long long misr::mf_lr_tiles(int H, int W, int s, int K) {
+    const long long h = H / s, w = W / s;
+    const long long nt = ((h + kMfTI - 1) / kMfTI) * ((w + kMfTJ - 1) / kMfTJ);
+    return (long long)K * ((nt + kMfLRG - 1) / kMfLRG);
+}
+
+long long misr::mf_hr_tiles(int H, int W) {
+    return (long long)((H + kMfTU - 1) / kMfTU) * ((W + kMfTV - 1) / kMfTV);
+}
+
+// Matrix-free form of a general operator (Eq. sisr, A_k = D B_k M_k from its
+// factors).  Per frame: the inverse warp; the half extents eu, ev of the
+// preimage of a pixel's bilinear support (|r - pr| < 1, |c - pc| < 1 maps to
+// |u - u(pr, pc)| < |gi0| + |gi1|); the candidates per axis (floor(2 eu) + 1
+// from floor(u - eu) + 1); the caps on an adjoint tile's back-projection
+// window (every candidate of the tile's pixels: floor of the preimage's
+// extent plus 2, one position of slack) and its residual window, which with
+// the padded kernel must fit the kernel's LDS.  The blur-and-bin kernel: LR pixel
+// (i, j) averages the s x s block (s i + a, s j + b) of the PSF-blurred
+// warped image, and the blur takes h[pa + R][pb + R] times the warped image
+// at (U - pa, V - pb), so the warped image at (s i + al - R, s j + be - R)
+// weighs C[al][be] = sum over a, b < s of h[a + 2R - al][b + 2R - be] / s^2
+// (terms outside the PSF dropped).
+bool misr::general_mf_plan(const misr_geometry *g, OpDev *hd, std::vector<float> *ker) {
+    if (g->general_ell) return false;
+    const int s = g->scale, K = g->n_frames, P = g->psf_size, Q = s + P - 1, R = (P - 1) / 2;
+    if (Q > kMfQmax || K > kMaxK) return false;
+    OpDev tmp;
+    OpDev &d = hd ? *hd : tmp;
+    for (int k = 0; k < K; ++k) {
+        double m[6];
+        general_warp(g, k, m);
+        const double det = m[0] * m[4] - m[1] * m[3];
+        if (!(std::fabs(det) > 1e-9)) return false;
+        const double gi[6] = {m[4] / det, -m[1] / det, 0.0, -m[3] / det, m[0] / det, 0.0};
+        const double eu = std::fabs(gi[0]) + std::fabs(gi[1]);
+        const double ev = std::fabs(gi[3]) + std::fabs(gi[4]);
+        if (!(eu <= 64.0 && ev <= 64.0)) return false;
+        const double lu = (kMfTU - 1) * std::fabs(gi[0]) + (kMfTV - 1) * std::fabs(gi[1]) + 2 * eu;
+        const double lv = (kMfTU - 1) * std::fabs(gi[3]) + (kMfTV - 1) * std::fabs(gi[4]) + 2 * ev;
+        const long long ru = (long long)std::floor(lu) + 3, rv = (long long)std::floor(lv) + 3;
+        const long long nt = (Q + s - 1) / s;
+        const long long ni = (ru + s - 1) / s + nt, nj = (rv + s - 1) / s + nt;
+        if (ru * rv + ni * nj > kMfWin || s * nt > kMfQP) return false;
+        std::copy(m, m + 6, d.gm[k]);
+        d.gi[k][0] = gi[0];
+        d.gi[k][1] = gi[1];
+        d.gi[k][2] = -(gi[0] * m[2] + gi[1] * m[5]);
+        d.gi[k][3] = gi[3];
+        d.gi[k][4] = gi[4];
+        d.gi[k][5] = -(gi[3] * m[2] + gi[4] * m[5]);
+        d.eu[k] = eu;
+        d.ev[k] = ev;
+        d.ncu[k] = (int)std::floor(2 * eu) + 1;
+        d.ncv[k] = (int)std::floor(2 * ev) + 1;
+        d.ru[k] = (int)ru;
+        d.rv[k] = (int)rv;
+    }
+    d.mf = 1;
+    d.P = P;
+    d.Q = Q;
+    if (ker) {
+        ker->assign((size_t)K * Q * Q, 0.f);
+        std::vector<double> hk((size_t)P * P);
+        for (int k = 0; k < K; ++k) {
+            general_psf(g, k, hk.data());
+            for (int al = 0; al < Q; ++al)
+                for (int be = 0; be < Q; ++be) {
+                    double c = 0.0;
+                    for (int a = 0; a < s; ++a)
+                        for (int b = 0; b < s; ++b) {
+                            const int ia = a + 2 * R - al, ib = b + 2 * R - be;
+                            if (ia >= 0 && ia < P && ib >= 0 && ib < P) c += hk[ia * P + ib];
+                        }
+                    (*ker)[((size_t)k * Q + al) * Q + be] = (float)(c / ((double)s * s));
+                }
+        }
+    }
+    return true;
+}
+
+// Builds a general operator: matrix-free where general_mf_plan takes it,
+// else A and A^T as ELL matrices (host, FP64 weights rounded to FP32 once),
+// uploaded.
 static misr_status build_general(misr_op *op, const misr_geometry *g) {
     op->general = true;
     op->L = op->Lp = op->TH = op->TW = op->TWt = 0;
@@ -332,25 +440,27 @@ static misr_status build_general(misr_op *op, const misr_geometry *g) {
     const long long rows = (long long)K * h * w, n = (long long)H * W;
     op->shifts.assign(2 * (size_t)K, 0.0);
     if (g->shifts_lr) op->shifts.assign(g->shifts_lr, g->shifts_lr + 2 * K);
+    {
+        OpDev &hd = op->host;
+        std::memset(&hd, 0, sizeof hd);
+        hd.H = H;
+        hd.W = W;
+        hd.s = s;
+        hd.K = K;
+        std::vector<float> ker;
+        if (general_mf_plan(g, &hd, &ker)) {
+            MISR_HIP(op->gker.ensure(ker.size() * 4));
+            MISR_HIP(hipMemcpy(op->gker.p, ker.data(), ker.size() * 4, hipMemcpyHostToDevice));
+            hd.gker = op->gker.as<float>();
+            MISR_HIP(op->opdev.ensure(sizeof(OpDev)));
+            MISR_HIP(hipMemcpy(op->opdev.p, &hd, sizeof hd, hipMemcpyHostToDevice));
+            return MISR_OK;
+        }
+    }
     std::vector<double> warp(6 * (size_t)K), psf((size_t)K * P * P);
     for (int k = 0; k < K; ++k) {
-        double *m = warp.data() + 6 * k;
-        if (g->warps) {
-            std::copy(g->warps + 6 * k, g->warps + 6 * k + 6, m);
-        } else {
-            const double mm[6] = {1.0, 0.0, s * op->shifts[2 * k + 1], 0.0, 1.0,
-                                  s * op->shifts[2 * k]};
-            std::copy(mm, mm + 6, m);
-        }
-        double *hk = psf.data() + (size_t)k * P * P;
-        if (g->psf_2d) {
-            std::copy(g->psf_2d + (size_t)k * P * P, g->psf_2d + (size_t)(k + 1) * P * P, hk);
-        } else {
-            const double *vy = g->psf_frames ? g->psf_frames + (size_t)k * 2 * P : g->psf_1d;
-            const double *vx = g->psf_frames ? vy + P : g->psf_1d;
-            for (int a = 0; a < P; ++a)
-                for (int b = 0; b < P; ++b) hk[a * P + b] = vy[a] * vx[b];
-        }
+        general_warp(g, k, warp.data() + 6 * k);
+        general_psf(g, k, psf.data() + (size_t)k * P * P);
     }
     // rows in parallel chunks: (columns, weights) per row, then the ELL width
     const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -437,7 +547,7 @@ static misr_status build_general(misr_op *op, const misr_geometry *g) {
     MISR_HIP(hipMemcpy(op->t_col.p, tcol.data(), tcol.size() * 4, hipMemcpyHostToDevice));
     MISR_HIP(hipMemcpy(op->t_val.p, tval.data(), tval.size() * 4, hipMemcpyHostToDevice));
     OpDev &hd = op->host;
-    std::memset(&hd, 0, sizeof hd);
+    std::memset(&hd, 0, sizeof hd);   // mf = 0: the stored form
     hd.H = H;
     hd.W = W;
     hd.s = s;
@@ -683,8 +793,8 @@ void misr::add_views(const misr_op *op, const misr_params &prm, const void *y, v
     P.y = y;
     P.op = op->opdev.as<OpDev>();
     if (op->general) {
-        // one untiled FP32 view; items of kGenRows rows, LR rows (role 0)
-        // then HR rows (role 1), in both lists
+        // one untiled FP32 view; LR items (role 0) then HR items (role 1),
+        // in both lists
         P.x[0] = x;
         P.x[1] = bufs->x1.p;
         P.p[0] = bufs->p0.as<float>();
@@ -698,11 +808,16 @@ void misr::add_views(const misr_op *op, const misr_params &prm, const void *y, v
         P.ox1 = P.ux1 = op->W;
         const int pj = (int)projs.size();
         projs.push_back(P);
+        // matrix-free: LR tiles (all frames) then HR tiles; stored: blocks
+        // of kGenRows LR rows then HR rows
         const long long rows = (long long)op->K * (op->H / op->s) * (op->W / op->s);
         const long long n = (long long)op->H * op->W;
+        const long long nlr = op->host.mf ? mf_lr_tiles(op->H, op->W, op->s, op->K)
+                                          : (rows + kGenRows - 1) / kGenRows;
+        const long long nhr = op->host.mf ? mf_hr_tiles(op->H, op->W) : (n + kGenRows - 1) / kGenRows;
         for (auto *lst : {&items, &items_u}) {
-            for (long long b = 0; b * kGenRows < rows; ++b) lst->push_back(Item{pj, (int)b, 0, 0});
-            for (long long b = 0; b * kGenRows < n; ++b) lst->push_back(Item{pj, (int)b, 1, 0});
+            for (long long b = 0; b < nlr; ++b) lst->push_back(Item{pj, (int)b, 0, 0});
+            for (long long b = 0; b < nhr; ++b) lst->push_back(Item{pj, (int)b, 1, 0});
         }
         return;
     }
@@ -1010,9 +1125,10 @@ extern "C" misr_status misr_forward(const misr_op *cop, misr_dtype dt, const voi
     MISR_HIP(set_device(op->ctx->dev));
     if (op->general) {
         if (dt != MISR_F32) return set_error(MISR_E_INVAL, "general operators take FP32 images");
-        MISR_HIP(launch_general_forward((hipStream_t)stream, op->opdev.as<OpDev>(),
-                                        (long long)op->K * (op->H / op->s) * (op->W / op->s),
-                                        (const float *)x, (float *)y));
+        MISR_HIP(launch_general_forward(
+            (hipStream_t)stream, op->opdev.as<OpDev>(),
+            (long long)op->K * (op->H / op->s) * (op->W / op->s), (const float *)x, (float *)y,
+            op->host.mf ? mf_lr_tiles(op->H, op->W, op->s, op->K) : 0));
         return MISR_OK;
     }
     Plan &pl = op->plan;
@@ -1038,7 +1154,8 @@ extern "C" misr_status misr_adjoint(const misr_op *cop, misr_dtype dt, const voi
     if (op->general) {
         if (dt != MISR_F32) return set_error(MISR_E_INVAL, "general operators take FP32 images");
         MISR_HIP(launch_general_adjoint((hipStream_t)stream, op->opdev.as<OpDev>(),
-                                        (long long)op->H * op->W, (const float *)r, x));
+                                        (long long)op->H * op->W, (const float *)r, x,
+                                        op->host.mf ? mf_hr_tiles(op->H, op->W) : 0));
         return MISR_OK;
     }
     Plan &pl = op->plan;

@@ -30,10 +30,19 @@ constexpr int st_y(int code) { return code >> 4; }
 // extent / s beyond it (band_pad_after).
 //
 // General operators (affine warps or non-separable PSFs, where A_k does not
-// factor) instead carry A = [A_0; ...; A_{K-1}] as an ELL matrix over the
-// K h w LR rows, a_w entries per row, entry q of row r at [q * rows + r]
-// (padding: weight 0 on one of the row's own columns), and its transpose the
-// same way over the H W HR rows; wy/wx are then NULL.
+// factor; wy/wx are then NULL) are evaluated from their factors (mf = 1):
+// per frame the warp (row gm[k][0] u + gm[k][1] v + gm[k][2], column
+// gm[k][3] u + gm[k][4] v + gm[k][5] for HR pixel (u, v)), its inverse gi[k]
+// (u = gi[k][0] r + gi[k][1] c + gi[k][2], v likewise), the half extents
+// eu/ev of the preimage of a pixel's bilinear support (|u - u(r, c)| < eu),
+// the candidates per axis ncu/ncv (floor(2 eu) + 1), the caps ru/rv on the
+// back-projection window of an adjoint tile, and gker: the blur-and-bin
+// kernel C_k[a][b] (Q x Q, Q = s + P - 1) that takes the warped image at
+// (s i + a - R, s j + b - R) to LR pixel (i, j).  Warps whose windows exceed
+// the kernels' LDS (mf = 0) instead carry A = [A_0; ...; A_{K-1}] as an ELL
+// matrix over the K h w LR rows, a_w entries per row, entry q of row r at
+// [q * rows + r] (padding: weight 0 on one of the row's own columns), and
+// its transpose the same way over the H W HR rows.
 struct OpDev {
     const float *wy;
     const float *wx;
@@ -46,7 +55,27 @@ struct OpDev {
     const float *a_val;
     const int *t_col;
     const float *t_val;
+    int mf, P, Q, pad_;
+    int ncu[kMaxK], ncv[kMaxK], ru[kMaxK], rv[kMaxK];
+    double gm[kMaxK][6], gi[kMaxK][6];
+    double eu[kMaxK], ev[kMaxK];
+    const float *gker;
 };
+
+// Matrix-free general kernels: the forward takes LR tiles of kMfTI x kMfTJ
+// pixels (one per thread), the adjoint and update HR tiles of kMfTU x kMfTV
+// pixels (four per thread).  LDS: the forward's warped window holds
+// (s (kMfTI - 1) + Q) x (s (kMfTJ - 1) + Q) floats (at most kMfZ); the
+// adjoint's residual and back-projection windows together at most kMfWin,
+// its copy of the kernel padded to s ceil(Q / s) rows and columns at most
+// kMfQP^2.
+constexpr int kMfTI = 8, kMfTJ = 32;
+constexpr int kMfLRG = 1;   // LR tiles per forward work item
+constexpr int kMfTU = 16, kMfTV = 64;
+constexpr int kMfQmax = 4 + 15 - 1;
+constexpr int kMfQP = 20;
+constexpr int kMfZ = (4 * (kMfTI - 1) + kMfQmax) * (4 * (kMfTJ - 1) + kMfQmax);
+constexpr int kMfWin = 7424;
 
 // Rows (LR or HR pixels) per work item of the general-operator kernels; an
 // item's tx is its role: 0 LR rows (forward, residual), 1 HR rows (adjoint,

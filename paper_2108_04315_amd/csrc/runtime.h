@@ -39,10 +39,11 @@ hipError_t launch_adjoint(int S, int Lp, int grid, hipStream_t stream, const Pro
 // items (kind as launch_image), and the standalone FP32 operators
 hipError_t launch_general(int grid, hipStream_t stream, const Proj *projs, const Item *items,
                           const int *n_items, double *partials, int kind);
+// (mf_tiles > 0: a matrix-free operator, one workgroup per tile)
 hipError_t launch_general_forward(hipStream_t stream, const OpDev *op, long long rows,
-                                  const float *x, float *y);
+                                  const float *x, float *y, long long mf_tiles);
 hipError_t launch_general_adjoint(hipStream_t stream, const OpDev *op, long long n,
-                                  const float *r, float *x);
+                                  const float *r, float *x, long long mf_tiles);
 hipError_t launch_scalar(int grid, hipStream_t stream, const SolveRef *refs, const int *n_refs,
                          const double *partials, const double *partials_u, int phase);
 hipError_t launch_halo(hipStream_t stream, const Proj *projs, const HaloCopy *copies,
@@ -273,6 +274,7 @@ struct misr_op {
     // matrices (L = Lp = TH = TW = 0; the work-list class key is (s, 0))
     bool general = false;
     misr::DevMem a_col, a_val, t_col, t_val;
+    misr::DevMem gker;                 // matrix-free: blur-and-bin kernels (K x Q x Q)
     misr::OpDev host;
     std::mutex mu;
     // final SCG state of the last misr_scg_solve (read by misr_scg_status)
@@ -298,6 +300,16 @@ int band_length(const misr_geometry *g);
 // Zero weight rows after each frame's row (pad_y) and column (pad_x) tables
 // of a banded operator of scale S and compiled band Lp.
 void band_pad_after(int S, int Lp, int &pad_y, int &pad_x);
+// General geometry: whether the matrix-free kernels take it (every frame's
+// warp invertible and its adjoint windows within the LDS) unless
+// general_ell asks for the stored form; with hd non-NULL also fills its
+// matrix-free fields (mf, P, Q, gm, gi, eu, ev, ncu, ncv, ru, rv) and, with
+// ker non-NULL, the blur-and-bin kernels (K x Q x Q).
+bool general_mf_plan(const misr_geometry *g, OpDev *hd, std::vector<float> *ker);
+// Work items of a matrix-free general operator: groups of kMfLRG LR tiles
+// over all frames, HR tiles.
+long long mf_lr_tiles(int H, int W, int s, int K);
+long long mf_hr_tiles(int H, int W);
 
 
 // Tile grid of a tiled solve: tile t = (a, b) owns HR rows [a T, (a+1) T) and

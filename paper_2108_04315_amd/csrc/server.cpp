@@ -32,11 +32,11 @@ double now_us() {
 }
 
 struct OpKey {
-    int H, W, s, K, P;
+    int H, W, s, K, P, ell;
     std::vector<double> shifts, psf, psf_frames, warps, psf_2d;
     bool operator<(const OpKey &o) const {
-        return std::tie(H, W, s, K, P, shifts, psf, psf_frames, warps, psf_2d) <
-               std::tie(o.H, o.W, o.s, o.K, o.P, o.shifts, o.psf, o.psf_frames, o.warps,
+        return std::tie(H, W, s, K, P, ell, shifts, psf, psf_frames, warps, psf_2d) <
+               std::tie(o.H, o.W, o.s, o.K, o.P, o.ell, o.shifts, o.psf, o.psf_frames, o.warps,
                         o.psf_2d);
     }
 };
@@ -228,7 +228,10 @@ static size_t list_bytes(const misr_request &q, bool general) {
     long long ni = 0, nu = 0, nviews = 1, nhalo = 0;
     auto cd = [](long long a, long long b) { return (a + b - 1) / b; };
     if (general) {
-        ni = nu = cd((long long)K * (H / s) * (W / s), kGenRows) + cd((long long)H * W, kGenRows);
+        ni = nu = general_mf_plan(&q.geom, nullptr, nullptr)
+                      ? mf_lr_tiles(H, W, s, K) + mf_hr_tiles(H, W)
+                      : cd((long long)K * (H / s) * (W / s), kGenRows) +
+                            cd((long long)H * W, kGenRows);
     } else {
         const int Lp = padded_band(s, band_length(&q.geom));
         const int TH = tile_hr(s, Lp), TW = tile_wr(s, Lp), TWt = tile_wt(s, Lp);
@@ -259,10 +262,15 @@ static size_t list_bytes(const misr_request &q, bool general) {
 }
 
 // Device bytes of an operator's tables before it is built: the banded
-// factors' weight rows, or the sparse A and A^T of a general geometry (at most
+// factors' weight rows, a matrix-free general operator's blur-and-bin
+// kernels, or the sparse A and A^T of a stored general geometry (at most
 // (P + s + 2)^2 entries of 8 B per LR pixel and frame, each way).
 static size_t op_bytes_estimate(const misr_geometry &g, bool general) {
     const long long h = g.hr_h / g.scale, w = g.hr_w / g.scale;
+    if (general && general_mf_plan(&g, nullptr, nullptr)) {
+        const long long Q = g.scale + g.psf_size - 1;
+        return (size_t)(4 * Q * Q * g.n_frames) + sizeof(OpDev);
+    }
     if (general) {
         const long long e = (long long)(g.psf_size + g.scale + 2) * (g.psf_size + g.scale + 2);
         return (size_t)(2 * 8 * e * g.n_frames * h * w) + sizeof(OpDev);
@@ -277,7 +285,7 @@ static size_t op_bytes_estimate(const misr_geometry &g, bool general) {
 // Device bytes an operator holds.
 static size_t op_bytes(const misr_op *op) {
     return op->wy.n + op->wx.n + op->opdev.n + op->a_col.n + op->a_val.n + op->t_col.n +
-           op->t_val.n;
+           op->t_val.n + op->gker.n;
 }
 
 void misr_server::evict_idle(int keep, size_t need, const std::vector<SReq *> *spare) {
@@ -848,8 +856,9 @@ extern "C" misr_status misr_server_submit(misr_server *s, const misr_request *re
     if (general) r->bytes += (size_t)m * K * 4;   // the residual buffer
     r->bytes += list_bytes(*req, general);
     r->op_bytes = op_bytes_estimate(req->geom, general);
-    r->key = OpKey{req->geom.hr_h, req->geom.hr_w, req->geom.scale, K, P, r->shifts, r->psf,
-                   r->psf_frames, r->warps, r->psf_2d};
+    r->key = OpKey{req->geom.hr_h, req->geom.hr_w, req->geom.scale, K, P,
+                   general ? req->geom.general_ell : 0, r->shifts, r->psf, r->psf_frames,
+                   r->warps, r->psf_2d};
     r->stats.t_submit_us = now_us();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->closing) return set_error(MISR_E_INVAL, "server is shutting down");

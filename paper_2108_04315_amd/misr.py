@@ -47,7 +47,7 @@ class misr_geometry(C.Structure):
                 ("n_frames", C.c_int32), ("shifts_lr", C.POINTER(C.c_double)),
                 ("psf_size", C.c_int32), ("psf_1d", C.POINTER(C.c_double)),
                 ("psf_frames", C.POINTER(C.c_double)), ("warps", C.POINTER(C.c_double)),
-                ("psf_2d", C.POINTER(C.c_double))]
+                ("psf_2d", C.POINTER(C.c_double)), ("general_ell", C.c_int32)]
 
 
 class misr_params(C.Structure):
@@ -194,11 +194,19 @@ def default_params(**kw) -> misr_params:
     return p
 
 
-def make_geometry(H: int, W: int, s: int, shifts, psf, warps=None):
+def make_geometry(H: int, W: int, s: int, shifts, psf, warps=None, general_ell: bool = False):
     """Returns (misr_geometry, keepalive arrays).  psf: (P,) taps shared by
     all frames and both axes, (K, 2, P) per frame (vertical taps, then
     horizontal taps), or (K, P, P) non-separable per frame; warps: None or
-    (K, 6) affine coefficients per frame (the general operator)."""
+    (K, 6) affine coefficients per frame (the general operator);
+    general_ell: store a general operator as sparse matrices even where the
+    matrix-free kernels apply."""
+    g, keep = _make_geometry(H, W, s, shifts, psf, warps)
+    g.general_ell = 1 if general_ell else 0
+    return g, keep
+
+
+def _make_geometry(H: int, W: int, s: int, shifts, psf, warps):
     sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64).reshape(-1, 2))
     pa = np.asarray(psf, dtype=np.float64)
     dp = C.POINTER(C.c_double)
@@ -249,14 +257,16 @@ class Operator:
     psf: (P,) taps for every frame and axis, (K, 2, P) per frame, or
     (K, P, P) non-separable per frame; warps: None (the shifts) or (K, 6)
     affine coefficients per frame.  A non-separable PSF or warps give the
-    general (sparse) operator."""
+    general operator (matrix-free where its kernels apply; general_ell stores
+    it as sparse matrices instead)."""
 
-    def __init__(self, ctx: Context, H: int, W: int, s: int, shifts, psf, warps=None):
+    def __init__(self, ctx: Context, H: int, W: int, s: int, shifts, psf, warps=None,
+                 general_ell: bool = False):
         self.ctx = ctx
         self.H, self.W, self.s = H, W, s
         self.shifts = np.asarray(shifts, dtype=np.float64).reshape(-1, 2)
         self.K = self.shifts.shape[0]
-        g, keep = make_geometry(H, W, s, self.shifts, psf, warps)
+        g, keep = make_geometry(H, W, s, self.shifts, psf, warps, general_ell)
         h = C.c_void_p()
         check(lib.misr_op_create(ctx.h, C.byref(g), C.byref(h)))
         self.h = h
@@ -458,12 +468,12 @@ class Server:
         self._keep = {}
 
     def submit(self, H, W, s, shifts, psf, y, x0, x_out, params: misr_params | None = None,
-               on_device: bool = True, warps=None) -> int:
+               on_device: bool = True, warps=None, general_ell: bool = False) -> int:
         """Queues one solve; y, x0, x_out are device tensors (or host numpy
         arrays with on_device=False) that must stay alive until it finishes;
         x0 may be None with params.x_init > 0 (start point computed on the
-        device); psf and warps as for Operator."""
-        g, keep = make_geometry(H, W, s, shifts, psf, warps)
+        device); psf, warps and general_ell as for Operator."""
+        g, keep = make_geometry(H, W, s, shifts, psf, warps, general_ell)
         p = params or default_params()
         if on_device:
             p.img_dtype = dtype_code(x_out)

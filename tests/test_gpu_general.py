@@ -1,9 +1,11 @@
 """General operators (A_k = D B_k M_k with per-frame affine warps M_k and/or
-non-separable PSFs B_k, held as sparse matrices) through the C ABI, against
-the FP64 oracle: forward and adjoint, cost and gradient (L2 and L1 data
-terms), the SCG solve, a batch and a served stream mixing general and banded
-operators, the banded operator reproduced by its general form, and the
-parameters the general path rejects."""
+non-separable PSFs B_k; matrix-free by default, stored as sparse matrices on
+request or when the warp's windows exceed the kernels' local memory) through
+the C ABI, against the FP64 oracle: forward and adjoint, cost and gradient
+(L2 and L1 data terms), the SCG solve, both forms against each other, large
+rotations, a batch and a served stream mixing general and banded operators,
+the banded operator reproduced by its general form, and the parameters the
+general path rejects."""
 import math
 
 import numpy as np
@@ -79,12 +81,14 @@ def _geometry(H, W, s, K, P, kind, seed=0):
     return shifts, psf, warps
 
 
+@pytest.mark.parametrize("ell", [False, True], ids=["matrix_free", "stored"])
 @pytest.mark.parametrize("H,W,s,K,P,kind", CASES)
-def test_general_operators_and_cost_grad(misr, ctx, H, W, s, K, P, kind):
+def test_general_operators_and_cost_grad(misr, ctx, H, W, s, K, P, kind, ell):
     import torch
     shifts, psf, warps = _geometry(H, W, s, K, P, kind)
-    op = misr.Operator(ctx, H, W, s, shifts, psf, warps=warps)
+    op = misr.Operator(ctx, H, W, s, shifts, psf, warps=warps, general_ell=ell)
     assert op.band == 0
+    assert (op.sparse_width[0] > 0) == ell
     rng = np.random.default_rng(7)
     x = _f32(rng.uniform(0, 1, (H, W)))
     y = to_np(op.forward(to_dev(x)))
@@ -148,15 +152,19 @@ def test_general_form_of_a_banded_operator(misr, ctx):
     x0 = _f32(synth.bicubic_upsample(y[0], s))
     banded = misr.Operator(ctx, H, W, s, shifts, taps)
     general = misr.Operator(ctx, H, W, s, shifts, np.stack([np.outer(taps, taps)] * K))
-    assert banded.band > 0 and general.band == 0
-    assert banded.sparse_width == (0, 0)
-    aw, tw = general.sparse_width
+    stored = misr.Operator(ctx, H, W, s, shifts, np.stack([np.outer(taps, taps)] * K),
+                           general_ell=True)
+    assert banded.band > 0 and general.band == 0 and stored.band == 0
+    assert banded.sparse_width == (0, 0) and general.sparse_width == (0, 0)
+    aw, tw = stored.sparse_width
     # a row of A spans at most s + P HR pixels per axis (the block, the PSF,
     # one more for the bilinear neighbours), so a column of A^T meets at most
     # ceil((s + P) / s) LR pixels per axis and frame
     assert 0 < aw <= (s + P) ** 2 and 0 < tw <= K * (-(-(s + P) // s)) ** 2
     xv = to_dev(x_gt)
     assert rel_l2(to_np(general.forward(xv)), to_np(banded.forward(xv))) <= TOL_OP
+    assert rel_l2(to_np(stored.forward(xv)), to_np(banded.forward(xv))) <= TOL_OP
+    stored.close()
     xb, xg = to_dev(x0), to_dev(x0)
     tb, _ = banded.scg_solve(to_dev(y), xb, misr.default_params(n_iter=n))
     tg, _ = general.scg_solve(to_dev(y), xg, misr.default_params(n_iter=n))
@@ -268,3 +276,71 @@ def test_served_general_and_banded_requests(misr, ctx):
         torch.cuda.synchronize()
         assert torch.equal(out, x)
         op.close()
+
+
+def test_matrix_free_equals_stored_form_solve(misr, ctx):
+    """The matrix-free and the stored form of one general geometry: the same
+    solve up to FP32 rounding (weights composed in FP32 against FP64-merged
+    matrix entries), the same accept decisions, both within the SCG bound of
+    the oracle."""
+    H, W, s, K, P, n = 64, 56, 2, 4, 5, 25
+    shifts, psf, warps, y, x0 = _solve_problem(H, W, s, K, P, "both", 31)
+    x_o, tr_o, _ = oscg.solve(y, shifts, psf, s, x0, n, warps=warps)
+    res = []
+    for ell in (False, True):
+        op = misr.Operator(ctx, H, W, s, shifts, psf, warps=warps, general_ell=ell)
+        x = to_dev(x0)
+        its, _ = op.scg_solve(to_dev(y), x, misr.default_params(n_iter=n))
+        res.append((to_np(x), [t["success"] for t in its]))
+        op.close()
+    print(f"matrix-free vs stored: rel-L2 {rel_l2(res[0][0], res[1][0]):.3e}")
+    assert rel_l2(res[0][0], res[1][0]) <= TOL_SCG
+    assert res[0][1] == res[1][1] == [t["success"] for t in tr_o]
+    for x, _ in res:
+        assert rel_l2(x, x_o) <= TOL_SCG
+
+
+@pytest.mark.parametrize("deg", [30.0, 45.0, 90.0, 135.0])
+def test_matrix_free_large_rotations(misr, ctx, deg):
+    """Rotations far from the identity (their back-projection windows are
+    the tile's preimage, up to about 60 x 60 positions): forward, adjoint and
+    the gradient against the oracle, on a ragged size at scale 3."""
+    import torch
+    H, W, s, K, P = 48, 57, 3, 2, 5
+    th = math.radians(deg)
+    warps = np.stack([rot_warp(th * (k + 1) / K, H, W, 0.3 * k, -0.2 * k) for k in range(K)])
+    rng = np.random.default_rng(int(deg))
+    psf = psfs_2d(rng, K, P)
+    shifts = np.zeros((K, 2))
+    op = misr.Operator(ctx, H, W, s, shifts, psf, warps=warps)
+    assert op.sparse_width == (0, 0)
+    x = _f32(rng.uniform(0, 1, (H, W)))
+    y = to_np(op.forward(to_dev(x)))
+    assert rel_l2(y, oracle.forward(x, shifts, psf, s, warps=warps)) <= TOL_OP
+    r = _f32(rng.standard_normal(y.shape))
+    xa = to_np(op.adjoint(to_dev(r)))
+    assert rel_l2(xa, oracle.adjoint(r, shifts, psf, s, H, W, warps=warps)) <= TOL_OP
+    yy = _f32(y + 0.01 * rng.standard_normal(y.shape))
+    J, g_ref, _ = oracle.cost_grad(x, yy, shifts, psf, s, warps=warps)
+    cost, g = op.cost_grad(to_dev(x), to_dev(yy), misr.default_params(n_iter=0))
+    torch.cuda.synchronize()
+    assert abs(cost.cpu().numpy()[0] - J) <= TOL_OP * J
+    assert rel_l2(to_np(g), g_ref) <= TOL_OP
+    op.close()
+
+
+def test_strong_shrink_falls_back_to_stored_form(misr, ctx):
+    """A warp that shrinks the image 4x (each HR pixel samples x 4 pixels
+    apart): the preimage of an adjoint tile exceeds the matrix-free kernels'
+    local memory, so the operator is stored as sparse matrices; it still
+    matches the oracle."""
+    H, W, s, K, P = 48, 40, 2, 2, 3
+    warps = np.array([[0.25, 0.0, 10.0, 0.0, 0.25, 8.0], [0.25, 0.01, 11.0, -0.01, 0.25, 9.0]])
+    shifts = np.zeros((K, 2))
+    psf = psfs_2d(np.random.default_rng(5), K, P)
+    op = misr.Operator(ctx, H, W, s, shifts, psf, warps=warps)
+    assert op.sparse_width[0] > 0
+    x = _f32(np.random.default_rng(6).uniform(0, 1, (H, W)))
+    y = to_np(op.forward(to_dev(x)))
+    assert rel_l2(y, oracle.forward(x, shifts, psf, s, warps=warps)) <= TOL_OP
+    op.close()
