@@ -350,7 +350,7 @@ static void general_psf(const misr_geometry *g, int k, double *hk) {
 
 long long misr::mf_lr_tiles(int H, int W, int s, int K) {
     const long long h = H / s, w = W / s;
-    const long long nt = ((h + kMfTI - 1) / kMfTI) * ((w + kMfTJ - 1) / kMfTJ);
+    const long long nt = ((h + mf_ti(s) - 1) / mf_ti(s)) * ((w + kMfTJ - 1) / kMfTJ);
     return (long long)K * ((nt + kMfLRG - 1) / kMfLRG);
 }
 
@@ -692,10 +692,10 @@ static misr_status check_general(const misr_op *op, const misr_params &p) {
     return MISR_OK;
 }
 
-// Residual buffer of a general solve (K h w floats).
+// LR vectors of a general solve (kGenVecs x K h w floats).
 static hipError_t ensure_res(const misr_op *op, SolveBufs &b) {
     if (!op->general) return hipSuccess;
-    return b.res.ensure((size_t)op->K * (op->H / op->s) * (op->W / op->s) * 4);
+    return b.res.ensure((size_t)kGenVecs * op->K * (op->H / op->s) * (op->W / op->s) * 4);
 }
 
 // ------------------------------------------------------------- plan build
@@ -801,7 +801,12 @@ void misr::add_views(const misr_op *op, const misr_params &prm, const void *y, v
         P.p[1] = bufs->p1.as<float>();
         P.g[0] = bufs->g0.as<float>();
         P.g[1] = bufs->g1.as<float>();
+        const size_t m = (size_t)op->K * (op->H / op->s) * (op->W / op->s);
         P.res = bufs->res.as<float>();
+        P.ax[0] = P.res + m;
+        P.ax[1] = P.res + 2 * m;
+        P.ap[0] = P.res + 3 * m;
+        P.ap[1] = P.res + 4 * m;
         P.ld = P.Wb = op->W;
         P.Hb = op->H;
         P.oy1 = P.uy1 = op->H;
@@ -995,7 +1000,8 @@ struct Launcher {
             hipError_t e =
                 cls[c].Lp == 0
                     ? launch_general(cls[c].count, s, pd.projs.as<Proj>(), items + cls[c].start,
-                                     cnt() + off + c, part + (size_t)cls[c].start * kNV, kind)
+                                     cnt() + off + c, part + (size_t)cls[c].start * kNV, kind,
+                                     cls[c].S)
                     : launch_image(cls[c].S, cls[c].Lp, cls[c].count, s, pd.projs.as<Proj>(),
                                    items + cls[c].start, cnt() + off + c,
                                    part + (size_t)cls[c].start * kNV, kind, pl.code());

@@ -68,8 +68,8 @@ FI float mf_sample(int H, int W, int u, int v, double r, double c, V vec) {
 // (frames in turn, tiles row-major); frame, tile row and column, or false
 // past the frame's last tile.
 FI bool mf_lr_tile(const AS4 OpDev &op, int t, int q, int &k, int &ti, int &tj) {
-    const int h = op.H / op.s, w = op.W / op.s;
-    const int nti = (h + kMfTI - 1) / kMfTI, ntj = (w + kMfTJ - 1) / kMfTJ;
+    const int h = op.H / op.s, w = op.W / op.s, TI = mf_ti(op.s);
+    const int nti = (h + TI - 1) / TI, ntj = (w + kMfTJ - 1) / kMfTJ;
     const int ng = (nti * ntj + kMfLRG - 1) / kMfLRG;
     k = t / ng;
     const int c = (t - k * ng) * kMfLRG + q;
@@ -84,14 +84,18 @@ FI bool mf_lr_tile(const AS4 OpDev &op, int t, int q, int &k, int &ti, int &tj) 
 // product's rounding error, so the truncation is exact.
 FI int mf_div(int e, float inv) { return (int)(((float)e + 0.5f) * inv); }
 
-// (A_k v) at this thread's LR pixel (i, j) of LR tile (ti, tj) of frame k;
-// false past the frame.  zs: kMfZ floats of LDS, free again on return.
+// (A_k v) at this thread's LR pixels of LR tile (ti, tj) of frame k: rows
+// i + r, r < mf_ti(S) / 8, column j, into out[r] (pixels past the frame
+// are computed and not used: the caller checks i + r < h, j < w).  zs: kMfZ
+// floats of LDS, free again on return.  A thread's two rows share the
+// window rows their kernels overlap on, read once.
 template <int S, class V>
-FI bool mf_forward(const AS4 OpDev &op, int k, int ti, int tj, V vec, float *zs, int &i, int &j,
-                   float &out) {
+FI void mf_forward(const AS4 OpDev &op, int k, int ti, int tj, V vec, float *zs, int &i, int &j,
+                   float (&out)[2]) {
+    constexpr int TI = mf_ti(S), RPT = TI / 8;
     const int H = op.H, W = op.W, Q = op.Q, R = (op.P - 1) / 2;
-    const int i0 = ti * kMfTI, j0 = tj * kMfTJ;
-    const int ZR = S * (kMfTI - 1) + Q, ZC = S * (kMfTJ - 1) + Q;
+    const int i0 = ti * TI, j0 = tj * kMfTJ;
+    const int ZR = S * (TI - 1) + Q, ZC = S * (kMfTJ - 1) + Q;
     const int u0 = S * i0 - R, v0 = S * j0 - R;
     const double m0 = op.gm[k][0], m1 = op.gm[k][1], m2 = op.gm[k][2];
     const double m3 = op.gm[k][3], m4 = op.gm[k][4], m5 = op.gm[k][5];
@@ -103,19 +107,28 @@ FI bool mf_forward(const AS4 OpDev &op, int k, int ti, int tj, V vec, float *zs,
                           fma(m3, u, fma(m4, v, m5)), vec);
     }
     __syncthreads();
-    const int il = threadIdx.x / kMfTJ, jl = threadIdx.x % kMfTJ;
+    const int il = (threadIdx.x / kMfTJ) * RPT, jl = threadIdx.x % kMfTJ;
     const AS4 float *ck = cst(op.gker) + (i64)k * Q * Q;
     const float *zb = zs + S * il * ZC + S * jl;
-    float acc = 0.f;
-    for (int a = 0; a < Q; ++a) {
+    float acc[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) acc[r] = 0.f;
+    for (int a = 0; a < Q + S * (RPT - 1); ++a) {
 #pragma unroll 4
-        for (int b = 0; b < Q; ++b) acc = fmaf(ck[a * Q + b], zb[a * ZC + b], acc);
+        for (int b = 0; b < Q; ++b) {
+            const float z = zb[a * ZC + b];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int ar = a - S * r;   // uniform
+                if (ar >= 0 && ar < Q) acc[r] = fmaf(ck[ar * Q + b], z, acc[r]);
+            }
+        }
     }
     __syncthreads();
     i = i0 + il;
     j = j0 + jl;
-    out = acc;
-    return i < H / S && j < W / S;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) out[r] = acc[r];
 }
 
 // Clamped conversion of a window bound (the operator's windows are small,
@@ -177,19 +190,33 @@ FI void mf_adjoint(const AS4 OpDev &op, int tu, int tv, Rf res, float *lds, floa
             if (b < QP) cpl[a * QP + b] = (a < Q && b < Q) ? ck[a * Q + b] : 0.f;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < RU * RV; e += kGenRows) {
-            const int a = mf_div(e, irv);
-            const int u = ua + a, v = va + e - a * RV;
-            float sum = 0.f;
-            if (u >= 0 && u < H && v >= 0 && v < W) {
-                const int qu = fdiv(u + R, S), qv = fdiv(v + R, S);
-                const float *cr = cpl + (u + R - S * qu) * QP + (v + R - S * qv);
-                const float *rr = rsm + (qu - i0) * NJ + (qv - j0);
-                for (int t = 0; t < NT; ++t)
-                    for (int t2 = 0; t2 < NT; ++t2)
-                        sum = fmaf(cr[S * (t * QP + t2)], rr[-t * NJ - t2], sum);
+        // the taps, with their count fixed at compile time where it is small
+        auto backproj = [&](auto ntc) {
+            constexpr int NTC = decltype(ntc)::value;
+            const int nt = NTC > 0 ? NTC : NT;
+            for (int e = threadIdx.x; e < RU * RV; e += kGenRows) {
+                const int a = mf_div(e, irv);
+                const int u = ua + a, v = va + e - a * RV;
+                float sum = 0.f;
+                if (u >= 0 && u < H && v >= 0 && v < W) {
+                    const int qu = fdiv(u + R, S), qv = fdiv(v + R, S);
+                    const float *cr = cpl + (u + R - S * qu) * QP + (v + R - S * qv);
+                    const float *rr = rsm + (qu - i0) * NJ + (qv - j0);
+#pragma unroll
+                    for (int t = 0; t < nt; ++t)
+#pragma unroll
+                        for (int t2 = 0; t2 < nt; ++t2)
+                            sum = fmaf(cr[S * (t * QP + t2)], rr[-t * NJ - t2], sum);
+                }
+                wt[e] = sum;
             }
-            wt[e] = sum;
+        };
+        switch (NT) {   // uniform
+        case 2: backproj(std::integral_constant<int, 2>{}); break;
+        case 3: backproj(std::integral_constant<int, 3>{}); break;
+        case 4: backproj(std::integral_constant<int, 4>{}); break;
+        case 5: backproj(std::integral_constant<int, 5>{}); break;
+        default: backproj(std::integral_constant<int, 0>{}); break;
         }
         __syncthreads();
         const double m0 = op.gm[k][0], m1 = op.gm[k][1], m2 = op.gm[k][2];
@@ -197,17 +224,32 @@ FI void mf_adjoint(const AS4 OpDev &op, int tu, int tv, Rf res, float *lds, floa
         const float m0f = (float)m0, m1f = (float)m1, m3f = (float)m3, m4f = (float)m4;
         const int ncu = op.ncu[k], ncv = op.ncv[k];
         const bool c33 = ncu == 3 && ncv == 3;   // the near-identity warps (uniform)
+        // tile-relative coordinates in FP32 (magnitudes of the tile's extent):
+        // the preimage of the tile's corner pixel (U0, V0) less the window's
+        // origin, and the warped coordinate of the window's origin less the
+        // corner pixel, both from FP64 once per tile.  A rounding that moves a
+        // pixel's first candidate by one position changes only candidates at
+        // the edge of its support, whose tent weights are zero to rounding.
+        const float ub0 = (float)(fma(g0, (double)U0, fma(g1, (double)V0, g2)) - ua);
+        const float vb0 = (float)(fma(g3, (double)U0, fma(g4, (double)V0, g5)) - va);
+        const float rb0 = (float)(fma(m0, (double)ua, fma(m1, (double)va, m2)) - U0);
+        const float cb0 = (float)(fma(m3, (double)ua, fma(m4, (double)va, m5)) - V0);
+        const float g0f = (float)g0, g1f = (float)g1, g3f = (float)g3, g4f = (float)g4;
+        const float euf = (float)eu, evf = (float)ev;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int pr = U0 + row + 4 * t, pc = V0 + lane;
-            if (pr > U1 || pc > V1) continue;
-            const double uc = fma(g0, (double)pr, fma(g1, (double)pc, g2));
-            const double vc = fma(g3, (double)pr, fma(g4, (double)pc, g5));
-            const int us = mf_int(floor(uc - eu)) + 1, vs = mf_int(floor(vc - ev)) + 1;
-            // warped coordinate of the first candidate relative to the pixel
-            const float d0r = (float)(fma(m0, (double)us, fma(m1, (double)vs, m2)) - pr);
-            const float d0c = (float)(fma(m3, (double)us, fma(m4, (double)vs, m5)) - pc);
-            const float *wb = wt + (us - ua) * RV + (vs - va);
+            const int dr = row + 4 * t, dc = lane;
+            if (U0 + dr > U1 || V0 + dc > V1) continue;
+            // first candidate, relative to the window's origin, kept inside
+            // the window (a rounding at the edge moves it by one)
+            const float uq = fmaf((float)dr, g0f, fmaf((float)dc, g1f, ub0)) - euf;
+            const float vq = fmaf((float)dr, g3f, fmaf((float)dc, g4f, vb0)) - evf;
+            const int ous = min(max(0, (int)floorf(uq) + 1), RU - ncu);
+            const int ovs = min(max(0, (int)floorf(vq) + 1), RV - ncv);
+            // its warped coordinate relative to the pixel
+            const float d0r = fmaf((float)ous, m0f, fmaf((float)ovs, m1f, rb0)) - (float)dr;
+            const float d0c = fmaf((float)ous, m3f, fmaf((float)ovs, m4f, cb0)) - (float)dc;
+            const float *wb = wt + ous * RV + ovs;
             float a_t = 0.f;
             auto cand = [&](int a, int b) {
                 const float dr = fmaf((float)b, m1f, fmaf((float)a, m0f, d0r));
@@ -375,12 +417,16 @@ FI double gen_data_curv(const ScgState &st, const Proj &P, i64 r, float ap, floa
 
 // trial / cost+gradient, LR rows (an LR tile, or kGenRows ELL rows): the
 // forward at x_t = x + alpha p (mode 1) or x (mode 0), the residual term and
-// the data cost
+// the data cost.  Matrix-free: mode 0 applies A to x and keeps A x (and
+// A p = 0 for the zero start direction); mode 1 takes A x + alpha A p from
+// the kept vectors (A is linear), with no forward.
 __global__ void __launch_bounds__(kGenRows) k_gen_trial_lr(const Proj *projs, const Item *items,
                                                            const int *n_items, double *partials,
                                                            int mode) {
     __shared__ double red[kNV * (kGenRows / 64)];
-    __shared__ float zs[kMfZ];
+    // the warped window of the matrix-free forward (mode 0 only: the launch
+    // sizes it, so the elementwise mode 1 runs at full occupancy)
+    extern __shared__ float zs[];
     const int it = blockIdx.x;
     if (it >= *n_items) return;
     const Item itm = items[it];
@@ -397,13 +443,27 @@ __global__ void __launch_bounds__(kGenRows) k_gen_trial_lr(const Proj *projs, co
     // mode 0 reads x alone: p is not yet initialised there
     auto xt = [&](i64 c) { return mode == 1 ? fmaf(af, p[c], x[c]) : x[c]; };
     double e = 0.0;
-    if (op.mf) {
+    if (op.mf && mode == 1) {
+        // elementwise: item t takes LR rows [t kGenRows, (t + 1) kGenRows)
+        // (there are at least as many LR items as such blocks)
+        const i64 r = (i64)itm.ty * kGenRows + threadIdx.x;
+        if (r < (i64)op.K * h * w)
+            e = gen_residual(st, P, r, fmaf(af, glb(P.ap[xc])[r], glb(P.ax[xc])[r]));
+    } else if (op.mf) {
         int k, ti, tj, i, j;
-        float ax;
         mf_by_scale(op.s, [&](auto S) {
-            for (int q = 0; q < kMfLRG && mf_lr_tile(op, itm.ty, q, k, ti, tj); ++q)
-                if (mf_forward<S.value>(op, k, ti, tj, xt, zs, i, j, ax))
-                    e += gen_residual(st, P, ((i64)k * h + i) * w + j, ax);
+            for (int q = 0; q < kMfLRG && mf_lr_tile(op, itm.ty, q, k, ti, tj); ++q) {
+                float ax[2];
+                mf_forward<S.value>(op, k, ti, tj, xt, zs, i, j, ax);
+#pragma unroll
+                for (int r = 0; r < mf_ti(S.value) / 8; ++r)
+                    if (i + r < h && j < w) {
+                        const i64 row = ((i64)k * h + i + r) * w + j;
+                        e += gen_residual(st, P, row, ax[r]);
+                        glbw(P.ax[xc])[row] = ax[r];
+                        glbw(P.ap[xc])[row] = 0.f;
+                    }
+            }
         });
     } else {
         const i64 rows = (i64)op.K * h * w;
@@ -566,11 +626,13 @@ __global__ void __launch_bounds__(kGenRows) k_gen_upd_hr(const Proj *projs, cons
 }
 
 // update, LR rows (an LR tile, or kGenRows ELL rows): the data part of the
-// curvature along the new p (x, p the new iterate and direction)
+// curvature along the new p (x, p the new iterate and direction).
+// Matrix-free: A p of the new direction by the forward, A x of the new
+// iterate as A x + alpha A p of the old one; both kept for the next trial.
 __global__ void __launch_bounds__(kGenRows) k_gen_upd_lr(const Proj *projs, const Item *items,
                                                          const int *n_items, double *partials) {
     __shared__ double red[kNV * (kGenRows / 64)];
-    __shared__ float zs[kMfZ];
+    extern __shared__ float zs[];   // the forward's warped window, sized by the launch
     const int it = blockIdx.x;
     if (it >= *n_items) return;
     const Item itm = items[it];
@@ -589,12 +651,21 @@ __global__ void __launch_bounds__(kGenRows) k_gen_upd_lr(const Proj *projs, cons
     double dd = 0.0;
     if (op.mf) {
         int k, ti, tj, i, j;
+        const int src = st.upd_src;
+        const float af = st.alpha_f;
         mf_by_scale(op.s, [&](auto S) {
             for (int q = 0; q < kMfLRG && mf_lr_tile(op, itm.ty, q, k, ti, tj); ++q) {
-                float ap, ax = 0.f;
-                bool ok = mf_forward<S.value>(op, k, ti, tj, fp, zs, i, j, ap);
-                if (l1) ok = mf_forward<S.value>(op, k, ti, tj, fx, zs, i, j, ax);   // uniform
-                if (ok) dd += gen_data_curv(st, P, ((i64)k * h + i) * w + j, ap, ax);
+                float ap[2];
+                mf_forward<S.value>(op, k, ti, tj, fp, zs, i, j, ap);
+#pragma unroll
+                for (int r = 0; r < mf_ti(S.value) / 8; ++r)
+                    if (i + r < h && j < w) {
+                        const i64 row = ((i64)k * h + i + r) * w + j;
+                        const float ax = fmaf(af, glb(P.ap[src])[row], glb(P.ax[src])[row]);
+                        glbw(P.ax[dst])[row] = ax;
+                        glbw(P.ap[dst])[row] = ap[r];
+                        dd += gen_data_curv(st, P, row, ap[r], ax);
+                    }
             }
         });
     } else {
@@ -639,11 +710,14 @@ __global__ void __launch_bounds__(kGenRows) k_mf_forward(const OpDev *opp, const
     const int h = op.H / op.s, w = op.W / op.s;
     const AS1 float *xg = glb(x);
     int k, ti, tj, i, j;
-    float ax;
     mf_by_scale(op.s, [&](auto S) {
-        for (int q = 0; q < kMfLRG && mf_lr_tile(op, blockIdx.x, q, k, ti, tj); ++q)
-            if (mf_forward<S.value>(op, k, ti, tj, [&](i64 c) { return xg[c]; }, zs, i, j, ax))
-                y[((i64)k * h + i) * w + j] = ax;
+        for (int q = 0; q < kMfLRG && mf_lr_tile(op, blockIdx.x, q, k, ti, tj); ++q) {
+            float ax[2];
+            mf_forward<S.value>(op, k, ti, tj, [&](i64 c) { return xg[c]; }, zs, i, j, ax);
+#pragma unroll
+            for (int r = 0; r < mf_ti(S.value) / 8; ++r)
+                if (i + r < h && j < w) y[((i64)k * h + i + r) * w + j] = ax[r];
+        }
     });
 }
 
@@ -672,17 +746,19 @@ __global__ void __launch_bounds__(kGenRows) k_mf_adjoint(const OpDev *opp, const
 // A pass over one class of general items: the trial and the cost+gradient
 // run the LR rows then the HR rows, the update the HR rows then the LR rows.
 hipError_t launch_general(int grid, hipStream_t stream, const Proj *projs, const Item *items,
-                          const int *n_items, double *partials, int kind) {
+                          const int *n_items, double *partials, int kind, int S) {
     if (grid <= 0) return hipSuccess;
+    // the forward's warped window for the class's scale (any P)
+    const size_t zb = (size_t)mf_zwin(S) * sizeof(float);
     if (kind == 2) {
         hipLaunchKernelGGL(k_gen_upd_hr, dim3(grid), dim3(kGenRows), 0, stream, projs, items,
                            n_items, partials);
-        hipLaunchKernelGGL(k_gen_upd_lr, dim3(grid), dim3(kGenRows), 0, stream, projs, items,
+        hipLaunchKernelGGL(k_gen_upd_lr, dim3(grid), dim3(kGenRows), zb, stream, projs, items,
                            n_items, partials);
     } else {
         const int mode = kind == 1 ? 1 : 0;
-        hipLaunchKernelGGL(k_gen_trial_lr, dim3(grid), dim3(kGenRows), 0, stream, projs, items,
-                           n_items, partials, mode);
+        hipLaunchKernelGGL(k_gen_trial_lr, dim3(grid), dim3(kGenRows), mode == 0 ? zb : 0, stream,
+                           projs, items, n_items, partials, mode);
         hipLaunchKernelGGL(k_gen_trial_hr, dim3(grid), dim3(kGenRows), 0, stream, projs, items,
                            n_items, partials, mode);
     }

@@ -62,25 +62,33 @@ struct OpDev {
     const float *gker;
 };
 
-// Matrix-free general kernels: the forward takes LR tiles of kMfTI x kMfTJ
-// pixels (one per thread), the adjoint and update HR tiles of kMfTU x kMfTV
-// pixels (four per thread).  LDS: the forward's warped window holds
-// (s (kMfTI - 1) + Q) x (s (kMfTJ - 1) + Q) floats (at most kMfZ); the
+// Matrix-free general kernels: the forward takes LR tiles of mf_ti(s) x
+// kMfTJ pixels (one or two rows per thread), the adjoint and update HR tiles
+// of kMfTU x kMfTV pixels (four per thread).  LDS: the forward's warped
+// window holds (s (mf_ti(s) - 1) + Q) x (s (kMfTJ - 1) + Q) floats (at most
+// kMfZ); the
 // adjoint's residual and back-projection windows together at most kMfWin,
 // its copy of the kernel padded to s ceil(Q / s) rows and columns at most
 // kMfQP^2.
-constexpr int kMfTI = 8, kMfTJ = 32;
+constexpr int kMfTJ = 32;
+__host__ __device__ constexpr int mf_ti(int) { return 8; }
 constexpr int kMfLRG = 1;   // LR tiles per forward work item
 constexpr int kMfTU = 16, kMfTV = 64;
 constexpr int kMfQmax = 4 + 15 - 1;
 constexpr int kMfQP = 20;
-constexpr int kMfZ = (4 * (kMfTI - 1) + kMfQmax) * (4 * (kMfTJ - 1) + kMfQmax);
+__host__ __device__ constexpr int mf_zwin(int s) {
+    return (s * (mf_ti(s) - 1) + s + 14) * (s * (kMfTJ - 1) + s + 14);
+}
+__host__ __device__ constexpr int mf_cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kMfZ = mf_cmax(mf_cmax(mf_zwin(1), mf_zwin(2)), mf_cmax(mf_zwin(3), mf_zwin(4)));
 constexpr int kMfWin = 7424;
 
 // Rows (LR or HR pixels) per work item of the general-operator kernels; an
 // item's tx is its role: 0 LR rows (forward, residual), 1 HR rows (adjoint,
 // prior, update).
 constexpr int kGenRows = 256;
+// LR vectors of a general solve: the residual term, A x and A p (two each).
+constexpr int kGenVecs = 5;
 
 // One image (or one tile of an image held separately in HBM) in a work list.
 // Buffers are H-major with row stride ld; buffer pixel (u, v) is global
@@ -102,6 +110,10 @@ struct Proj {
     struct ScgState *st; // the solve this view belongs to
     const OpDev *op;
     float *res;          // general operators: the residual term per LR row (K h w)
+    // matrix-free general operators: A x[i] and A p[i] per LR row (K h w
+    // each), kept with the iterate so that the trial's forward at x + alpha p
+    // is A x + alpha A p
+    float *ax[2], *ap[2];
 };
 
 // Halo exchange: rows x cols pixels at global (gy, gx) of view src's owned

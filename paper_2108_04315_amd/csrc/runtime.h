@@ -38,7 +38,7 @@ hipError_t launch_adjoint(int S, int Lp, int grid, hipStream_t stream, const Pro
 // general operators (general_kernels.hip): one pass over a class of general
 // items (kind as launch_image), and the standalone FP32 operators
 hipError_t launch_general(int grid, hipStream_t stream, const Proj *projs, const Item *items,
-                          const int *n_items, double *partials, int kind);
+                          const int *n_items, double *partials, int kind, int S);
 // (mf_tiles > 0: a matrix-free operator, one workgroup per tile)
 hipError_t launch_general_forward(hipStream_t stream, const OpDev *op, long long rows,
                                   const float *x, float *y, long long mf_tiles);
@@ -207,7 +207,8 @@ inline int frame_stype(const misr_params &p) {
 // iterate).
 struct SolveBufs {
     DevMem x1, p0, p1, g0, g1, x0w;
-    DevMem res;   // general operators: the residual term per LR row
+    DevMem res;   // general operators: the residual term per LR row, then
+                  // A x[0], A x[1], A p[0], A p[1] (kGenVecs LR vectors)
     void set_pool(MemPool *pl) {
         x1.pool = p0.pool = p1.pool = g0.pool = g1.pool = x0w.pool = res.pool = pl;
     }

@@ -142,12 +142,15 @@ __device__ void scg_phase_b(ScgState &s, const double *v, IterRec *trace) {
 // rather than once per dependent access.
 constexpr int kStW = (int)(sizeof(ScgState) / 8);
 static_assert(sizeof(ScgState) % 8 == 0 && kStW <= kNT, "state copied by 8-byte words");
+// Threads of the scalar kernel (a solve's partial sums, one row per work
+// item, four loads each in flight per round; 1024 threads measured slower).
+constexpr int kST = kNT;
 
-__global__ void __launch_bounds__(kNT) k_scalar(const SolveRef *refs, const int *n_refs,
+__global__ void __launch_bounds__(kST) k_scalar(const SolveRef *refs, const int *n_refs,
                                                 const double *__restrict__ partials,
                                                 const double *__restrict__ partials_u,
                                                 int phase) {
-    __shared__ double red[kNV * (kNT / 64)];
+    __shared__ double red[kNV * (kST / 64)];
     __shared__ double tot[kNV];
     __shared__ ScgState sst;
     unsigned long long *sw = reinterpret_cast<unsigned long long *>(&sst);
@@ -166,25 +169,26 @@ __global__ void __launch_bounds__(kNT) k_scalar(const SolveRef *refs, const int 
         // (a solve may hold thousands of items); past the end an item is
         // loaded from a valid address and counted as zero, so each thread
         // adds its items in the same order whatever the count, and in one
-        // memory round trip per 4 x kNT items
+        // memory round trip per kSU x kST items
+        constexpr int kSU = 4;   // (eight measured slower)
         double v[kNV] = {0, 0, 0, 0, 0, 0};
         const int end = i0 + ni;
-        for (int i = i0 + threadIdx.x; i < end; i += 4 * kNT) {
-            double t[4][kNV];
+        for (int i = i0 + threadIdx.x; i < end; i += kSU * kST) {
+            double t[kSU][kNV];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const int j = (i + a * kNT < end) ? i + a * kNT : i;
+            for (int a = 0; a < kSU; ++a) {
+                const int j = (i + a * kST < end) ? i + a * kST : i;
 #pragma unroll
                 for (int q = 0; q < kNV; ++q) t[a][q] = pt[(long long)j * kNV + q];
             }
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < kSU; ++a)
 #pragma unroll
-                for (int q = 0; q < kNV; ++q) v[q] += (i + a * kNT < end) ? t[a][q] : 0.0;
+                for (int q = 0; q < kNV; ++q) v[q] += (i + a * kST < end) ? t[a][q] : 0.0;
         }
         // the sums are used only where the phase needs them (scg_phase_a
         // reads them after an accepted pass only)
-        block_sum_store<kNV, kNT>(v, tot, red);   // its barriers also publish sst
+        block_sum_store<kNV, kST>(v, tot, red);   // its barriers also publish sst
         if (threadIdx.x == 0) {
             if (phase == PH_INIT)
                 scg_init(sst, tot);
@@ -493,7 +497,7 @@ hipError_t launch_adjoint(int S, int Lp, int grid, hipStream_t stream, const Pro
 
 hipError_t launch_scalar(int grid, hipStream_t stream, const SolveRef *refs, const int *n_refs,
                          const double *partials, const double *partials_u, int phase) {
-    hipLaunchKernelGGL(k_scalar, dim3(grid), dim3(kNT), 0, stream, refs, n_refs, partials,
+    hipLaunchKernelGGL(k_scalar, dim3(grid), dim3(kST), 0, stream, refs, n_refs, partials,
                        partials_u, phase);
     return hipGetLastError();
 }

@@ -348,7 +348,8 @@ bool misr_server::setup(SReq *r) {
         return false;
     const long long m = (long long)(g.hr_h / g.scale) * (g.hr_w / g.scale) * g.n_frames;
     if (!r->tiled && r->bufs.ensure_view(r->n, q.params) != hipSuccess) return false;
-    if (r->op->general && r->bufs.res.ensure((size_t)m * 4) != hipSuccess) return false;
+    if (r->op->general && r->bufs.res.ensure((size_t)kGenVecs * m * 4) != hipSuccess)
+        return false;
     const size_t per = (size_t)std::max(1, q.params.n_iter);
     if (r->dstate.ensure(sizeof(ScgState) + per * sizeof(IterRec)) != hipSuccess) return false;
     r->st_dev = r->dstate.as<ScgState>();
@@ -532,7 +533,7 @@ hipError_t misr_server::enqueue_image(List &L, int kind, bool fresh) {
         hipError_t e =
             cls[c].Lp == 0
                 ? launch_general(n, stream, L.projs.as<Proj>(), items + first, L.cnt(cidx),
-                                 part + (size_t)first * kNV, kind)
+                                 part + (size_t)first * kNV, kind, cls[c].S)
                 : launch_image(cls[c].S, cls[c].Lp, n, stream, L.projs.as<Proj>(), items + first,
                                L.cnt(cidx), part + (size_t)first * kNV, kind, code);
         if (e != hipSuccess) return e;
@@ -853,7 +854,7 @@ extern "C" misr_status misr_server_submit(misr_server *s, const misr_request *re
     const long long m = (long long)(req->geom.hr_h / req->geom.scale) *
                         (req->geom.hr_w / req->geom.scale);
     r->bytes = request_bytes(*req, r->n, r->es, req->geom.n_frames, m);
-    if (general) r->bytes += (size_t)m * K * 4;   // the residual buffer
+    if (general) r->bytes += (size_t)kGenVecs * m * K * 4;   // its LR vectors
     r->bytes += list_bytes(*req, general);
     r->op_bytes = op_bytes_estimate(req->geom, general);
     r->key = OpKey{req->geom.hr_h, req->geom.hr_w, req->geom.scale, K, P,
