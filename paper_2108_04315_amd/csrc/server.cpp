@@ -399,6 +399,7 @@ void misr_server::release(SReq *r) {
     r->bufs.g0.release();
     r->bufs.g1.release();
     r->bufs.x0w.release();
+    r->bufs.res.release();
     r->tiles.bufs.clear();
     r->tiles.x0.clear();
     std::lock_guard<std::mutex> lk(mu);
