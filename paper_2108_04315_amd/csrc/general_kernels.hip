@@ -84,15 +84,14 @@ FI bool mf_lr_tile(const AS4 OpDev &op, int t, int q, int &k, int &ti, int &tj) 
 // product's rounding error, so the truncation is exact.
 FI int mf_div(int e, float inv) { return (int)(((float)e + 0.5f) * inv); }
 
-// (A_k v) at this thread's LR pixels of LR tile (ti, tj) of frame k: rows
-// i + r, r < mf_ti(S) / 8, column j, into out[r] (pixels past the frame
-// are computed and not used: the caller checks i + r < h, j < w).  zs: kMfZ
-// floats of LDS, free again on return.  A thread's two rows share the
-// window rows their kernels overlap on, read once.
+// (A_k v) at this thread's LR pixels of LR tile (ti, tj) of frame k: row i,
+// columns j + 32 c, c < kMfCPT, into out[c] (pixels past the frame are
+// computed and not used: the caller checks i < h, j + 32 c < w).  zs: the
+// warped window, free again on return.
 template <int S, class V>
 FI void mf_forward(const AS4 OpDev &op, int k, int ti, int tj, V vec, float *zs, int &i, int &j,
-                   float (&out)[2]) {
-    constexpr int TI = mf_ti(S), RPT = TI / 8;
+                   float (&out)[kMfCPT]) {
+    constexpr int TI = mf_ti(S);
     const int H = op.H, W = op.W, Q = op.Q, R = (op.P - 1) / 2;
     const int i0 = ti * TI, j0 = tj * kMfTJ;
     const int ZR = S * (TI - 1) + Q, ZC = S * (kMfTJ - 1) + Q;
@@ -107,28 +106,25 @@ FI void mf_forward(const AS4 OpDev &op, int k, int ti, int tj, V vec, float *zs,
                           fma(m3, u, fma(m4, v, m5)), vec);
     }
     __syncthreads();
-    const int il = (threadIdx.x / kMfTJ) * RPT, jl = threadIdx.x % kMfTJ;
+    const int il = threadIdx.x / 32, jl = threadIdx.x % 32;
     const AS4 float *ck = cst(op.gker) + (i64)k * Q * Q;
     const float *zb = zs + S * il * ZC + S * jl;
-    float acc[RPT];
+    float acc[kMfCPT];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) acc[r] = 0.f;
-    for (int a = 0; a < Q + S * (RPT - 1); ++a) {
+    for (int c = 0; c < kMfCPT; ++c) acc[c] = 0.f;
+    for (int a = 0; a < Q; ++a) {
 #pragma unroll 4
         for (int b = 0; b < Q; ++b) {
-            const float z = zb[a * ZC + b];
+            const float cw = ck[a * Q + b];
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                const int ar = a - S * r;   // uniform
-                if (ar >= 0 && ar < Q) acc[r] = fmaf(ck[ar * Q + b], z, acc[r]);
-            }
+            for (int c = 0; c < kMfCPT; ++c) acc[c] = fmaf(cw, zb[a * ZC + b + S * 32 * c], acc[c]);
         }
     }
     __syncthreads();
     i = i0 + il;
     j = j0 + jl;
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) out[r] = acc[r];
+    for (int c = 0; c < kMfCPT; ++c) out[c] = acc[c];
 }
 
 // Clamped conversion of a window bound (the operator's windows are small,
@@ -444,23 +440,26 @@ __global__ void __launch_bounds__(kGenRows) k_gen_trial_lr(const Proj *projs, co
     auto xt = [&](i64 c) { return mode == 1 ? fmaf(af, p[c], x[c]) : x[c]; };
     double e = 0.0;
     if (op.mf && mode == 1) {
-        // elementwise: item t takes LR rows [t kGenRows, (t + 1) kGenRows)
-        // (there are at least as many LR items as such blocks)
-        const i64 r = (i64)itm.ty * kGenRows + threadIdx.x;
-        if (r < (i64)op.K * h * w)
-            e = gen_residual(st, P, r, fmaf(af, glb(P.ap[xc])[r], glb(P.ax[xc])[r]));
+        // elementwise: item t takes LR rows [t B, (t + 1) B), B = kGenRows
+        // kMfCPT (there are at least as many LR items as such blocks)
+#pragma unroll
+        for (int c = 0; c < kMfCPT; ++c) {
+            const i64 r = ((i64)itm.ty * kMfCPT + c) * kGenRows + threadIdx.x;
+            if (r < (i64)op.K * h * w)
+                e += gen_residual(st, P, r, fmaf(af, glb(P.ap[xc])[r], glb(P.ax[xc])[r]));
+        }
     } else if (op.mf) {
         int k, ti, tj, i, j;
         mf_by_scale(op.s, [&](auto S) {
             for (int q = 0; q < kMfLRG && mf_lr_tile(op, itm.ty, q, k, ti, tj); ++q) {
-                float ax[2];
+                float ax[kMfCPT];
                 mf_forward<S.value>(op, k, ti, tj, xt, zs, i, j, ax);
 #pragma unroll
-                for (int r = 0; r < mf_ti(S.value) / 8; ++r)
-                    if (i + r < h && j < w) {
-                        const i64 row = ((i64)k * h + i + r) * w + j;
-                        e += gen_residual(st, P, row, ax[r]);
-                        glbw(P.ax[xc])[row] = ax[r];
+                for (int c = 0; c < kMfCPT; ++c)
+                    if (i < h && j + 32 * c < w) {
+                        const i64 row = ((i64)k * h + i) * w + j + 32 * c;
+                        e += gen_residual(st, P, row, ax[c]);
+                        glbw(P.ax[xc])[row] = ax[c];
                         glbw(P.ap[xc])[row] = 0.f;
                     }
             }
@@ -655,16 +654,16 @@ __global__ void __launch_bounds__(kGenRows) k_gen_upd_lr(const Proj *projs, cons
         const float af = st.alpha_f;
         mf_by_scale(op.s, [&](auto S) {
             for (int q = 0; q < kMfLRG && mf_lr_tile(op, itm.ty, q, k, ti, tj); ++q) {
-                float ap[2];
+                float ap[kMfCPT];
                 mf_forward<S.value>(op, k, ti, tj, fp, zs, i, j, ap);
 #pragma unroll
-                for (int r = 0; r < mf_ti(S.value) / 8; ++r)
-                    if (i + r < h && j < w) {
-                        const i64 row = ((i64)k * h + i + r) * w + j;
+                for (int c = 0; c < kMfCPT; ++c)
+                    if (i < h && j + 32 * c < w) {
+                        const i64 row = ((i64)k * h + i) * w + j + 32 * c;
                         const float ax = fmaf(af, glb(P.ap[src])[row], glb(P.ax[src])[row]);
                         glbw(P.ax[dst])[row] = ax;
-                        glbw(P.ap[dst])[row] = ap[r];
-                        dd += gen_data_curv(st, P, row, ap[r], ax);
+                        glbw(P.ap[dst])[row] = ap[c];
+                        dd += gen_data_curv(st, P, row, ap[c], ax);
                     }
             }
         });
@@ -712,11 +711,11 @@ __global__ void __launch_bounds__(kGenRows) k_mf_forward(const OpDev *opp, const
     int k, ti, tj, i, j;
     mf_by_scale(op.s, [&](auto S) {
         for (int q = 0; q < kMfLRG && mf_lr_tile(op, blockIdx.x, q, k, ti, tj); ++q) {
-            float ax[2];
+            float ax[kMfCPT];
             mf_forward<S.value>(op, k, ti, tj, [&](i64 c) { return xg[c]; }, zs, i, j, ax);
 #pragma unroll
-            for (int r = 0; r < mf_ti(S.value) / 8; ++r)
-                if (i + r < h && j < w) y[((i64)k * h + i + r) * w + j] = ax[r];
+            for (int c = 0; c < kMfCPT; ++c)
+                if (i < h && j + 32 * c < w) y[((i64)k * h + i) * w + j + 32 * c] = ax[c];
         }
     });
 }

@@ -63,14 +63,15 @@ struct OpDev {
 };
 
 // Matrix-free general kernels: the forward takes LR tiles of mf_ti(s) x
-// kMfTJ pixels (one or two rows per thread), the adjoint and update HR tiles
+// kMfTJ pixels (kMfCPT columns per thread), the adjoint and update HR tiles
 // of kMfTU x kMfTV pixels (four per thread).  LDS: the forward's warped
 // window holds (s (mf_ti(s) - 1) + Q) x (s (kMfTJ - 1) + Q) floats (at most
 // kMfZ); the
 // adjoint's residual and back-projection windows together at most kMfWin,
 // its copy of the kernel padded to s ceil(Q / s) rows and columns at most
 // kMfQP^2.
-constexpr int kMfTJ = 32;
+constexpr int kMfCPT = 2;               // forward: LR columns per thread, 32 apart
+constexpr int kMfTJ = 32 * kMfCPT;
 __host__ __device__ constexpr int mf_ti(int) { return 8; }
 constexpr int kMfLRG = 1;   // LR tiles per forward work item
 constexpr int kMfTU = 16, kMfTV = 64;
