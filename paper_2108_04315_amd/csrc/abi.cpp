@@ -778,10 +778,19 @@ hipError_t misr::ensure_tiles(const misr_op *op, const misr_params &p, TileSet &
     return hipSuccess;
 }
 
+// Tiles of a view in work-list order (strip_tile).  Each XCD takes a
+// contiguous run of the list, and a tile re-reads its window's margin rows
+// from the tiles above and below it: a wide image is listed in strips of a
+// few tile columns, so that those neighbours are a few items apart and their
+// rows still in the XCD's L2, instead of a whole tile row apart (the windows
+// of the 64 tiles of a 6144-px row fill an XCD's 4 MB L2).
 static void add_items(std::vector<Item> &items, int pj, int rows, int cols, int TH, int TW) {
     const int nty = (rows + TH - 1) / TH, ntx = (cols + TW - 1) / TW;
-    for (int ty = 0; ty < nty; ++ty)
-        for (int tx = 0; tx < ntx; ++tx) items.push_back(Item{pj, ty, tx, 0});
+    for (int i = 0; i < nty * ntx; ++i) {
+        int ty, tx;
+        strip_tile(i, nty, ntx, ty, tx);
+        items.push_back(Item{pj, ty, tx, 0});
+    }
 }
 
 void misr::add_views(const misr_op *op, const misr_params &prm, const void *y, void *x,

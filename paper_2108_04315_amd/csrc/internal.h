@@ -124,6 +124,22 @@ struct HaloCopy {
     int gy, gx, rows, cols;
 };
 
+// Work-list order of a view's tiles: row-major, or for a view more than
+// kStripMin tiles wide, strips of kStripTiles tile columns, each listed
+// row by row (down the strip, then the next strip).
+constexpr int kStripTiles = 8, kStripMin = 32;
+__host__ __device__ inline void strip_tile(int i, int nty, int ntx, int &ty, int &tx) {
+    if (ntx <= kStripMin) {
+        ty = i / ntx;
+        tx = i - ty * ntx;
+        return;
+    }
+    const int s = i / (kStripTiles * nty), loc = i - s * kStripTiles * nty;
+    const int ws = ntx - kStripTiles * s < kStripTiles ? ntx - kStripTiles * s : kStripTiles;
+    ty = loc / ws;
+    tx = kStripTiles * s + loc - ty * ws;
+}
+
 struct Item {
     int proj;            // index into Proj array
     int ty, tx;          // tile coordinates in the owned rectangle

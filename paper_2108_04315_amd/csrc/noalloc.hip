@@ -54,7 +54,7 @@ Layout layout(long long n_items) {
 
 // Writes the solver state (objective weights), the view (pointing at that
 // state) and the item list of one untiled image into the workspace: item i
-// is tile (i / ntx, i % ntx), the order of the library's own work lists.
+// is tile strip_tile(i), the order of the library's own work lists.
 __global__ void k_noalloc_setup(Proj P, ScgState S, int nty, int ntx, unsigned char *base,
                                 Layout l) {
     const int n = nty * ntx;
@@ -66,7 +66,11 @@ __global__ void k_noalloc_setup(Proj P, ScgState S, int nty, int ntx, unsigned c
         *(Proj *)(base + l.proj) = P;
         *(int *)(base + l.cnt) = n;
     }
-    if (i < n) ((Item *)(base + l.items))[i] = Item{0, i / ntx, i - (i / ntx) * ntx, 0};
+    if (i < n) {
+        int ty, tx;
+        strip_tile(i, nty, ntx, ty, tx);
+        ((Item *)(base + l.items))[i] = Item{0, ty, tx, 0};
+    }
 }
 
 }  // namespace
