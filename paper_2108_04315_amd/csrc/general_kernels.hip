@@ -198,9 +198,9 @@ FI void mf_adjoint(const AS4 OpDev &op, int tu, int tv, Rf res, float *lds, floa
                     const int qu = fdiv(u + R, S), qv = fdiv(v + R, S);
                     const float *cr = cpl + (u + R - S * qu) * QP + (v + R - S * qv);
                     const float *rr = rsm + (qu - i0) * NJ + (qv - j0);
-#pragma unroll
+#pragma unroll 6
                     for (int t = 0; t < nt; ++t)
-#pragma unroll
+#pragma unroll 6
                         for (int t2 = 0; t2 < nt; ++t2)
                             sum = fmaf(cr[S * (t * QP + t2)], rr[-t * NJ - t2], sum);
                 }
