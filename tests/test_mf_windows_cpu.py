@@ -18,7 +18,7 @@ scales 1-4, rotations up to 135 degrees):
 * the gathered adjoint equals the oracle's (it is the forward's transpose).
 
 The tile sizes and caps below restate the kernels' constants (LR tiles of
-8 x 32, HR tiles of 16 x 64, the cap floor(15 |g0| + 63 |g1| + 2 e) + 3).
+8 x 64, HR tiles of 16 x 64, the cap floor(15 |g0| + 63 |g1| + 2 e) + 3).
 """
 import math
 
@@ -26,9 +26,8 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2108_04315_amd import synth
 
-TI, TJ, TU, TV = 8, 32, 16, 64
+TI, TJ, TU, TV = 8, 64, 16, 64
 
 
 @pytest.fixture(scope="module", autouse=True)
