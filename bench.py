@@ -203,9 +203,12 @@ def serving_leg(misr, ctx, n_req: int = 200, loads=(0.5, 0.8, 1.0), seed: int = 
     paths.  Both paths compute each request's start point (bicubic of frame 0)
     on the device.  The server admits in arrival order while the admitted
     solves hold fewer than fill_mpx million HR pixels, so small requests share
-    the device and large ones keep first-come order.  Served results must
-    equal plain ones bit for bit.  Requests of one (size, scale) share one
-    synthetic projection."""
+    the device and large ones keep first-come order; (c) served earliest
+    finish first (server order 2: each ~3 ms cycle advances the admitted
+    solves with the least key, the request's arrival plus the device time of
+    its work left, up to fill_mpx million HR pixels; the others wait on the
+    device).  Served results must equal plain ones bit for bit.  Requests of
+    one (size, scale) share one synthetic projection."""
     import torch
     rng = np.random.default_rng(seed)
     geoms = [(int(rng.choice(sizes)), int(rng.choice([2, 3]))) for _ in range(n_req)]
@@ -221,6 +224,7 @@ def serving_leg(misr, ctx, n_req: int = 200, loads=(0.5, 0.8, 1.0), seed: int = 
         return misr.default_params(n_iter=SERVE_ITERS, x_init=1)
     hr_px = sum(g[0] * g[0] * g[1] * g[1] for g in geoms)
     srv = misr.Server(ctx, hbm_budget_bytes=96 << 30, fill_mpx=fill_mpx)
+    srv_ef = misr.Server(ctx, hbm_budget_bytes=96 << 30, fill_mpx=fill_mpx, order=2)
     # plain: one result buffer per geometry (one solve at a time); served: one
     # per request (admitted requests run together, each in its own buffer)
     outs_p = {g: torch.empty_like(probs[g]["x0"]) for g in probs}
@@ -242,9 +246,11 @@ def serving_leg(misr, ctx, n_req: int = 200, loads=(0.5, 0.8, 1.0), seed: int = 
             lat.append(t_end - arrivals[i])
         return lat, t_end
 
-    def run_served(arrivals, idx=None):
+    def run_served(arrivals, idx=None, server=None):
+        server = srv if server is None else server
         idx = list(range(n_req)) if idx is None else idx
-        _note(f"serving: served run of {len(idx)} requests")
+        _note(f"serving: served run of {len(idx)} requests"
+              + (" (earliest finish)" if server is srv_ef else ""))
         torch.cuda.synchronize()
         ids = []
         t0 = time.perf_counter()
@@ -252,15 +258,15 @@ def serving_leg(misr, ctx, n_req: int = 200, loads=(0.5, 0.8, 1.0), seed: int = 
             while time.perf_counter() - t0 < arrivals[k]:
                 time.sleep(2e-5)
             pb = probs[geoms[i]]
-            ids.append(srv.submit(pb["H"], pb["H"], pb["s"], pb["shifts"], pb["psf"], pb["y"],
-                                  None, outs_s[i], params(geoms[i])))
+            ids.append(server.submit(pb["H"], pb["H"], pb["s"], pb["shifts"], pb["psf"], pb["y"],
+                                     None, outs_s[i], params(geoms[i])))
         stats = []
         for k, rid in enumerate(ids):
             if k % 50 == 49:
                 _note(f"serving: served request {k + 1} done")
-            if srv.wait(rid, 600_000_000) != misr.OK:
+            if server.wait(rid, 600_000_000) != misr.OK:
                 raise RuntimeError("served request did not finish")
-            st, stt = srv.poll(rid)
+            st, stt = server.poll(rid)
             if st != misr.REQ_DONE:
                 raise RuntimeError(f"served request failed: status {stt.status}")
             stats.append(stt)
@@ -282,6 +288,8 @@ def serving_leg(misr, ctx, n_req: int = 200, loads=(0.5, 0.8, 1.0), seed: int = 
         probs[g]["op"].scg_solve(probs[g]["y"], outs_p[g], params(g), trace=False)
     run_served([0.0] * len(first), first)
     equal = same(first)
+    run_served([0.0] * len(first), first, srv_ef)
+    equal = equal and same(first)
 
     zeros = np.zeros(n_req)
     _, span_p = run_plain(zeros)
@@ -309,17 +317,25 @@ def serving_leg(misr, ctx, n_req: int = 200, loads=(0.5, 0.8, 1.0), seed: int = 
         lat_p, sp_p = run_plain(arr)
         lat_s, sp_s = run_served(arr)
         equal = equal and same()
-        tp_p, tp_s = hr_px / sp_p / 1e6, hr_px / sp_s / 1e6
+        lat_e, sp_e = run_served(arr, server=srv_ef)
+        equal = equal and same()
+        tp_p, tp_s, tp_e = hr_px / sp_p / 1e6, hr_px / sp_s / 1e6, hr_px / sp_e / 1e6
         key = f"load_{load:.2f}"
         res[key] = {
             "arrival_rate_per_s": load * cap_plain,
             "plain": {"p50_ms": pct(lat_p, 50), "p99_ms": pct(lat_p, 99), "hr_mpx_per_s": tp_p},
-            "served": {"p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99), "hr_mpx_per_s": tp_s}}
+            "served": {"p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99), "hr_mpx_per_s": tp_s},
+            "served_earliest_finish": {"p50_ms": pct(lat_e, 50), "p99_ms": pct(lat_e, 99),
+                                       "hr_mpx_per_s": tp_e}}
         verdict[key] = {"served_higher_throughput": tp_s > tp_p,
-                        "served_lower_p99": pct(lat_s, 99) < pct(lat_p, 99)}
+                        "served_lower_p99": pct(lat_s, 99) < pct(lat_p, 99),
+                        "earliest_finish_higher_throughput": tp_e > tp_p,
+                        "earliest_finish_lower_p50": pct(lat_e, 50) < pct(lat_p, 50),
+                        "earliest_finish_lower_p99": pct(lat_e, 99) < pct(lat_p, 99)}
     res["served_vs_plain"] = verdict
     res["served_equals_plain_bitwise"] = bool(equal)
     srv.close()
+    srv_ef.close()
     return res
 
 

@@ -382,6 +382,25 @@ typedef struct {
                                  request would not fit the budget.  Evicting
                                  waits for the device (misr_op_destroy).
                                  Negative: MISR_E_INVAL */
+    int32_t order;            /* 0: every admitted solve advances in every
+                                 cycle (admission as fill_mpx says).  1 and 2:
+                                 requests are admitted in arrival order while
+                                 memory and slots allow (fill_mpx holds none
+                                 back), and each cycle (about 3 ms of device
+                                 time) advances the admitted solves first in
+                                 the order's key, arrival order among equals,
+                                 as many as fit in fill_mpx million HR pixels
+                                 (at least one; fill_mpx 0: all).  1, shortest
+                                 remaining work first: key HR pixels x passes
+                                 left (a large request waits while smaller
+                                 ones keep arriving); 2, earliest finish
+                                 first: key submit time + the device time of
+                                 the work left at the server's running
+                                 estimate (a request that has waited long
+                                 enough is no longer overtaken).  A solve left
+                                 out of a cycle keeps its state on the device
+                                 and resumes unchanged; results do not depend
+                                 on the order.  Other values: MISR_E_INVAL */
 } misr_server_config;
 
 /* Occupancy of a server (misr_server_query). */

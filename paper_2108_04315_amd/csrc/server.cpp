@@ -9,7 +9,9 @@
 // launches over one work list of (view, tile) items, so requests that arrive
 // while others run join at the next pass boundary.  Each solve keeps its own
 // state and reductions (fixed order per solve), so its result does not depend
-// on which other solves share the launches.
+// on which other solves share the launches, nor on the cycles it sits out
+// when the server orders the admitted solves (shortest or earliest finish
+// first).
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -68,6 +70,7 @@ struct SReq {
     size_t es = 4;
     int passes = 0;       // passes enqueued
     bool fresh = true;    // init not yet enqueued
+    bool sel = false;     // advanced by the cycle being built
     // device memory owned by the server for this request
     DevMem xwork, ydev, dstate;
     SolveBufs bufs;
@@ -181,7 +184,7 @@ struct misr_server {
     // the requests being admitted (spare) are kept
     void evict_idle(int keep, size_t need, const std::vector<SReq *> *spare = nullptr);
     int max_idle() const { return cfg.max_idle_ops > 0 ? cfg.max_idle_ops : 8; }
-    hipError_t enqueue_init(List &L);
+    hipError_t enqueue_init(List &L, const std::vector<SReq *> &rs);
     hipError_t enqueue_image(List &L, int kind, bool fresh);
     hipError_t enqueue_scalar(List &L, int phase, bool fresh);
     hipError_t enqueue_halo(List &L, bool fresh);
@@ -565,13 +568,13 @@ hipError_t misr_server::enqueue_halo(List &L, bool fresh) {
 // their tiles; cost and gradient at x0 (and its halo
 // exchange), Moller's init, update pass (p = -g0) with curvature, then steps
 // 1-5 of their first pass.
-hipError_t misr_server::enqueue_init(List &L) {
+hipError_t misr_server::enqueue_init(List &L, const std::vector<SReq *> &rs) {
     hipError_t e = hipSuccess;
-    for (SReq *r : active)   // start points computed on the device
+    for (SReq *r : rs)   // start points computed on the device
         if (e == hipSuccess && r->fresh && r->req.params.x_init > 0)
             e = launch_init(stream, r->req.params.x_init, init_args(r->op), r->ydev_ptr,
                             r->x0dev, (int)r->req.params.img_dtype);
-    for (SReq *r : active)
+    for (SReq *r : rs)
         if (e == hipSuccess && r->fresh && r->staged)
             e = launch_scatter(stream, L.projs.as<Proj>() + r->view0, r->nviews,
                                view_stype(r->req.params), (int)r->req.params.img_dtype);
@@ -645,14 +648,15 @@ void misr_server::run() {
             });
             if (closing && queue.empty() && active.empty() && !P.pending) break;
             // admission by free device memory, slots and host state slots,
-            // first come first served
+            // first come first served (orders 1 and 2: fill_mpx then picks the
+            // solves of each cycle instead of holding requests back)
             const int cap = std::min<int>(std::max(1, cfg.max_slots), (int)free_slots.size() +
                                                                            (int)active.size());
             double held_mpx = 0;   // HR pixels of the solves that will run next cycle
             for (SReq *r : active) held_mpx += r->n * 1e-6;
             while (!queue.empty() && (int)(active.size() + admitted.size()) < cap) {
                 SReq *r = queue.front();
-                if (cfg.fill_mpx > 0 && !(active.empty() && admitted.empty()) &&
+                if (cfg.order == 0 && cfg.fill_mpx > 0 && !(active.empty() && admitted.empty()) &&
                     held_mpx + r->n * 1e-6 > cfg.fill_mpx)
                     break;
                 // its buffers, and its operator's tables unless cached
@@ -700,15 +704,37 @@ void misr_server::run() {
         }
         hipError_t e = hipSuccess;
         if (!active.empty()) {
+            // the solves this cycle advances: all admitted ones, or those first
+            // by the order's key, as many as fill_mpx holds: the work left
+            // (shortest first), or the arrival time plus the device time the
+            // work left takes at the current estimate (earliest finish first)
+            std::vector<SReq *> run = active;
+            if (cfg.order > 0 && cfg.fill_mpx > 0) {
+                const double us_px = us_per_mpx_pass * 1e-6;
+                auto key = [&](const SReq *r) {
+                    const double left = (double)r->n * (r->req.params.n_iter - r->passes);
+                    return cfg.order == 1 ? left : r->stats.t_submit_us + us_px * left;
+                };
+                std::stable_sort(run.begin(), run.end(),
+                                 [&](const SReq *a, const SReq *b) { return key(a) < key(b); });
+                std::vector<SReq *> pick;
+                double m = 0;
+                for (SReq *r : run)
+                    if (pick.empty() || m + r->n * 1e-6 <= cfg.fill_mpx) {
+                        pick.push_back(r);
+                        m += r->n * 1e-6;
+                    }
+                run.swap(pick);
+            }
             // passes this cycle: about 3 ms of device time, at most 64, and no
             // further than the earliest completion
             double mpx = 0;
-            for (SReq *r : active) mpx += r->n * 1e-6;
+            for (SReq *r : run) mpx += r->n * 1e-6;
             int n_ep = (int)(3000.0 / std::max(1e-3, us_per_mpx_pass * mpx));
             n_ep = std::max(1, std::min(64, n_ep));
-            for (SReq *r : active) n_ep = std::min(n_ep, r->req.params.n_iter - r->passes);
+            for (SReq *r : run) n_ep = std::min(n_ep, r->req.params.n_iter - r->passes);
             n_ep = std::max(n_ep, 0);
-            if (build_list(C.list, active) != hipSuccess) {
+            if (build_list(C.list, run) != hipSuccess) {
                 // no work list for this cycle: its requests fail before any launch
                 for (SReq *r : active) {
                     r->drop_state = MISR_REQ_FAILED;
@@ -716,13 +742,14 @@ void misr_server::run() {
                     C.dropped.push_back(r);
                 }
                 active.clear();
+                run.clear();
                 n_ep = 0;
             }
-            if (!active.empty()) e = hipEventRecord(C.ev0, stream);
+            if (!run.empty()) e = hipEventRecord(C.ev0, stream);
             bool any_fresh = false;
-            for (SReq *r : active) any_fresh |= r->fresh;
-            if (e == hipSuccess && any_fresh) e = enqueue_init(C.list);
-            for (SReq *r : active) r->fresh = false;
+            for (SReq *r : run) any_fresh |= r->fresh;
+            if (e == hipSuccess && any_fresh) e = enqueue_init(C.list, run);
+            for (SReq *r : run) r->fresh = false;
             // Each pass ends with steps 1-5 of the next one (phase A), so that
             // no partial sums outlive a cycle: the next cycle's list may place
             // a running solve's items elsewhere.  After a solve's last pass
@@ -737,10 +764,15 @@ void misr_server::run() {
             }
             // finished solves: current iterate into the caller's buffer and the
             // final state into the request's pinned slot
+            for (SReq *r : run) {
+                r->passes += n_ep;
+                r->sel = true;
+            }
             std::vector<SReq *> still;
             for (SReq *r : active) {
-                r->passes += n_ep;
-                if (r->passes < r->req.params.n_iter) {
+                const bool sel = r->sel;
+                r->sel = false;
+                if (!sel || r->passes < r->req.params.n_iter) {
                     still.push_back(r);
                     continue;
                 }
@@ -790,6 +822,7 @@ extern "C" misr_status misr_server_create(misr_ctx *ctx, const misr_server_confi
         return set_error(MISR_E_INVAL,
                          "max_slots >= 1, hbm_budget_bytes > 0 and fill_mpx >= 0 required");
     if (cfg->max_idle_ops < 0) return set_error(MISR_E_INVAL, "max_idle_ops >= 0 required");
+    if (cfg->order < 0 || cfg->order > 2) return set_error(MISR_E_INVAL, "order 0, 1 or 2 required");
     *out = nullptr;
     if (hipSetDevice(ctx->dev) != hipSuccess) return set_error(MISR_E_HIP, "hipSetDevice");
     auto s = std::make_unique<misr_server>();

@@ -84,7 +84,7 @@ class misr_request(C.Structure):
 class misr_server_config(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32),
                 ("max_queue", C.c_int32), ("fail_alloc_n", C.c_int32), ("fill_mpx", C.c_int32),
-                ("fail_list_n", C.c_int32), ("max_idle_ops", C.c_int32)]
+                ("fail_list_n", C.c_int32), ("max_idle_ops", C.c_int32), ("order", C.c_int32)]
 
 
 class misr_server_info(C.Structure):
@@ -459,9 +459,9 @@ class Server:
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 64,
                  max_queue: int = 0, fail_alloc_n: int = 0, fill_mpx: int = 0,
-                 fail_list_n: int = 0, max_idle_ops: int = 0):
+                 fail_list_n: int = 0, max_idle_ops: int = 0, order: int = 0):
         cfg = misr_server_config(hbm_budget_bytes, max_slots, max_queue, fail_alloc_n, fill_mpx,
-                                 fail_list_n, max_idle_ops)
+                                 fail_list_n, max_idle_ops, order)
         h = C.c_void_p()
         check(lib.misr_server_create(ctx.h, C.byref(cfg), C.byref(h)))
         self.h = h

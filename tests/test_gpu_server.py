@@ -366,3 +366,64 @@ def test_operator_eviction_negative_rejected(misr, ctx):
     """max_idle_ops < 0 is refused (host-side check, before any device work)."""
     with pytest.raises(misr.MisrError):
         misr.Server(ctx, hbm_budget_bytes=1 << 30, max_idle_ops=-1)
+
+
+def _finish_order(misr, ctx, order, p_big, p_small, solo_big, solo_small):
+    """Two large requests, then a small one, submitted back to back under a
+    1 Mpx fill; returns their completion times after checking every result
+    against its solo solve."""
+    import torch
+    srv = misr.Server(ctx, hbm_budget_bytes=2 << 30, fill_mpx=1, order=order)
+    reqs = [(p_big, 200, solo_big), (p_big, 200, solo_big), (p_small, 5, solo_small)]
+    ids, outs = [], []
+    for p, n, _ in reqs:
+        x0 = to_dev(_f32(p.x0))
+        out = torch.empty_like(x0)
+        outs.append(out)
+        ids.append(srv.submit(p.H, p.W, p.s, p.shifts, p.psf, to_dev(_f32(p.y)), x0, out,
+                              misr.default_params(n_iter=n)))
+    dones = []
+    for rid, out, (_, n, ref) in zip(ids, outs, reqs):
+        assert srv.wait(rid, 120_000_000) == misr.OK
+        st, stt = srv.poll(rid)
+        assert st == misr.REQ_DONE and stt.n_passes == n
+        assert torch.equal(out, ref)
+        dones.append(stt.t_done_us)
+    srv.close()
+    return dones
+
+
+def test_shortest_first_order(misr, ctx):
+    """order = 1: the small request submitted after two large ones (1024^2 HR,
+    200 passes; 64^2 HR, 5 passes) finishes first, the large ones in arrival
+    order (the first has less work left once it has run, the second sits out
+    its cycles); order = 0 under the same fill keeps arrival order.  Every
+    result equals its solo solve bit for bit either way."""
+    p_big = problem(512, 2, 0.8, None, jitter=0.05, n_iter=200, seeds=(41, 42, 43))
+    p_small = problem(32, 2, 0.8, None, jitter=0.05, n_iter=5, seeds=(44, 45, 46))
+    solo_big = _solo(misr, ctx, p_big, 200)
+    solo_small = _solo(misr, ctx, p_small, 5)
+    a, b, c = _finish_order(misr, ctx, 1, p_big, p_small, solo_big, solo_small)
+    assert c < a < b
+    a, b, c = _finish_order(misr, ctx, 0, p_big, p_small, solo_big, solo_small)
+    assert a < b < c
+
+
+def test_earliest_finish_order(misr, ctx):
+    """order = 2 (key: submit time + device time of the work left): the small
+    request's key (a few ms after the large ones' submit, tiny work left) is
+    below the second large one's, so it finishes before it; every result
+    equals its solo solve bit for bit."""
+    p_big = problem(512, 2, 0.8, None, jitter=0.05, n_iter=200, seeds=(41, 42, 43))
+    p_small = problem(32, 2, 0.8, None, jitter=0.05, n_iter=5, seeds=(44, 45, 46))
+    solo_big = _solo(misr, ctx, p_big, 200)
+    solo_small = _solo(misr, ctx, p_small, 5)
+    a, b, c = _finish_order(misr, ctx, 2, p_big, p_small, solo_big, solo_small)
+    assert a < b and c < b
+
+
+@pytest.mark.parametrize("order", [-1, 3])
+def test_order_out_of_range_rejected(misr, ctx, order):
+    """order other than 0, 1 or 2 is refused (host-side check, before any device work)."""
+    with pytest.raises(misr.MisrError):
+        misr.Server(ctx, hbm_budget_bytes=1 << 30, order=order)
