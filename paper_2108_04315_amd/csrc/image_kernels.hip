@@ -578,7 +578,11 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     const AS4 OpDev &opg = op;
     const i64 Wg = opg.W;
     // window of x_t into LDS: every load first (clamped, unconditional), then
-    // the arithmetic, so that the loads are in flight together
+    // the arithmetic, so that the loads are in flight together.  Global loads
+    // are issued at raised wave priority (here, for g_k and for the frames):
+    // the other workgroup on the CU is usually in a compute phase, and its
+    // waves would otherwise delay the issue of the loads (measured: k_trial
+    // 65.4 -> 64.0 us at 2048^2)
     using WM = WinMap<T>;
     const int lane0 = tid & 63, wv0 = uni(tid >> 6);
     WinCol wc[WM::NC];
@@ -586,6 +590,7 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     for (int c = 0; c < WM::NC; ++c) wc[c] = win_col<T>(lane0, c, o.v0, Wb);
     if (mode == 1) {
         float xr[WM::NR][WM::NC], pr[WM::NR][WM::NC];
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int r = 0; r < WM::NR; ++r) {
             const int ub = o.u0 - T::EXT + wv0 + kNWI * r;
@@ -596,6 +601,7 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
                 pr[r][c] = pb[rb + wc[c].vc];
             }
         }
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int r = 0; r < WM::NR; ++r) {
             const int row = wv0 + kNWI * r, ub = o.u0 - T::EXT + row;
@@ -665,9 +671,11 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
         pass2<S, L, TV>(hx, NI, NJ, wyk, iA, h - 1, [&](int i0, int j, const float (&av)[T::CI]) {
             const int gj = jA + j;
             float yv[T::CI];
+            __builtin_amdgcn_s_setprio(2);
 #pragma unroll
             for (int c = 0; c < T::CI; ++c)
                 yv[c] = SY::ld(yk, (i64)min(iA + i0 + c, h - 1) * w + gj) * yscale;
+            __builtin_amdgcn_s_setprio(0);
             const bool own_j = (S * gj >= o.V0) && (S * gj < P.gx0 + o.v1);
 #pragma unroll
             for (int c = 0; c < T::CI; ++c) {
@@ -727,12 +735,14 @@ FI void tile_trial(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, in
     constexpr bool PRE = TV == 0;
     float gkv[ONR][ONC];
     auto load_gk = [&]() {
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int r = 0; r < ONR; ++r) {
             const i64 rb = (i64)min(o.u0 + wv0 + kNWI * r, o.u1 - 1) * ld;
 #pragma unroll
             for (int c = 0; c < ONC; ++c) gkv[r][c] = gk[rb + ocol[c]];
         }
+        __builtin_amdgcn_s_setprio(0);
     };
     if (PRE && mode == 1) load_gk();
     float gam[8];
@@ -886,13 +896,15 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
     const i64 Wg = W;
     double pp = 0.0, pr = 0.0;
     {
-        // every load first (clamped, unconditional), then the update
+        // every load first (clamped, unconditional, at raised wave priority
+        // as in the trial pass), then the update
         using WM = WinMap<T>;
         const int lane0 = tid & 63, wv0 = uni(tid >> 6);
         WinCol wc[WM::NC];
 #pragma unroll
         for (int c = 0; c < WM::NC; ++c) wc[c] = win_col<T>(lane0, c, o.v0, Wb);
         float xr[WM::NR][WM::NC], pr0[WM::NR][WM::NC], gr[WM::NR][WM::NC];
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int r = 0; r < WM::NR; ++r) {
             const int ub = o.u0 - T::EXT + wv0 + kNWI * r;
@@ -904,6 +916,7 @@ FI void tile_upcurv(const AS4 Proj &P, const AS4 ScgState &st, int ty, int tx, f
                 gr[r][c] = gt[rb + wc[c].vc];
             }
         }
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int r = 0; r < WM::NR; ++r) {
             const int row = wv0 + kNWI * r, ub = o.u0 - T::EXT + row;
