@@ -528,7 +528,9 @@ def bench_precision(misr, ctx, K, Wm, L=2048, s=3, n_iter=100):
         _note(f"precision6144: mode {name}")
         y = y32.to(dt)
         prm = misr.default_params(n_iter=n_iter, x_work=xw)
-        xs = [x032.to(dt) for _ in range(K + Wm)]
+        # a copy each (x032.to(float32) would be x032 itself, and every solve
+        # would start from the previous one's result)
+        xs = [x032.to(dt, copy=True) for _ in range(K + Wm)]
         torch.cuda.synchronize()
         for i in range(Wm):
             op.scg_solve(y, xs[i], prm, trace=False)
