@@ -333,6 +333,17 @@ def serving_leg(misr, ctx, n_req: int = 200, loads=(0.5, 0.8, 1.0), seed: int = 
                         "earliest_finish_lower_p50": pct(lat_e, 50) < pct(lat_p, 50),
                         "earliest_finish_lower_p99": pct(lat_e, 99) < pct(lat_p, 99)}
     res["served_vs_plain"] = verdict
+
+    def loads_where(flag):
+        ks = [k[5:] for k, v in verdict.items() if v[flag]]
+        return "at every load" if len(ks) == len(verdict) else (
+            "at load " + ", ".join(ks) if ks else "at no load")
+    res["served_vs_plain_summary"] = (
+        f"first-come served: higher throughput {loads_where('served_higher_throughput')}, "
+        f"lower p99 {loads_where('served_lower_p99')}; earliest-finish order: higher "
+        f"throughput {loads_where('earliest_finish_higher_throughput')}, lower p50 "
+        f"{loads_where('earliest_finish_lower_p50')}, lower p99 "
+        f"{loads_where('earliest_finish_lower_p99')}")
     res["served_equals_plain_bitwise"] = bool(equal)
     srv.close()
     srv_ef.close()
