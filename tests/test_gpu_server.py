@@ -427,3 +427,40 @@ def test_order_out_of_range_rejected(misr, ctx, order):
     """order other than 0, 1 or 2 is refused (host-side check, before any device work)."""
     with pytest.raises(misr.MisrError):
         misr.Server(ctx, hbm_budget_bytes=1 << 30, order=order)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_paused_tiled_and_untiled_requests_match_plain(misr, ctx, order):
+    """Under a 1 Mpx fill two 1024^2-HR requests (one split into 2 x 2 tiles
+    with an 8-LR-px halo, one whole) cannot share a cycle, so the order runs
+    them by turns with a small request overtaking both: every cycle a solve
+    sits out leaves its state (tile halos included) on the device, and each
+    result equals its plain solve bit for bit."""
+    import torch
+    pb = problem(512, 2, 0.8, None, jitter=0.05, n_iter=60, seeds=(51, 52, 53))
+    ps = problem(40, 2, 0.8, None, jitter=0.05, n_iter=8, seeds=(54, 55, 56))
+    prm_t = misr.default_params(n_iter=60, tile_lr=256, halo_lr=8)
+    op = misr.Operator(ctx, pb.H, pb.W, pb.s, pb.shifts, pb.psf)
+    yb = to_dev(_f32(pb.y))
+    ref_t = to_dev(_f32(pb.x0))
+    op.scg_solve(yb, ref_t, prm_t)
+    ref_w = _solo(misr, ctx, pb, 60)
+    ref_s = _solo(misr, ctx, ps, 8)
+    srv = misr.Server(ctx, hbm_budget_bytes=2 << 30, fill_mpx=1, order=order)
+    reqs = [(pb, prm_t, ref_t), (pb, misr.default_params(n_iter=60), ref_w),
+            (ps, misr.default_params(n_iter=8), ref_s)]
+    ids, outs = [], []
+    for p, prm, _ in reqs:
+        x0 = to_dev(_f32(p.x0))
+        out = torch.empty_like(x0)
+        outs.append(out)
+        ids.append(srv.submit(p.H, p.W, p.s, p.shifts, p.psf, to_dev(_f32(p.y)), x0, out, prm))
+    dones = []
+    for rid, out, (_, prm, ref) in zip(ids, outs, reqs):
+        assert srv.wait(rid, 120_000_000) == misr.OK
+        st, stt = srv.poll(rid)
+        assert st == misr.REQ_DONE and stt.status == misr.OK and stt.n_passes == prm.n_iter
+        assert torch.equal(out, ref), f"max diff {float((out - ref).abs().max())}"
+        dones.append(stt.t_done_us)
+    srv.close()
+    assert dones[2] < dones[1]
