@@ -144,15 +144,30 @@ def misr_curvature_exact(shifts, psf, s, lambda_reg=0.01, alpha_btv=0.4, eps=1e-
 
 def solve(prob_y, shifts, psf, s, x0, n_iter, lambda_reg=0.01, alpha_btv=0.4, eps=1e-3,
           w=3, sigma=1e-4, lam1=1e-6, exact_curvature=False, data_p=2, eps_data=1e-3,
-          warps=None):
+          warps=None, progress=None):
     """SCG solve of the MISR objective (Eq. misr: L2 data term, or the
     Charbonnier-smoothed L1 term for data_p = 1), Moller's finite-difference
     curvature unless exact_curvature (L2, translational warps only); warps:
-    per-frame affine coefficients (see ops) instead of the shifts."""
+    per-frame affine coefficients (see ops) instead of the shifts.
+    progress(n): called after the n-th objective evaluation (log lines of
+    long runs; takes no part in the arithmetic)."""
     if exact_curvature and (data_p != 2 or warps is not None):
         raise ValueError("the closed-form curvature here covers the L2 data term and shifts")
     f = misr_objective(prob_y, shifts, psf, s, lambda_reg, alpha_btv, eps, w, data_p, eps_data,
                        warps)
     curv = misr_curvature_exact(shifts, psf, s, lambda_reg, alpha_btv, eps, w) \
         if exact_curvature else None
+    if progress is not None:
+        f = _counted(f, progress)
     return scg_minimize(f, x0, n_iter, sigma, lam1, curvature=curv)
+
+
+def _counted(f, progress):
+    n = [0]
+
+    def g(x, need_grad):
+        out = f(x, need_grad)
+        n[0] += 1
+        progress(n[0])
+        return out
+    return g

@@ -2,14 +2,15 @@
 full-size parity tests (tests/test_gpu_fullsize.py) and the benchmark's
 oracle leg.
 
-    python tests/golden/make_fullsize_refs.py [name ...]   (default: all)
+    python tests/golden/make_fullsize_refs.py [--out DIR] [name ...]   (default: all)
 
 Every input is drawn by the seeded generator (paper_2108_04315_amd.synth)
 with clean frames from the oracle's own forward operator, rounded to float32
 (what the FP32 GPU path receives), and solved by the oracle's literal SCG
 (Moller's method with the finite-difference curvature) for the workload's
-pass count.  Nothing here calls the HIP library.  Outputs go to
-tests/golden/fullsize/<name>.npz (not tracked: 2-17 MB each):
+pass count, on at most OMP_NUM_THREADS host threads.  Nothing here calls the
+HIP library.  Outputs go to tests/golden/fullsize/<name>.npz, or to DIR
+(not tracked: 2-17 MB each):
 
   x        the oracle image (float32), whole for plain2048, else at `idx`
   idx      sorted flat pixel indices of the sample (int32; absent when whole)
@@ -104,7 +105,10 @@ def make(name: str, spec: dict, threads: int) -> None:
     t1 = time.perf_counter()
     print(f"{name}: inputs {p.H}x{p.W}, K={p.K} in {t1 - t0:.1f} s; solving "
           f"{spec['n_iter']} passes", flush=True)
-    x, recs, _ = oscg.solve(y, p.shifts, p.psf, p.s, x0, spec["n_iter"])
+    def progress(n):
+        if n % 10 == 0:
+            print(f"{name}: {n} evaluations, {time.perf_counter() - t1:.0f} s", flush=True)
+    x, recs, _ = oscg.solve(y, p.shifts, p.psf, p.s, x0, spec["n_iter"], progress=progress)
     t2 = time.perf_counter()
     trace = np.array([[r[k] for k in TRACE_KEYS] for r in recs], dtype=np.float64)
     out = dict(trace=trace, y_sha=np.array(sha), norm_x=np.array(np.linalg.norm(x)),
@@ -129,8 +133,12 @@ def make(name: str, spec: dict, threads: int) -> None:
 
 
 def main(argv):
+    global OUT
+    if argv[:1] == ["--out"]:
+        OUT, argv = os.path.abspath(argv[1]), argv[2:]
     todo = argv or list(specs())
     threads = len(os.sched_getaffinity(0))
+    threads = min(threads, int(os.environ.get("OMP_NUM_THREADS", threads)))
     sp = specs()
     for name in todo:
         make(name, sp[name], threads)
